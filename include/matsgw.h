@@ -1,0 +1,233 @@
+/*
+ * matsgw.h -- C ABI of the MI355X Matsubara-time GW hot path.
+ *
+ * The operations follow Chu et al., "All-electron self-consistent GW in the
+ * Matsubara-time domain" (arXiv:1602.02313):
+ *   polarization P(q,tau)            eq. irpol (with G(-tau) = -G(beta-tau), Basics of the Theory)
+ *   tau <-> i omega transforms       eq. trans (cubic-spline quadrature, "Analytic continuation")
+ *   screened interaction W~(q,i nu)  eq. scrv and the W~ Dyson equation ("Screened Coulomb potential"),
+ *                                    solved on the bosonic Matsubara axis
+ *   correlation self-energy          eq. sigc
+ *   exchange self-energy             Sigma^x = -G(0-) v delta(tau), product-basis form of eq. sigx
+ *   Dyson update of G                eqs. dysongf, zxjk, zcjk, solved on the fermionic axis
+ *
+ * Conventions shared by every call
+ *   - Every call returns int: MSGW_OK (0) or a negative MSGW_E* code; nothing
+ *     throws across the ABI.  msgw_last_error() gives a message for the last
+ *     failure on a context.
+ *   - Arguments are validated on the host before anything is enqueued; a
+ *     failing call enqueues nothing.
+ *   - Device calls are asynchronous on the caller's stream (a hipStream_t
+ *     passed as void*, NULL = the default stream) and never synchronise the
+ *     device unless stated.
+ *   - Ownership: the caller owns every device buffer, including the workspace.
+ *     The library allocates no device memory; the context owns its host-side
+ *     tables.  One context serves one host thread.
+ *   - Layouts: row-major, 0-based.  Complex data are interleaved (re, im):
+ *     "c128" = 2 x double, "c64" = 2 x float.  Hermitian outputs are stored in
+ *     full.
+ *   - Indices: n is a band at k, m a band at k-q.  M^I_nm(k,q) is the paper's
+ *     M^{k-q}_{mn}(G_I, q) (eq. mmatrix).  s = problem.scale = -1/(Omega N_k).
+ *   - tau[0] = 0 holds the 0+ limit and tau[ntau-1] = beta the beta- limit.
+ *
+ * Array shapes used below (nbmax = max_k Nb_k):
+ *   G_tau      f64  [nk][nbmax][ntau]     entries n >= Nb_k are ignored / written 0
+ *   M (per q)  c128 or c64, for k = 0..nk-1 a block [NI_q][Nb_k][Nb_{k-q}];
+ *              q blocks are packed one after another starting at q0
+ *              (msgw_m_layout gives the offsets)
+ *   P_tau      c128 [q][ntau][NI_q][NI_q]     packed over the q range of the call
+ *   P_iw, Wt_iw, R_iw  c128 [q][niw_b][NI_q][NI_q]
+ *   Wt_tau     c128 [q][ntau][NI_q][NI_q]
+ *   v          f64  [q][NI_q]                packed over the q range of the call
+ *   Sigma_tau  f64  [nk][nbmax][ntau] (DIAG)  or c128 [nk][nbmax][nbmax][ntau] (FULL)
+ *   Sigma_x    f64  [nk][nbmax]       (DIAG)  or c128 [nk][nbmax][nbmax]       (FULL)
+ *   eps, sigma_static        f64 [nk][nbmax]
+ *   Sigma_c_iw, G_iw         c128 [nk][nbmax][niw_f]
+ */
+#ifndef MATSGW_H
+#define MATSGW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define MSGW_OK        0
+#define MSGW_EINVAL   (-1)   /* bad argument (null pointer, out-of-range enum or index) */
+#define MSGW_ESHAPE   (-2)   /* inconsistent sizes, tau mesh not mirror symmetric, ...  */
+#define MSGW_EHIP     (-3)   /* a HIP runtime call failed (message has the HIP error)    */
+#define MSGW_ENOMEM   (-4)   /* workspace missing or too small for the request           */
+#define MSGW_ENOCONV  (-5)   /* reserved: iteration did not converge                      */
+#define MSGW_ENOTSUP  (-6)   /* combination not supported (limits are in the message)     */
+
+/* precision of the two contractions (polarization, self_energy) */
+#define MSGW_FP64    0   /* FP64 arithmetic throughout                                  */
+#define MSGW_FP32    1   /* FP32 MFMA, FP32 accumulation per k, FP64 across k            */
+#define MSGW_BF16X3  2   /* 3-term BF16 split (hi*hi + hi*lo + lo*hi) on MFMA, FP32 accumulate */
+
+/* storage type of M */
+#define MSGW_C128    0
+#define MSGW_C64     1
+
+/* statistics of a transform */
+#define MSGW_FERMION 0   /* omega_n = (2n+1) pi / beta */
+#define MSGW_BOSON   1   /* nu_n    =  2n    pi / beta */
+
+/* self-energy mode */
+#define MSGW_SIGMA_DIAG 0   /* Sigma_nn(k,tau), the diagonal approximation of the paper */
+#define MSGW_SIGMA_FULL 1   /* Sigma_nn'(k,tau), full band matrix (FP64 only)           */
+
+/* chemical potential handling in msgw_dyson */
+#define MSGW_MU_FIXED  0
+#define MSGW_MU_SEARCH 1
+
+/* bits of the device flag word written by msgw_dyson */
+#define MSGW_FLAG_NAN        1   /* a non-finite value in Sigma or G   */
+#define MSGW_FLAG_NOBRACKET  2   /* n_target outside [N(lo), N(hi)]     */
+
+/* hard limits (checked by set_problem / the calls) */
+#define MSGW_MAX_NI   1024   /* product-basis size per q (screen keeps a row per thread) */
+#define MSGW_MAX_NB   1024
+#define MSGW_MIN_NTAU 4      /* not-a-knot spline needs four points */
+
+typedef struct msgw_ctx msgw_ctx;
+
+typedef struct {
+    int           nk;         /* number of k points = number of q points                        */
+    const int*    kmq;        /* host [nk*nk]: kmq[q*nk + k] = index of k - q                       */
+    const int*    nb;         /* host [nk]: Nb_k, bands at k                                         */
+    const int*    ni;         /* host [nk]: NI_q, product-basis size at q                            */
+    int           ntau;       /* points of the tau mesh, including 0 and beta                        */
+    const double* tau;        /* host [ntau]: 0 = tau_0 < ... < tau_{ntau-1} = beta, mirror symmetric */
+    double        beta;       /* inverse temperature                                                 */
+    int           niw_f;      /* positive fermionic Matsubara frequencies                            */
+    int           niw_b;      /* non-negative bosonic Matsubara frequencies (nu_0 = 0 included)      */
+    double        scale;      /* s = -1/(Omega N_k), prefactor of P, Sigma^c and Sigma^x             */
+    int           sigma_mode; /* MSGW_SIGMA_DIAG or MSGW_SIGMA_FULL                                  */
+} msgw_problem;
+
+/* ---- context ---------------------------------------------------------------------------- */
+
+/* Create a context bound to HIP device `hip_device`.  *out is NULL on failure. */
+int msgw_create(msgw_ctx** out, int hip_device);
+/* Destroy a context (NULL is accepted).  Does not touch caller-owned device memory. */
+int msgw_destroy(msgw_ctx* c);
+/* Message of the last failed call on c ("" if none).  Valid until the next call on c. */
+const char* msgw_last_error(const msgw_ctx* c);
+
+/* Set the problem.  Host-synchronous; copies every input.  Builds the FP64 transform
+ * weights (not-a-knot cubic spline integrated exactly against e^{i omega tau}).
+ * ESHAPE: ntau < 4, tau not increasing, tau[0] != 0, tau[ntau-1] != beta, or
+ * |tau_i + tau_{ntau-1-i} - beta| > 1e-12 beta for some i.  Invalidates the workspace. */
+int msgw_set_problem(msgw_ctx* c, const msgw_problem* p);
+
+/* Bytes of device workspace needed for calls covering at most nq_max q points at once. */
+int msgw_workspace_size(msgw_ctx* c, int nq_max, size_t* bytes);
+/* Attach caller-owned device workspace (>= msgw_workspace_size for some nq_max) and upload
+ * the constant tables into it.  Host-synchronous.  The buffer must outlive its use. */
+int msgw_set_workspace(msgw_ctx* c, void* dptr, size_t bytes);
+
+/* Layout of M: offsets (in complex elements) of the (q,k) block relative to the start of
+ * q's block, and the size of q's block.  off may be NULL. */
+int msgw_m_layout(const msgw_ctx* c, int q, int64_t* off /*[nk] or NULL*/, int64_t* qsize);
+
+/* ---- hot path ------------------------------------------------------------------------------ */
+
+/* a1. Reference Green's function (eq. for G^0_j(k|tau)):
+ * G_tau[k][n][i] = -exp(-E tau_i) (1 - n_F(E)), E = eps[k][n] - mu, for n < Nb_k (0 otherwise),
+ * evaluated in the overflow-free form.  eps: device f64 [nk][nbmax]; G_tau: device. */
+int msgw_green0(msgw_ctx* c, void* stream, const double* eps, double mu, double* G_tau);
+
+/* a2. Polarization (eq. irpol):
+ * P_IJ(q,tau_i) = s sum_k sum_{n<Nb_k} sum_{m<Nb_{k-q}} M^I_nm G_n(k,tau_i) G_m(k-q,tau_{ntau-1-i}) conj(M^J_nm)
+ * for q = q0..q0+nq-1.  M (device, m_dtype) starts at q0's block; G_tau device; P_tau (device c128)
+ * is overwritten.  precision MSGW_FP64 needs MSGW_C128 M; FP32/BF16X3 need MSGW_C64 M. */
+int msgw_polarization(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
+                      const double* G_tau, int precision, void* P_tau);
+
+/* a3, a7 and G(tau) -> G(i omega).  Forward transform (eq. trans) along the tau axis:
+ * f_iw[b][n][e] = int_0^beta e^{i w_n tau} f(tau) dtau, with f given at the mesh points as
+ * f_tau[b][i][e] (b < nblk, i < ntau, e < len; real f64 if !f_is_complex, else c128), integrated
+ * as the not-a-knot cubic spline.  stat selects omega_n (niw_f values) or nu_n (niw_b values).
+ * e_ref (device f64 [nblk*len], FERMION only, may be NULL): the spline is applied to
+ * f - G0(e_ref) and the exact 1/(i w_n - e_ref) is added, so a 0/beta jump is carried exactly.
+ * f_iw: device c128 [nblk][niw][len]. */
+int msgw_tau_to_iw(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t len,
+                   const void* f_tau, int f_is_complex, const double* e_ref, void* f_iw);
+
+/* Inverse transform (truncated Matsubara sum), f_iw[b][n][e] -> f_tau[b][i][e]:
+ *   FERMION (mat_n == 0, real output f64):
+ *     f(tau_i) = G0(e_ref,tau_i) + (2/beta) sum_{n<niw_f} Re[e^{-i w_n tau_i}(f(i w_n) - 1/(i w_n - e_ref))]
+ *     (e_ref may be NULL: no reference term).
+ *   BOSON (mat_n > 0, len == mat_n^2, Hermitian pair f(-i nu) = f(i nu)^H, c128 output):
+ *     f(tau_i) = add(tau_i) + (1/beta)[f_0 + sum_{n>=1}(e^{-i nu_n tau_i} f_n + e^{i nu_n tau_i} f_n^H)]
+ *     add_tau (device c128 [nblk][ntau][len] or NULL). */
+int msgw_iw_to_tau(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t len, int mat_n,
+                   const void* f_iw, const void* add_tau, const double* e_ref, void* f_tau);
+
+/* a4. Screened interaction on the bosonic axis (W~ Dyson equation, eq. scrv, on i nu):
+ * chi~ = v^1/2 P v^1/2;  W~ = v^1/2 [(1 - chi~)^-1 - 1] v^1/2;  R = W~ - v P v.
+ * (1 - chi~) is inverted in FP64 by blocked Gauss-Jordan with partial (row) pivoting.
+ * P_iw, Wt_iw, R_iw: device c128 [q][niw_b][NI_q][NI_q]; v: device f64 [q][NI_q]; R_iw may be NULL.
+ * info: device int [nq*niw_b], 0 or 1 + the first column whose pivot was exactly zero. */
+int msgw_screen(msgw_ctx* c, void* stream, int q0, int nq, const void* P_iw, const double* v,
+                void* Wt_iw, void* R_iw, int* info);
+
+/* a5. W~(q,tau_i) = v P(q,tau_i) v + (1/beta)[R(i nu_0) + sum_{n>=1}(e^{-i nu_n tau_i} R(i nu_n)
+ *                    + e^{i nu_n tau_i} R(i nu_n)^H)]
+ * (R(-i nu) = R(i nu)^H because P(tau) is Hermitian).  R_iw, P_tau, v as above; Wt_tau device c128. */
+int msgw_screened_tau(msgw_ctx* c, void* stream, int q0, int nq, const void* R_iw,
+                      const void* P_tau, const double* v, void* Wt_tau);
+
+/* a6. Correlation self-energy (eq. sigc), ACCUMULATED into Sigma_tau:
+ * DIAG: Sigma_n(k,tau_i) += s sum_q sum_m G_m(k-q,tau_i) Re sum_IJ conj(M^I_nm) W~_IJ(q,tau_i) M^J_nm
+ * FULL: Sigma_nn'(k,tau_i) += s sum_q sum_m G_m(k-q,tau_i) sum_IJ conj(M^I_nm) W~_IJ M^J_n'm (FP64 only).
+ * The caller zeroes Sigma_tau before the first q.  Wt_tau: device c128 [q][ntau][NI_q][NI_q]. */
+int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
+                     const double* G_tau, const void* Wt_tau, int precision, void* Sigma_tau);
+
+/* a6b. Exchange self-energy, ACCUMULATED (product-basis form of eq. sigx with f = G(0-)):
+ * DIAG: Sigma^x_n(k) += s sum_q sum_m f_m(k-q) sum_I v_I |M^I_nm|^2 ; FULL: the n,n' matrix
+ * s sum_q sum_m f_m sum_I v_I conj(M^I_nm) M^I_n'm.  The occupations are read from the Green's
+ * function, f_m(k) = G_m(k, 0-) = -G_tau[k][m][ntau-1].  FP64 arithmetic for either M dtype. */
+int msgw_sigma_x(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
+                 const double* G_tau, const double* v, void* Sigma_x);
+
+/* a8. Dyson update of the diagonal G on the fermionic axis and the chemical potential:
+ * E = eps + sigma_static - mu;  G(i w_n) = 1/(i w_n - E - Sigma^c(i w_n));
+ * N(mu) = sum_nk [n_F(E) + (2/beta) sum_{n<niw_f} Re(G - 1/(i w_n - E))];
+ * MSGW_MU_SEARCH: mu by 200 fixed bisection steps on [min(eps+sigma_static) - 50/beta,
+ * max(...) + 50/beta] so that N(mu) = n_target (device-side, graph-capturable);
+ * MSGW_MU_FIXED: mu is read from *mu.  Then G(tau) by the FERMION inverse transform with
+ * e_ref = E.  mu, n_out: device f64 scalars (mu in/out); flags: device int (MSGW_FLAG_*).
+ * G_iw may be NULL. */
+int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
+               const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
+               double* G_tau, double* n_out, int* flags);
+
+/* a9 (loop control).  Matsubara-axis gap proxy used to follow the self-consistent loop:
+ * E^QP_nk = eps + sigma_static + Re Sigma^c_nk(i w_0) - mu over all (n < Nb_k, k), and
+ * *gap = E_(N+1) - E_(N) (ascending order, 1-based) with N = n_index, 1 <= N < number of states.
+ * The paper reads gaps off analytically continued spectra instead; this proxy involves no
+ * continuation.  Sigma_c_iw: device c128 [nk][nbmax][niw_f]; mu: device scalar; gap: device f64. */
+int msgw_gap(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
+             const void* Sigma_c_iw, const double* mu, int n_index, double* gap);
+
+/* ---- input generation (not part of the method) ---------------------------------------------- */
+
+/* Synthetic M for q0..q0+nq-1 in the layout above (c128 or c64): complex Gaussian with
+ * E|M^I|^2 = 1/(1+I/16), drawn by Philox4x32-10 (key = seed, counter = (orbit index lo, hi, I,
+ * 0x4D475731)) and Box-Muller in FP64.  symmetric != 0: one draw per orbit of the time-reversal /
+ * pair symmetry (k,q,n,m) -> (q-k,q,m,n) and (k,q,n,m) -> (-k,-q,n,m)+conj, keyed by the
+ * orbit's smallest linear index ((q nk + k) nbmax + n) nbmax + m; an orbit fixed by a conjugating
+ * element is real.  -k and q-k are read from kmq (k index 0 must be Gamma). */
+int msgw_synth_M(msgw_ctx* c, void* stream, uint64_t seed, int q0, int nq, int symmetric,
+                 int m_dtype, void* M);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MATSGW_H */

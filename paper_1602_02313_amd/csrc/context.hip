@@ -1,0 +1,522 @@
+// Host side of the C ABI: context, validation, FP64 transform weights, workspace.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <sstream>
+
+#include "internal.h"
+
+using cplx = std::complex<double>;
+using namespace msgw;
+
+struct msgw_ctx {
+    int device = 0;
+    std::string err;
+    bool have_problem = false;
+    Host h;
+    // host tables
+    std::vector<cplx> wf, wb, ef, eb;
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_ready = false;
+    Dev d;
+    size_t scratch_off = 0;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---- dense LU with partial pivoting (host, small systems) ----
+void lu_solve_multi(std::vector<double> A, int n, std::vector<double>& B, int nrhs) {
+    // A: n*n row-major; B: n*nrhs row-major, overwritten with the solution.
+    std::vector<int> piv(n);
+    for (int j = 0; j < n; ++j) {
+        int p = j;
+        for (int i = j + 1; i < n; ++i)
+            if (std::fabs(A[i * n + j]) > std::fabs(A[p * n + j])) p = i;
+        if (A[p * n + j] == 0.0) throw Error(MSGW_ESHAPE, "singular spline system (repeated tau?)");
+        if (p != j) {
+            for (int c = 0; c < n; ++c) std::swap(A[j * n + c], A[p * n + c]);
+            for (int c = 0; c < nrhs; ++c) std::swap(B[j * nrhs + c], B[p * nrhs + c]);
+        }
+        for (int i = j + 1; i < n; ++i) {
+            double f = A[i * n + j] / A[j * n + j];
+            if (f == 0.0) continue;
+            for (int c = j; c < n; ++c) A[i * n + c] -= f * A[j * n + c];
+            for (int c = 0; c < nrhs; ++c) B[i * nrhs + c] -= f * B[j * nrhs + c];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        for (int c = 0; c < nrhs; ++c) {
+            double s = B[i * nrhs + c];
+            for (int k = i + 1; k < n; ++k) s -= A[i * n + k] * B[k * nrhs + c];
+            B[i * nrhs + c] = s / A[i * n + i];
+        }
+    }
+}
+
+// Moments J_p(w, h) = int_0^h t^p e^{i w t} dt, p = 0..3.
+void moments(double w, double h, cplx J[4]) {
+    const cplx I(0.0, 1.0);
+    if (std::fabs(w * h) < 0.5) {
+        // series: J_p = h^{p+1} sum_j (i w h)^j / (j! (p + j + 1))
+        cplx z = I * (w * h);
+        for (int p = 0; p < 4; ++p) {
+            cplx term = 1.0, acc = 0.0;
+            for (int j = 0; j < 30; ++j) {
+                if (j) term *= z / double(j);
+                acc += term / double(p + j + 1);
+            }
+            J[p] = acc * std::pow(h, p + 1);
+        }
+    } else {
+        cplx e = std::exp(I * (w * h));
+        cplx iw = I * w;
+        J[0] = (e - 1.0) / iw;
+        for (int p = 1; p < 4; ++p) J[p] = (std::pow(h, p) * e - double(p) * J[p - 1]) / iw;
+    }
+}
+
+// Forward weights W[n][j]: F(i w_n) = sum_j W[n][j] f_j for the not-a-knot cubic spline of f
+// integrated exactly against e^{i w tau} over [0, beta].
+void spline_filon_weights(const std::vector<double>& tau, int niw, bool fermion, double beta,
+                          std::vector<cplx>& W) {
+    const int n = (int)tau.size();
+    const int N = n - 1;  // intervals
+    std::vector<double> h(N);
+    for (int i = 0; i < N; ++i) h[i] = tau[i + 1] - tau[i];
+    // second derivatives sig = X f, from A sig = Rm f
+    std::vector<double> A(n * n, 0.0), X(n * n, 0.0);
+    A[0 * n + 0] = -1.0 / h[0];
+    A[0 * n + 1] = 1.0 / h[0] + 1.0 / h[1];
+    A[0 * n + 2] = -1.0 / h[1];
+    for (int i = 1; i < n - 1; ++i) {
+        A[i * n + i - 1] = h[i - 1];
+        A[i * n + i] = 2.0 * (h[i - 1] + h[i]);
+        A[i * n + i + 1] = h[i];
+        X[i * n + i + 1] += 6.0 / h[i];
+        X[i * n + i] += -6.0 / h[i] - 6.0 / h[i - 1];
+        X[i * n + i - 1] += 6.0 / h[i - 1];
+    }
+    A[(n - 1) * n + n - 3] = -1.0 / h[n - 3];
+    A[(n - 1) * n + n - 2] = 1.0 / h[n - 3] + 1.0 / h[n - 2];
+    A[(n - 1) * n + n - 1] = -1.0 / h[n - 2];
+    lu_solve_multi(A, n, X, n);  // X[i][j] = d sig_i / d f_j
+    W.assign(size_t(niw) * n, cplx(0.0));
+    for (int w = 0; w < niw; ++w) {
+        double om = (fermion ? (2.0 * w + 1.0) : 2.0 * w) * kPi / beta;
+        for (int i = 0; i < N; ++i) {
+            cplx J[4];
+            moments(om, h[i], J);
+            cplx ph = std::exp(cplx(0.0, om * tau[i]));
+            for (int p = 0; p < 4; ++p) J[p] *= ph;
+            // a_i = f_i ; b_i = (f_{i+1}-f_i)/h - h (2 s_i + s_{i+1})/6 ; c_i = s_i/2 ;
+            // d_i = (s_{i+1} - s_i)/(6h)
+            cplx* row = &W[size_t(w) * n];
+            row[i] += J[0];
+            row[i + 1] += J[1] / h[i];
+            row[i] -= J[1] / h[i];
+            for (int j = 0; j < n; ++j) {
+                double si = X[i * n + j], si1 = X[(i + 1) * n + j];
+                if (si == 0.0 && si1 == 0.0) continue;
+                row[j] += J[1] * (-h[i] * (2.0 * si + si1) / 6.0) + J[2] * (si / 2.0) +
+                          J[3] * ((si1 - si) / (6.0 * h[i]));
+            }
+        }
+    }
+}
+
+void set_err(msgw_ctx* c, const std::string& m) {
+    if (c) c->err = m;
+}
+
+template <class F>
+int guarded(msgw_ctx* c, F&& f) {
+    if (!c) return MSGW_EINVAL;
+    try {
+        c->err.clear();
+        f();
+        return MSGW_OK;
+    } catch (const Error& e) {
+        set_err(c, e.what());
+        return e.code;
+    } catch (const std::exception& e) {
+        set_err(c, e.what());
+        return MSGW_EINVAL;
+    }
+}
+
+void need(bool cond, int code, const std::string& msg) {
+    if (!cond) throw Error(code, msg);
+}
+
+void require_ready(msgw_ctx* c) {
+    need(c->have_problem, MSGW_EINVAL, "no problem set (msgw_set_problem)");
+    need(c->ws_ready, MSGW_ENOMEM, "no workspace attached (msgw_set_workspace)");
+    MSGW_HIP(hipSetDevice(c->device));
+}
+
+void check_qrange(msgw_ctx* c, int q0, int nq) {
+    need(q0 >= 0 && nq >= 1 && q0 + nq <= c->h.nk, MSGW_EINVAL, "q range outside [0, nk)");
+}
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+int msgw_create(msgw_ctx** out, int hip_device) {
+    if (!out) return MSGW_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return MSGW_EHIP;
+    if (hip_device < 0 || hip_device >= n) return MSGW_EINVAL;
+    auto* c = new (std::nothrow) msgw_ctx();
+    if (!c) return MSGW_EINVAL;
+    c->device = hip_device;
+    *out = c;
+    return MSGW_OK;
+}
+
+int msgw_destroy(msgw_ctx* c) {
+    delete c;
+    return MSGW_OK;
+}
+
+const char* msgw_last_error(const msgw_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int msgw_set_problem(msgw_ctx* c, const msgw_problem* p) {
+    return guarded(c, [&] {
+        need(p != nullptr, MSGW_EINVAL, "null problem");
+        need(p->kmq && p->nb && p->ni && p->tau, MSGW_EINVAL, "null table in problem");
+        need(p->nk >= 1, MSGW_ESHAPE, "nk must be >= 1");
+        need(p->ntau >= MSGW_MIN_NTAU, MSGW_ESHAPE, "ntau must be >= 4 (not-a-knot spline)");
+        need(p->niw_f >= 1 && p->niw_b >= 1, MSGW_ESHAPE, "niw_f and niw_b must be >= 1");
+        need(p->beta > 0 && std::isfinite(p->beta), MSGW_EINVAL, "beta must be positive");
+        need(std::isfinite(p->scale), MSGW_EINVAL, "scale must be finite");
+        need(p->sigma_mode == MSGW_SIGMA_DIAG || p->sigma_mode == MSGW_SIGMA_FULL, MSGW_EINVAL,
+             "bad sigma_mode");
+        Host h;
+        h.nk = p->nk;
+        h.ntau = p->ntau;
+        h.niw_f = p->niw_f;
+        h.niw_b = p->niw_b;
+        h.beta = p->beta;
+        h.scale = p->scale;
+        h.sigma_mode = p->sigma_mode;
+        h.kmq.assign(p->kmq, p->kmq + size_t(p->nk) * p->nk);
+        h.nb.assign(p->nb, p->nb + p->nk);
+        h.ni.assign(p->ni, p->ni + p->nk);
+        h.tau.assign(p->tau, p->tau + p->ntau);
+        for (int v : h.kmq) need(v >= 0 && v < h.nk, MSGW_EINVAL, "kmq entry out of range");
+        for (int v : h.nb) need(v >= 1 && v <= MSGW_MAX_NB, MSGW_ESHAPE, "Nb_k outside [1, 1024]");
+        for (int v : h.ni) need(v >= 1 && v <= MSGW_MAX_NI, MSGW_ESHAPE, "NI_q outside [1, 1024]");
+        need(h.tau[0] == 0.0, MSGW_ESHAPE, "tau[0] must be 0");
+        need(std::fabs(h.tau.back() - h.beta) <= 1e-12 * h.beta, MSGW_ESHAPE, "tau[-1] must be beta");
+        for (int i = 0; i + 1 < h.ntau; ++i)
+            need(h.tau[i + 1] > h.tau[i], MSGW_ESHAPE, "tau must be strictly increasing");
+        for (int i = 0; i < h.ntau; ++i)
+            need(std::fabs(h.tau[i] + h.tau[h.ntau - 1 - i] - h.beta) <= 1e-12 * h.beta,
+                 MSGW_ESHAPE, "tau mesh is not mirror symmetric (tau_i + tau_{N-i} != beta)");
+        h.nbmax = *std::max_element(h.nb.begin(), h.nb.end());
+        h.nimax = *std::max_element(h.ni.begin(), h.ni.end());
+        const int nk = h.nk;
+        h.moff.assign(size_t(nk) * nk, 0);
+        h.mpre.assign(nk + 1, 0);
+        h.ppre.assign(nk + 1, 0);
+        h.wpre.assign(nk + 1, 0);
+        h.vpre.assign(nk + 1, 0);
+        for (int q = 0; q < nk; ++q) {
+            int64_t off = 0;
+            for (int k = 0; k < nk; ++k) {
+                h.moff[size_t(q) * nk + k] = off;
+                off += int64_t(h.ni[q]) * h.nb[k] * h.nb[h.kmq[size_t(q) * nk + k]];
+            }
+            h.mpre[q + 1] = h.mpre[q] + off;
+            h.ppre[q + 1] = h.ppre[q] + int64_t(h.ntau) * h.ni[q] * h.ni[q];
+            h.wpre[q + 1] = h.wpre[q] + int64_t(h.niw_b) * h.ni[q] * h.ni[q];
+            h.vpre[q + 1] = h.vpre[q] + h.ni[q];
+        }
+        // transform tables
+        std::vector<cplx> wf, wb;
+        spline_filon_weights(h.tau, h.niw_f, true, h.beta, wf);
+        spline_filon_weights(h.tau, h.niw_b, false, h.beta, wb);
+        std::vector<cplx> ef(size_t(h.ntau) * h.niw_f), eb(size_t(h.ntau) * h.niw_b);
+        for (int i = 0; i < h.ntau; ++i) {
+            for (int n = 0; n < h.niw_f; ++n)
+                ef[size_t(i) * h.niw_f + n] = std::exp(cplx(0.0, -(2.0 * n + 1.0) * kPi / h.beta * h.tau[i]));
+            for (int n = 0; n < h.niw_b; ++n)
+                eb[size_t(i) * h.niw_b + n] = std::exp(cplx(0.0, -(2.0 * n) * kPi / h.beta * h.tau[i]));
+        }
+        c->h = std::move(h);
+        c->wf = std::move(wf);
+        c->wb = std::move(wb);
+        c->ef = std::move(ef);
+        c->eb = std::move(eb);
+        c->have_problem = true;
+        c->ws_ready = false;
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+    });
+}
+
+static size_t tables_bytes(const Host& h) {
+    size_t b = 0;
+    b += align_up(sizeof(double) * h.ntau);
+    b += align_up(sizeof(double2) * size_t(h.niw_f) * h.ntau) * 2;
+    b += align_up(sizeof(double2) * size_t(h.niw_b) * h.ntau) * 2;
+    b += align_up(sizeof(int) * size_t(h.nk) * h.nk);
+    b += align_up(sizeof(int) * h.nk) * 2;
+    b += align_up(sizeof(int64_t) * size_t(h.nk) * h.nk);
+    b += align_up(sizeof(int64_t) * (h.nk + 1)) * 4;
+    return b;
+}
+
+static size_t scratch_needed(const Host& h, int nq_max) {
+    return scratch_E_bytes(h) + align_up(mfma_scratch_bytes(h, nq_max));
+}
+
+int msgw_workspace_size(msgw_ctx* c, int nq_max, size_t* bytes) {
+    return guarded(c, [&] {
+        need(c->have_problem, MSGW_EINVAL, "no problem set");
+        need(bytes != nullptr, MSGW_EINVAL, "null bytes");
+        need(nq_max >= 1 && nq_max <= c->h.nk, MSGW_EINVAL, "nq_max outside [1, nk]");
+        *bytes = tables_bytes(c->h) + scratch_needed(c->h, nq_max);
+    });
+}
+
+int msgw_set_workspace(msgw_ctx* c, void* dptr, size_t bytes) {
+    return guarded(c, [&] {
+        need(c->have_problem, MSGW_EINVAL, "no problem set");
+        need(dptr != nullptr, MSGW_EINVAL, "null workspace");
+        need((reinterpret_cast<uintptr_t>(dptr) & 255) == 0, MSGW_EINVAL, "workspace must be 256-byte aligned");
+        const Host& h = c->h;
+        size_t tb = tables_bytes(h);
+        need(bytes >= tb + scratch_needed(h, 1), MSGW_ENOMEM, "workspace smaller than msgw_workspace_size(nq_max=1)");
+        MSGW_HIP(hipSetDevice(c->device));
+        char* base = static_cast<char*>(dptr);
+        size_t off = 0;
+        auto put = [&](const void* src, size_t n) -> void* {
+            void* p = base + off;
+            if (n) MSGW_HIP(hipMemcpy(p, src, n, hipMemcpyHostToDevice));
+            off += align_up(n);
+            return p;
+        };
+        Dev d;
+        d.nk = h.nk;
+        d.ntau = h.ntau;
+        d.niw_f = h.niw_f;
+        d.niw_b = h.niw_b;
+        d.nbmax = h.nbmax;
+        d.nimax = h.nimax;
+        d.beta = h.beta;
+        d.scale = h.scale;
+        d.tau = (const double*)put(h.tau.data(), sizeof(double) * h.ntau);
+        d.wf = (const double2*)put(c->wf.data(), sizeof(double2) * c->wf.size());
+        d.ef = (const double2*)put(c->ef.data(), sizeof(double2) * c->ef.size());
+        d.wb = (const double2*)put(c->wb.data(), sizeof(double2) * c->wb.size());
+        d.eb = (const double2*)put(c->eb.data(), sizeof(double2) * c->eb.size());
+        d.kmq = (const int*)put(h.kmq.data(), sizeof(int) * h.kmq.size());
+        d.nb = (const int*)put(h.nb.data(), sizeof(int) * h.nk);
+        d.ni = (const int*)put(h.ni.data(), sizeof(int) * h.nk);
+        d.moff = (const int64_t*)put(h.moff.data(), sizeof(int64_t) * h.moff.size());
+        d.mpre = (const int64_t*)put(h.mpre.data(), sizeof(int64_t) * (h.nk + 1));
+        d.ppre = (const int64_t*)put(h.ppre.data(), sizeof(int64_t) * (h.nk + 1));
+        d.wpre = (const int64_t*)put(h.wpre.data(), sizeof(int64_t) * (h.nk + 1));
+        d.vpre = (const int64_t*)put(h.vpre.data(), sizeof(int64_t) * (h.nk + 1));
+        need(off == tb, MSGW_EINVAL, "internal: table size mismatch");
+        d.scratch = base + off;
+        d.scratch_bytes = bytes - off;
+        c->d = d;
+        c->ws = base;
+        c->ws_bytes = bytes;
+        c->ws_ready = true;
+    });
+}
+
+int msgw_m_layout(const msgw_ctx* cc, int q, int64_t* off, int64_t* qsize) {
+    msgw_ctx* c = const_cast<msgw_ctx*>(cc);
+    return guarded(c, [&] {
+        need(c->have_problem, MSGW_EINVAL, "no problem set");
+        need(q >= 0 && q < c->h.nk, MSGW_EINVAL, "q out of range");
+        need(qsize != nullptr, MSGW_EINVAL, "null qsize");
+        if (off)
+            for (int k = 0; k < c->h.nk; ++k) off[k] = c->h.moff[size_t(q) * c->h.nk + k];
+        *qsize = c->h.mpre[q + 1] - c->h.mpre[q];
+    });
+}
+
+int msgw_green0(msgw_ctx* c, void* stream, const double* eps, double mu, double* G_tau) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(eps && G_tau, MSGW_EINVAL, "null pointer");
+        need(std::isfinite(mu), MSGW_EINVAL, "mu must be finite");
+        launch_green0(c->d, S(stream), eps, mu, G_tau);
+    });
+}
+
+int msgw_synth_M(msgw_ctx* c, void* stream, uint64_t seed, int q0, int nq, int symmetric,
+                 int m_dtype, void* M) {
+    return guarded(c, [&] {
+        require_ready(c);
+        check_qrange(c, q0, nq);
+        need(M != nullptr, MSGW_EINVAL, "null M");
+        need(m_dtype == MSGW_C128 || m_dtype == MSGW_C64, MSGW_EINVAL, "bad m_dtype");
+        launch_synth_M(c->d, c->h, S(stream), seed, q0, nq, symmetric, m_dtype, M);
+    });
+}
+
+int msgw_polarization(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
+                      const double* G_tau, int precision, void* P_tau) {
+    return guarded(c, [&] {
+        require_ready(c);
+        check_qrange(c, q0, nq);
+        need(M && G_tau && P_tau, MSGW_EINVAL, "null pointer");
+        if (precision == MSGW_FP64) {
+            need(m_dtype == MSGW_C128, MSGW_EINVAL, "MSGW_FP64 needs MSGW_C128 M");
+            launch_pol_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, P_tau);
+        } else if (precision == MSGW_FP32 || precision == MSGW_BF16X3) {
+            need(m_dtype == MSGW_C64, MSGW_EINVAL, "MSGW_FP32 / MSGW_BF16X3 need MSGW_C64 M");
+            int rc = launch_pol_mfma(c->d, c->h, S(stream), q0, nq, M, G_tau, precision, P_tau);
+            need(rc == MSGW_OK, rc, "polarization: unsupported shape for the MFMA path");
+        } else {
+            throw Error(MSGW_EINVAL, "bad precision");
+        }
+    });
+}
+
+int msgw_tau_to_iw(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t len,
+                   const void* f_tau, int f_is_complex, const double* e_ref, void* f_iw) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(stat == MSGW_FERMION || stat == MSGW_BOSON, MSGW_EINVAL, "bad stat");
+        need(nblk >= 0 && len >= 0, MSGW_EINVAL, "negative size");
+        need(f_tau && f_iw, MSGW_EINVAL, "null pointer");
+        need(!(e_ref && stat == MSGW_BOSON), MSGW_EINVAL, "e_ref is for FERMION data");
+        if (nblk == 0 || len == 0) return;
+        launch_fwd(c->d, S(stream), stat, nblk, len, f_tau, f_is_complex, e_ref, f_iw);
+    });
+}
+
+int msgw_iw_to_tau(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t len, int mat_n,
+                   const void* f_iw, const void* add_tau, const double* e_ref, void* f_tau) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(f_iw && f_tau, MSGW_EINVAL, "null pointer");
+        need(nblk >= 0 && len >= 0, MSGW_EINVAL, "negative size");
+        if (stat == MSGW_FERMION) {
+            need(mat_n == 0, MSGW_EINVAL, "FERMION inverse transform is scalar (mat_n = 0)");
+            need(add_tau == nullptr, MSGW_EINVAL, "add_tau is for BOSON matrices");
+            if (nblk == 0 || len == 0) return;
+            launch_inv_fermion(c->d, S(stream), nblk, len, f_iw, e_ref, (double*)f_tau);
+        } else if (stat == MSGW_BOSON) {
+            need(mat_n > 0 && int64_t(mat_n) * mat_n == len, MSGW_ESHAPE, "BOSON needs len == mat_n^2");
+            need(e_ref == nullptr, MSGW_EINVAL, "e_ref is for FERMION data");
+            if (nblk == 0) return;
+            launch_inv_boson(c->d, S(stream), nblk, mat_n, f_iw, add_tau, nullptr, f_tau);
+        } else {
+            throw Error(MSGW_EINVAL, "bad stat");
+        }
+    });
+}
+
+int msgw_screen(msgw_ctx* c, void* stream, int q0, int nq, const void* P_iw, const double* v,
+                void* Wt_iw, void* R_iw, int* info) {
+    return guarded(c, [&] {
+        require_ready(c);
+        check_qrange(c, q0, nq);
+        need(P_iw && v && Wt_iw && info, MSGW_EINVAL, "null pointer");
+        need(P_iw != Wt_iw, MSGW_EINVAL, "P_iw and Wt_iw must not alias");
+        launch_screen(c->d, c->h, S(stream), q0, nq, P_iw, v, Wt_iw, R_iw, info);
+    });
+}
+
+int msgw_screened_tau(msgw_ctx* c, void* stream, int q0, int nq, const void* R_iw,
+                      const void* P_tau, const double* v, void* Wt_tau) {
+    return guarded(c, [&] {
+        require_ready(c);
+        check_qrange(c, q0, nq);
+        need(R_iw && P_tau && v && Wt_tau, MSGW_EINVAL, "null pointer");
+        const Host& h = c->h;
+        for (int q = q0; q < q0 + nq; ++q) {
+            int n = h.ni[q];
+            const char* R = (const char*)R_iw + sizeof(double2) * (h.wpre[q] - h.wpre[q0]);
+            const char* P = (const char*)P_tau + sizeof(double2) * (h.ppre[q] - h.ppre[q0]);
+            char* W = (char*)Wt_tau + sizeof(double2) * (h.ppre[q] - h.ppre[q0]);
+            const double* vq = v + (h.vpre[q] - h.vpre[q0]);
+            launch_inv_boson(c->d, S(stream), 1, n, R, P, vq, W);
+        }
+    });
+}
+
+int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
+                     const double* G_tau, const void* Wt_tau, int precision, void* Sigma_tau) {
+    return guarded(c, [&] {
+        require_ready(c);
+        check_qrange(c, q0, nq);
+        need(M && G_tau && Wt_tau && Sigma_tau, MSGW_EINVAL, "null pointer");
+        if (c->h.sigma_mode == MSGW_SIGMA_FULL) {
+            need(precision == MSGW_FP64 && m_dtype == MSGW_C128, MSGW_ENOTSUP,
+                 "MSGW_SIGMA_FULL runs in MSGW_FP64 with MSGW_C128 M");
+            launch_sig_full_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, Sigma_tau);
+            return;
+        }
+        if (precision == MSGW_FP64) {
+            need(m_dtype == MSGW_C128, MSGW_EINVAL, "MSGW_FP64 needs MSGW_C128 M");
+            launch_sig_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, Sigma_tau);
+        } else if (precision == MSGW_FP32 || precision == MSGW_BF16X3) {
+            need(m_dtype == MSGW_C64, MSGW_EINVAL, "MSGW_FP32 / MSGW_BF16X3 need MSGW_C64 M");
+            int rc = launch_sig_mfma(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, precision,
+                                     Sigma_tau);
+            need(rc == MSGW_OK, rc, "self_energy: workspace too small or unsupported shape for the MFMA path");
+        } else {
+            throw Error(MSGW_EINVAL, "bad precision");
+        }
+    });
+}
+
+int msgw_sigma_x(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
+                 const double* G_tau, const double* v, void* Sigma_x) {
+    return guarded(c, [&] {
+        require_ready(c);
+        check_qrange(c, q0, nq);
+        need(M && G_tau && v && Sigma_x, MSGW_EINVAL, "null pointer");
+        need(m_dtype == MSGW_C128 || m_dtype == MSGW_C64, MSGW_EINVAL, "bad m_dtype");
+        launch_sigma_x(c->d, c->h, S(stream), q0, nq, M, m_dtype, G_tau, v, Sigma_x,
+                       c->h.sigma_mode == MSGW_SIGMA_FULL);
+    });
+}
+
+int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
+               const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
+               double* G_tau, double* n_out, int* flags) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(eps && sigma_static && Sigma_c_iw && mu && G_tau && n_out && flags, MSGW_EINVAL,
+             "null pointer");
+        need(mu_mode == MSGW_MU_FIXED || mu_mode == MSGW_MU_SEARCH, MSGW_EINVAL, "bad mu_mode");
+        need(std::isfinite(n_target) && n_target >= 0, MSGW_EINVAL, "bad n_target");
+        launch_dyson(c->d, c->h, S(stream), eps, sigma_static, Sigma_c_iw, n_target,
+                     mu_mode == MSGW_MU_SEARCH, mu, G_iw, G_tau, n_out, flags);
+    });
+}
+
+int msgw_gap(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
+             const void* Sigma_c_iw, const double* mu, int n_index, double* gap) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(eps && sigma_static && Sigma_c_iw && mu && gap, MSGW_EINVAL, "null pointer");
+        int64_t nstate = 0;
+        for (int k = 0; k < c->h.nk; ++k) nstate += c->h.nb[k];
+        need(n_index >= 1 && n_index < nstate, MSGW_EINVAL, "n_index outside [1, number of states)");
+        launch_gap(c->d, c->h, S(stream), eps, sigma_static, Sigma_c_iw, mu, n_index, gap);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Internal declarations shared by the host context and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/matsgw.h"
+
+namespace msgw {
+
+// Error carrying an ABI return code.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define MSGW_HIP(call)                                                                    \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::msgw::Error(MSGW_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// Device-resident constant tables (they live in the caller's workspace) plus the
+// sizes every kernel needs.  Passed by value to the launchers.
+struct Dev {
+    int nk = 0, ntau = 0, niw_f = 0, niw_b = 0, nbmax = 0, nimax = 0;
+    double beta = 0, scale = 0;
+    const double* tau = nullptr;      // [ntau]
+    const double2* wf = nullptr;      // [niw_f][ntau]  forward fermionic weights
+    const double2* wb = nullptr;      // [niw_b][ntau]  forward bosonic weights
+    const double2* ef = nullptr;      // [ntau][niw_f]  exp(-i w_n tau_i)
+    const double2* eb = nullptr;      // [ntau][niw_b]  exp(-i nu_n tau_i)
+    const int* kmq = nullptr;         // [nk*nk]
+    const int* nb = nullptr;          // [nk]
+    const int* ni = nullptr;          // [nk]
+    const int64_t* moff = nullptr;    // [nk*nk] offset of block (q,k) inside q's M block
+    const int64_t* mpre = nullptr;    // [nk+1]  prefix over q of M block sizes
+    const int64_t* ppre = nullptr;    // [nk+1]  prefix over q of ntau*NI_q^2
+    const int64_t* wpre = nullptr;    // [nk+1]  prefix over q of niw_b*NI_q^2
+    const int64_t* vpre = nullptr;    // [nk+1]  prefix over q of NI_q
+    char* scratch = nullptr;          // per-call scratch
+    size_t scratch_bytes = 0;
+};
+
+// Host mirror of the problem (used for launch shapes and validation).
+struct Host {
+    int nk = 0, ntau = 0, niw_f = 0, niw_b = 0, nbmax = 0, nimax = 0, sigma_mode = 0;
+    double beta = 0, scale = 0;
+    std::vector<int> kmq, nb, ni;
+    std::vector<double> tau;
+    std::vector<int64_t> moff, mpre, ppre, wpre, vpre;
+};
+
+// ---- launchers (defined in the kernel files) ----
+void launch_green0(const Dev& d, hipStream_t s, const double* eps, double mu, double* G);
+void launch_synth_M(const Dev& d, const Host& h, hipStream_t s, uint64_t seed, int q0, int nq,
+                    int symmetric, int m_dtype, void* M);
+void launch_fwd(const Dev& d, hipStream_t s, int stat, int64_t nblk, int64_t len, const void* f,
+                int f_cplx, const double* eref, void* out);
+void launch_inv_fermion(const Dev& d, hipStream_t s, int64_t nblk, int64_t len, const void* F,
+                        const double* eref, double* out);
+void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, const void* F,
+                      const void* add, const double* v, void* out);
+void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
+                   const double* v, void* Wt_iw, void* R_iw, int* info);
+void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                    int m_dtype, const double* occ, const double* v, void* out, int full);
+void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
+                  const double* sstat, const void* sigc, double n_target, int search, double* mu,
+                  void* G_iw, double* G_tau, double* n_out, int* flags);
+void launch_gap(const Dev& d, const Host& h, hipStream_t s, const double* eps,
+                const double* sstat, const void* sigc, const double* mu, int n_index, double* gap);
+// contractions
+void launch_pol_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                     const double* G, void* P);
+void launch_sig_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                     const double* G, const void* W, void* Sig);
+void launch_sig_full_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
+                          const void* M, const double* G, const void* W, void* Sig);
+int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                    const double* G, int precision, void* P);
+int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                    const double* G, const void* W, int precision, void* Sig);
+size_t mfma_scratch_bytes(const Host& h, int nq_max);
+
+// Scratch layout: [E array of msgw_dyson: nk*nbmax doubles][MFMA conversion buffers].
+inline size_t scratch_E_bytes(const Host& h) {
+    return (sizeof(double) * size_t(h.nk) * h.nbmax + 255) & ~size_t(255);
+}
+inline double* scratch_E(const Dev& d) { return reinterpret_cast<double*>(d.scratch); }
+inline char* scratch_mfma(const Dev& d, const Host& h) { return d.scratch + scratch_E_bytes(h); }
+inline size_t scratch_mfma_bytes(const Dev& d, const Host& h) {
+    return d.scratch_bytes > scratch_E_bytes(h) ? d.scratch_bytes - scratch_E_bytes(h) : 0;
+}
+
+// ---- small device helpers ----
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+// Reference Green's function -exp(-E t)(1 - n_F(E)) in the overflow-free form.
+__device__ __forceinline__ double g0_tau(double E, double t, double beta) {
+    double a = fabs(E);
+    double den = 1.0 + exp(-beta * a);
+    return E >= 0.0 ? -exp(-a * t) / den : -exp(-a * (beta - t)) / den;
+}
+
+}  // namespace msgw

@@ -1,0 +1,654 @@
+// G0, synthetic M, tau <-> i omega transforms, exchange self-energy, Dyson + chemical potential.
+// All arithmetic here is FP64.
+#include "internal.h"
+
+namespace msgw {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+inline unsigned ceil_div(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
+
+__device__ __forceinline__ double2 ld_c(const void* p, int64_t i, bool c64) {
+    if (c64) {
+        float2 f = reinterpret_cast<const float2*>(p)[i];
+        return make_double2(f.x, f.y);
+    }
+    return reinterpret_cast<const double2*>(p)[i];
+}
+
+// 1 / (i w - E)
+__device__ __forceinline__ double2 inv_iw_minus(double w, double E) {
+    double den = E * E + w * w;
+    return make_double2(-E / den, -w / den);
+}
+
+__device__ __forceinline__ double2 cdiv(double2 a, double2 b) {
+    // a / b, scaled to avoid overflow for large |b|
+    double s = fmax(fabs(b.x), fabs(b.y));
+    double bx = b.x / s, by = b.y / s;
+    double den = bx * bx + by * by;
+    return make_double2((a.x * bx + a.y * by) / (den * s), (a.y * bx - a.x * by) / (den * s));
+}
+
+__device__ __forceinline__ double fermi(double E, double beta) {
+    double x = beta * E;
+    double ex = exp(-fabs(x));
+    return x >= 0.0 ? ex / (1.0 + ex) : 1.0 / (1.0 + ex);
+}
+
+// ---------------------------------------------------------------------------------------------
+// a1: G0
+// ---------------------------------------------------------------------------------------------
+__global__ void k_green0(const double* __restrict__ eps, double mu, const int* __restrict__ nb,
+                         const double* __restrict__ tau, int nk, int nbmax, int ntau, double beta,
+                         double* __restrict__ G) {
+    int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t tot = int64_t(nk) * nbmax * ntau;
+    if (e >= tot) return;
+    int i = int(e % ntau);
+    int64_t kn = e / ntau;
+    int n = int(kn % nbmax), k = int(kn / nbmax);
+    G[e] = (n < nb[k]) ? g0_tau(eps[kn] - mu, tau[i], beta) : 0.0;
+}
+
+// ---------------------------------------------------------------------------------------------
+// synthetic M: Philox4x32-10 + Box-Muller, one draw per symmetry orbit
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = uint64_t(0xD2511F53u) * c[0];
+        uint64_t p1 = uint64_t(0xCD9E8D57u) * c[2];
+        uint32_t hi0 = uint32_t(p0 >> 32), lo0 = uint32_t(p0);
+        uint32_t hi1 = uint32_t(p1 >> 32), lo1 = uint32_t(p1);
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+    return (double(a >> 5) * 67108864.0 + double(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
+}
+
+__global__ void k_synth(const int* __restrict__ kmq, const int* __restrict__ nb,
+                        const int* __restrict__ ni, const int64_t* __restrict__ moff,
+                        const int64_t* __restrict__ mpre, int nk, int nbmax, int q0, uint64_t seed,
+                        int symmetric, int c64, void* __restrict__ M) {
+    const int qk = blockIdx.y;
+    const int q = q0 + qk / nk, k = qk % nk;
+    const int kq = kmq[q * nk + k];
+    const int nn = nb[k], nm = nb[kq], nI = ni[q];
+    const int64_t blk = int64_t(nI) * nn * nm;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= blk) return;
+    const int m = int(e % nm);
+    const int n = int((e / nm) % nn);
+    const int I = int(e / (int64_t(nn) * nm));
+    auto lin = [&](int Q, int K, int N, int Mi) -> uint64_t {
+        return ((uint64_t(Q) * nk + K) * nbmax + N) * uint64_t(nbmax) + Mi;
+    };
+    uint64_t xe = lin(q, k, n, m), canon = xe;
+    bool conj = false, real = false;
+    if (symmetric) {
+        int mq = kmq[q * nk + 0];    // -q
+        int mk = kmq[k * nk + 0];    // -k
+        int qmk = kmq[k * nk + q];   // q - k
+        uint64_t xa = lin(q, qmk, m, n);
+        uint64_t xb = lin(mq, mk, n, m);
+        uint64_t xab = lin(mq, kq, m, n);
+        canon = min(min(xe, xa), min(xb, xab));
+        conj = (canon != xe) && (canon != xa);
+        real = (xb == xe) || (xab == xe);
+    }
+    uint32_t c[4] = {uint32_t(canon), uint32_t(canon >> 32), uint32_t(I), 0x4D475731u};
+    philox10(c, uint32_t(seed), uint32_t(seed >> 32));
+    double u1 = u53(c[0], c[1]), u2 = u53(c[2], c[3]);
+    double rad = sqrt(-2.0 * log(u1));
+    double ang = 2.0 * kPi * u2;
+    double z0 = rad * cos(ang), z1 = rad * sin(ang);
+    double var = 1.0 / (1.0 + double(I) / 16.0);
+    double re, im;
+    if (real) {
+        re = sqrt(var) * z0;
+        im = 0.0;
+    } else {
+        double sc = sqrt(var / 2.0);
+        re = sc * z0;
+        im = conj ? -(sc * z1) : sc * z1;
+    }
+    int64_t at = (mpre[q] - mpre[q0]) + moff[q * nk + k] + e;
+    if (c64)
+        reinterpret_cast<float2*>(M)[at] = make_float2(float(re), float(im));
+    else
+        reinterpret_cast<double2*>(M)[at] = make_double2(re, im);
+}
+
+// ---------------------------------------------------------------------------------------------
+// forward transform: out[b][n][e] = sum_i W[n][i] (f[b][i][e] - G0(E, tau_i)) (+ 1/(i w_n - E))
+// ---------------------------------------------------------------------------------------------
+constexpr int FCH = 16;
+
+template <bool CPLX>
+__global__ void k_fwd(const double2* __restrict__ W, int niw, int ntau, int64_t nblk, int64_t len,
+                      const void* __restrict__ f, const double* __restrict__ eref,
+                      const double* __restrict__ tau, double beta, int fermion,
+                      double2* __restrict__ out) {
+    int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= nblk * len) return;
+    int64_t b = idx / len, e = idx % len;
+    int n0 = blockIdx.y * FCH;
+    double E = eref ? eref[idx] : 0.0;
+    double2 acc[FCH];
+#pragma unroll
+    for (int j = 0; j < FCH; ++j) acc[j] = make_double2(0.0, 0.0);
+    for (int i = 0; i < ntau; ++i) {
+        int64_t at = (b * ntau + i) * len + e;
+        double2 fi;
+        if (CPLX)
+            fi = reinterpret_cast<const double2*>(f)[at];
+        else
+            fi = make_double2(reinterpret_cast<const double*>(f)[at], 0.0);
+        if (eref) fi.x -= g0_tau(E, tau[i], beta);
+#pragma unroll
+        for (int j = 0; j < FCH; ++j) {
+            int n = min(n0 + j, niw - 1);
+            double2 w = W[int64_t(n) * ntau + i];
+            acc[j].x += w.x * fi.x - w.y * fi.y;
+            acc[j].y += w.x * fi.y + w.y * fi.x;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < FCH; ++j) {
+        int n = n0 + j;
+        if (n >= niw) break;
+        double2 o = acc[j];
+        if (eref) {
+            double w = (fermion ? (2.0 * n + 1.0) : 2.0 * n) * kPi / beta;
+            o = cadd(o, inv_iw_minus(w, E));
+        }
+        out[(b * niw + n) * len + e] = o;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// inverse fermionic transform (real output)
+// ---------------------------------------------------------------------------------------------
+constexpr int ICH = 16;
+
+__global__ void k_inv_f(const double2* __restrict__ ef, int niw, int ntau, int64_t nblk,
+                        int64_t len, const double2* __restrict__ F, const double* __restrict__ eref,
+                        const double* __restrict__ tau, double beta, double* __restrict__ out) {
+    int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= nblk * len) return;
+    int64_t b = idx / len, e = idx % len;
+    int i0 = blockIdx.y * ICH;
+    double E = eref ? eref[idx] : 0.0;
+    double acc[ICH];
+#pragma unroll
+    for (int j = 0; j < ICH; ++j) acc[j] = 0.0;
+    for (int n = 0; n < niw; ++n) {
+        double2 Fn = F[(b * niw + n) * len + e];
+        if (eref) {
+            double w = (2.0 * n + 1.0) * kPi / beta;
+            double2 r = inv_iw_minus(w, E);
+            Fn.x -= r.x;
+            Fn.y -= r.y;
+        }
+#pragma unroll
+        for (int j = 0; j < ICH; ++j) {
+            int i = min(i0 + j, ntau - 1);
+            double2 p = ef[int64_t(i) * niw + n];
+            acc[j] += p.x * Fn.x - p.y * Fn.y;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < ICH; ++j) {
+        int i = i0 + j;
+        if (i >= ntau) break;
+        double r = (2.0 / beta) * acc[j];
+        if (eref) r += g0_tau(E, tau[i], beta);
+        out[(b * ntau + i) * len + e] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// inverse bosonic transform of Hermitian-pair matrices, with an optional exact-in-tau term
+// add (scaled v_I add_IJ v_J when v is given)
+// ---------------------------------------------------------------------------------------------
+constexpr int BCH = 8;
+
+__global__ void k_inv_b(const double2* __restrict__ eb, int niw, int ntau, int64_t nblk, int n,
+                        const double2* __restrict__ F, const double2* __restrict__ add,
+                        const double* __restrict__ v, double beta, double2* __restrict__ out) {
+    int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t nn = int64_t(n) * n;
+    if (idx >= nblk * nn) return;
+    int64_t b = idx / nn, e = idx % nn;
+    int I = int(e / n), J = int(e % n);
+    int i0 = blockIdx.y * BCH;
+    double2 acc[BCH];
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) acc[j] = make_double2(0.0, 0.0);
+    const double2* Fb = F + b * niw * nn;
+    {
+        double2 a = Fb[e];
+#pragma unroll
+        for (int j = 0; j < BCH; ++j) acc[j] = a;
+    }
+    for (int w = 1; w < niw; ++w) {
+        double2 a = Fb[int64_t(w) * nn + e];
+        double2 t = Fb[int64_t(w) * nn + int64_t(J) * n + I];
+        // e^{-i nu tau} a + e^{+i nu tau} conj(t)
+#pragma unroll
+        for (int j = 0; j < BCH; ++j) {
+            int i = min(i0 + j, ntau - 1);
+            double2 p = eb[int64_t(i) * niw + w];
+            acc[j].x += (p.x * a.x - p.y * a.y) + (p.x * t.x - p.y * t.y);
+            acc[j].y += (p.x * a.y + p.y * a.x) - (p.x * t.y + p.y * t.x);
+        }
+    }
+    double vv = v ? v[I] * v[J] : 1.0;
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) {
+        int i = i0 + j;
+        if (i >= ntau) break;
+        int64_t at = (b * ntau + i) * nn + e;
+        double2 r = make_double2(acc[j].x / beta, acc[j].y / beta);
+        if (add) {
+            double2 a = add[at];
+            r.x += vv * a.x;
+            r.y += vv * a.y;
+        }
+        out[at] = r;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// exchange self-energy
+// ---------------------------------------------------------------------------------------------
+__device__ double block_sum(double x, double* red) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (l == 0) red[w] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    return t;
+}
+
+// DIAG: block per (q, k, n); threads over m
+__global__ void k_sigx_diag(Dev d, int q0, const void* __restrict__ M, int c64,
+                            const double* __restrict__ occ, const double* __restrict__ v,
+                            double* __restrict__ out) {
+    __shared__ double red[16];
+    const int n = blockIdx.x;
+    const int q = q0 + blockIdx.z, k = blockIdx.y;
+    const int nk = d.nk;
+    const int kq = d.kmq[q * nk + k];
+    const int nn = d.nb[k], nm = d.nb[kq], nI = d.ni[q];
+    if (n >= nn) return;
+    const int64_t base = (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
+    const double* vq = v + (d.vpre[q] - d.vpre[q0]);
+    double part = 0.0;
+    for (int m = threadIdx.x; m < nm; m += blockDim.x) {
+        double s = 0.0;
+        for (int I = 0; I < nI; ++I) {
+            double2 x = ld_c(M, base + (int64_t(I) * nn + n) * nm + m, c64);
+            s += vq[I] * (x.x * x.x + x.y * x.y);
+        }
+        part += (-occ[(int64_t(kq) * d.nbmax + m) * d.ntau + d.ntau - 1]) * s;
+    }
+    double tot = block_sum(part, red);
+    if (threadIdx.x == 0) atomicAdd(&out[int64_t(k) * d.nbmax + n], d.scale * tot);
+}
+
+// FULL: block per (q, k, n); threads over n'
+__global__ void k_sigx_full(Dev d, int q0, const void* __restrict__ M, int c64,
+                            const double* __restrict__ occ, const double* __restrict__ v,
+                            double2* __restrict__ out) {
+    const int n = blockIdx.x;
+    const int q = q0 + blockIdx.z, k = blockIdx.y;
+    const int nk = d.nk;
+    const int kq = d.kmq[q * nk + k];
+    const int nn = d.nb[k], nm = d.nb[kq], nI = d.ni[q];
+    if (n >= nn) return;
+    const int64_t base = (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
+    const double* vq = v + (d.vpre[q] - d.vpre[q0]);
+    for (int np = threadIdx.x; np < nn; np += blockDim.x) {
+        double2 s = make_double2(0.0, 0.0);
+        for (int m = 0; m < nm; ++m) {
+            double f = (-occ[(int64_t(kq) * d.nbmax + m) * d.ntau + d.ntau - 1]);
+            double2 t = make_double2(0.0, 0.0);
+            for (int I = 0; I < nI; ++I) {
+                double2 a = ld_c(M, base + (int64_t(I) * nn + n) * nm + m, c64);
+                double2 b = ld_c(M, base + (int64_t(I) * nn + np) * nm + m, c64);
+                // conj(a) b
+                t.x += vq[I] * (a.x * b.x + a.y * b.y);
+                t.y += vq[I] * (a.x * b.y - a.y * b.x);
+            }
+            s.x += f * t.x;
+            s.y += f * t.y;
+        }
+        double2* o = &out[(int64_t(k) * d.nbmax + n) * d.nbmax + np];
+        atomicAdd(&o->x, d.scale * s.x);
+        atomicAdd(&o->y, d.scale * s.y);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Dyson + chemical potential (one block) and G(i w), G(tau)
+// ---------------------------------------------------------------------------------------------
+struct DysonArgs {
+    const double* eps;
+    const double* sstat;
+    const double2* sigc;
+    const int* nb;
+    int nk, nbmax, niw;
+    double beta, n_target;
+};
+
+__device__ double number_partial(const DysonArgs& a, const double* E0, double mu) {
+    double part = 0.0;
+    const int64_t nstate = int64_t(a.nk) * a.nbmax;
+    for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
+        int k = int(b / a.nbmax), n = int(b % a.nbmax);
+        if (n >= a.nb[k]) continue;
+        double E = E0[b] - mu;
+        double acc = 0.0;
+        const double2* S = a.sigc + b * a.niw;
+        for (int w = 0; w < a.niw; ++w) {
+            double om = (2.0 * w + 1.0) * kPi / a.beta;
+            double2 z = make_double2(-E, om);               // i w - E
+            double2 s = S[w];
+            double2 zs = make_double2(z.x - s.x, z.y - s.y);  // i w - E - Sigma
+            // G - G_ref = Sigma / ((i w - E - Sigma)(i w - E))
+            double2 d = cdiv(s, cmul(zs, z));
+            acc += d.x;
+        }
+        part += fermi(E, a.beta) + (2.0 / a.beta) * acc;
+    }
+    return part;
+}
+
+__global__ __launch_bounds__(1024) void k_dyson_mu(DysonArgs a, int search, double* mu_io,
+                                                   double* n_out, int* flags, double* Eout) {
+    __shared__ double red[16];
+    const int64_t nstate = int64_t(a.nk) * a.nbmax;
+    // E0 = eps + sstat, written to Eout as scratch first
+    double lo = 1e300, hi = -1e300;
+    int bad = 0;
+    for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
+        int k = int(b / a.nbmax), n = int(b % a.nbmax);
+        if (n >= a.nb[k]) {
+            Eout[b] = 0.0;
+            continue;
+        }
+        double e0 = a.eps[b] + a.sstat[b];
+        Eout[b] = e0;
+        if (!isfinite(e0)) bad = 1;
+        lo = fmin(lo, e0);
+        hi = fmax(hi, e0);
+        for (int w = 0; w < a.niw; ++w) {
+            double2 s = a.sigc[b * a.niw + w];
+            if (!isfinite(s.x) || !isfinite(s.y)) bad = 1;
+        }
+    }
+    // min / max / or via shuffles + LDS
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o));
+        hi = fmax(hi, __shfl_xor(hi, o));
+        bad |= __shfl_xor(bad, o);
+    }
+    __shared__ double rlo[16], rhi[16];
+    __shared__ int rbad[16];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+    if (l == 0) {
+        rlo[w] = lo;
+        rhi[w] = hi;
+        rbad[w] = bad;
+    }
+    __syncthreads();
+    lo = 1e300;
+    hi = -1e300;
+    bad = 0;
+    for (int i = 0; i < nw; ++i) {
+        lo = fmin(lo, rlo[i]);
+        hi = fmax(hi, rhi[i]);
+        bad |= rbad[i];
+    }
+    int fl = bad ? MSGW_FLAG_NAN : 0;
+    double mu;
+    if (search) {
+        lo -= 50.0 / a.beta;
+        hi += 50.0 / a.beta;
+        double Nlo = block_sum(number_partial(a, Eout, lo), red);
+        double Nhi = block_sum(number_partial(a, Eout, hi), red);
+        if (!(Nlo <= a.n_target && a.n_target <= Nhi)) fl |= MSGW_FLAG_NOBRACKET;
+        for (int s = 0; s < 200; ++s) {
+            double mid = 0.5 * (lo + hi);
+            double N = block_sum(number_partial(a, Eout, mid), red);
+            if (N < a.n_target)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        mu = 0.5 * (lo + hi);
+    } else {
+        mu = *mu_io;
+    }
+    double N = block_sum(number_partial(a, Eout, mu), red);
+    if (!isfinite(N)) fl |= MSGW_FLAG_NAN;
+    __syncthreads();
+    for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
+        int k = int(b / a.nbmax), n = int(b % a.nbmax);
+        if (n < a.nb[k]) Eout[b] = Eout[b] - mu;
+    }
+    if (threadIdx.x == 0) {
+        *mu_io = mu;
+        *n_out = N;
+        *flags = fl;
+    }
+}
+
+__global__ void k_dyson_g(const double2* __restrict__ ef, const double* __restrict__ tau,
+                          DysonArgs a, int ntau, const double* __restrict__ E_,
+                          double2* __restrict__ G_iw, double* __restrict__ G_tau) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t nstate = int64_t(a.nk) * a.nbmax;
+    if (b >= nstate) return;
+    const int k = int(b / a.nbmax), n = int(b % a.nbmax);
+    const int i0 = blockIdx.y * ICH;
+    if (n >= a.nb[k]) {
+        if (G_iw && blockIdx.y == 0)
+            for (int w = 0; w < a.niw; ++w) G_iw[b * a.niw + w] = make_double2(0.0, 0.0);
+        for (int j = 0; j < ICH && i0 + j < ntau; ++j) G_tau[b * ntau + i0 + j] = 0.0;
+        return;
+    }
+    const double E = E_[b];
+    double acc[ICH];
+#pragma unroll
+    for (int j = 0; j < ICH; ++j) acc[j] = 0.0;
+    for (int w = 0; w < a.niw; ++w) {
+        double om = (2.0 * w + 1.0) * kPi / a.beta;
+        double2 z = make_double2(-E, om);
+        double2 s = a.sigc[b * a.niw + w];
+        double2 zs = make_double2(z.x - s.x, z.y - s.y);
+        if (G_iw && blockIdx.y == 0) G_iw[b * a.niw + w] = cdiv(make_double2(1.0, 0.0), zs);
+        double2 d = cdiv(s, cmul(zs, z));
+#pragma unroll
+        for (int j = 0; j < ICH; ++j) {
+            int i = min(i0 + j, ntau - 1);
+            double2 p = ef[int64_t(i) * a.niw + w];
+            acc[j] += p.x * d.x - p.y * d.y;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < ICH; ++j) {
+        int i = i0 + j;
+        if (i >= ntau) break;
+        G_tau[b * ntau + i] = g0_tau(E, tau[i], a.beta) + (2.0 / a.beta) * acc[j];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// gap proxy: E_(N+1) - E_(N) of E^QP = eps + sstat + Re Sigma^c(i w_0) - mu (one block)
+// ---------------------------------------------------------------------------------------------
+__device__ double block_max(double x, double* red) {
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (l == 0) red[w] = x;
+    __syncthreads();
+    double t = -INFINITY;
+    for (int i = 0; i < nw; ++i) t = fmax(t, red[i]);
+    return t;
+}
+
+__device__ double eqp(const DysonArgs& a, double mu, int64_t b) {
+    return a.eps[b] + a.sstat[b] + a.sigc[b * a.niw].x - mu;
+}
+
+// value of the N-th smallest E^QP (1-based)
+__device__ double select_nth(const DysonArgs& a, double mu, int N, double lo, double hi, double* red) {
+    const int64_t nstate = int64_t(a.nk) * a.nbmax;
+    for (int s = 0; s < 200; ++s) {
+        double mid = 0.5 * (lo + hi);
+        double cnt = 0.0;
+        for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
+            int k = int(b / a.nbmax), n = int(b % a.nbmax);
+            if (n < a.nb[k] && eqp(a, mu, b) <= mid) cnt += 1.0;
+        }
+        cnt = block_sum(cnt, red);
+        if (cnt >= N)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    double best = -INFINITY;
+    for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
+        int k = int(b / a.nbmax), n = int(b % a.nbmax);
+        if (n < a.nb[k]) {
+            double e = eqp(a, mu, b);
+            if (e <= hi) best = fmax(best, e);
+        }
+    }
+    return block_max(best, red);
+}
+
+__global__ __launch_bounds__(1024) void k_gap(DysonArgs a, const double* mu_p, int N, double* gap) {
+    __shared__ double red[16];
+    const double mu = *mu_p;
+    const int64_t nstate = int64_t(a.nk) * a.nbmax;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
+        int k = int(b / a.nbmax), n = int(b % a.nbmax);
+        if (n >= a.nb[k]) continue;
+        double e = eqp(a, mu, b);
+        lo = fmin(lo, e);
+        hi = fmax(hi, e);
+    }
+    hi = block_max(hi, red);
+    lo = -block_max(-lo, red);
+    const double start = lo - (1.0 + fabs(lo));
+    const double eN = select_nth(a, mu, N, start, hi, red);
+    const double eN1 = select_nth(a, mu, N + 1, start, hi, red);
+    if (threadIdx.x == 0) *gap = eN1 - eN;
+}
+
+}  // namespace
+
+void launch_gap(const Dev& d, const Host& h, hipStream_t s, const double* eps,
+                const double* sstat, const void* sigc, const double* mu, int n_index, double* gap) {
+    (void)h;
+    DysonArgs a{eps, sstat, (const double2*)sigc, d.nb, d.nk, d.nbmax, d.niw_f, d.beta, 0.0};
+    hipLaunchKernelGGL(k_gap, dim3(1), dim3(1024), 0, s, a, mu, n_index, gap);
+    MSGW_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------------
+void launch_green0(const Dev& d, hipStream_t s, const double* eps, double mu, double* G) {
+    int64_t tot = int64_t(d.nk) * d.nbmax * d.ntau;
+    hipLaunchKernelGGL(k_green0, dim3(ceil_div(tot, 256)), dim3(256), 0, s, eps, mu, d.nb, d.tau, d.nk,
+                       d.nbmax, d.ntau, d.beta, G);
+    MSGW_HIP(hipGetLastError());
+}
+
+void launch_synth_M(const Dev& d, const Host& h, hipStream_t s, uint64_t seed, int q0, int nq,
+                    int symmetric, int m_dtype, void* M) {
+    int64_t maxblk = 0;
+    for (int q = q0; q < q0 + nq; ++q)
+        for (int k = 0; k < h.nk; ++k)
+            maxblk = std::max<int64_t>(maxblk, int64_t(h.ni[q]) * h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
+    if (int64_t(nq) * h.nk > 65535) throw Error(MSGW_ENOTSUP, "synth_M: nq * nk must be <= 65535");
+    hipLaunchKernelGGL(k_synth, dim3(ceil_div(maxblk, 256), nq * h.nk), dim3(256), 0, s, d.kmq, d.nb, d.ni,
+                       d.moff, d.mpre, d.nk, d.nbmax, q0, seed, symmetric, m_dtype == MSGW_C64, M);
+    MSGW_HIP(hipGetLastError());
+}
+
+void launch_fwd(const Dev& d, hipStream_t s, int stat, int64_t nblk, int64_t len, const void* f,
+                int f_cplx, const double* eref, void* out) {
+    const bool fer = stat == MSGW_FERMION;
+    const int niw = fer ? d.niw_f : d.niw_b;
+    const double2* W = fer ? d.wf : d.wb;
+    dim3 grid(ceil_div(nblk * len, 256), ceil_div(niw, FCH));
+    if (grid.x > 0x7fffffff) throw Error(MSGW_ENOTSUP, "tau_to_iw: nblk * len too large");
+    if (f_cplx)
+        hipLaunchKernelGGL(k_fwd<true>, grid, dim3(256), 0, s, W, niw, d.ntau, nblk, len, f, eref,
+                           d.tau, d.beta, int(fer), (double2*)out);
+    else
+        hipLaunchKernelGGL(k_fwd<false>, grid, dim3(256), 0, s, W, niw, d.ntau, nblk, len, f, eref,
+                           d.tau, d.beta, int(fer), (double2*)out);
+    MSGW_HIP(hipGetLastError());
+}
+
+void launch_inv_fermion(const Dev& d, hipStream_t s, int64_t nblk, int64_t len, const void* F,
+                        const double* eref, double* out) {
+    dim3 grid(ceil_div(nblk * len, 256), ceil_div(d.ntau, ICH));
+    hipLaunchKernelGGL(k_inv_f, grid, dim3(256), 0, s, d.ef, d.niw_f, d.ntau, nblk, len,
+                       (const double2*)F, eref, d.tau, d.beta, out);
+    MSGW_HIP(hipGetLastError());
+}
+
+void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, const void* F,
+                      const void* add, const double* v, void* out) {
+    dim3 grid(ceil_div(nblk * int64_t(mat_n) * mat_n, 256), ceil_div(d.ntau, BCH));
+    hipLaunchKernelGGL(k_inv_b, grid, dim3(256), 0, s, d.eb, d.niw_b, d.ntau, nblk, mat_n,
+                       (const double2*)F, (const double2*)add, v, d.beta, (double2*)out);
+    MSGW_HIP(hipGetLastError());
+}
+
+void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                    int m_dtype, const double* occ, const double* v, void* out, int full) {
+    dim3 grid(h.nbmax, h.nk, nq);
+    if (full)
+        hipLaunchKernelGGL(k_sigx_full, grid, dim3(64), 0, s, d, q0, M, m_dtype == MSGW_C64, occ, v,
+                           (double2*)out);
+    else
+        hipLaunchKernelGGL(k_sigx_diag, grid, dim3(256), 0, s, d, q0, M, m_dtype == MSGW_C64, occ, v,
+                           (double*)out);
+    MSGW_HIP(hipGetLastError());
+}
+
+void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
+                  const double* sstat, const void* sigc, double n_target, int search, double* mu,
+                  void* G_iw, double* G_tau, double* n_out, int* flags) {
+    DysonArgs a{eps, sstat, (const double2*)sigc, d.nb, d.nk, d.nbmax, d.niw_f, d.beta, n_target};
+    double* E = scratch_E(d);
+    hipLaunchKernelGGL(k_dyson_mu, dim3(1), dim3(1024), 0, s, a, search, mu, n_out, flags, E);
+    MSGW_HIP(hipGetLastError());
+    int64_t nstate = int64_t(h.nk) * h.nbmax;
+    hipLaunchKernelGGL(k_dyson_g, dim3(ceil_div(nstate, 128), ceil_div(h.ntau, ICH)), dim3(128), 0, s, d.ef,
+                       d.tau, a, d.ntau, E, (double2*)G_iw, G_tau);
+    MSGW_HIP(hipGetLastError());
+}
+
+}  // namespace msgw

@@ -1,0 +1,214 @@
+// Screened interaction on the bosonic Matsubara axis, FP64.
+//
+// For each (q, nu):  A = 1 - v^1/2 P v^1/2 is inverted in place by blocked Gauss-Jordan with
+// partial (row) pivoting, then W~ = v^1/2 (A^-1 - 1) v^1/2 and R = W~ - v P v.  This is the
+// W~ Dyson equation W~ = v P v + v P W~ after the tau convolution becomes a product on i nu.
+//
+// One work-group of 1024 threads owns one matrix (n <= 1024).  Panel of SB columns:
+//   1. for each panel column j: pick the pivot row (max |re| + |im| over rows >= j), swap the
+//      full rows, scale the pivot row and eliminate column j from every other row -- on the
+//      panel columns only.  The panel then holds the columns J of T = E_last ... E_first.
+//   2. every column c outside the panel (thread c) gets c <- T c = c + (T[:,J] - I[:,J]) c[J].
+// At the end the in-place result is A^-1 with permuted columns; the swaps are undone in
+// reverse order while writing W~ and R.
+#include "internal.h"
+
+namespace msgw {
+namespace {
+
+constexpr int SB = 16;      // panel width
+constexpr int RCH = 64;     // rows of the panel staged in LDS per chunk of the update
+constexpr int NT = 1024;
+
+__device__ __forceinline__ double2 cmuls(double2 a, double2 b) { return cmul(a, b); }
+
+__device__ __forceinline__ double2 crecip(double2 a) {
+    double s = fmax(fabs(a.x), fabs(a.y));
+    double ax = a.x / s, ay = a.y / s;
+    double den = (ax * ax + ay * ay) * s;
+    return make_double2(ax / den, -ay / den);
+}
+
+__global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __restrict__ Piw,
+                                               const double* __restrict__ v,
+                                               double2* __restrict__ Wt, double2* __restrict__ R,
+                                               int* __restrict__ info) {
+    __shared__ double sv[MSGW_MAX_NI];
+    __shared__ int perm[MSGW_MAX_NI];
+    __shared__ int idx[MSGW_MAX_NI];
+    __shared__ double2 buf[MSGW_MAX_NI];        // pivot column multipliers / row buffer
+    __shared__ double2 tch[RCH][SB];
+    __shared__ double rv[16];
+    __shared__ int ri[16];
+    __shared__ int s_info;
+
+    const int mi = blockIdx.x;
+    const int q = q0 + mi / d.niw_b, nu = mi % d.niw_b;
+    const int n = d.ni[q];
+    const int tid = threadIdx.x;
+    const int64_t off = (d.wpre[q] - d.wpre[q0]) + int64_t(nu) * n * n;
+    double2* A = Wt + off;
+    const double2* P = Piw + off;
+    double2* Rq = R ? R + off : nullptr;
+    const double* vq = v + (d.vpre[q] - d.vpre[q0]);
+
+    for (int i = tid; i < n; i += NT) sv[i] = sqrt(vq[i]);
+    if (tid == 0) s_info = 0;
+    __syncthreads();
+    for (int64_t e = tid; e < int64_t(n) * n; e += NT) {
+        int i = int(e / n), j = int(e % n);
+        double2 p = P[e];
+        double f = -sv[i] * sv[j];
+        double2 a = make_double2(f * p.x, f * p.y);
+        if (i == j) a.x += 1.0;
+        A[e] = a;
+    }
+    __syncthreads();
+
+    for (int j0 = 0; j0 < n; j0 += SB) {
+        const int jb = min(SB, n - j0);
+        for (int jj = 0; jj < jb; ++jj) {
+            const int j = j0 + jj;
+            // ---- pivot search: max |re| + |im| in column j, rows >= j (smallest index on ties)
+            double best = -1.0;
+            int bi = n;
+            for (int i = j + tid; i < n; i += NT) {
+                double2 x = A[int64_t(i) * n + j];
+                double m = fabs(x.x) + fabs(x.y);
+                if (m > best) {
+                    best = m;
+                    bi = i;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                double ob = __shfl_xor(best, o);
+                int oi = __shfl_xor(bi, o);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if ((tid & 63) == 0) {
+                rv[tid >> 6] = best;
+                ri[tid >> 6] = bi;
+            }
+            __syncthreads();
+            best = -1.0;
+            bi = n;
+            for (int w = 0; w < NT / 64; ++w)
+                if (rv[w] > best || (rv[w] == best && ri[w] < bi)) {
+                    best = rv[w];
+                    bi = ri[w];
+                }
+            const int p = (bi < n) ? bi : j;  // all-NaN column: keep the row
+            if (tid == 0) perm[j] = p;
+            if (p != j)
+                for (int c = tid; c < n; c += NT) {
+                    double2 t = A[int64_t(j) * n + c];
+                    A[int64_t(j) * n + c] = A[int64_t(p) * n + c];
+                    A[int64_t(p) * n + c] = t;
+                }
+            __syncthreads();
+            const double2 piv = A[int64_t(j) * n + j];
+            if (tid == 0 && piv.x == 0.0 && piv.y == 0.0 && s_info == 0) s_info = j + 1;
+            const double2 inv = crecip(piv);
+            for (int i = tid; i < n; i += NT) buf[i] = A[int64_t(i) * n + j];
+            __syncthreads();
+            if (tid < jb) {
+                const int c = j0 + tid;
+                double2* a = &A[int64_t(j) * n + c];
+                *a = (c == j) ? inv : cmuls(*a, inv);
+            }
+            __syncthreads();
+            for (int e = tid; e < n * jb; e += NT) {
+                const int i = e / jb, c = j0 + e % jb;
+                if (i == j) continue;
+                const double2 f = buf[i];
+                double2* a = &A[int64_t(i) * n + c];
+                if (c == j) {
+                    double2 t = cmuls(f, inv);
+                    *a = make_double2(-t.x, -t.y);
+                } else {
+                    double2 r = A[int64_t(j) * n + c];
+                    double2 x = *a;
+                    x.x -= f.x * r.x - f.y * r.y;
+                    x.y -= f.x * r.y + f.y * r.x;
+                    *a = x;
+                }
+            }
+            __syncthreads();
+        }
+        // ---- update of the columns outside the panel: c <- c + (T[:,J] - I[:,J]) c[J]
+        const int c = tid;
+        const bool own = (c < n) && (c < j0 || c >= j0 + jb);
+        double2 cj[SB];
+#pragma unroll
+        for (int t = 0; t < SB; ++t)
+            cj[t] = (own && t < jb) ? A[int64_t(j0 + t) * n + c] : make_double2(0.0, 0.0);
+        for (int i0 = 0; i0 < n; i0 += RCH) {
+            __syncthreads();
+            for (int e = tid; e < RCH * SB; e += NT) {
+                const int r = e / SB, t = e % SB;
+                tch[r][t] = (i0 + r < n && t < jb) ? A[int64_t(i0 + r) * n + j0 + t]
+                                                   : make_double2(0.0, 0.0);
+            }
+            __syncthreads();
+            if (own) {
+                const int rmax = min(RCH, n - i0);
+                for (int r = 0; r < rmax; ++r) {
+                    const int i = i0 + r;
+                    double2 s = (i >= j0 && i < j0 + jb) ? make_double2(0.0, 0.0)
+                                                          : A[int64_t(i) * n + c];
+#pragma unroll
+                    for (int t = 0; t < SB; ++t) {
+                        const double2 tv = tch[r][t];
+                        s.x += tv.x * cj[t].x - tv.y * cj[t].y;
+                        s.y += tv.x * cj[t].y + tv.y * cj[t].x;
+                    }
+                    A[int64_t(i) * n + c] = s;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- undo the column permutation, form W~ and R
+    if (tid == 0) {
+        for (int c = 0; c < n; ++c) idx[c] = c;
+        for (int j = n - 1; j >= 0; --j) {
+            int t = idx[j];
+            idx[j] = idx[perm[j]];
+            idx[perm[j]] = t;
+        }
+    }
+    __syncthreads();
+    for (int i = 0; i < n; ++i) {
+        for (int c = tid; c < n; c += NT) buf[c] = A[int64_t(i) * n + c];
+        __syncthreads();
+        for (int c = tid; c < n; c += NT) {
+            double2 x = buf[idx[c]];
+            if (c == i) x.x -= 1.0;
+            const double f = sv[i] * sv[c];
+            double2 w = make_double2(f * x.x, f * x.y);
+            A[int64_t(i) * n + c] = w;
+            if (Rq) {
+                const double vv = vq[i] * vq[c];
+                double2 p = P[int64_t(i) * n + c];
+                Rq[int64_t(i) * n + c] = make_double2(w.x - vv * p.x, w.y - vv * p.y);
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) info[mi] = s_info;
+}
+
+}  // namespace
+
+void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
+                   const double* v, void* Wt_iw, void* R_iw, int* info) {
+    hipLaunchKernelGGL(k_screen, dim3(nq * h.niw_b), dim3(NT), 0, s, d, q0, (const double2*)P_iw, v,
+                       (double2*)Wt_iw, (double2*)R_iw, info);
+    MSGW_HIP(hipGetLastError());
+}
+
+}  // namespace msgw

@@ -1,0 +1,199 @@
+"""Device-resident driver of the Matsubara-time GW loop (one GPU).
+
+Owns the torch buffers and sequences the C-ABI calls; every step of the path
+runs in libmatsgw's kernels.  Loop structure of the paper's "Scheme for scGW"
+subsection: G0W0 is the first pass, GW0 keeps W~ from the first iteration and
+scGW updates everything.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib as L
+
+
+class HostM:
+    """M from host arrays: q -> flat complex numpy array in the library layout."""
+
+    def __init__(self, per_q, dtype):
+        self.per_q = per_q
+        self.dtype = dtype
+        self._cache = {}
+
+    def __call__(self, run, q0, nq):
+        import torch
+        key = (q0, nq)
+        if key not in self._cache:
+            flat = np.concatenate([np.asarray(self.per_q(q)).reshape(-1) for q in range(q0, q0 + nq)])
+            ct = torch.complex128 if self.dtype == L.C128 else torch.complex64
+            self._cache = {key: torch.from_numpy(flat).to(ct).to(run.device)}
+        return self._cache[key]
+
+
+class ResidentM:
+    """All q blocks resident in one device tensor (complex, library layout)."""
+
+    def __init__(self, tensor, mpre):
+        self.t = tensor
+        self.mpre = mpre
+
+    def __call__(self, run, q0, nq):
+        return self.t[self.mpre[q0]:self.mpre[q0 + nq]]
+
+
+class SynthM:
+    """M generated on the device per q batch by msgw_synth_M (Philox4x32-10)."""
+
+    def __init__(self, seed, symmetric=True):
+        self.seed = seed
+        self.symmetric = symmetric
+        self.buf = None
+
+    def __call__(self, run, q0, nq):
+        import torch
+        size = int(run.mpre[q0 + nq] - run.mpre[q0])
+        ct = torch.complex128 if run.m_dtype == L.C128 else torch.complex64
+        if self.buf is None or self.buf.numel() < size or self.buf.dtype != ct:
+            self.buf = torch.empty(size, dtype=ct, device=run.device)
+        out = self.buf[:size]
+        run.ctx.synth_M(self.seed, q0, nq, self.symmetric, run.m_dtype, out, stream=run.stream)
+        return out
+
+
+class GWRun:
+    """State of one run: problem tables, workspace, G, Sigma and per-q-batch buffers."""
+
+    def __init__(self, nk, kmq, nb, ni, tau, beta, niw_f, niw_b, scale, eps, v, n_target,
+                 precision=L.FP64, sigma_mode=L.SIGMA_DIAG, q_batch=1, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream
+        self.nk = int(nk)
+        self.nb = np.asarray(nb, dtype=np.int32)
+        self.ni = np.asarray(ni, dtype=np.int32)
+        self.kmq = np.asarray(kmq, dtype=np.int32).reshape(self.nk, self.nk)
+        self.tau = np.asarray(tau, dtype=np.float64)
+        self.ntau = self.tau.size
+        self.beta = float(beta)
+        self.niw_f, self.niw_b = int(niw_f), int(niw_b)
+        self.nbmax = int(self.nb.max())
+        self.precision = precision
+        self.sigma_mode = sigma_mode
+        self.m_dtype = L.C128 if precision == L.FP64 else L.C64
+        self.n_target = float(n_target)
+        self.q_batch = int(q_batch)
+        self.ctx = L.Context(device)
+        self.ctx.set_problem(self.nk, self.kmq, self.nb, self.ni, self.tau, self.beta,
+                             self.niw_f, self.niw_b, scale, sigma_mode)
+        ws_bytes = self.ctx.workspace_size(self.q_batch)
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        self.ctx.set_workspace(self.ws)
+        # prefixes of the packed per-q arrays
+        nk = self.nk
+        self.mpre = np.zeros(nk + 1, dtype=np.int64)
+        for q in range(nk):
+            self.mpre[q + 1] = self.mpre[q] + self.ctx.m_layout(q, nk)[1]
+        self.ppre = np.concatenate([[0], np.cumsum(self.ntau * self.ni.astype(np.int64) ** 2)])
+        self.wpre = np.concatenate([[0], np.cumsum(self.niw_b * self.ni.astype(np.int64) ** 2)])
+        self.vpre = np.concatenate([[0], np.cumsum(self.ni.astype(np.int64))])
+        f64, c128 = torch.float64, torch.complex128
+        dev = self.device
+        self.eps = torch.from_numpy(np.ascontiguousarray(eps, dtype=np.float64)).to(dev)
+        self.v = torch.from_numpy(np.concatenate([np.asarray(x, dtype=np.float64) for x in v])).to(dev)
+        self.G_tau = torch.zeros((nk, self.nbmax, self.ntau), dtype=f64, device=dev)
+        if sigma_mode == L.SIGMA_FULL:
+            self.sig_tau = torch.zeros((nk, self.nbmax, self.nbmax, self.ntau), dtype=c128, device=dev)
+            self.sig_x = torch.zeros((nk, self.nbmax, self.nbmax), dtype=c128, device=dev)
+        else:
+            self.sig_tau = torch.zeros((nk, self.nbmax, self.ntau), dtype=f64, device=dev)
+            self.sig_x = torch.zeros((nk, self.nbmax), dtype=f64, device=dev)
+        self.sig_iw = torch.zeros((nk, self.nbmax, self.niw_f), dtype=c128, device=dev)
+        self.G_iw = torch.zeros((nk, self.nbmax, self.niw_f), dtype=c128, device=dev)
+        self.mu = torch.zeros(1, dtype=f64, device=dev)
+        self.N = torch.zeros(1, dtype=f64, device=dev)
+        self.gap_d = torch.zeros(1, dtype=f64, device=dev)
+        self.flags = torch.zeros(1, dtype=torch.int32, device=dev)
+        # per q batch
+        maxp = max(int(self.ppre[q + self.q_batch] - self.ppre[q])
+                   for q in range(0, nk - self.q_batch + 1)) if nk >= self.q_batch else int(self.ppre[-1])
+        maxw = max(int(self.wpre[q + self.q_batch] - self.wpre[q])
+                   for q in range(0, nk - self.q_batch + 1)) if nk >= self.q_batch else int(self.wpre[-1])
+        self.P_tau = torch.empty(maxp, dtype=c128, device=dev)
+        self.Wt_tau = torch.empty(maxp, dtype=c128, device=dev)
+        self.P_iw = torch.empty(maxw, dtype=c128, device=dev)
+        self.Wt_iw = torch.empty(maxw, dtype=c128, device=dev)
+        self.R_iw = torch.empty(maxw, dtype=c128, device=dev)
+        self.info = torch.zeros(self.q_batch * self.niw_b, dtype=torch.int32, device=dev)
+        self.W_frozen = None
+
+    # -- steps ---------------------------------------------------------------------------------
+    def green0(self, mu=0.0):
+        self.ctx.green0(self.eps, mu, self.G_tau, stream=self.stream)
+
+    def _batches(self):
+        q = 0
+        while q < self.nk:
+            nq = min(self.q_batch, self.nk - q)
+            yield q, nq
+            q += nq
+
+    def q_block(self, M_source, q0, nq, keep=None):
+        """P -> P(i nu) -> W~(i nu) -> W~(tau) -> Sigma^c, Sigma^x for q0..q0+nq-1."""
+        ctx, st = self.ctx, self.stream
+        M = M_source(self, q0, nq)
+        if self.W_frozen is None or q0 not in self.W_frozen:
+            ctx.polarization(q0, nq, M, self.m_dtype, self.G_tau, self.precision, self.P_tau, stream=st)
+            for q in range(q0, q0 + nq):
+                n = int(self.ni[q])
+                p0 = int(self.ppre[q] - self.ppre[q0])
+                w0 = int(self.wpre[q] - self.wpre[q0])
+                ctx.tau_to_iw(L.BOSON, 1, n * n, self.P_tau[p0:], 1, None, self.P_iw[w0:], stream=st)
+            ctx.screen(q0, nq, self.P_iw, self.v[self.vpre[q0]:], self.Wt_iw, self.R_iw, self.info,
+                       stream=st)
+            ctx.screened_tau(q0, nq, self.R_iw, self.P_tau, self.v[self.vpre[q0]:], self.Wt_tau,
+                             stream=st)
+            Wt = self.Wt_tau
+            if keep is not None:
+                keep[q0] = self.Wt_tau[:int(self.ppre[q0 + nq] - self.ppre[q0])].clone()
+        else:
+            Wt = self.W_frozen[q0]
+        ctx.self_energy(q0, nq, M, self.m_dtype, self.G_tau, Wt, self.precision, self.sig_tau, stream=st)
+        ctx.sigma_x(q0, nq, M, self.m_dtype, self.G_tau, self.v[self.vpre[q0]:], self.sig_x, stream=st)
+
+    def sigma_pass(self, M_source, keep_W=False):
+        """Sigma^c(tau), Sigma^x and Sigma^c(i w) from the current G (all q)."""
+        self.sig_tau.zero_()
+        self.sig_x.zero_()
+        keep = {} if keep_W else None
+        for q0, nq in self._batches():
+            self.q_block(M_source, q0, nq, keep=keep)
+        if keep_W:
+            self.W_frozen = keep
+        if self.sigma_mode == L.SIGMA_DIAG:
+            self.ctx.tau_to_iw(L.FERMION, self.nk * self.nbmax, 1, self.sig_tau, 0, None, self.sig_iw,
+                               stream=self.stream)
+
+    def dyson(self, search=True):
+        self.ctx.dyson(self.eps, self.sig_x, self.sig_iw, self.n_target,
+                       L.MU_SEARCH if search else L.MU_FIXED, self.mu, self.G_iw, self.G_tau,
+                       self.N, self.flags, stream=self.stream)
+
+    def gap(self):
+        self.ctx.gap(self.eps, self.sig_x, self.sig_iw, self.mu, int(round(self.n_target)),
+                     self.gap_d, stream=self.stream)
+
+    def run(self, M_source, mode="g0w0", niter=1):
+        """Returns a list of per-iteration dicts (host copies of mu, N, gap, flags)."""
+        self.green0(0.0)
+        self.mu.zero_()
+        self.W_frozen = None
+        hist = []
+        for it in range(1 if mode == "g0w0" else niter):
+            self.sigma_pass(M_source, keep_W=(mode == "gw0" and it == 0))
+            if mode != "g0w0":
+                self.dyson(True)
+            self.gap()
+            hist.append(dict(mu=float(self.mu.item()), N=float(self.N.item()),
+                             gap=float(self.gap_d.item()), flags=int(self.flags.item())))
+        return hist

@@ -1,0 +1,336 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded inputs.
+
+FP64 path gate: relative Frobenius error <= 1e-10 per array.
+"""
+import numpy as np
+import pytest
+
+import gwinputs as gi
+import oracle as o
+from gpu_util import host_M, make_run, np_, rel
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+# several 64-wide tiles plus a ragged tail in NI, uneven band counts, UPM mesh
+SMALL = gi.tiny(name="small", grid=(2, 2, 1), nocc=3, nemp=4, ni=37, ntau=20, beta=12.0, niw=24)
+UNEVEN = gi.Config(name="uneven", grid=(3, 2, 1),
+                   bands=((2, -1.0, -0.2), (6, 0.1, 1.5)), nb=None, ni=None,
+                   nb_range=(3, 8), ni_range=(5, 70), ntau=20, mesh="upm", beta=20.0,
+                   niw_f=16, niw_b=16)
+TILES = gi.tiny(name="tiles", grid=(2, 1, 1), nocc=4, nemp=5, ni=133, ntau=10, beta=8.0, niw=12)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def oracle_G(prob, mu=0.0):
+    return o.green0(prob.eps, prob.nb, prob.tau, prob.cfg.beta, mu)
+
+
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN])
+def test_green0(torch, cfg):
+    prob, run = make_run(cfg)
+    run.green0(0.3)
+    torch.cuda.synchronize()
+    assert rel(np_(run.G_tau), oracle_G(prob, 0.3)) < 1e-13
+
+
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_synth_M_matches_host_generator(torch, cfg, symmetric):
+    import paper_1602_02313_amd as amd
+    prob, run = make_run(cfg)
+    g = gi.MGenerator(cfg, symmetric=symmetric)
+    ref = np.concatenate([g.q_packed(q) for q in range(cfg.nk)])
+    for dt, ct in ((amd.C128, torch.complex128), (amd.C64, torch.complex64)):
+        buf = torch.empty(ref.size, dtype=ct, device="cuda")
+        run.ctx.synth_M(cfg.seed, 0, cfg.nk, symmetric, dt, buf)
+        torch.cuda.synchronize()
+        got = np_(buf)
+        if dt == amd.C128:
+            assert np.max(np.abs(got - ref)) <= 1e-14 * np.max(np.abs(ref))
+        else:
+            want = ref.astype(np.complex64)
+            assert np.max(np.abs(got - want)) <= 2e-7 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
+def test_polarization_fp64(torch, cfg):
+    import paper_1602_02313_amd as amd
+    prob, run = make_run(cfg, q_batch=cfg.nk)
+    g, src = host_M(cfg, amd.C128)
+    run.green0(0.0)
+    M = src(run, 0, cfg.nk)
+    run.ctx.polarization(0, cfg.nk, M, amd.C128, run.G_tau, amd.FP64, run.P_tau)
+    torch.cuda.synchronize()
+    G = oracle_G(prob)
+    P = np_(run.P_tau)
+    for q in range(cfg.nk):
+        ref = o.polarization(g.q_blocks(q), G, prob.kmq[q], cfg.scale)
+        got = P[run.ppre[q]:run.ppre[q + 1]].reshape(ref.shape)
+        assert rel(got, ref) < TOL, q
+
+
+@pytest.mark.parametrize("stat", [0, 1])
+def test_tau_to_iw(torch, stat):
+    prob, run = make_run(SMALL)
+    cfg = SMALL
+    rng = np.random.default_rng(2)
+    nblk, ln = 5, 7
+    niw = cfg.niw_f if stat == 0 else cfg.niw_b
+    for cplx in (False, True):
+        f = rng.normal(size=(nblk, prob.tau.size, ln))
+        if cplx:
+            f = f + 1j * rng.normal(size=f.shape)
+        ft = torch.from_numpy(f).cuda()
+        out = torch.empty((nblk, niw, ln), dtype=torch.complex128, device="cuda")
+        run.ctx.tau_to_iw(stat, nblk, ln, ft, int(cplx), None, out)
+        torch.cuda.synchronize()
+        ref = np.moveaxis(o.tau_to_iw(np.moveaxis(f, 1, 0), prob.tau, cfg.beta, stat, niw), 0, 1)
+        assert rel(np_(out), ref) < 1e-12
+    if stat == 0:
+        # with reference energies: f = G0(E) + smooth remainder
+        E = rng.uniform(-1, 1, size=(nblk, ln))
+        f = np.moveaxis(o.green0_tau(E, prob.tau, cfg.beta), -1, 1) + 0.1 * rng.normal(size=(nblk, prob.tau.size, ln))
+        out = torch.empty((nblk, niw, ln), dtype=torch.complex128, device="cuda")
+        run.ctx.tau_to_iw(0, nblk, ln, torch.from_numpy(f).cuda(), 0, torch.from_numpy(E).cuda(), out)
+        torch.cuda.synchronize()
+        ref = np.moveaxis(o.tau_to_iw(np.moveaxis(f, 1, 0), prob.tau, cfg.beta, 0, niw, e_ref=E), 0, 1)
+        assert rel(np_(out), ref) < 1e-12
+
+
+def test_iw_to_tau(torch):
+    prob, run = make_run(SMALL)
+    cfg = SMALL
+    rng = np.random.default_rng(3)
+    nblk, ln = 4, 6
+    F = rng.normal(size=(nblk, cfg.niw_f, ln)) + 1j * rng.normal(size=(nblk, cfg.niw_f, ln))
+    E = rng.uniform(-1, 1, size=(nblk, ln))
+    out = torch.empty((nblk, prob.tau.size, ln), dtype=torch.float64, device="cuda")
+    for eref in (None, E):
+        run.ctx.iw_to_tau(0, nblk, ln, 0, torch.from_numpy(F).cuda(), None,
+                          None if eref is None else torch.from_numpy(eref).cuda(), out)
+        torch.cuda.synchronize()
+        ref = np.moveaxis(o.iw_to_tau_fermion(np.moveaxis(F, 1, 0), prob.tau, cfg.beta, e_ref=eref), 0, 1)
+        assert rel(np_(out), ref) < 1e-12
+    n = 9
+    R = rng.normal(size=(cfg.niw_b, n, n)) + 1j * rng.normal(size=(cfg.niw_b, n, n))
+    add = rng.normal(size=(prob.tau.size, n, n)) + 1j * rng.normal(size=(prob.tau.size, n, n))
+    out = torch.empty((prob.tau.size, n, n), dtype=torch.complex128, device="cuda")
+    run.ctx.iw_to_tau(1, 1, n * n, n, torch.from_numpy(R).cuda(), torch.from_numpy(add).cuda(), None, out)
+    torch.cuda.synchronize()
+    ref = o.iw_to_tau_boson_herm(R, prob.tau, cfg.beta, add_tau=add)
+    assert rel(np_(out), ref) < 1e-12
+
+
+def _oracle_pw(prob, g, q, G):
+    cfg = prob.cfg
+    P = o.polarization(g.q_blocks(q), G, prob.kmq[q], cfg.scale)
+    Piw = o.tau_to_iw(P, prob.tau, cfg.beta, o.BOSON, cfg.niw_b)
+    W, R = o.screen(Piw, prob.v[q])
+    Wt = o.wt_tau(R, P, prob.v[q], prob.tau, cfg.beta)
+    return P, Piw, W, R, Wt
+
+
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
+def test_screen_and_screened_tau(torch, cfg):
+    prob, run = make_run(cfg, q_batch=cfg.nk)
+    g = gi.MGenerator(cfg)
+    G = oracle_G(prob)
+    Piw_all, P_all, refs = [], [], []
+    for q in range(cfg.nk):
+        P, Piw, W, R, Wt = _oracle_pw(prob, g, q, G)
+        P_all.append(P.ravel())
+        Piw_all.append(Piw.ravel())
+        refs.append((W, R, Wt))
+    run.P_iw.copy_(torch.from_numpy(np.concatenate(Piw_all)))
+    run.P_tau.copy_(torch.from_numpy(np.concatenate(P_all)))
+    run.ctx.screen(0, cfg.nk, run.P_iw, run.v, run.Wt_iw, run.R_iw, run.info)
+    run.ctx.screened_tau(0, cfg.nk, run.R_iw, run.P_tau, run.v, run.Wt_tau)
+    torch.cuda.synchronize()
+    assert int(run.info.abs().max()) == 0
+    Wg, Rg, Wtg = np_(run.Wt_iw), np_(run.R_iw), np_(run.Wt_tau)
+    for q, (W, R, Wt) in enumerate(refs):
+        w0, w1 = run.wpre[q], run.wpre[q + 1]
+        p0, p1 = run.ppre[q], run.ppre[q + 1]
+        assert rel(Wg[w0:w1].reshape(W.shape), W) < TOL
+        assert rel(Rg[w0:w1].reshape(R.shape), R) < 1e-9
+        assert rel(Wtg[p0:p1].reshape(Wt.shape), Wt) < TOL
+
+
+def test_screen_non_hermitian(torch):
+    """General complex P (no symmetry): the pivoted inversion still matches LAPACK's solve."""
+    cfg = SMALL
+    prob, run = make_run(cfg, q_batch=1)
+    rng = np.random.default_rng(9)
+    n = cfg.ni
+    P = (rng.normal(size=(cfg.niw_b, n, n)) + 1j * rng.normal(size=(cfg.niw_b, n, n))) * 0.05
+    run.P_iw[:P.size].copy_(torch.from_numpy(P.ravel()))
+    run.ctx.screen(0, 1, run.P_iw, run.v, run.Wt_iw, run.R_iw, run.info)
+    torch.cuda.synchronize()
+    W, R = o.screen(P, prob.v[0])
+    assert rel(np_(run.Wt_iw)[:P.size].reshape(W.shape), W) < TOL
+
+
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
+def test_self_energy_and_exchange_fp64(torch, cfg):
+    import paper_1602_02313_amd as amd
+    prob, run = make_run(cfg, q_batch=1)
+    g, src = host_M(cfg, amd.C128)
+    G = oracle_G(prob)
+    run.green0(0.0)
+    run.sig_tau.zero_()
+    run.sig_x.zero_()
+    ref_c = 0
+    ref_x = 0
+    for q in range(cfg.nk):
+        _, _, _, _, Wt = _oracle_pw(prob, g, q, G)
+        run.Wt_tau[:Wt.size].copy_(torch.from_numpy(Wt.ravel()))
+        M = src(run, q, 1)
+        run.ctx.self_energy(q, 1, M, amd.C128, run.G_tau, run.Wt_tau, amd.FP64, run.sig_tau)
+        run.ctx.sigma_x(q, 1, M, amd.C128, run.G_tau, run.v[run.vpre[q]:], run.sig_x)
+        ref_c = ref_c + o.sigma_c(g.q_blocks(q), G, prob.kmq[q], Wt, cfg.scale)
+        ref_x = ref_x + o.sigma_x(g.q_blocks(q), -G[:, :, -1], prob.kmq[q], prob.v[q], cfg.scale)
+    torch.cuda.synchronize()
+    assert rel(np_(run.sig_tau), ref_c) < TOL
+    assert rel(np_(run.sig_x), ref_x) < TOL
+
+
+def test_self_energy_full_mode(torch):
+    import paper_1602_02313_amd as amd
+    cfg = gi.tiny(name="full", grid=(2, 1, 1), nocc=2, nemp=3, ni=11, ntau=10, beta=6.0, niw=8)
+    prob, run = make_run(cfg, sigma_mode=amd.SIGMA_FULL)
+    g, src = host_M(cfg, amd.C128)
+    G = oracle_G(prob)
+    run.green0(0.0)
+    run.sig_tau.zero_()
+    run.sig_x.zero_()
+    ref_c = ref_x = 0
+    for q in range(cfg.nk):
+        _, _, _, _, Wt = _oracle_pw(prob, g, q, G)
+        run.Wt_tau[:Wt.size].copy_(torch.from_numpy(Wt.ravel()))
+        M = src(run, q, 1)
+        run.ctx.self_energy(q, 1, M, amd.C128, run.G_tau, run.Wt_tau, amd.FP64, run.sig_tau)
+        run.ctx.sigma_x(q, 1, M, amd.C128, run.G_tau, run.v[run.vpre[q]:], run.sig_x)
+        ref_c = ref_c + o.sigma_c(g.q_blocks(q), G, prob.kmq[q], Wt, cfg.scale, full=True)
+        ref_x = ref_x + o.sigma_x(g.q_blocks(q), -G[:, :, -1], prob.kmq[q], prob.v[q], cfg.scale, full=True)
+    torch.cuda.synchronize()
+    assert rel(np_(run.sig_tau), ref_c) < TOL
+    assert rel(np_(run.sig_x), ref_x) < TOL
+
+
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN])
+def test_dyson_and_gap(torch, cfg):
+    prob, run = make_run(cfg)
+    rng = np.random.default_rng(4)
+    nb = prob.eps.shape[1]
+    w = o.matsubara(o.FERMION, cfg.niw_f, cfg.beta)
+    # a causal two-pole self-energy per state plus a static shift
+    a = rng.uniform(0.05, 0.2, size=(cfg.nk, nb, 1))
+    p = rng.uniform(-1, 1, size=(cfg.nk, nb, 1))
+    sig = a / (1j * w[None, None, :] - p)
+    sstat = rng.uniform(-0.2, 0.2, size=(cfg.nk, nb))
+    run.sig_iw.copy_(torch.from_numpy(sig))
+    run.sig_x.copy_(torch.from_numpy(sstat))
+    for search in (True, False):
+        if not search:
+            run.mu.fill_(0.0123)
+        run.dyson(search)
+        run.gap()
+        torch.cuda.synchronize()
+        d = o.dyson(prob.eps, prob.nb, sstat, sig, cfg.beta, prob.tau, prob.n_target,
+                    mu0=0.0123, search=search)
+        assert int(run.flags.item()) == 0
+        assert abs(run.N.item() - d["N"]) < 1e-10 * d["N"]
+        assert rel(np_(run.G_tau), d["G_tau"]) < TOL
+        assert rel(np_(run.G_iw), d["G_iw"]) < TOL
+        if search:
+            assert abs(run.N.item() - prob.n_target) < 1e-9 * prob.n_target
+        gp = o.gap_proxy(prob.eps, prob.nb, sstat, sig[..., 0], run.mu.item(), prob.n_target)
+        assert abs(run.gap_d.item() - gp) < 1e-10 * max(1.0, abs(gp))
+
+
+def test_dyson_flags_nan(torch):
+    prob, run = make_run(SMALL)
+    run.sig_iw.fill_(float("nan"))
+    run.sig_x.zero_()
+    run.dyson(True)
+    torch.cuda.synchronize()
+    assert int(run.flags.item()) & 1
+
+
+# ---------------------------------------------------------------------------------------------
+# end to end on the 2x2x2, 16-band, NI = 64 workload
+# ---------------------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c1_oracle():
+    prob = gi.make_problem(gi.C1)
+    g = gi.MGenerator(gi.C1)
+    return prob, g, o.run_loop(prob, g, "scgw", 2)
+
+
+def test_end_to_end_c1_scgw_fp64(torch, c1_oracle):
+    import paper_1602_02313_amd as amd
+    prob, g, hist = c1_oracle
+    _, run = make_run(gi.C1, q_batch=2)
+    src = amd.HostM(lambda q: g.q_packed(q), amd.C128)
+    out = run.run(src, "scgw", 2)
+    torch.cuda.synchronize()
+    for it in range(2):
+        assert out[it]["flags"] == 0
+        assert abs(out[it]["N"] - hist[it]["N"]) < 1e-10 * hist[it]["N"]
+        assert abs(out[it]["gap"] - hist[it]["gap"]) < 1e-10 * abs(hist[it]["gap"])
+    assert rel(np_(run.sig_tau), hist[-1]["sigc_tau"]) < TOL
+    assert rel(np_(run.sig_x), hist[-1]["sigx"]) < TOL
+    assert rel(np_(run.sig_iw), hist[-1]["sigc_iw"]) < TOL
+    assert rel(np_(run.G_tau), hist[-1]["G_tau"]) < TOL
+
+
+def test_end_to_end_c1_g0w0_and_gw0(torch, c1_oracle):
+    import paper_1602_02313_amd as amd
+    prob, g, _ = c1_oracle
+    src = amd.HostM(lambda q: g.q_packed(q), amd.C128)
+    for mode, nit in (("g0w0", 1), ("gw0", 2)):
+        hist = o.run_loop(prob, g, mode, nit)
+        _, run = make_run(gi.C1, q_batch=8)
+        out = run.run(src, mode, nit)
+        torch.cuda.synchronize()
+        assert rel(np_(run.sig_tau), hist[-1]["sigc_tau"]) < TOL
+        assert abs(out[-1]["gap"] - hist[-1]["gap"]) < 1e-10 * abs(hist[-1]["gap"])
+
+
+# ---------------------------------------------------------------------------------------------
+# error paths (host-side validation, nothing enqueued)
+# ---------------------------------------------------------------------------------------------
+def test_validation_errors(torch):
+    import paper_1602_02313_amd as amd
+    prob, run = make_run(SMALL)
+    ctx = amd.Context(0)
+    bad = prob.tau.copy()
+    bad[3] += 1e-3                      # breaks tau_i + tau_{N-i} = beta
+    with pytest.raises(amd.MsgwError) as e:
+        ctx.set_problem(SMALL.nk, prob.kmq, prob.nb, prob.ni, bad, SMALL.beta, 8, 8, -0.25)
+    assert e.value.code == -2
+    with pytest.raises(amd.MsgwError) as e:
+        ctx.set_problem(SMALL.nk, prob.kmq, prob.nb, prob.ni, prob.tau[:3], SMALL.beta, 8, 8, -0.25)
+    assert e.value.code == -2
+    ctx.set_problem(SMALL.nk, prob.kmq, prob.nb, prob.ni, prob.tau, SMALL.beta, 8, 8, -0.25)
+    with pytest.raises(amd.MsgwError) as e:
+        ctx.green0(run.eps, 0.0, run.G_tau)                   # no workspace yet
+    assert e.value.code == -4
+    with pytest.raises(amd.MsgwError) as e:
+        run.ctx.polarization(0, SMALL.nk + 1, run.P_tau, amd.C128, run.G_tau, amd.FP64, run.P_tau)
+    assert e.value.code == -1
+    with pytest.raises(amd.MsgwError) as e:
+        run.ctx.polarization(0, 1, run.P_tau, amd.C64, run.G_tau, amd.FP64, run.P_tau)
+    assert e.value.code == -1
+    with pytest.raises(amd.MsgwError):
+        run.ctx.polarization(0, 1, run.P_tau, amd.C128, run.G_tau, 7, run.P_tau)
