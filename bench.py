@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark of the Matsubara-time GW hot path on one MI355X.
+
+A step is one full pass of the path over the 4x4x4 k-grid, 64-band, NI = 400,
+81-point UPM workload: G0 -> P(q,tau) -> P(q,i nu) -> W~(q,i nu) -> W~(q,tau) ->
+Sigma^c(k,tau), Sigma^x -> Sigma^c(k,i omega) -> Dyson with the mu search -> gap
+proxy, for all 64 q.  The inputs (energies, tau mesh, Coulomb kernel and the
+complex matrix elements M for every q, 54 GB in complex64) are resident in HBM
+before the timed region; M is drawn on the device by the library's Philox
+generator.  The metric is the P + Sigma effective TFLOP/s (dense complex flop
+model, 8 real flops per complex multiply-add) over the whole step.
+
+    python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# dense MFMA peaks of MI355X (TFLOP/s).  A split-BF16 product costs three BF16 products, so its
+# effective FP32-equivalent peak is the BF16 peak / 3.
+PEAK_BF16 = 2516.6
+PEAK = {"bf16x3": PEAK_BF16 / 3.0, "fp32": 157.3, "fp64": 78.6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flop_model(prob):
+    """Dense complex flop counts of P and Sigma^c (DIAG) for all q."""
+    cfg = prob.cfg
+    ntau = prob.tau.size
+    fp = fs = 0.0
+    for q in range(cfg.nk):
+        for k in range(cfg.nk):
+            nn, nm = int(prob.nb[k]), int(prob.nb[prob.kmq[q, k]])
+            ni = int(prob.ni[q])
+            fp += 8.0 * ni * ni * nn * nm * ntau
+            fs += 8.0 * ni * ni * nn * nm * ntau + 8.0 * ni * nn * nm * ntau
+    return fp, fs
+
+
+def cpu_baseline(cfg, prob, budget_s=12.0):
+    """The FP64 oracle's polarization on a bounded sample of the same workload (host cores)."""
+    import gwinputs as gi
+    import oracle as o
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    R = 160
+    rows = np.arange(R)
+    g = gi.MGenerator(cfg)
+    blocks = [g.block(0, k, rows=rows) for k in range(cfg.nk)]
+    G = o.green0(prob.eps, prob.nb, prob.tau, cfg.beta)
+    done, flops, t_used = [], 0.0, 0.0
+    for it in range(prob.tau.size):
+        t0 = time.perf_counter()
+        o.polarization(blocks, G, prob.kmq[0], cfg.scale, taus=[it])
+        t_used += time.perf_counter() - t0
+        done.append(it)
+        flops += sum(8.0 * R * R * b.shape[1] * b.shape[2] for b in blocks)
+        if t_used > budget_s:
+            break
+    return {"value": flops / t_used / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "sample": f"polarization of q=0, I,J < {R}, all 64 k, {len(done)} of {prob.tau.size} tau "
+                      f"points ({flops:.3e} flop in {t_used:.1f} s); numpy FP64 with "
+                      f"{cores} BLAS threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
+    ap.add_argument("--q-batch", type=int, default=4)
+    ap.add_argument("--fp64-ref-q", type=int, default=1,
+                    help="q points on which the FP64 GPU path is timed for comparison (0: skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus "
+              f"{args.gpus}); the q axis would be sharded across GPUs with one all-reduce of "
+              f"Sigma, which is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import gwinputs as gi
+    import paper_1602_02313_amd as amd
+    from paper_1602_02313_amd.driver import EventTimer
+
+    cfg = gi.CONFIGS[args.config]
+    prob = gi.make_problem(cfg)
+    prec = {"bf16x3": amd.BF16X3, "fp32": amd.FP32, "fp64": amd.FP64}[args.precision]
+    log(f"[bench] {cfg.name}: nk={cfg.nk} nb={int(prob.nb.max())} NI={int(prob.ni.max())} "
+        f"ntau={prob.tau.size} niw={cfg.niw_f} precision={args.precision}")
+    run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
+                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=prec,
+                    q_batch=args.q_batch)
+    ct = torch.complex128 if run.m_dtype == amd.C128 else torch.complex64
+    M = torch.empty(int(run.mpre[-1]), dtype=ct, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.ctx.synth_M(cfg.seed, 0, cfg.nk, 1, run.m_dtype, M)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    log(f"[bench] M resident: {M.numel() * M.element_size() / 1e9:.1f} GB generated in {t_gen:.2f} s")
+    src = amd.ResidentM(M, run.mpre)
+
+    def step():
+        run.green0(0.0)
+        run.mu.zero_()
+        run.sigma_pass(src)
+        run.dyson(True)
+        run.gap()
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f} s")
+    timer = EventTimer()
+    run.timer = timer
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        log(f"[bench] step {s} done at {time.perf_counter() - t0:.2f} s")
+    t_tot = time.perf_counter() - t0
+    run.timer = None
+    ms_step = 1e3 * t_tot / args.steps
+    kern = timer.summary()
+    fp, fs = flop_model(prob)
+    value = (fp + fs) / (ms_step / 1e3) / 1e12
+    flags, gap, N = int(run.flags.item()), float(run.gap_d.item()), float(run.N.item())
+
+    # per-kernel times and the dominant contraction's roofline
+    nb_q = -(-cfg.nk // args.q_batch)
+    ksum = {k: float(np.sum(v)) / args.steps for k, v in kern.items()}
+    kavg = {k: float(np.mean(v)) for k, v in kern.items()}
+    per_launch = {"polarization": fp / nb_q, "self_energy": fs / nb_q}
+    dom = max(("polarization", "self_energy"), key=lambda k: ksum.get(k, 0.0))
+    achieved = per_launch[dom] / (kavg[dom] / 1e3) / 1e12
+    peak = PEAK[args.precision]
+    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 1),
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": dom, "flop_per_launch": per_launch[dom],
+            "avg_launch_ms": round(kavg[dom], 3)}
+    if args.precision == "bf16x3":
+        roof["mfma_bf16_frac"] = round(3.0 * achieved / PEAK_BF16, 4)
+        roof["peak_basis"] = "bf16 dense 2516.6 TFLOP/s / 3 products per split product"
+    kernels = {k: {"ms_per_step": round(ksum[k], 3), "launches_per_step": len(kern[k]) // args.steps}
+               for k in kern}
+    kernels["polarization"]["tflops"] = round(fp / (ksum["polarization"] / 1e3) / 1e12, 2)
+    kernels["self_energy"]["tflops"] = round(fs / (ksum["self_energy"] / 1e3) / 1e12, 2)
+
+    # the FP64 GPU path on the same inputs (a q subset, same shapes)
+    fp64_ref = None
+    if args.fp64_ref_q > 0 and args.precision != "fp64":
+        nq = args.fp64_ref_q
+        ref = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f,
+                        cfg.niw_b, cfg.scale, prob.eps, prob.v, prob.n_target,
+                        precision=amd.FP64, q_batch=nq)
+        M64 = torch.empty(int(ref.mpre[nq]), dtype=torch.complex128, device="cuda")
+        ref.ctx.synth_M(cfg.seed, 0, nq, 1, amd.C128, M64)
+        ref.green0(0.0)
+        t64 = EventTimer()
+        ref.timer = t64
+        ref.sig_tau.zero_()
+        ref.sig_x.zero_()
+        ref.q_block(amd.ResidentM(M64, ref.mpre), 0, nq)
+        k64 = t64.summary()
+        fp1 = fp * nq / cfg.nk
+        fs1 = fs * nq / cfg.nk
+        tp, ts = k64["polarization"][0] / 1e3, k64["self_energy"][0] / 1e3
+        fp64_ref = {"q_points": nq, "polarization_tflops": round(fp1 / tp / 1e12, 2),
+                    "self_energy_tflops": round(fs1 / ts / 1e12, 2),
+                    "p_plus_sigma_tflops": round((fp1 + fs1) / (tp + ts) / 1e12, 2),
+                    "p_plus_sigma_s_extrapolated": round((tp + ts) * cfg.nk / nq, 2),
+                    "peak": PEAK["fp64"]}
+        del M64, ref
+        torch.cuda.empty_cache()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, prob)
+
+    line = {
+        "metric": "P+Sigma effective TFLOP/s and s per scGW iteration, split-FP32 vs FP64 GPU",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 2),
+        "s_per_iteration": round(ms_step / 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16x3 (split fp32 on bf16 MFMA, fp32 accumulate) + f64",
+                  "fp32": "f32 MFMA + f64", "fp64": "f64"}[args.precision],
+        "data": "synthetic (seeded Philox matrix elements, model bands, diagonal Coulomb kernel)",
+        "config": {"workload": f"{cfg.name}: one G0W0 + Dyson pass, all 64 q",
+                   "nk": cfg.nk, "nb": int(prob.nb.max()), "ni": int(prob.ni.max()),
+                   "ntau": int(prob.tau.size), "niw_f": cfg.niw_f, "niw_b": cfg.niw_b,
+                   "beta": cfg.beta, "precision": args.precision, "q_batch": args.q_batch,
+                   "flops_p": fp, "flops_sigma": fs},
+        "roofline": roof,
+        "kernels": kernels,
+        "fp64_gpu_reference": fp64_ref,
+        "cpu_baseline": cpu,
+        "m_generation_s": round(t_gen, 3),
+        "check": {"flags": flags, "N": N, "n_target": prob.n_target, "gap_Ha": gap},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

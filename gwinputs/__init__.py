@@ -357,8 +357,8 @@ class MGenerator:
         return ((np.uint64(q) * np.uint64(nk) + np.asarray(k, dtype=np.uint64)) * nbm
                 + np.asarray(n, dtype=np.uint64)) * nbm + np.asarray(m, dtype=np.uint64)
 
-    def block(self, q: int, k: int, dtype=np.complex128) -> np.ndarray:
-        """M^I_nm(k, q) as an array [NI_q, Nb_k, Nb_{k-q}]."""
+    def block(self, q: int, k: int, dtype=np.complex128, rows=None) -> np.ndarray:
+        """M^I_nm(k, q) as an array [NI_q, Nb_k, Nb_{k-q}] (or only the I in `rows`)."""
         nI = int(self.ni[q])
         nn = int(self.nb[k])
         kq = int(self.kmq[q, k])
@@ -381,7 +381,8 @@ class MGenerator:
             canon = x_e
             conj = np.zeros(x_e.shape, dtype=bool)
             real = np.zeros(x_e.shape, dtype=bool)
-        I = np.arange(nI, dtype=np.uint32)[:, None, None]
+        I = (np.arange(nI, dtype=np.uint32) if rows is None
+             else np.asarray(rows, dtype=np.uint32))[:, None, None]
         c0 = (canon & _U32).astype(np.uint32)[None]
         c1 = (canon >> np.uint64(32)).astype(np.uint32)[None]
         r0, r1, r2, r3 = philox4x32_10(c0, c1, I, np.uint32(TAG_M), self.seed)

@@ -1,18 +1,545 @@
-// Mixed-precision contractions on the matrix cores (placeholder until the MFMA kernels land).
+// Mixed-precision contractions on the CDNA4 matrix cores.
+//
+// Polarization (eq. irpol):  P_IJ(q,tau) = s sum_k sum_{nm} M^I_nm g_nm(tau) conj(M^J_nm),
+//   g_nm(tau) = G_n(k,tau) G_m(k-q,beta-tau).
+// Correlation self-energy (eq. sigc, diagonal): Y(tau) = W~(q,tau) M(q,k),
+//   Sigma_n(k,tau) += s sum_m G_m(k-q,tau) Re sum_I conj(M^I_nm) Y^I_nm.
+//
+// Complex products use the interleaved real embedding: with K' = (K, re/im),
+//   Re(x conj(y)) = [xr, xi].[yr, yi],  Im(x conj(y)) = [xi, -xr].[yr, yi]
+//   Re(w m) = [wr, wi].[mr, -mi],       Im(w m) = [wr, wi].[mi, mr]
+// so every complex contraction is two real MFMA chains sharing one operand.
+//
+// Precisions
+//   FP32:   v_mfma_f32_16x16x4_f32, FP32 operands and accumulation.
+//   BF16X3: each FP32 operand x is split into hi = bf16(x) and lo = bf16(x - hi) (round to nearest
+//           even), and x.y ~ hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 with FP32
+//           accumulation; the dropped lo.lo term is ~2^-16 relative.
+// In both, the FP32 accumulators of the polarization are flushed into the FP64 output every
+// FLUSH_STEPS K-steps, so the FP32 sums never run over more than 4096 complex terms.
+//
+// One wave (64 lanes) per work-group; each wave owns a (16 WI) x (16 WJ) x T output tile and
+// streams its operands straight from global memory (the tiles of neighbouring waves overlap,
+// the reuse is served by L2).
 #include "internal.h"
 
 namespace msgw {
+namespace {
 
-size_t mfma_scratch_bytes(const Host&, int) { return 0; }
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-int launch_pol_mfma(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*, int,
-                    void*) {
-    return MSGW_ENOTSUP;
+constexpr int PREC_FP32 = MSGW_FP32;
+constexpr int PREC_BF16X3 = MSGW_BF16X3;
+constexpr int NB_LDS = 256;       // band limit of the MFMA path (G slices staged in LDS)
+constexpr int FLUSH_STEPS = 256;  // K-steps of 16 complex between FP64 flushes
+
+inline unsigned ceil_div(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
+
+// ---- bf16 helpers -------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
+    bf16x2 v = {(__bf16)a, (__bf16)b};  // v_cvt_pk_bf16_f32, round to nearest even
+    return __builtin_bit_cast(uint32_t, v);
+}
+__device__ __forceinline__ float bf_lo(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float bf_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+// split a complex pair (re, im) into packed hi and lo bf16 pairs
+__device__ __forceinline__ void split2(float re, float im, uint32_t& h, uint32_t& l) {
+    h = pk_bf16(re, im);
+    l = pk_bf16(re - bf_lo(h), im - bf_hi(h));
+}
+// (re, im) -> (im, -re): rotate by 16 bits, flip the sign of the new high half
+__device__ __forceinline__ uint32_t rot_neg(uint32_t p) {
+    return __builtin_amdgcn_alignbit(p, p, 16) ^ 0x80000000u;
+}
+// (re, im) -> (re, -im)
+__device__ __forceinline__ uint32_t conj_pk(uint32_t p) { return p ^ 0x80000000u; }
+// (re, im) -> (im, re)
+__device__ __forceinline__ uint32_t swap_pk(uint32_t p) { return __builtin_amdgcn_alignbit(p, p, 16); }
+
+__device__ __forceinline__ floatx4 mfma_bf16(u32x4 a, u32x4 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-int launch_sig_mfma(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
-                    const void*, int, void*) {
-    return MSGW_ENOTSUP;
+// Complex elements a lane holds per 16-element K step:
+//   BF16X3: K = 4*(lane/16) + e, e < 4 (the 8 consecutive bf16 of the 16x16x32 operand)
+//   FP32:   K = 2*e + (lane/16)/2, e < 8, component (lane/16)%2 (one 16x16x4 slice per e)
+template <int PREC>
+struct Lay {
+    static constexpr int NE = PREC == PREC_BF16X3 ? 4 : 8;
+    __device__ static int koff(int g4, int e) { return PREC == PREC_BF16X3 ? 4 * g4 + e : 2 * e + (g4 >> 1); }
+};
+
+// =================================================================================================
+// polarization
+// =================================================================================================
+template <int WI, int WJ, int T, int PREC>
+__global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restrict__ M,
+                                            const double* __restrict__ G,
+                                            double2* __restrict__ P, int ntJ, int ntG) {
+    using LY = Lay<PREC>;
+    constexpr int NE = LY::NE;
+    __shared__ float Ga[NB_LDS * T];
+    __shared__ float Gb[NB_LDS * T];
+    const int lane = threadIdx.x, r16 = lane & 15, g4 = lane >> 4;
+    const int q = q0 + blockIdx.y;
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int NI = d.ni[q];
+    int bx = blockIdx.x;
+    const int tg = bx % ntG;
+    bx /= ntG;
+    const int tj = bx % ntJ, ti = bx / ntJ;
+    const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
+    if (i0 >= NI || j0 >= NI) return;
+
+    floatx4 acc[WI][WJ][T][2];
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+
+    const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
+    double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
+    const double sc = d.scale;
+    bool first = true;
+    int since = 0;
+
+    auto flush = [&]() {
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int it = t0 + t;
+#pragma unroll
+            for (int a = 0; a < WI; ++a)
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int I = i0 + 16 * a + 4 * g4 + rr, J = j0 + 16 * b + r16;
+                        if (it < ntau && I < NI && J < NI) {
+                            double2* p = &Pq[int64_t(it) * NI * NI + int64_t(I) * NI + J];
+                            double re = sc * double(acc[a][b][t][0][rr]);
+                            double im = sc * double(acc[a][b][t][1][rr]);
+                            if (!first) {
+                                double2 o = *p;
+                                re += o.x;
+                                im += o.y;
+                            }
+                            *p = make_double2(re, im);
+                        }
+                    }
+                    acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+                }
+        }
+        first = false;
+        since = 0;
+    };
+
+    for (int k = 0; k < nk; ++k) {
+        const int kq = d.kmq[q * nk + k];
+        const int nn = d.nb[k], nm = d.nb[kq];
+        const int Kk = nn * nm;
+        const float2* A = Mq + d.moff[q * nk + k];
+        __syncthreads();
+        for (int e = lane; e < nn * T; e += 64) {
+            const int n = e / T, t = e - n * T;
+            const int it = min(t0 + t, ntau - 1);
+            Ga[e] = float(G[(int64_t(k) * nbmax + n) * ntau + it]);
+        }
+        for (int e = lane; e < nm * T; e += 64) {
+            const int m = e / T, t = e - m * T;
+            const int it = min(t0 + t, ntau - 1);
+            Gb[e] = float(G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - it)]);
+        }
+        __syncthreads();
+        int n0 = 0, m0 = 0;  // (n, m) of the first K of the current step
+        const int nsteps = (Kk + 15) / 16;
+        for (int s = 0; s < nsteps; ++s) {
+            const int kb = s * 16;
+            int gi[NE];   // n index * T into Ga
+            int gj[NE];   // m index * T into Gb
+            bool ve[NE];
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int ko = LY::koff(g4, e);
+                ve[e] = kb + ko < Kk;
+                int mm = m0 + ko, nx = n0;
+                while (mm >= nm) {
+                    mm -= nm;
+                    ++nx;
+                }
+                gi[e] = min(nx, nn - 1) * T;
+                gj[e] = mm * T;
+            }
+            float2 xa[WI][NE], yb[WJ][NE];
+#pragma unroll
+            for (int a = 0; a < WI; ++a) {
+                const int I = i0 + 16 * a + r16;
+#pragma unroll
+                for (int e = 0; e < NE; ++e)
+                    xa[a][e] = (ve[e] && I < NI) ? A[int64_t(I) * Kk + kb + LY::koff(g4, e)]
+                                                 : make_float2(0.f, 0.f);
+            }
+#pragma unroll
+            for (int b = 0; b < WJ; ++b) {
+                const int J = j0 + 16 * b + r16;
+#pragma unroll
+                for (int e = 0; e < NE; ++e)
+                    yb[b][e] = (ve[e] && J < NI) ? A[int64_t(J) * Kk + kb + LY::koff(g4, e)]
+                                                 : make_float2(0.f, 0.f);
+            }
+            if constexpr (PREC == PREC_BF16X3) {
+                u32x4 xh[WI], xl[WI], xh2[WI], xl2[WI];
+#pragma unroll
+                for (int a = 0; a < WI; ++a)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        uint32_t h, l;
+                        split2(xa[a][e].x, xa[a][e].y, h, l);
+                        xh[a][e] = h;
+                        xl[a][e] = l;
+                        xh2[a][e] = rot_neg(h);
+                        xl2[a][e] = rot_neg(l);
+                    }
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    float g[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) g[e] = Ga[gi[e] + t] * Gb[gj[e] + t];
+#pragma unroll
+                    for (int b = 0; b < WJ; ++b) {
+                        u32x4 yh, yl;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            uint32_t h, l;
+                            split2(g[e] * yb[b][e].x, g[e] * yb[b][e].y, h, l);
+                            yh[e] = h;
+                            yl[e] = l;
+                        }
+#pragma unroll
+                        for (int a = 0; a < WI; ++a) {
+                            acc[a][b][t][0] = mfma_bf16(xh[a], yh, acc[a][b][t][0]);
+                            acc[a][b][t][1] = mfma_bf16(xh2[a], yh, acc[a][b][t][1]);
+                        }
+#pragma unroll
+                        for (int a = 0; a < WI; ++a) {
+                            acc[a][b][t][0] = mfma_bf16(xh[a], yl, acc[a][b][t][0]);
+                            acc[a][b][t][1] = mfma_bf16(xh2[a], yl, acc[a][b][t][1]);
+                        }
+#pragma unroll
+                        for (int a = 0; a < WI; ++a) {
+                            acc[a][b][t][0] = mfma_bf16(xl[a], yh, acc[a][b][t][0]);
+                            acc[a][b][t][1] = mfma_bf16(xl2[a], yh, acc[a][b][t][1]);
+                        }
+                    }
+                }
+            } else {
+                const bool imc = g4 & 1;  // this lane holds the imaginary component
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const float g = Ga[gi[e] + t] * Gb[gj[e] + t];
+#pragma unroll
+                        for (int b = 0; b < WJ; ++b) {
+                            const float y = g * (imc ? yb[b][e].y : yb[b][e].x);
+#pragma unroll
+                            for (int a = 0; a < WI; ++a) {
+                                const float x1 = imc ? xa[a][e].y : xa[a][e].x;
+                                const float x2 = imc ? -xa[a][e].x : xa[a][e].y;
+                                acc[a][b][t][0] = mfma_f32(x1, y, acc[a][b][t][0]);
+                                acc[a][b][t][1] = mfma_f32(x2, y, acc[a][b][t][1]);
+                            }
+                        }
+                    }
+                }
+            }
+            m0 += 16;
+            while (m0 >= nm) {
+                m0 -= nm;
+                ++n0;
+            }
+            if (++since == FLUSH_STEPS) flush();
+        }
+    }
+    if (since > 0 || first) flush();
+}
+
+// =================================================================================================
+// self-energy
+// =================================================================================================
+// W~(q,tau) converted once per call: FP32 -> c64 plane; BF16X3 -> hi and lo planes of packed
+// (re, im) bf16 pairs.  Layout per q: [ntau][NI][NI], q blocks packed over the call's q range.
+__global__ void k_convert_w(const double2* __restrict__ W, int64_t n, int prec,
+                            float2* __restrict__ w32, uint32_t* __restrict__ whi,
+                            uint32_t* __restrict__ wlo) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 v = W[i];
+    const float re = float(v.x), im = float(v.y);
+    if (prec == PREC_FP32) {
+        w32[i] = make_float2(re, im);
+    } else {
+        uint32_t h, l;
+        split2(re, im, h, l);
+        whi[i] = h;
+        wlo[i] = l;
+    }
+}
+
+template <int WI, int WJ, int T, int PREC>
+__global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restrict__ M,
+                                            const double* __restrict__ G,
+                                            const float2* __restrict__ w32,
+                                            const uint32_t* __restrict__ whi,
+                                            const uint32_t* __restrict__ wlo,
+                                            double* __restrict__ Sig, int ntC, int ntG) {
+    using LY = Lay<PREC>;
+    constexpr int NE = LY::NE;
+    const int lane = threadIdx.x, r16 = lane & 15, g4 = lane >> 4;
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int q = q0 + blockIdx.y / nk, k = blockIdx.y % nk;
+    const int kq = d.kmq[q * nk + k];
+    const int nn = d.nb[k], nm = d.nb[kq], NI = d.ni[q];
+    const int Kk = nn * nm;
+    int bx = blockIdx.x;
+    const int tg = bx % ntG;
+    bx /= ntG;
+    const int tc = bx % ntC, ti = bx / ntC;
+    const int i0 = ti * 16 * WI, c0 = tc * 16 * WJ, t0 = tg * T;
+    if (i0 >= NI || c0 >= Kk) return;
+    (void)nn;
+
+    const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
+    const int64_t wbase = d.ppre[q] - d.ppre[q0];
+
+    floatx4 acc[WI][WJ][T][2];
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+
+    const int nsteps = (NI + 15) / 16;
+    for (int s = 0; s < nsteps; ++s) {
+        const int jb = s * 16;
+        float2 mb[WJ][NE];
+#pragma unroll
+        for (int b = 0; b < WJ; ++b) {
+            const int col = c0 + 16 * b + r16;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int J = jb + LY::koff(g4, e);
+                mb[b][e] = (J < NI && col < Kk) ? A[int64_t(J) * Kk + col] : make_float2(0.f, 0.f);
+            }
+        }
+        if constexpr (PREC == PREC_BF16X3) {
+            u32x4 bh_re[WJ], bl_re[WJ], bh_im[WJ], bl_im[WJ];
+#pragma unroll
+            for (int b = 0; b < WJ; ++b)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t h, l;
+                    split2(mb[b][e].x, mb[b][e].y, h, l);
+                    bh_re[b][e] = conj_pk(h);
+                    bl_re[b][e] = conj_pk(l);
+                    bh_im[b][e] = swap_pk(h);
+                    bl_im[b][e] = swap_pk(l);
+                }
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const int it = min(t0 + t, ntau - 1);
+#pragma unroll
+                for (int a = 0; a < WI; ++a) {
+                    const int I = i0 + 16 * a + r16;
+                    u32x4 ah, al;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int J = jb + 4 * g4 + e;
+                        const bool ok = I < NI && J < NI;
+                        const int64_t at = wbase + int64_t(it) * NI * NI + int64_t(I) * NI + J;
+                        ah[e] = ok ? whi[at] : 0u;
+                        al[e] = ok ? wlo[at] : 0u;
+                    }
+#pragma unroll
+                    for (int b = 0; b < WJ; ++b) {
+                        acc[a][b][t][0] = mfma_bf16(ah, bh_re[b], acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma_bf16(ah, bh_im[b], acc[a][b][t][1]);
+                    }
+#pragma unroll
+                    for (int b = 0; b < WJ; ++b) {
+                        acc[a][b][t][0] = mfma_bf16(ah, bl_re[b], acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma_bf16(ah, bl_im[b], acc[a][b][t][1]);
+                    }
+#pragma unroll
+                    for (int b = 0; b < WJ; ++b) {
+                        acc[a][b][t][0] = mfma_bf16(al, bh_re[b], acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma_bf16(al, bh_im[b], acc[a][b][t][1]);
+                    }
+                }
+            }
+        } else {
+            const bool imc = g4 & 1;
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const int it = min(t0 + t, ntau - 1);
+#pragma unroll
+                for (int a = 0; a < WI; ++a) {
+                    const int I = i0 + 16 * a + r16;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int J = jb + LY::koff(g4, e);
+                        const bool ok = I < NI && J < NI;
+                        const float2 w = ok ? w32[wbase + int64_t(it) * NI * NI + int64_t(I) * NI + J]
+                                            : make_float2(0.f, 0.f);
+                        const float x = imc ? w.y : w.x;
+#pragma unroll
+                        for (int b = 0; b < WJ; ++b) {
+                            const float bre = imc ? -mb[b][e].y : mb[b][e].x;
+                            const float bim = imc ? mb[b][e].x : mb[b][e].y;
+                            acc[a][b][t][0] = mfma_f32(x, bre, acc[a][b][t][0]);
+                            acc[a][b][t][1] = mfma_f32(x, bim, acc[a][b][t][1]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // epilogue: Re(conj(M) Y) over this tile's rows, weighted by G_m, summed per band n
+    const double sc = d.scale;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int it = t0 + t;
+        if (it >= ntau) break;
+        double part[WJ];
+#pragma unroll
+        for (int b = 0; b < WJ; ++b) {
+            const int col = c0 + 16 * b + r16;
+            float s = 0.f;
+            if (col < Kk) {
+#pragma unroll
+                for (int a = 0; a < WI; ++a)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int I = i0 + 16 * a + 4 * g4 + rr;
+                        if (I < NI) {
+                            const float2 m = A[int64_t(I) * Kk + col];
+                            s += m.x * acc[a][b][t][0][rr] + m.y * acc[a][b][t][1][rr];
+                        }
+                    }
+            }
+            double v = s;
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (col < Kk) {
+                const int n = col / nm, m = col - (col / nm) * nm;
+                v *= G[(int64_t(kq) * nbmax + m) * ntau + it];
+            }
+            part[b] = v;
+        }
+        // sum the tile's columns band by band (columns are consecutive (n, m) pairs)
+        const int cl = min(c0 + 16 * WJ, Kk) - 1;
+        const int nlo = c0 / nm, nhi = cl / nm;
+        for (int nx = nlo; nx <= nhi; ++nx) {
+            double v = 0.0;
+#pragma unroll
+            for (int b = 0; b < WJ; ++b) {
+                const int col = c0 + 16 * b + r16;
+                if (col < Kk && col / nm == nx) v += part[b];
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], sc * v);
+        }
+    }
+}
+
+// =================================================================================================
+// dispatch (tile shapes per precision; see the autotuner in the host driver)
+// =================================================================================================
+struct PolCfg {
+    int WI, WJ, T;
+};
+
+template <int WI, int WJ, int T, int PREC>
+void run_pol(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+             const double* G, void* P) {
+    int maxi = 0;
+    for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
+    const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
+    hipLaunchKernelGGL((k_pol<WI, WJ, T, PREC>), dim3(ntI * ntJ * ntG, nq), dim3(64), 0, s, d, q0,
+                       (const float2*)M, G, (double2*)P, ntJ, ntG);
+    MSGW_HIP(hipGetLastError());
+}
+
+template <int WI, int WJ, int T, int PREC>
+void run_sig(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+             const double* G, const float2* w32, const uint32_t* whi, const uint32_t* wlo, void* Sig) {
+    int maxi = 0, maxc = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        maxi = std::max(maxi, h.ni[q]);
+        for (int k = 0; k < h.nk; ++k)
+            maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
+    }
+    const int ntI = ceil_div(maxi, 16 * WI), ntC = ceil_div(maxc, 16 * WJ), ntG = ceil_div(h.ntau, T);
+    hipLaunchKernelGGL((k_sig<WI, WJ, T, PREC>), dim3(ntI * ntC * ntG, nq * h.nk), dim3(64), 0, s,
+                       d, q0, (const float2*)M, G, w32, whi, wlo, (double*)Sig, ntC, ntG);
+    MSGW_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+size_t mfma_scratch_bytes(const Host& h, int nq_max) {
+    // converted W~ for the q range of one self_energy call: 8 bytes per complex element
+    // (c64 for FP32, hi + lo bf16 pairs for BF16X3)
+    std::vector<int64_t> sz(h.nk);
+    for (int q = 0; q < h.nk; ++q) sz[q] = int64_t(h.ntau) * h.ni[q] * h.ni[q];
+    int64_t best = 0;
+    for (int q = 0; q + nq_max <= h.nk; ++q) {
+        int64_t t = 0;
+        for (int j = q; j < q + nq_max; ++j) t += sz[j];
+        best = std::max(best, t);
+    }
+    return size_t(best) * 8;
+}
+
+int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                    const double* G, int precision, void* P) {
+    if (h.nbmax > NB_LDS) return MSGW_ENOTSUP;
+    if (int64_t(nq) > 65535) return MSGW_ENOTSUP;
+    if (precision == MSGW_BF16X3)
+        run_pol<2, 2, 4, PREC_BF16X3>(d, h, s, q0, nq, M, G, P);
+    else
+        run_pol<2, 2, 4, PREC_FP32>(d, h, s, q0, nq, M, G, P);
+    return MSGW_OK;
+}
+
+int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                    const double* G, const void* W, int precision, void* Sig) {
+    if (int64_t(nq) * h.nk > 65535) return MSGW_ENOTSUP;
+    const int64_t n = h.ppre[q0 + nq] - h.ppre[q0];
+    if (size_t(n) * 8 > scratch_mfma_bytes(d, h)) return MSGW_ENOMEM;
+    char* sc = scratch_mfma(d, h);
+    float2* w32 = reinterpret_cast<float2*>(sc);
+    uint32_t* whi = reinterpret_cast<uint32_t*>(sc);
+    uint32_t* wlo = whi + n;
+    hipLaunchKernelGGL(k_convert_w, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const double2*)W, n,
+                       precision, w32, whi, wlo);
+    MSGW_HIP(hipGetLastError());
+    if (precision == MSGW_BF16X3)
+        run_sig<2, 4, 4, PREC_BF16X3>(d, h, s, q0, nq, M, G, w32, whi, wlo, Sig);
+    else
+        run_sig<2, 2, 4, PREC_FP32>(d, h, s, q0, nq, M, G, w32, whi, wlo, Sig);
+    return MSGW_OK;
 }
 
 }  // namespace msgw

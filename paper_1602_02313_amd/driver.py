@@ -7,6 +7,9 @@ scGW updates everything.
 """
 from __future__ import annotations
 
+import contextlib
+from collections import defaultdict
+
 import numpy as np
 
 from . import _lib as L
@@ -58,6 +61,34 @@ class SynthM:
         out = self.buf[:size]
         run.ctx.synth_M(self.seed, q0, nq, self.symmetric, run.m_dtype, out, stream=run.stream)
         return out
+
+
+class EventTimer:
+    """HIP events recorded around each library call on the launch stream."""
+
+    def __init__(self, stream=None):
+        import torch
+        self.torch = torch
+        self.stream = stream
+        self.events = defaultdict(list)
+
+    @contextlib.contextmanager
+    def __call__(self, name):
+        T = self.torch
+        st = self.stream if self.stream is not None else T.cuda.current_stream()
+        a, b = T.cuda.Event(enable_timing=True), T.cuda.Event(enable_timing=True)
+        a.record(st)
+        yield
+        b.record(st)
+        self.events[name].append((a, b))
+
+    def reset(self):
+        self.events.clear()
+
+    def summary(self):
+        """name -> list of durations in ms (synchronises)."""
+        self.torch.cuda.synchronize()
+        return {k: [a.elapsed_time(b) for a, b in v] for k, v in self.events.items()}
 
 
 class GWRun:
@@ -126,10 +157,15 @@ class GWRun:
         self.R_iw = torch.empty(maxw, dtype=c128, device=dev)
         self.info = torch.zeros(self.q_batch * self.niw_b, dtype=torch.int32, device=dev)
         self.W_frozen = None
+        self.timer = None
+
+    def _t(self, name):
+        return self.timer(name) if self.timer is not None else contextlib.nullcontext()
 
     # -- steps ---------------------------------------------------------------------------------
     def green0(self, mu=0.0):
-        self.ctx.green0(self.eps, mu, self.G_tau, stream=self.stream)
+        with self._t("green0"):
+            self.ctx.green0(self.eps, mu, self.G_tau, stream=self.stream)
 
     def _batches(self):
         q = 0
@@ -143,23 +179,38 @@ class GWRun:
         ctx, st = self.ctx, self.stream
         M = M_source(self, q0, nq)
         if self.W_frozen is None or q0 not in self.W_frozen:
-            ctx.polarization(q0, nq, M, self.m_dtype, self.G_tau, self.precision, self.P_tau, stream=st)
-            for q in range(q0, q0 + nq):
-                n = int(self.ni[q])
-                p0 = int(self.ppre[q] - self.ppre[q0])
-                w0 = int(self.wpre[q] - self.wpre[q0])
-                ctx.tau_to_iw(L.BOSON, 1, n * n, self.P_tau[p0:], 1, None, self.P_iw[w0:], stream=st)
-            ctx.screen(q0, nq, self.P_iw, self.v[self.vpre[q0]:], self.Wt_iw, self.R_iw, self.info,
-                       stream=st)
-            ctx.screened_tau(q0, nq, self.R_iw, self.P_tau, self.v[self.vpre[q0]:], self.Wt_tau,
-                             stream=st)
+            with self._t("polarization"):
+                ctx.polarization(q0, nq, M, self.m_dtype, self.G_tau, self.precision, self.P_tau,
+                                 stream=st)
+            with self._t("tau_to_iw_P"):
+                if len(set(int(x) for x in self.ni[q0:q0 + nq])) == 1:
+                    # equal NI: the q blocks form one [nq][ntau][NI^2] batch
+                    n = int(self.ni[q0])
+                    ctx.tau_to_iw(L.BOSON, nq, n * n, self.P_tau, 1, None, self.P_iw, stream=st)
+                else:
+                    for q in range(q0, q0 + nq):
+                        n = int(self.ni[q])
+                        p0 = int(self.ppre[q] - self.ppre[q0])
+                        w0 = int(self.wpre[q] - self.wpre[q0])
+                        ctx.tau_to_iw(L.BOSON, 1, n * n, self.P_tau[p0:], 1, None, self.P_iw[w0:],
+                                      stream=st)
+            with self._t("screen"):
+                ctx.screen(q0, nq, self.P_iw, self.v[self.vpre[q0]:], self.Wt_iw, self.R_iw,
+                           self.info, stream=st)
+            with self._t("screened_tau"):
+                ctx.screened_tau(q0, nq, self.R_iw, self.P_tau, self.v[self.vpre[q0]:],
+                                 self.Wt_tau, stream=st)
             Wt = self.Wt_tau
             if keep is not None:
                 keep[q0] = self.Wt_tau[:int(self.ppre[q0 + nq] - self.ppre[q0])].clone()
         else:
             Wt = self.W_frozen[q0]
-        ctx.self_energy(q0, nq, M, self.m_dtype, self.G_tau, Wt, self.precision, self.sig_tau, stream=st)
-        ctx.sigma_x(q0, nq, M, self.m_dtype, self.G_tau, self.v[self.vpre[q0]:], self.sig_x, stream=st)
+        with self._t("self_energy"):
+            ctx.self_energy(q0, nq, M, self.m_dtype, self.G_tau, Wt, self.precision, self.sig_tau,
+                            stream=st)
+        with self._t("sigma_x"):
+            ctx.sigma_x(q0, nq, M, self.m_dtype, self.G_tau, self.v[self.vpre[q0]:], self.sig_x,
+                        stream=st)
 
     def sigma_pass(self, M_source, keep_W=False):
         """Sigma^c(tau), Sigma^x and Sigma^c(i w) from the current G (all q)."""
@@ -171,15 +222,24 @@ class GWRun:
         if keep_W:
             self.W_frozen = keep
         if self.sigma_mode == L.SIGMA_DIAG:
-            self.ctx.tau_to_iw(L.FERMION, self.nk * self.nbmax, 1, self.sig_tau, 0, None, self.sig_iw,
-                               stream=self.stream)
+            with self._t("tau_to_iw_sigma"):
+                self.ctx.tau_to_iw(L.FERMION, self.nk * self.nbmax, 1, self.sig_tau, 0, None,
+                                   self.sig_iw, stream=self.stream)
 
     def dyson(self, search=True):
+        with self._t("dyson"):
+            self._dyson(search)
+
+    def _dyson(self, search):
         self.ctx.dyson(self.eps, self.sig_x, self.sig_iw, self.n_target,
                        L.MU_SEARCH if search else L.MU_FIXED, self.mu, self.G_iw, self.G_tau,
                        self.N, self.flags, stream=self.stream)
 
     def gap(self):
+        with self._t("gap"):
+            self._gap()
+
+    def _gap(self):
         self.ctx.gap(self.eps, self.sig_x, self.sig_iw, self.mu, int(round(self.n_target)),
                      self.gap_d, stream=self.stream)
 

@@ -1,0 +1,167 @@
+"""GPU parity of the mixed-precision (FP32 and split-BF16) contractions against the FP64 oracle.
+
+Gates (relative Frobenius error per array against the FP64 oracle):
+  FP32 MFMA:       P and Sigma^c <= 2e-6
+  BF16X3 (split):  P and Sigma^c <= 1e-5 on the small shapes; Sigma^c <= 2e-6 at full size
+The inputs M are stored in complex64 for these paths; that rounding (2^-24 relative) is part
+of the measured error.
+"""
+import numpy as np
+import pytest
+
+import gwinputs as gi
+import oracle as o
+from gpu_util import make_run, np_, rel
+from test_gpu_parity import SMALL, TILES, UNEVEN, _oracle_pw, oracle_G
+
+pytestmark = pytest.mark.gpu
+
+GATE = {1: 2e-6, 2: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _m64(cfg, run, g):
+    import torch
+    flat = np.concatenate([g.q_packed(q) for q in range(cfg.nk)]).astype(np.complex64)
+    return torch.from_numpy(flat).to(run.device)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
+def test_polarization_mixed(torch, cfg, prec):
+    import paper_1602_02313_amd as amd
+    prob, run = make_run(cfg, precision=prec, q_batch=cfg.nk)
+    g = gi.MGenerator(cfg)
+    M = _m64(cfg, run, g)
+    run.green0(0.0)
+    run.ctx.polarization(0, cfg.nk, M, amd.C64, run.G_tau, prec, run.P_tau)
+    torch.cuda.synchronize()
+    G = oracle_G(prob)
+    P = np_(run.P_tau)
+    worst = 0.0
+    for q in range(cfg.nk):
+        ref = o.polarization(g.q_blocks(q), G, prob.kmq[q], cfg.scale)
+        got = P[run.ppre[q]:run.ppre[q + 1]].reshape(ref.shape)
+        worst = max(worst, rel(got, ref))
+    print(f"P {cfg.name} prec={prec}: rel {worst:.2e}")
+    assert worst < GATE[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
+def test_self_energy_mixed(torch, cfg, prec):
+    import paper_1602_02313_amd as amd
+    prob, run = make_run(cfg, precision=prec, q_batch=1)
+    g = gi.MGenerator(cfg)
+    G = oracle_G(prob)
+    run.green0(0.0)
+    run.sig_tau.zero_()
+    ref = 0
+    off = np.concatenate([[0], np.cumsum([g.q_packed(q).size for q in range(cfg.nk)])])
+    M = _m64(cfg, run, g)
+    for q in range(cfg.nk):
+        _, _, _, _, Wt = _oracle_pw(prob, g, q, G)
+        run.Wt_tau[:Wt.size].copy_(torch.from_numpy(Wt.ravel()))
+        run.ctx.self_energy(q, 1, M[off[q]:off[q + 1]], amd.C64, run.G_tau, run.Wt_tau, prec, run.sig_tau)
+        ref = ref + o.sigma_c(g.q_blocks(q), G, prob.kmq[q], Wt, cfg.scale)
+    torch.cuda.synchronize()
+    e = rel(np_(run.sig_tau), ref)
+    print(f"Sigma {cfg.name} prec={prec}: rel {e:.2e}")
+    assert e < GATE[prec]
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_end_to_end_c1_mixed(torch, prec):
+    import paper_1602_02313_amd as amd
+    cfg = gi.C1
+    prob = gi.make_problem(cfg)
+    g = gi.MGenerator(cfg)
+    hist = o.run_loop(prob, g, "g0w0", 1)
+    _, run = make_run(cfg, precision=prec, q_batch=8)
+    src = amd.HostM(lambda q: g.q_packed(q), amd.C64)
+    out = run.run(src, "g0w0", 1)
+    torch.cuda.synchronize()
+    es = rel(np_(run.sig_tau), hist[0]["sigc_tau"])
+    ex = rel(np_(run.sig_x), hist[0]["sigx"])
+    eg = abs(out[0]["gap"] - hist[0]["gap"])
+    print(f"c1 G0W0 prec={prec}: Sigma^c rel {es:.2e}, Sigma^x rel {ex:.2e}, gap err {eg:.3e} Ha "
+          f"(gap {hist[0]['gap']:.4f} Ha)")
+    assert es < GATE[prec] and ex < 1e-6
+
+
+# ---------------------------------------------------------------------------------------------
+# full-size shapes (64 k-points, 64 bands, NI = 400, 81 tau points), sampled against the oracle
+# ---------------------------------------------------------------------------------------------
+C2 = gi.C2
+
+
+@pytest.fixture(scope="module")
+def c2_setup(torch):
+    import paper_1602_02313_amd as amd
+    prob = gi.make_problem(C2)
+    run = amd.GWRun(C2.nk, prob.kmq, prob.nb, prob.ni, prob.tau, C2.beta, C2.niw_f, C2.niw_b,
+                    C2.scale, prob.eps, prob.v, prob.n_target, precision=amd.BF16X3, q_batch=1)
+    size = int(run.mpre[1] - run.mpre[0])
+    M = torch.empty(size, dtype=torch.complex64, device="cuda")
+    run.ctx.synth_M(C2.seed, 0, 1, 1, amd.C64, M)
+    run.green0(0.0)
+    torch.cuda.synchronize()
+    return prob, run, M
+
+
+@pytest.mark.parametrize("prec", [2, 1])
+def test_full_size_polarization_sampled(torch, c2_setup, prec):
+    import paper_1602_02313_amd as amd
+    prob, run, M = c2_setup
+    run.ctx.polarization(0, 1, M, amd.C64, run.G_tau, prec, run.P_tau)
+    torch.cuda.synchronize()
+    NI, ntau = 400, prob.tau.size
+    P = np_(run.P_tau[:ntau * NI * NI]).reshape(ntau, NI, NI)
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(NI, 12, replace=False))
+    cols = np.sort(np.concatenate([rows[:4], rng.choice(NI, 8, replace=False)]))
+    taus = [0, 17, 40, 80]
+    g = gi.MGenerator(C2)
+    sel = np.union1d(rows, cols)
+    blocks = [g.block(0, k, rows=sel) for k in range(C2.nk)]
+    G = oracle_G(prob)
+    ri, ci = np.searchsorted(sel, rows), np.searchsorted(sel, cols)
+    ref = o.polarization(blocks, G, prob.kmq[0], C2.scale, taus=taus, rows=ri, cols=ci)
+    got = P[np.ix_(taus, rows, cols)]
+    e = rel(got, ref)
+    print(f"full-size P prec={prec}: rel {e:.2e} on {got.size} sampled entries")
+    assert e < GATE[prec]
+
+
+@pytest.mark.parametrize("prec", [2, 1])
+def test_full_size_self_energy_sampled(torch, c2_setup, prec):
+    import paper_1602_02313_amd as amd
+    prob, run, M = c2_setup
+    NI, ntau = 400, prob.tau.size
+    rng = np.random.default_rng(1)
+    # a Hermitian W~(tau) with the magnitude profile of the screened interaction (decaying in I)
+    d = 1.0 / (1.0 + np.arange(NI) / 16.0)
+    W = (rng.normal(size=(ntau, NI, NI)) + 1j * rng.normal(size=(ntau, NI, NI))) * 0.01
+    W = W + np.conj(np.swapaxes(W, 1, 2)) + np.diag(d)[None] * 5.0
+    W = W * np.sqrt(d)[None, :, None] * np.sqrt(d)[None, None, :]
+    run.Wt_tau[:W.size].copy_(torch.from_numpy(W.ravel()))
+    run.sig_tau.zero_()
+    run.ctx.self_energy(0, 1, M, amd.C64, run.G_tau, run.Wt_tau, prec, run.sig_tau)
+    torch.cuda.synchronize()
+    S = np_(run.sig_tau)
+    g = gi.MGenerator(C2)
+    G = oracle_G(prob)
+    ks, taus = [0, 37], [0, 40, 80]
+    Mq = [g.block(0, k) if k in ks else None for k in range(C2.nk)]
+    ref = o.sigma_c(Mq, G, prob.kmq[0], W, C2.scale, taus=taus, ks=ks)
+    got = S[np.ix_(ks, np.arange(S.shape[1]), taus)]
+    e = rel(got, ref)
+    print(f"full-size Sigma prec={prec}: rel {e:.2e}")
+    assert e < (2e-6 if prec == 2 else GATE[prec])
