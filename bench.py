@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--fp64-ref-q", type=int, default=1,
                     help="q points on which the FP64 GPU path is timed for comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus "
@@ -119,6 +120,11 @@ def main():
     t_gen = time.perf_counter() - t0
     log(f"[bench] M resident: {M.numel() * M.element_size() / 1e9:.1f} GB generated in {t_gen:.2f} s")
     src = amd.ResidentM(M, run.mpre)
+    tuned = {}
+    if not args.no_autotune:
+        from paper_1602_02313_amd import autotune
+        for op, (v, name, times) in autotune.tune(run, src, reps=1, log=log).items():
+            tuned[["polarization", "self_energy"][op]] = {"variant": v, "tile": name, "ms": times}
 
     def step():
         run.green0(0.0)
@@ -222,6 +228,7 @@ def main():
         "fp64_gpu_reference": fp64_ref,
         "cpu_baseline": cpu,
         "m_generation_s": round(t_gen, 3),
+        "autotune": tuned,
         "check": {"flags": flags, "N": N, "n_target": prob.n_target, "gap_Ha": gap},
     }
     print(json.dumps(line), flush=True)

@@ -216,6 +216,20 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
 int msgw_gap(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
              const void* Sigma_c_iw, const double* mu, int n_index, double* gap);
 
+/* ---- tile shapes of the MFMA paths (used by the autotuner) ---------------------------------- */
+
+#define MSGW_OP_POLARIZATION 0
+#define MSGW_OP_SELF_ENERGY  1
+
+/* Number of compiled tile-shape variants for an op (MSGW_OP_*) in MSGW_FP32 or MSGW_BF16X3, or a
+ * negative error code.  Every variant computes the same result to rounding. */
+int msgw_variant_count(int op, int precision);
+/* Static description of a variant ("WI2 WJ2 T4": 16*WI x 16*WJ output tile per wave, T tau points
+ * per work-group), or NULL when out of range. */
+const char* msgw_variant_name(int op, int precision, int variant);
+/* Select the variant used by subsequent calls on c (default 0). */
+int msgw_set_variant(msgw_ctx* c, int op, int precision, int variant);
+
 /* ---- input generation (not part of the method) ---------------------------------------------- */
 
 /* Synthetic M for q0..q0+nq-1 in the layout above (c128 or c64): complex Gaussian with

@@ -30,8 +30,9 @@ EXPORTS = [
     "msgw_workspace_size", "msgw_set_workspace", "msgw_m_layout", "msgw_green0",
     "msgw_polarization", "msgw_tau_to_iw", "msgw_iw_to_tau", "msgw_screen",
     "msgw_screened_tau", "msgw_self_energy", "msgw_sigma_x", "msgw_dyson", "msgw_gap",
-    "msgw_synth_M",
+    "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant",
 ]
+OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 
 
 class MsgwError(RuntimeError):
@@ -88,6 +89,12 @@ def load_library():
         f.restype = ctypes.c_int
     lib.msgw_last_error.argtypes = [P]
     lib.msgw_last_error.restype = ctypes.c_char_p
+    lib.msgw_variant_count.argtypes = [I, I]
+    lib.msgw_variant_count.restype = ctypes.c_int
+    lib.msgw_variant_name.argtypes = [I, I, I]
+    lib.msgw_variant_name.restype = ctypes.c_char_p
+    lib.msgw_set_variant.argtypes = [P, I, I, I]
+    lib.msgw_set_variant.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -220,6 +227,16 @@ class Context:
     def gap(self, eps, sigma_static, Sigma_c_iw, mu, n_index, gap, stream=None):
         self._check(self.lib.msgw_gap(self._c, _stream(stream), _ptr(eps), _ptr(sigma_static),
                                       _ptr(Sigma_c_iw), _ptr(mu), int(n_index), _ptr(gap)))
+
+    def variants(self, op, precision):
+        """Names of the compiled tile-shape variants of an MFMA op."""
+        n = self.lib.msgw_variant_count(int(op), int(precision))
+        if n < 0:
+            raise MsgwError(n, "bad op or precision")
+        return [self.lib.msgw_variant_name(int(op), int(precision), v).decode() for v in range(n)]
+
+    def set_variant(self, op, precision, variant):
+        self._check(self.lib.msgw_set_variant(self._c, int(op), int(precision), int(variant)))
 
     def synth_M(self, seed, q0, nq, symmetric, m_dtype, M, stream=None):
         self._check(self.lib.msgw_synth_M(self._c, _stream(stream), int(seed), q0, nq,

@@ -22,7 +22,7 @@ struct msgw_ctx {
     size_t ws_bytes = 0;
     bool ws_ready = false;
     Dev d;
-    size_t scratch_off = 0;
+    int variant[2][3] = {{0, 0, 0}, {0, 0, 0}};  // [op][precision] tile shape of the MFMA paths
 };
 
 namespace {
@@ -383,7 +383,8 @@ int msgw_polarization(msgw_ctx* c, void* stream, int q0, int nq, const void* M, 
             launch_pol_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, P_tau);
         } else if (precision == MSGW_FP32 || precision == MSGW_BF16X3) {
             need(m_dtype == MSGW_C64, MSGW_EINVAL, "MSGW_FP32 / MSGW_BF16X3 need MSGW_C64 M");
-            int rc = launch_pol_mfma(c->d, c->h, S(stream), q0, nq, M, G_tau, precision, P_tau);
+            int rc = launch_pol_mfma(c->d, c->h, S(stream), q0, nq, M, G_tau, precision,
+                                     c->variant[MSGW_OP_POLARIZATION][precision], P_tau);
             need(rc == MSGW_OK, rc, "polarization: unsupported shape for the MFMA path");
         } else {
             throw Error(MSGW_EINVAL, "bad precision");
@@ -473,7 +474,7 @@ int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, i
         } else if (precision == MSGW_FP32 || precision == MSGW_BF16X3) {
             need(m_dtype == MSGW_C64, MSGW_EINVAL, "MSGW_FP32 / MSGW_BF16X3 need MSGW_C64 M");
             int rc = launch_sig_mfma(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, precision,
-                                     Sigma_tau);
+                                     c->variant[MSGW_OP_SELF_ENERGY][precision], Sigma_tau);
             need(rc == MSGW_OK, rc, "self_energy: workspace too small or unsupported shape for the MFMA path");
         } else {
             throw Error(MSGW_EINVAL, "bad precision");
@@ -504,6 +505,25 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
         need(std::isfinite(n_target) && n_target >= 0, MSGW_EINVAL, "bad n_target");
         launch_dyson(c->d, c->h, S(stream), eps, sigma_static, Sigma_c_iw, n_target,
                      mu_mode == MSGW_MU_SEARCH, mu, G_iw, G_tau, n_out, flags);
+    });
+}
+
+int msgw_variant_count(int op, int precision) {
+    if (op != MSGW_OP_POLARIZATION && op != MSGW_OP_SELF_ENERGY) return MSGW_EINVAL;
+    if (precision != MSGW_FP32 && precision != MSGW_BF16X3) return MSGW_EINVAL;
+    return mfma_variant_count(op, precision);
+}
+
+const char* msgw_variant_name(int op, int precision, int variant) {
+    return mfma_variant_name(op, precision, variant);
+}
+
+int msgw_set_variant(msgw_ctx* c, int op, int precision, int variant) {
+    return guarded(c, [&] {
+        int n = msgw_variant_count(op, precision);
+        need(n > 0, MSGW_EINVAL, "bad op or precision");
+        need(variant >= 0 && variant < n, MSGW_EINVAL, "variant out of range");
+        c->variant[op][precision] = variant;
     });
 }
 

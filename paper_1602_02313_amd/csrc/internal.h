@@ -83,9 +83,11 @@ void launch_sig_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
 void launch_sig_full_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
                           const void* M, const double* G, const void* W, void* Sig);
 int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-                    const double* G, int precision, void* P);
+                    const double* G, int precision, int variant, void* P);
 int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-                    const double* G, const void* W, int precision, void* Sig);
+                    const double* G, const void* W, int precision, int variant, void* Sig);
+int mfma_variant_count(int op, int precision);
+const char* mfma_variant_name(int op, int precision, int variant);
 size_t mfma_scratch_bytes(const Host& h, int nq_max);
 
 // Scratch layout: [E array of msgw_dyson: nk*nbmax doubles][MFMA conversion buffers].

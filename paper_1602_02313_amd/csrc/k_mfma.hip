@@ -15,12 +15,16 @@
 //   BF16X3: each FP32 operand x is split into hi = bf16(x) and lo = bf16(x - hi) (round to nearest
 //           even), and x.y ~ hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 with FP32
 //           accumulation; the dropped lo.lo term is ~2^-16 relative.
-// In both, the FP32 accumulators of the polarization are flushed into the FP64 output every
-// FLUSH_STEPS K-steps, so the FP32 sums never run over more than 4096 complex terms.
+// The FP32 accumulators of the polarization are flushed into the FP64 output every FLUSH_STEPS
+// K-steps, so an FP32 sum never runs over more than 4096 complex terms.
 //
-// One wave (64 lanes) per work-group; each wave owns a (16 WI) x (16 WJ) x T output tile and
-// streams its operands straight from global memory (the tiles of neighbouring waves overlap,
-// the reuse is served by L2).
+// One wave (64 lanes) per work-group.  Each wave owns a (16 WI) x (16 WJ) x T output tile and
+// streams its operands from global memory; reuse between waves is served by L2.  To make that
+// reuse happen, work-groups are ordered XCD-aware: the hardware deals consecutive work-group ids
+// round-robin to the 8 XCDs, so id b is mapped to work item (b % 8) * per + b / 8 -- each XCD
+// walks a contiguous slice of the work -- and the work space (rows x columns) is cut into
+// super-tiles of SR x SC items (about the number of waves resident on one XCD), so the waves
+// running together on an XCD share SR row panels and SC column panels in its L2.
 #include "internal.h"
 
 namespace msgw {
@@ -35,8 +39,10 @@ constexpr int PREC_FP32 = MSGW_FP32;
 constexpr int PREC_BF16X3 = MSGW_BF16X3;
 constexpr int NB_LDS = 256;       // band limit of the MFMA path (G slices staged in LDS)
 constexpr int FLUSH_STEPS = 256;  // K-steps of 16 complex between FP64 flushes
+constexpr int PAD = 64;           // W~ planes are zero-padded to a multiple of PAD
 
 inline unsigned ceil_div(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
 // ---- bf16 helpers -------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
@@ -76,25 +82,63 @@ struct Lay {
     __device__ static int koff(int g4, int e) { return PREC == PREC_BF16X3 ? 4 * g4 + e : 2 * e + (g4 >> 1); }
 };
 
+// ---- XCD-aware ordering ---------------------------------------------------------------------------
+struct Order {
+    int R, C;      // work rows and columns per q
+    int SR, SC;    // super-tile
+    int nSC;       // super-tiles per row of super-tiles
+    int per_q;     // padded items per q
+    int total;     // nq * per_q
+};
+
+Order make_order(int R, int C, int nq) {
+    Order o;
+    o.R = R;
+    o.C = C;
+    o.SC = C <= 32 ? C : 16;
+    o.SR = std::max(1, 128 / o.SC);
+    o.nSC = (C + o.SC - 1) / o.SC;
+    const int nSR = (R + o.SR - 1) / o.SR;
+    o.per_q = nSR * o.nSC * o.SR * o.SC;
+    o.total = nq * o.per_q;
+    return o;
+}
+
+unsigned grid_of(const Order& o) { return unsigned(round_up(o.total, 8)); }
+
+// returns false for padding items
+__device__ __forceinline__ bool work_item(const Order& o, int& qrel, int& r, int& c) {
+    const int per = gridDim.x >> 3;
+    int w = int(blockIdx.x & 7) * per + int(blockIdx.x >> 3);
+    if (w >= o.total) return false;
+    qrel = w / o.per_q;
+    w -= qrel * o.per_q;
+    const int sts = o.SR * o.SC;
+    const int st = w / sts, in = w - st * sts;
+    const int sr = st / o.nSC, sc = st - sr * o.nSC;
+    r = sr * o.SR + in / o.SC;
+    c = sc * o.SC + in % o.SC;
+    return r < o.R && c < o.C;
+}
+
 // =================================================================================================
 // polarization
 // =================================================================================================
 template <int WI, int WJ, int T, int PREC>
 __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restrict__ M,
                                             const double* __restrict__ G,
-                                            double2* __restrict__ P, int ntJ, int ntG) {
+                                            double2* __restrict__ P, Order od, int ntI) {
     using LY = Lay<PREC>;
     constexpr int NE = LY::NE;
     __shared__ float Ga[NB_LDS * T];
     __shared__ float Gb[NB_LDS * T];
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
     const int lane = threadIdx.x, r16 = lane & 15, g4 = lane >> 4;
-    const int q = q0 + blockIdx.y;
+    const int q = q0 + qrel;
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int NI = d.ni[q];
-    int bx = blockIdx.x;
-    const int tg = bx % ntG;
-    bx /= ntG;
-    const int tj = bx % ntJ, ti = bx / ntJ;
+    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
     const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
     if (i0 >= NI || j0 >= NI) return;
 
@@ -142,11 +186,30 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
         since = 0;
     };
 
+    // rows used by this lane (clamped into range; out-of-range rows are zeroed by `keep`)
+    int rowI[WI], rowJ[WJ];
+    float keepI[WI], keepJ[WJ];
+#pragma unroll
+    for (int a = 0; a < WI; ++a) {
+        const int I = i0 + 16 * a + r16;
+        rowI[a] = min(I, NI - 1);
+        keepI[a] = I < NI ? 1.f : 0.f;
+    }
+#pragma unroll
+    for (int b = 0; b < WJ; ++b) {
+        const int J = j0 + 16 * b + r16;
+        rowJ[b] = min(J, NI - 1);
+        keepJ[b] = J < NI ? 1.f : 0.f;
+    }
+
     for (int k = 0; k < nk; ++k) {
         const int kq = d.kmq[q * nk + k];
         const int nn = d.nb[k], nm = d.nb[kq];
         const int Kk = nn * nm;
         const float2* A = Mq + d.moff[q * nk + k];
+        // 16-byte vector loads of 4 consecutive complex values when every row start is aligned
+        const bool vec = PREC == PREC_BF16X3 && (Kk & 3) == 0 &&
+                         (reinterpret_cast<uintptr_t>(A) & 31) == 0;
         __syncthreads();
         for (int e = lane; e < nn * T; e += 64) {
             const int n = e / T, t = e - n * T;
@@ -179,21 +242,40 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
                 gj[e] = mm * T;
             }
             float2 xa[WI][NE], yb[WJ][NE];
+            if (vec && kb + 16 <= Kk) {
 #pragma unroll
-            for (int a = 0; a < WI; ++a) {
-                const int I = i0 + 16 * a + r16;
+                for (int a = 0; a < WI; ++a) {
+                    const float4* p = reinterpret_cast<const float4*>(A + int64_t(rowI[a]) * Kk + kb + 4 * g4);
+                    const float4 u = p[0], v = p[1];
+                    xa[a][0] = make_float2(keepI[a] * u.x, keepI[a] * u.y);
+                    xa[a][1] = make_float2(keepI[a] * u.z, keepI[a] * u.w);
+                    xa[a][2] = make_float2(keepI[a] * v.x, keepI[a] * v.y);
+                    xa[a][3] = make_float2(keepI[a] * v.z, keepI[a] * v.w);
+                }
 #pragma unroll
-                for (int e = 0; e < NE; ++e)
-                    xa[a][e] = (ve[e] && I < NI) ? A[int64_t(I) * Kk + kb + LY::koff(g4, e)]
-                                                 : make_float2(0.f, 0.f);
-            }
+                for (int b = 0; b < WJ; ++b) {
+                    const float4* p = reinterpret_cast<const float4*>(A + int64_t(rowJ[b]) * Kk + kb + 4 * g4);
+                    const float4 u = p[0], v = p[1];
+                    yb[b][0] = make_float2(keepJ[b] * u.x, keepJ[b] * u.y);
+                    yb[b][1] = make_float2(keepJ[b] * u.z, keepJ[b] * u.w);
+                    yb[b][2] = make_float2(keepJ[b] * v.x, keepJ[b] * v.y);
+                    yb[b][3] = make_float2(keepJ[b] * v.z, keepJ[b] * v.w);
+                }
+            } else {
 #pragma unroll
-            for (int b = 0; b < WJ; ++b) {
-                const int J = j0 + 16 * b + r16;
+                for (int a = 0; a < WI; ++a)
 #pragma unroll
-                for (int e = 0; e < NE; ++e)
-                    yb[b][e] = (ve[e] && J < NI) ? A[int64_t(J) * Kk + kb + LY::koff(g4, e)]
-                                                 : make_float2(0.f, 0.f);
+                    for (int e = 0; e < NE; ++e)
+                        xa[a][e] = (ve[e] && keepI[a] != 0.f)
+                                       ? A[int64_t(rowI[a]) * Kk + kb + LY::koff(g4, e)]
+                                       : make_float2(0.f, 0.f);
+#pragma unroll
+                for (int b = 0; b < WJ; ++b)
+#pragma unroll
+                    for (int e = 0; e < NE; ++e)
+                        yb[b][e] = (ve[e] && keepJ[b] != 0.f)
+                                       ? A[int64_t(rowJ[b]) * Kk + kb + LY::koff(g4, e)]
+                                       : make_float2(0.f, 0.f);
             }
             if constexpr (PREC == PREC_BF16X3) {
                 u32x4 xh[WI], xl[WI], xh2[WI], xl2[WI];
@@ -275,14 +357,20 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
 // =================================================================================================
 // self-energy
 // =================================================================================================
-// W~(q,tau) converted once per call: FP32 -> c64 plane; BF16X3 -> hi and lo planes of packed
-// (re, im) bf16 pairs.  Layout per q: [ntau][NI][NI], q blocks packed over the call's q range.
-__global__ void k_convert_w(const double2* __restrict__ W, int64_t n, int prec,
+// W~(q,tau) converted once per call into zero-padded planes [ntau][NIp][NIp], NIp = NI rounded up
+// to PAD: FP32 -> one complex64 plane; BF16X3 -> hi and lo planes of packed (re, im) bf16 pairs.
+// q blocks are packed over the call's q range (wq[q] = offset in elements of each plane).
+__global__ void k_convert_w(const double2* __restrict__ W, int NI, int NIp, int ntau, int prec,
                             float2* __restrict__ w32, uint32_t* __restrict__ whi,
                             uint32_t* __restrict__ wlo) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = int64_t(ntau) * NIp * NIp;
     if (i >= n) return;
-    const double2 v = W[i];
+    const int J = int(i % NIp);
+    const int I = int((i / NIp) % NIp);
+    const int it = int(i / (int64_t(NIp) * NIp));
+    double2 v = make_double2(0.0, 0.0);
+    if (I < NI && J < NI) v = W[(int64_t(it) * NI + I) * NI + J];
     const float re = float(v.x), im = float(v.y);
     if (prec == PREC_FP32) {
         w32[i] = make_float2(re, im);
@@ -297,28 +385,33 @@ __global__ void k_convert_w(const double2* __restrict__ W, int64_t n, int prec,
 template <int WI, int WJ, int T, int PREC>
 __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restrict__ M,
                                             const double* __restrict__ G,
-                                            const float2* __restrict__ w32,
-                                            const uint32_t* __restrict__ whi,
-                                            const uint32_t* __restrict__ wlo,
-                                            double* __restrict__ Sig, int ntC, int ntG) {
+                                            const char* __restrict__ wsc, int64_t plane,
+                                            double* __restrict__ Sig, Order od, int ntI, int ntC) {
     using LY = Lay<PREC>;
     constexpr int NE = LY::NE;
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
     const int lane = threadIdx.x, r16 = lane & 15, g4 = lane >> 4;
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
-    const int q = q0 + blockIdx.y / nk, k = blockIdx.y % nk;
+    const int q = q0 + qrel;
+    const int tg = r / ntI, ti = r - tg * ntI;
+    const int k = c / ntC, tc = c - k * ntC;
     const int kq = d.kmq[q * nk + k];
-    const int nn = d.nb[k], nm = d.nb[kq], NI = d.ni[q];
-    const int Kk = nn * nm;
-    int bx = blockIdx.x;
-    const int tg = bx % ntG;
-    bx /= ntG;
-    const int tc = bx % ntC, ti = bx / ntC;
+    const int nm = d.nb[kq], NI = d.ni[q];
+    const int Kk = d.nb[k] * nm;
     const int i0 = ti * 16 * WI, c0 = tc * 16 * WJ, t0 = tg * T;
     if (i0 >= NI || c0 >= Kk) return;
-    (void)nn;
+    const int NIp = (NI + PAD - 1) / PAD * PAD;
+    int64_t wq = 0;  // offset of q's planes
+    for (int qq = q0; qq < q; ++qq) {
+        const int np = (d.ni[qq] + PAD - 1) / PAD * PAD;
+        wq += int64_t(ntau) * np * np;
+    }
+    const float2* w32 = reinterpret_cast<const float2*>(wsc) + wq;
+    const uint32_t* whi = reinterpret_cast<const uint32_t*>(wsc) + wq;
+    const uint32_t* wlo = reinterpret_cast<const uint32_t*>(wsc) + plane + wq;
 
     const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
-    const int64_t wbase = d.ppre[q] - d.ppre[q0];
 
     floatx4 acc[WI][WJ][T][2];
 #pragma unroll
@@ -327,6 +420,10 @@ __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restr
         for (int b = 0; b < WJ; ++b)
 #pragma unroll
             for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+
+    int tau_[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) tau_[t] = min(t0 + t, ntau - 1);
 
     const int nsteps = (NI + 15) / 16;
     for (int s = 0; s < nsteps; ++s) {
@@ -356,19 +453,11 @@ __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restr
                 }
 #pragma unroll
             for (int t = 0; t < T; ++t) {
-                const int it = min(t0 + t, ntau - 1);
 #pragma unroll
                 for (int a = 0; a < WI; ++a) {
-                    const int I = i0 + 16 * a + r16;
-                    u32x4 ah, al;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int J = jb + 4 * g4 + e;
-                        const bool ok = I < NI && J < NI;
-                        const int64_t at = wbase + int64_t(it) * NI * NI + int64_t(I) * NI + J;
-                        ah[e] = ok ? whi[at] : 0u;
-                        al[e] = ok ? wlo[at] : 0u;
-                    }
+                    const int64_t at = (int64_t(tau_[t]) * NIp + i0 + 16 * a + r16) * NIp + jb + 4 * g4;
+                    const u32x4 ah = *reinterpret_cast<const u32x4*>(whi + at);
+                    const u32x4 al = *reinterpret_cast<const u32x4*>(wlo + at);
 #pragma unroll
                     for (int b = 0; b < WJ; ++b) {
                         acc[a][b][t][0] = mfma_bf16(ah, bh_re[b], acc[a][b][t][0]);
@@ -390,16 +479,12 @@ __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restr
             const bool imc = g4 & 1;
 #pragma unroll
             for (int t = 0; t < T; ++t) {
-                const int it = min(t0 + t, ntau - 1);
 #pragma unroll
                 for (int a = 0; a < WI; ++a) {
-                    const int I = i0 + 16 * a + r16;
+                    const int64_t row = (int64_t(tau_[t]) * NIp + i0 + 16 * a + r16) * NIp + jb;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
-                        const int J = jb + LY::koff(g4, e);
-                        const bool ok = I < NI && J < NI;
-                        const float2 w = ok ? w32[wbase + int64_t(it) * NI * NI + int64_t(I) * NI + J]
-                                            : make_float2(0.f, 0.f);
+                        const float2 w = w32[row + LY::koff(g4, e)];
                         const float x = imc ? w.y : w.x;
 #pragma unroll
                         for (int b = 0; b < WJ; ++b) {
@@ -441,7 +526,7 @@ __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restr
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
             if (col < Kk) {
-                const int n = col / nm, m = col - (col / nm) * nm;
+                const int m = col - (col / nm) * nm;
                 v *= G[(int64_t(kq) * nbmax + m) * ntau + it];
             }
             part[b] = v;
@@ -464,11 +549,11 @@ __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restr
 }
 
 // =================================================================================================
-// dispatch (tile shapes per precision; see the autotuner in the host driver)
+// variants (tile shapes) and dispatch
 // =================================================================================================
-struct PolCfg {
-    int WI, WJ, T;
-};
+using PolFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*, void*);
+using SigFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
+                       const char*, int64_t, void*);
 
 template <int WI, int WJ, int T, int PREC>
 void run_pol(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
@@ -476,69 +561,128 @@ void run_pol(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const v
     int maxi = 0;
     for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
     const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
-    hipLaunchKernelGGL((k_pol<WI, WJ, T, PREC>), dim3(ntI * ntJ * ntG, nq), dim3(64), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, ntJ, ntG);
+    const Order od = make_order(ntG * ntI, ntJ, nq);
+    hipLaunchKernelGGL((k_pol<WI, WJ, T, PREC>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
+                       (const float2*)M, G, (double2*)P, od, ntI);
     MSGW_HIP(hipGetLastError());
 }
 
 template <int WI, int WJ, int T, int PREC>
 void run_sig(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-             const double* G, const float2* w32, const uint32_t* whi, const uint32_t* wlo, void* Sig) {
+             const double* G, const char* wsc, int64_t plane, void* Sig) {
     int maxi = 0, maxc = 0;
     for (int q = q0; q < q0 + nq; ++q) {
         maxi = std::max(maxi, h.ni[q]);
         for (int k = 0; k < h.nk; ++k)
             maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
     }
+    static_assert(16 * WI <= PAD, "row tiles must fit in the padded W~ planes");
     const int ntI = ceil_div(maxi, 16 * WI), ntC = ceil_div(maxc, 16 * WJ), ntG = ceil_div(h.ntau, T);
-    hipLaunchKernelGGL((k_sig<WI, WJ, T, PREC>), dim3(ntI * ntC * ntG, nq * h.nk), dim3(64), 0, s,
-                       d, q0, (const float2*)M, G, w32, whi, wlo, (double*)Sig, ntC, ntG);
+    const Order od = make_order(ntG * ntI, h.nk * ntC, nq);
+    hipLaunchKernelGGL((k_sig<WI, WJ, T, PREC>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
+                       (const float2*)M, G, wsc, plane, (double*)Sig, od, ntI, ntC);
     MSGW_HIP(hipGetLastError());
+}
+
+struct PolVariant {
+    const char* name;
+    PolFn fn;
+};
+struct SigVariant {
+    const char* name;
+    SigFn fn;
+};
+
+const PolVariant kPolBF16[] = {
+    {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_BF16X3>},
+    {"WI4 WJ1 T4", run_pol<4, 1, 4, PREC_BF16X3>},
+    {"WI4 WJ2 T2", run_pol<4, 2, 2, PREC_BF16X3>},
+    {"WI2 WJ4 T2", run_pol<2, 4, 2, PREC_BF16X3>},
+    {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3>},
+};
+const PolVariant kPolFP32[] = {
+    {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
+    {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_FP32>},
+};
+const SigVariant kSigBF16[] = {
+    {"WI2 WJ4 T4", run_sig<2, 4, 4, PREC_BF16X3>},
+    {"WI4 WJ2 T4", run_sig<4, 2, 4, PREC_BF16X3>},
+    {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_BF16X3>},
+    {"WI4 WJ4 T2", run_sig<4, 4, 2, PREC_BF16X3>},
+    {"WI2 WJ8 T2", run_sig<2, 8, 2, PREC_BF16X3>},
+};
+const SigVariant kSigFP32[] = {
+    {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>},
+    {"WI2 WJ4 T2", run_sig<2, 4, 2, PREC_FP32>},
+};
+
+template <class V, size_t N>
+constexpr int count_of(const V (&)[N]) {
+    return int(N);
+}
+
+int64_t plane_elems(const Host& h, int q0, int nq) {
+    int64_t n = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        const int np = round_up(h.ni[q], PAD);
+        n += int64_t(h.ntau) * np * np;
+    }
+    return n;
 }
 
 }  // namespace
 
+int mfma_variant_count(int op, int precision) {
+    if (op == MSGW_OP_POLARIZATION)
+        return precision == MSGW_BF16X3 ? count_of(kPolBF16) : precision == MSGW_FP32 ? count_of(kPolFP32) : 0;
+    if (op == MSGW_OP_SELF_ENERGY)
+        return precision == MSGW_BF16X3 ? count_of(kSigBF16) : precision == MSGW_FP32 ? count_of(kSigFP32) : 0;
+    return 0;
+}
+
+const char* mfma_variant_name(int op, int precision, int v) {
+    if (v < 0 || v >= mfma_variant_count(op, precision)) return nullptr;
+    if (op == MSGW_OP_POLARIZATION) return precision == MSGW_BF16X3 ? kPolBF16[v].name : kPolFP32[v].name;
+    return precision == MSGW_BF16X3 ? kSigBF16[v].name : kSigFP32[v].name;
+}
+
 size_t mfma_scratch_bytes(const Host& h, int nq_max) {
-    // converted W~ for the q range of one self_energy call: 8 bytes per complex element
-    // (c64 for FP32, hi + lo bf16 pairs for BF16X3)
-    std::vector<int64_t> sz(h.nk);
-    for (int q = 0; q < h.nk; ++q) sz[q] = int64_t(h.ntau) * h.ni[q] * h.ni[q];
+    // padded W~ planes for the q range of one self_energy call: 8 bytes per complex element
+    // (complex64 for FP32, hi + lo bf16 pairs for BF16X3)
     int64_t best = 0;
-    for (int q = 0; q + nq_max <= h.nk; ++q) {
-        int64_t t = 0;
-        for (int j = q; j < q + nq_max; ++j) t += sz[j];
-        best = std::max(best, t);
-    }
+    for (int q = 0; q + nq_max <= h.nk; ++q) best = std::max(best, plane_elems(h, q, nq_max));
     return size_t(best) * 8;
 }
 
 int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-                    const double* G, int precision, void* P) {
+                    const double* G, int precision, int variant, void* P) {
     if (h.nbmax > NB_LDS) return MSGW_ENOTSUP;
-    if (int64_t(nq) > 65535) return MSGW_ENOTSUP;
-    if (precision == MSGW_BF16X3)
-        run_pol<2, 2, 4, PREC_BF16X3>(d, h, s, q0, nq, M, G, P);
-    else
-        run_pol<2, 2, 4, PREC_FP32>(d, h, s, q0, nq, M, G, P);
+    const int n = mfma_variant_count(MSGW_OP_POLARIZATION, precision);
+    if (variant < 0 || variant >= n) return MSGW_EINVAL;
+    (precision == MSGW_BF16X3 ? kPolBF16 : kPolFP32)[variant].fn(d, h, s, q0, nq, M, G, P);
     return MSGW_OK;
 }
 
 int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-                    const double* G, const void* W, int precision, void* Sig) {
-    if (int64_t(nq) * h.nk > 65535) return MSGW_ENOTSUP;
-    const int64_t n = h.ppre[q0 + nq] - h.ppre[q0];
-    if (size_t(n) * 8 > scratch_mfma_bytes(d, h)) return MSGW_ENOMEM;
+                    const double* G, const void* W, int precision, int variant, void* Sig) {
+    const int nv = mfma_variant_count(MSGW_OP_SELF_ENERGY, precision);
+    if (variant < 0 || variant >= nv) return MSGW_EINVAL;
+    const int64_t plane = plane_elems(h, q0, nq);
+    if (size_t(plane) * 8 > scratch_mfma_bytes(d, h)) return MSGW_ENOMEM;
     char* sc = scratch_mfma(d, h);
-    float2* w32 = reinterpret_cast<float2*>(sc);
-    uint32_t* whi = reinterpret_cast<uint32_t*>(sc);
-    uint32_t* wlo = whi + n;
-    hipLaunchKernelGGL(k_convert_w, dim3(ceil_div(n, 256)), dim3(256), 0, s, (const double2*)W, n,
-                       precision, w32, whi, wlo);
-    MSGW_HIP(hipGetLastError());
-    if (precision == MSGW_BF16X3)
-        run_sig<2, 4, 4, PREC_BF16X3>(d, h, s, q0, nq, M, G, w32, whi, wlo, Sig);
-    else
-        run_sig<2, 2, 4, PREC_FP32>(d, h, s, q0, nq, M, G, w32, whi, wlo, Sig);
+    int64_t off = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        const int NI = h.ni[q], NIp = round_up(NI, PAD);
+        const int64_t n = int64_t(h.ntau) * NIp * NIp;
+        const double2* Wq = (const double2*)W + (h.ppre[q] - h.ppre[q0]);
+        hipLaunchKernelGGL(k_convert_w, dim3(ceil_div(n, 256)), dim3(256), 0, s, Wq, NI, NIp, h.ntau,
+                           precision, reinterpret_cast<float2*>(sc) + off,
+                           reinterpret_cast<uint32_t*>(sc) + off,
+                           reinterpret_cast<uint32_t*>(sc) + plane + off);
+        MSGW_HIP(hipGetLastError());
+        off += n;
+    }
+    (precision == MSGW_BF16X3 ? kSigBF16 : kSigFP32)[variant].fn(d, h, s, q0, nq, M, G, sc, plane, Sig);
     return MSGW_OK;
 }
 

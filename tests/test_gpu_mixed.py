@@ -27,20 +27,34 @@ def torch():
     return torch
 
 
+def _variants(prec, op):
+    """Indices of the compiled tile variants (just [0] when the library is not built)."""
+    try:
+        import paper_1602_02313_amd as amd
+        return list(range(amd.load_library().msgw_variant_count(op, prec)))
+    except ImportError:
+        return [0]
+
+
 def _m64(cfg, run, g):
     import torch
     flat = np.concatenate([g.q_packed(q) for q in range(cfg.nk)]).astype(np.complex64)
     return torch.from_numpy(flat).to(run.device)
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+def _small_cases(op):
+    return [(p, v) for p in (1, 2) for v in _variants(p, op)]
+
+
+@pytest.mark.parametrize("prec,variant", _small_cases(0))
 @pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
-def test_polarization_mixed(torch, cfg, prec):
+def test_polarization_mixed(torch, cfg, prec, variant):
     import paper_1602_02313_amd as amd
     prob, run = make_run(cfg, precision=prec, q_batch=cfg.nk)
     g = gi.MGenerator(cfg)
     M = _m64(cfg, run, g)
     run.green0(0.0)
+    run.ctx.set_variant(0, prec, variant)
     run.ctx.polarization(0, cfg.nk, M, amd.C64, run.G_tau, prec, run.P_tau)
     torch.cuda.synchronize()
     G = oracle_G(prob)
@@ -50,19 +64,20 @@ def test_polarization_mixed(torch, cfg, prec):
         ref = o.polarization(g.q_blocks(q), G, prob.kmq[q], cfg.scale)
         got = P[run.ppre[q]:run.ppre[q + 1]].reshape(ref.shape)
         worst = max(worst, rel(got, ref))
-    print(f"P {cfg.name} prec={prec}: rel {worst:.2e}")
+    print(f"P {cfg.name} prec={prec} variant={variant}: rel {worst:.2e}")
     assert worst < GATE[prec]
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec,variant", _small_cases(1))
 @pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
-def test_self_energy_mixed(torch, cfg, prec):
+def test_self_energy_mixed(torch, cfg, prec, variant):
     import paper_1602_02313_amd as amd
     prob, run = make_run(cfg, precision=prec, q_batch=1)
     g = gi.MGenerator(cfg)
     G = oracle_G(prob)
     run.green0(0.0)
     run.sig_tau.zero_()
+    run.ctx.set_variant(1, prec, variant)
     ref = 0
     off = np.concatenate([[0], np.cumsum([g.q_packed(q).size for q in range(cfg.nk)])])
     M = _m64(cfg, run, g)
@@ -73,7 +88,7 @@ def test_self_energy_mixed(torch, cfg, prec):
         ref = ref + o.sigma_c(g.q_blocks(q), G, prob.kmq[q], Wt, cfg.scale)
     torch.cuda.synchronize()
     e = rel(np_(run.sig_tau), ref)
-    print(f"Sigma {cfg.name} prec={prec}: rel {e:.2e}")
+    print(f"Sigma {cfg.name} prec={prec} variant={variant}: rel {e:.2e}")
     assert e < GATE[prec]
 
 
@@ -116,11 +131,17 @@ def c2_setup(torch):
     return prob, run, M
 
 
-@pytest.mark.parametrize("prec", [2, 1])
-def test_full_size_polarization_sampled(torch, c2_setup, prec):
+FULL_P = [(2, v) for v in _variants(2, 0)] + [(1, v) for v in _variants(1, 0)]
+FULL_S = [(2, v) for v in _variants(2, 1)] + [(1, v) for v in _variants(1, 1)]
+
+
+@pytest.mark.parametrize("prec,variant", FULL_P)
+def test_full_size_polarization_sampled(torch, c2_setup, prec, variant):
     import paper_1602_02313_amd as amd
     prob, run, M = c2_setup
+    run.ctx.set_variant(0, prec, variant)
     run.ctx.polarization(0, 1, M, amd.C64, run.G_tau, prec, run.P_tau)
+    run.ctx.set_variant(0, prec, 0)
     torch.cuda.synchronize()
     NI, ntau = 400, prob.tau.size
     P = np_(run.P_tau[:ntau * NI * NI]).reshape(ntau, NI, NI)
@@ -136,12 +157,12 @@ def test_full_size_polarization_sampled(torch, c2_setup, prec):
     ref = o.polarization(blocks, G, prob.kmq[0], C2.scale, taus=taus, rows=ri, cols=ci)
     got = P[np.ix_(taus, rows, cols)]
     e = rel(got, ref)
-    print(f"full-size P prec={prec}: rel {e:.2e} on {got.size} sampled entries")
+    print(f"full-size P prec={prec} variant={variant}: rel {e:.2e} on {got.size} sampled entries")
     assert e < GATE[prec]
 
 
-@pytest.mark.parametrize("prec", [2, 1])
-def test_full_size_self_energy_sampled(torch, c2_setup, prec):
+@pytest.mark.parametrize("prec,variant", FULL_S)
+def test_full_size_self_energy_sampled(torch, c2_setup, prec, variant):
     import paper_1602_02313_amd as amd
     prob, run, M = c2_setup
     NI, ntau = 400, prob.tau.size
@@ -153,7 +174,9 @@ def test_full_size_self_energy_sampled(torch, c2_setup, prec):
     W = W * np.sqrt(d)[None, :, None] * np.sqrt(d)[None, None, :]
     run.Wt_tau[:W.size].copy_(torch.from_numpy(W.ravel()))
     run.sig_tau.zero_()
+    run.ctx.set_variant(1, prec, variant)
     run.ctx.self_energy(0, 1, M, amd.C64, run.G_tau, run.Wt_tau, prec, run.sig_tau)
+    run.ctx.set_variant(1, prec, 0)
     torch.cuda.synchronize()
     S = np_(run.sig_tau)
     g = gi.MGenerator(C2)
@@ -163,5 +186,5 @@ def test_full_size_self_energy_sampled(torch, c2_setup, prec):
     ref = o.sigma_c(Mq, G, prob.kmq[0], W, C2.scale, taus=taus, ks=ks)
     got = S[np.ix_(ks, np.arange(S.shape[1]), taus)]
     e = rel(got, ref)
-    print(f"full-size Sigma prec={prec}: rel {e:.2e}")
+    print(f"full-size Sigma prec={prec} variant={variant}: rel {e:.2e}")
     assert e < (2e-6 if prec == 2 else GATE[prec])
