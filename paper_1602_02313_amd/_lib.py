@@ -62,6 +62,9 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_1602_02313_amd.build` (or __graft_entry__.build())")
+    # torch bundles its own HIP runtime under the same soname (libamdhip64.so.7); load it first so
+    # the library and torch's allocator and streams share one runtime in the process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I, L, D, U64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64
     sig = {

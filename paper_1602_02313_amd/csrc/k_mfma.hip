@@ -91,12 +91,13 @@ struct Order {
     int total;     // nq * per_q
 };
 
-Order make_order(int R, int C, int nq) {
+// window: work items resident at once on one XCD (waves or work-groups)
+Order make_order(int R, int C, int nq, int window = 128) {
     Order o;
     o.R = R;
     o.C = C;
-    o.SC = C <= 32 ? C : 16;
-    o.SR = std::max(1, 128 / o.SC);
+    o.SC = C <= 32 ? std::min(C, window) : std::min(16, window);
+    o.SR = std::max(1, window / o.SC);
     o.nSC = (C + o.SC - 1) / o.SC;
     const int nSR = (R + o.SR - 1) / o.SR;
     o.per_q = nSR * o.nSC * o.SR * o.SC;
@@ -549,6 +550,394 @@ __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restr
 }
 
 // =================================================================================================
+// self-energy, v3: M split and transposed once per call
+// =================================================================================================
+// Mt planes: for each (q, k) of the call, hi and lo bf16 pairs of M^J_col laid out [col][J] with J
+// zero-padded to NIp16 = NI rounded up to 16, so a lane's 4 consecutive J are one 16-byte load.
+// The (q, k) block starts at mt_base(q) + moff[q][k] / NI_q * NIp16.
+__device__ __forceinline__ int64_t mt_qbase(const Dev& d, int q0, int q) {
+    int64_t b = 0;
+    for (int qq = q0; qq < q; ++qq) {
+        const int ni = d.ni[qq];
+        b += (d.mpre[qq + 1] - d.mpre[qq]) / ni * ((ni + 15) / 16 * 16);
+    }
+    return b;
+}
+
+__global__ __launch_bounds__(256) void k_split_mt(Dev d, int q0, int q, const float2* __restrict__ M,
+                                                  uint32_t* __restrict__ mt, int64_t mtplane) {
+    __shared__ float2 tile[32][33];
+    const int nk = d.nk, k = blockIdx.y;
+    const int NI = d.ni[q], NIp16 = (NI + 15) / 16 * 16;
+    const int Kk = d.nb[k] * d.nb[d.kmq[q * nk + k]];
+    const int ntj = (NIp16 + 31) / 32;
+    const int j0 = (blockIdx.x % ntj) * 32, c0 = (blockIdx.x / ntj) * 32;
+    if (c0 >= Kk) return;
+    const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
+    const int64_t ob = mt_qbase(d, q0, q) + d.moff[q * nk + k] / NI * NIp16;
+    uint32_t* mh = mt + ob;
+    uint32_t* ml = mt + mtplane + ob;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int J = j0 + r, col = c0 + tx;
+        tile[r][tx] = (J < NI && col < Kk) ? A[int64_t(J) * Kk + col] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int col = c0 + r, J = j0 + tx;
+        if (col < Kk && J < NIp16) {
+            const float2 v = tile[tx][r];
+            uint32_t h, l;
+            split2(v.x, v.y, h, l);
+            mh[int64_t(col) * NIp16 + J] = h;
+            ml[int64_t(col) * NIp16 + J] = l;
+        }
+    }
+}
+
+template <int WI, int WJ, int T>
+__global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __restrict__ M,
+                                             const double* __restrict__ G,
+                                             const char* __restrict__ wsc, int64_t plane,
+                                             const uint32_t* __restrict__ mt, int64_t mtplane,
+                                             double* __restrict__ Sig, Order od, int ntI, int ntC) {
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
+    const int lane = threadIdx.x, r16 = lane & 15, g4 = lane >> 4;
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int q = q0 + qrel;
+    const int tg = r / ntI, ti = r - tg * ntI;
+    const int k = c / ntC, tc = c - k * ntC;
+    const int kq = d.kmq[q * nk + k];
+    const int nm = d.nb[kq], NI = d.ni[q];
+    const int Kk = d.nb[k] * nm;
+    const int i0 = ti * 16 * WI, c0 = tc * 16 * WJ, t0 = tg * T;
+    if (i0 >= NI || c0 >= Kk) return;
+    const int NIp = (NI + PAD - 1) / PAD * PAD, NIp16 = (NI + 15) / 16 * 16;
+    int64_t wq = 0;
+    for (int qq = q0; qq < q; ++qq) {
+        const int np = (d.ni[qq] + PAD - 1) / PAD * PAD;
+        wq += int64_t(ntau) * np * np;
+    }
+    const uint32_t* whi = reinterpret_cast<const uint32_t*>(wsc) + wq;
+    const uint32_t* wlo = reinterpret_cast<const uint32_t*>(wsc) + plane + wq;
+    const int64_t mb0 = mt_qbase(d, q0, q) + d.moff[q * nk + k] / NI * NIp16;
+    const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
+
+    int colr[WJ];
+    uint32_t keep[WJ];
+#pragma unroll
+    for (int b = 0; b < WJ; ++b) {
+        const int col = c0 + 16 * b + r16;
+        colr[b] = min(col, Kk - 1);
+        keep[b] = col < Kk ? 0xffffffffu : 0u;
+    }
+    floatx4 acc[WI][WJ][T][2];
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+    int tau_[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) tau_[t] = min(t0 + t, ntau - 1);
+
+    const int nsteps = NIp16 / 16;
+    for (int s = 0; s < nsteps; ++s) {
+        const int jb = s * 16;
+        u32x4 bh_re[WJ], bl_re[WJ], bh_im[WJ], bl_im[WJ];
+#pragma unroll
+        for (int b = 0; b < WJ; ++b) {
+            const int64_t at = mb0 + int64_t(colr[b]) * NIp16 + jb + 4 * g4;
+            const u32x4 h = *reinterpret_cast<const u32x4*>(mt + at);
+            const u32x4 l = *reinterpret_cast<const u32x4*>(mt + mtplane + at);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t he = h[e] & keep[b], le = l[e] & keep[b];
+                bh_re[b][e] = conj_pk(he);
+                bl_re[b][e] = conj_pk(le);
+                bh_im[b][e] = swap_pk(he);
+                bl_im[b][e] = swap_pk(le);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+#pragma unroll
+            for (int a = 0; a < WI; ++a) {
+                const int64_t at = (int64_t(tau_[t]) * NIp + i0 + 16 * a + r16) * NIp + jb + 4 * g4;
+                const u32x4 ah = *reinterpret_cast<const u32x4*>(whi + at);
+                const u32x4 al = *reinterpret_cast<const u32x4*>(wlo + at);
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+                    acc[a][b][t][0] = mfma_bf16(ah, bh_re[b], acc[a][b][t][0]);
+                    acc[a][b][t][1] = mfma_bf16(ah, bh_im[b], acc[a][b][t][1]);
+                }
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+                    acc[a][b][t][0] = mfma_bf16(ah, bl_re[b], acc[a][b][t][0]);
+                    acc[a][b][t][1] = mfma_bf16(ah, bl_im[b], acc[a][b][t][1]);
+                }
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+                    acc[a][b][t][0] = mfma_bf16(al, bh_re[b], acc[a][b][t][0]);
+                    acc[a][b][t][1] = mfma_bf16(al, bh_im[b], acc[a][b][t][1]);
+                }
+            }
+        }
+    }
+
+    const double sc = d.scale;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int it = t0 + t;
+        if (it >= ntau) break;
+        double part[WJ];
+#pragma unroll
+        for (int b = 0; b < WJ; ++b) {
+            const int col = c0 + 16 * b + r16;
+            float s = 0.f;
+            if (col < Kk) {
+#pragma unroll
+                for (int a = 0; a < WI; ++a)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int I = i0 + 16 * a + 4 * g4 + rr;
+                        if (I < NI) {
+                            const float2 m = A[int64_t(I) * Kk + col];
+                            s += m.x * acc[a][b][t][0][rr] + m.y * acc[a][b][t][1][rr];
+                        }
+                    }
+            }
+            double v = s;
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (col < Kk) {
+                const int m = col - (col / nm) * nm;
+                v *= G[(int64_t(kq) * nbmax + m) * ntau + it];
+            }
+            part[b] = v;
+        }
+        const int cl = min(c0 + 16 * WJ, Kk) - 1;
+        const int nlo = c0 / nm, nhi = cl / nm;
+        for (int nx = nlo; nx <= nhi; ++nx) {
+            double v = 0.0;
+#pragma unroll
+            for (int b = 0; b < WJ; ++b) {
+                const int col = c0 + 16 * b + r16;
+                if (col < Kk && col / nm == nx) v += part[b];
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], sc * v);
+        }
+    }
+}
+
+// =================================================================================================
+// polarization, v3: four waves share the scaled and split J-side operand through LDS
+// =================================================================================================
+// Work-group = 4 waves stacked along I (wave w owns rows i0 + 16 WI w ...), all sharing the same J
+// columns and tau group.  Per K-step the (J tile b, tau t) fragments split(g(tau) M^J) are computed
+// once per work-group -- each wave takes every 4th (b, t) pair -- into a double-buffered LDS area,
+// so the per-tau scaling and splitting is amortised over 4 WI row tiles instead of WI.
+template <int WI, int WJ, int T>
+__global__ __launch_bounds__(256) void k_pol3(Dev d, int q0, const float2* __restrict__ M,
+                                              const double* __restrict__ G,
+                                              double2* __restrict__ P, Order od, int ntI) {
+    constexpr int NW = 4, NP = WJ * T;
+    __shared__ float Ga[NB_LDS * T];
+    __shared__ float Gb[NB_LDS * T];
+    __shared__ u32x4 Bs[2][NP][2][64];
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, g4 = lane >> 4;
+    const int q = q0 + qrel;
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int NI = d.ni[q];
+    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
+    const int ib = ti * NW * 16 * WI;
+    const int i0 = ib + wave * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
+    if (ib >= NI || j0 >= NI) return;  // uniform over the work-group
+    const bool active = i0 < NI;
+
+    floatx4 acc[WI][WJ][T][2];
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+
+    const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
+    double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
+    const double sc = d.scale;
+    bool first = true;
+    int since = 0;
+    auto flush = [&]() {
+        if (active) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                const int it = t0 + t;
+#pragma unroll
+                for (int a = 0; a < WI; ++a)
+#pragma unroll
+                    for (int b = 0; b < WJ; ++b)
+#pragma unroll
+                        for (int rr = 0; rr < 4; ++rr) {
+                            const int I = i0 + 16 * a + 4 * g4 + rr, J = j0 + 16 * b + r16;
+                            if (it < ntau && I < NI && J < NI) {
+                                double2* p = &Pq[int64_t(it) * NI * NI + int64_t(I) * NI + J];
+                                double re = sc * double(acc[a][b][t][0][rr]);
+                                double im = sc * double(acc[a][b][t][1][rr]);
+                                if (!first) {
+                                    double2 o = *p;
+                                    re += o.x;
+                                    im += o.y;
+                                }
+                                *p = make_double2(re, im);
+                            }
+                        }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < WI; ++a)
+#pragma unroll
+            for (int b = 0; b < WJ; ++b)
+#pragma unroll
+                for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+        first = false;
+        since = 0;
+    };
+
+    int rowI[WI];
+    float keepI[WI];
+#pragma unroll
+    for (int a = 0; a < WI; ++a) {
+        const int I = i0 + 16 * a + r16;
+        rowI[a] = min(I, NI - 1);
+        keepI[a] = I < NI ? 1.f : 0.f;
+    }
+
+    for (int k = 0; k < nk; ++k) {
+        const int kq = d.kmq[q * nk + k];
+        const int nn = d.nb[k], nm = d.nb[kq];
+        const int Kk = nn * nm;
+        const float2* A = Mq + d.moff[q * nk + k];
+        const bool vec = (Kk & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 31) == 0;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nn * T; e += 256) {
+            const int n = e / T, t = e - n * T;
+            Ga[e] = float(G[(int64_t(k) * nbmax + n) * ntau + min(t0 + t, ntau - 1)]);
+        }
+        for (int e = threadIdx.x; e < nm * T; e += 256) {
+            const int m = e / T, t = e - m * T;
+            Gb[e] = float(G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - min(t0 + t, ntau - 1))]);
+        }
+        __syncthreads();
+        const int nsteps = (Kk + 15) / 16;
+
+        // load the 4 complex values of row `row` this lane holds in step s (zero outside)
+        auto load4 = [&](int row, float keepv, int s, float2 v[4]) {
+            const int kb = s * 16 + 4 * g4;
+            if (vec && s * 16 + 16 <= Kk) {
+                const float4* p = reinterpret_cast<const float4*>(A + int64_t(row) * Kk + kb);
+                const float4 u = p[0], w = p[1];
+                v[0] = make_float2(keepv * u.x, keepv * u.y);
+                v[1] = make_float2(keepv * u.z, keepv * u.w);
+                v[2] = make_float2(keepv * w.x, keepv * w.y);
+                v[3] = make_float2(keepv * w.z, keepv * w.w);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[e] = (kb + e < Kk && keepv != 0.f) ? A[int64_t(row) * Kk + kb + e] : make_float2(0.f, 0.f);
+            }
+        };
+        // the J-side fragments of step s owned by this wave -> Bs[buf]
+        auto make_B = [&](int s, int buf) {
+            int gi[4], gj[4];
+            const int K0 = s * 16 + 4 * g4;
+            int nx = K0 / nm, mm = K0 - nx * nm;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                gi[e] = min(nx, nn - 1) * T;
+                gj[e] = mm * T;
+                if (++mm == nm) {
+                    mm = 0;
+                    ++nx;
+                }
+            }
+            for (int p = wave; p < NP; p += NW) {
+                const int b = p / T, t = p - b * T;
+                const int J = j0 + 16 * b + r16;
+                float2 y[4];
+                load4(min(J, NI - 1), J < NI ? 1.f : 0.f, s, y);
+                u32x4 yh, yl;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float g = Ga[gi[e] + t] * Gb[gj[e] + t];
+                    uint32_t h, l;
+                    split2(g * y[e].x, g * y[e].y, h, l);
+                    yh[e] = h;
+                    yl[e] = l;
+                }
+                Bs[buf][p][0][lane] = yh;
+                Bs[buf][p][1][lane] = yl;
+            }
+        };
+
+        make_B(0, 0);
+        __syncthreads();
+        for (int s = 0; s < nsteps; ++s) {
+            const int buf = s & 1;
+            u32x4 xh[WI], xl[WI], xh2[WI], xl2[WI];
+#pragma unroll
+            for (int a = 0; a < WI; ++a) {
+                float2 x[4];
+                load4(rowI[a], keepI[a], s, x);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t h, l;
+                    split2(x[e].x, x[e].y, h, l);
+                    xh[a][e] = h;
+                    xl[a][e] = l;
+                    xh2[a][e] = rot_neg(h);
+                    xl2[a][e] = rot_neg(l);
+                }
+            }
+            if (s + 1 < nsteps) make_B(s + 1, buf ^ 1);
+            if (active) {
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+#pragma unroll
+                    for (int b = 0; b < WJ; ++b) {
+                        const u32x4 yh = Bs[buf][b * T + t][0][lane];
+                        const u32x4 yl = Bs[buf][b * T + t][1][lane];
+#pragma unroll
+                        for (int a = 0; a < WI; ++a) {
+                            acc[a][b][t][0] = mfma_bf16(xh[a], yh, acc[a][b][t][0]);
+                            acc[a][b][t][1] = mfma_bf16(xh2[a], yh, acc[a][b][t][1]);
+                        }
+#pragma unroll
+                        for (int a = 0; a < WI; ++a) {
+                            acc[a][b][t][0] = mfma_bf16(xh[a], yl, acc[a][b][t][0]);
+                            acc[a][b][t][1] = mfma_bf16(xh2[a], yl, acc[a][b][t][1]);
+                        }
+#pragma unroll
+                        for (int a = 0; a < WI; ++a) {
+                            acc[a][b][t][0] = mfma_bf16(xl[a], yh, acc[a][b][t][0]);
+                            acc[a][b][t][1] = mfma_bf16(xl2[a], yh, acc[a][b][t][1]);
+                        }
+                    }
+            }
+            if (++since == FLUSH_STEPS) flush();
+            __syncthreads();
+        }
+    }
+    if (since > 0 || first) flush();
+}
+
+// =================================================================================================
 // variants (tile shapes) and dispatch
 // =================================================================================================
 using PolFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*, void*);
@@ -584,13 +973,48 @@ void run_sig(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const v
     MSGW_HIP(hipGetLastError());
 }
 
+// v3 self-energy: needs the split, transposed M planes (uses the `mt` arguments)
+template <int WI, int WJ, int T>
+void run_sig3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+              const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
+              void* Sig) {
+    int maxi = 0, maxc = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        maxi = std::max(maxi, h.ni[q]);
+        for (int k = 0; k < h.nk; ++k)
+            maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
+    }
+    static_assert(16 * WI <= PAD, "row tiles must fit in the padded W~ planes");
+    const int ntI = ceil_div(maxi, 16 * WI), ntC = ceil_div(maxc, 16 * WJ), ntG = ceil_div(h.ntau, T);
+    const Order od = make_order(ntG * ntI, h.nk * ntC, nq);
+    hipLaunchKernelGGL((k_sig3<WI, WJ, T>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
+                       (const float2*)M, G, wsc, plane, mt, mtplane, (double*)Sig, od, ntI, ntC);
+    MSGW_HIP(hipGetLastError());
+}
+
+template <int WI, int WJ, int T>
+void run_pol3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+              const double* G, void* P) {
+    int maxi = 0;
+    for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
+    const int ntI = ceil_div(maxi, 4 * 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
+    const Order od = make_order(ntG * ntI, ntJ, nq, 32);
+    hipLaunchKernelGGL((k_pol3<WI, WJ, T>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
+                       (const float2*)M, G, (double2*)P, od, ntI);
+    MSGW_HIP(hipGetLastError());
+}
+
+using Sig3Fn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
+                        const char*, int64_t, const uint32_t*, int64_t, void*);
+
 struct PolVariant {
     const char* name;
     PolFn fn;
 };
 struct SigVariant {
     const char* name;
-    SigFn fn;
+    SigFn fn;     // W~ planes only
+    Sig3Fn fn3;   // W~ planes + split transposed M
 };
 
 const PolVariant kPolBF16[] = {
@@ -599,21 +1023,31 @@ const PolVariant kPolBF16[] = {
     {"WI4 WJ2 T2", run_pol<4, 2, 2, PREC_BF16X3>},
     {"WI2 WJ4 T2", run_pol<2, 4, 2, PREC_BF16X3>},
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3>},
+    {"4 waves shared-B WI1 WJ4 T4", run_pol3<1, 4, 4>},
+    {"4 waves shared-B WI1 WJ5 T3", run_pol3<1, 5, 3>},
+    {"4 waves shared-B WI2 WJ2 T4", run_pol3<2, 2, 4>},
+    {"4 waves shared-B WI1 WJ2 T8", run_pol3<1, 2, 8>},
+    {"4 waves shared-B WI2 WJ4 T2", run_pol3<2, 4, 2>},
 };
 const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_FP32>},
 };
 const SigVariant kSigBF16[] = {
-    {"WI2 WJ4 T4", run_sig<2, 4, 4, PREC_BF16X3>},
-    {"WI4 WJ2 T4", run_sig<4, 2, 4, PREC_BF16X3>},
-    {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_BF16X3>},
-    {"WI4 WJ4 T2", run_sig<4, 4, 2, PREC_BF16X3>},
-    {"WI2 WJ8 T2", run_sig<2, 8, 2, PREC_BF16X3>},
+    {"WI2 WJ4 T4", run_sig<2, 4, 4, PREC_BF16X3>, nullptr},
+    {"WI4 WJ2 T4", run_sig<4, 2, 4, PREC_BF16X3>, nullptr},
+    {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_BF16X3>, nullptr},
+    {"WI4 WJ4 T2", run_sig<4, 4, 2, PREC_BF16X3>, nullptr},
+    {"WI2 WJ8 T2", run_sig<2, 8, 2, PREC_BF16X3>, nullptr},
+    {"split-M WI1 WJ8 T2", nullptr, run_sig3<1, 8, 2>},
+    {"split-M WI2 WJ4 T2", nullptr, run_sig3<2, 4, 2>},
+    {"split-M WI4 WJ4 T2", nullptr, run_sig3<4, 4, 2>},
+    {"split-M WI2 WJ4 T4", nullptr, run_sig3<2, 4, 4>},
+    {"split-M WI4 WJ2 T4", nullptr, run_sig3<4, 2, 4>},
 };
 const SigVariant kSigFP32[] = {
-    {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>},
-    {"WI2 WJ4 T2", run_sig<2, 4, 2, PREC_FP32>},
+    {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>, nullptr},
+    {"WI2 WJ4 T2", run_sig<2, 4, 2, PREC_FP32>, nullptr},
 };
 
 template <class V, size_t N>
@@ -627,6 +1061,13 @@ int64_t plane_elems(const Host& h, int q0, int nq) {
         const int np = round_up(h.ni[q], PAD);
         n += int64_t(h.ntau) * np * np;
     }
+    return n;
+}
+
+// elements of one plane of the split, transposed M for q0..q0+nq-1
+int64_t mt_elems(const Host& h, int q0, int nq) {
+    int64_t n = 0;
+    for (int q = q0; q < q0 + nq; ++q) n += (h.mpre[q + 1] - h.mpre[q]) / h.ni[q] * round_up(h.ni[q], 16);
     return n;
 }
 
@@ -647,10 +1088,12 @@ const char* mfma_variant_name(int op, int precision, int v) {
 }
 
 size_t mfma_scratch_bytes(const Host& h, int nq_max) {
-    // padded W~ planes for the q range of one self_energy call: 8 bytes per complex element
-    // (complex64 for FP32, hi + lo bf16 pairs for BF16X3)
+    // for the q range of one self_energy call: padded W~ planes and the split, transposed M planes,
+    // 8 bytes per complex element each (complex64 for FP32, hi + lo bf16 pairs for BF16X3)
     int64_t best = 0;
-    for (int q = 0; q + nq_max <= h.nk; ++q) best = std::max(best, plane_elems(h, q, nq_max));
+    for (int q = 0; q + nq_max <= h.nk; ++q)
+        best = std::max(best, round_up(int(std::min<int64_t>(plane_elems(h, q, nq_max), 1 << 30)), 64) +
+                                  mt_elems(h, q, nq_max));
     return size_t(best) * 8;
 }
 
@@ -667,8 +1110,11 @@ int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
                     const double* G, const void* W, int precision, int variant, void* Sig) {
     const int nv = mfma_variant_count(MSGW_OP_SELF_ENERGY, precision);
     if (variant < 0 || variant >= nv) return MSGW_EINVAL;
+    const SigVariant& V = (precision == MSGW_BF16X3 ? kSigBF16 : kSigFP32)[variant];
     const int64_t plane = plane_elems(h, q0, nq);
-    if (size_t(plane) * 8 > scratch_mfma_bytes(d, h)) return MSGW_ENOMEM;
+    const int64_t wsz = round_up(int(std::min<int64_t>(plane, 1 << 30)), 64);  // W~ planes, 256-B aligned
+    const int64_t mtp = V.fn3 ? mt_elems(h, q0, nq) : 0;
+    if (plane >= (int64_t(1) << 30) || size_t(wsz + mtp) * 8 > scratch_mfma_bytes(d, h)) return MSGW_ENOMEM;
     char* sc = scratch_mfma(d, h);
     int64_t off = 0;
     for (int q = q0; q < q0 + nq; ++q) {
@@ -682,7 +1128,19 @@ int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
         MSGW_HIP(hipGetLastError());
         off += n;
     }
-    (precision == MSGW_BF16X3 ? kSigBF16 : kSigFP32)[variant].fn(d, h, s, q0, nq, M, G, sc, plane, Sig);
+    if (!V.fn3) {
+        V.fn(d, h, s, q0, nq, M, G, sc, plane, Sig);
+        return MSGW_OK;
+    }
+    uint32_t* mt = reinterpret_cast<uint32_t*>(sc) + 2 * wsz;
+    for (int q = q0; q < q0 + nq; ++q) {
+        int maxc = 0;
+        for (int k = 0; k < h.nk; ++k) maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
+        const unsigned gx = ceil_div(round_up(h.ni[q], 16), 32) * ceil_div(maxc, 32);
+        hipLaunchKernelGGL(k_split_mt, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, (const float2*)M, mt, mtp);
+        MSGW_HIP(hipGetLastError());
+    }
+    V.fn3(d, h, s, q0, nq, M, G, sc, plane, mt, mtp, Sig);
     return MSGW_OK;
 }
 

@@ -26,6 +26,7 @@ def test_library_exports_every_declared_symbol():
     from paper_1602_02313_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
         pytest.skip("libmatsgw.so not built")
+    _lib.load_library()                      # loads torch's HIP runtime first
     lib = ctypes.CDLL(_lib.LIB_PATH)
     for n in declared():
         assert hasattr(lib, n), n
