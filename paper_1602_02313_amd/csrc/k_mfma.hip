@@ -125,7 +125,7 @@ __device__ __forceinline__ bool work_item(const Order& o, int& qrel, int& r, int
 // =================================================================================================
 // polarization
 // =================================================================================================
-template <int WI, int WJ, int T, int PREC>
+template <int WI, int WJ, int T, int PREC, bool PF>
 __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restrict__ M,
                                             const double* __restrict__ G,
                                             double2* __restrict__ P, Order od, int ntI) {
@@ -225,24 +225,9 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
         __syncthreads();
         int n0 = 0, m0 = 0;  // (n, m) of the first K of the current step
         const int nsteps = (Kk + 15) / 16;
-        for (int s = 0; s < nsteps; ++s) {
+        // raw FP32 operands of step s: rows I of this lane (xa) and rows J (yb)
+        auto load_raw = [&](int s, float2 (&xa)[WI][NE], float2 (&yb)[WJ][NE]) {
             const int kb = s * 16;
-            int gi[NE];   // n index * T into Ga
-            int gj[NE];   // m index * T into Gb
-            bool ve[NE];
-#pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                const int ko = LY::koff(g4, e);
-                ve[e] = kb + ko < Kk;
-                int mm = m0 + ko, nx = n0;
-                while (mm >= nm) {
-                    mm -= nm;
-                    ++nx;
-                }
-                gi[e] = min(nx, nn - 1) * T;
-                gj[e] = mm * T;
-            }
-            float2 xa[WI][NE], yb[WJ][NE];
             if (vec && kb + 16 <= Kk) {
 #pragma unroll
                 for (int a = 0; a < WI; ++a) {
@@ -267,16 +252,41 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
                 for (int a = 0; a < WI; ++a)
 #pragma unroll
                     for (int e = 0; e < NE; ++e)
-                        xa[a][e] = (ve[e] && keepI[a] != 0.f)
+                        xa[a][e] = (kb + LY::koff(g4, e) < Kk && keepI[a] != 0.f)
                                        ? A[int64_t(rowI[a]) * Kk + kb + LY::koff(g4, e)]
                                        : make_float2(0.f, 0.f);
 #pragma unroll
                 for (int b = 0; b < WJ; ++b)
 #pragma unroll
                     for (int e = 0; e < NE; ++e)
-                        yb[b][e] = (ve[e] && keepJ[b] != 0.f)
+                        yb[b][e] = (kb + LY::koff(g4, e) < Kk && keepJ[b] != 0.f)
                                        ? A[int64_t(rowJ[b]) * Kk + kb + LY::koff(g4, e)]
                                        : make_float2(0.f, 0.f);
+            }
+        };
+        float2 xa[WI][NE], yb[WJ][NE];
+        if (PF) load_raw(0, xa, yb);
+        for (int s = 0; s < nsteps; ++s) {
+            // PF: the next step's loads are issued before this step's arithmetic (register
+            // double-buffering), so their latency overlaps the split and the MFMAs
+            float2 xn[WI][NE], yn[WJ][NE];
+            if (PF) {
+                if (s + 1 < nsteps) load_raw(s + 1, xn, yn);
+            } else {
+                load_raw(s, xa, yb);
+            }
+            int gi[NE];   // n index * T into Ga
+            int gj[NE];   // m index * T into Gb
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const int ko = LY::koff(g4, e);
+                int mm = m0 + ko, nx = n0;
+                while (mm >= nm) {
+                    mm -= nm;
+                    ++nx;
+                }
+                gi[e] = min(nx, nn - 1) * T;
+                gj[e] = mm * T;
             }
             if constexpr (PREC == PREC_BF16X3) {
                 u32x4 xh[WI], xl[WI], xh2[WI], xl2[WI];
@@ -343,6 +353,16 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
                         }
                     }
                 }
+            }
+            if (PF) {
+#pragma unroll
+                for (int a = 0; a < WI; ++a)
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) xa[a][e] = xn[a][e];
+#pragma unroll
+                for (int b = 0; b < WJ; ++b)
+#pragma unroll
+                    for (int e = 0; e < NE; ++e) yb[b][e] = yn[b][e];
             }
             m0 += 16;
             while (m0 >= nm) {
@@ -595,7 +615,7 @@ __global__ __launch_bounds__(256) void k_split_mt(Dev d, int q0, int q, const fl
     }
 }
 
-template <int WI, int WJ, int T>
+template <int WI, int WJ, int T, bool PF>
 __global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __restrict__ M,
                                              const double* __restrict__ G,
                                              const char* __restrict__ wsc, int64_t plane,
@@ -644,17 +664,39 @@ __global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __rest
     for (int t = 0; t < T; ++t) tau_[t] = min(t0 + t, ntau - 1);
 
     const int nsteps = NIp16 / 16;
-    for (int s = 0; s < nsteps; ++s) {
+    // raw bf16 operands of step s (B: split M columns; A: W~ rows for each tau)
+    auto load_raw = [&](int s, u32x4 (&bh)[WJ], u32x4 (&bl)[WJ], u32x4 (&wh)[WI][T], u32x4 (&wl)[WI][T]) {
         const int jb = s * 16;
-        u32x4 bh_re[WJ], bl_re[WJ], bh_im[WJ], bl_im[WJ];
 #pragma unroll
         for (int b = 0; b < WJ; ++b) {
             const int64_t at = mb0 + int64_t(colr[b]) * NIp16 + jb + 4 * g4;
-            const u32x4 h = *reinterpret_cast<const u32x4*>(mt + at);
-            const u32x4 l = *reinterpret_cast<const u32x4*>(mt + mtplane + at);
+            bh[b] = *reinterpret_cast<const u32x4*>(mt + at);
+            bl[b] = *reinterpret_cast<const u32x4*>(mt + mtplane + at);
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int a = 0; a < WI; ++a) {
+                const int64_t at = (int64_t(tau_[t]) * NIp + i0 + 16 * a + r16) * NIp + jb + 4 * g4;
+                wh[a][t] = *reinterpret_cast<const u32x4*>(whi + at);
+                wl[a][t] = *reinterpret_cast<const u32x4*>(wlo + at);
+            }
+    };
+    u32x4 rbh[WJ], rbl[WJ], rwh[WI][T], rwl[WI][T];
+    if (PF) load_raw(0, rbh, rbl, rwh, rwl);
+    for (int s = 0; s < nsteps; ++s) {
+        u32x4 nbh[WJ], nbl[WJ], nwh[WI][T], nwl[WI][T];
+        if (PF) {
+            if (s + 1 < nsteps) load_raw(s + 1, nbh, nbl, nwh, nwl);
+        } else {
+            load_raw(s, rbh, rbl, rwh, rwl);
+        }
+        u32x4 bh_re[WJ], bl_re[WJ], bh_im[WJ], bl_im[WJ];
+#pragma unroll
+        for (int b = 0; b < WJ; ++b) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const uint32_t he = h[e] & keep[b], le = l[e] & keep[b];
+                const uint32_t he = rbh[b][e] & keep[b], le = rbl[b][e] & keep[b];
                 bh_re[b][e] = conj_pk(he);
                 bl_re[b][e] = conj_pk(le);
                 bh_im[b][e] = swap_pk(he);
@@ -665,9 +707,8 @@ __global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __rest
         for (int t = 0; t < T; ++t) {
 #pragma unroll
             for (int a = 0; a < WI; ++a) {
-                const int64_t at = (int64_t(tau_[t]) * NIp + i0 + 16 * a + r16) * NIp + jb + 4 * g4;
-                const u32x4 ah = *reinterpret_cast<const u32x4*>(whi + at);
-                const u32x4 al = *reinterpret_cast<const u32x4*>(wlo + at);
+                const u32x4 ah = rwh[a][t];
+                const u32x4 al = rwl[a][t];
 #pragma unroll
                 for (int b = 0; b < WJ; ++b) {
                     acc[a][b][t][0] = mfma_bf16(ah, bh_re[b], acc[a][b][t][0]);
@@ -684,6 +725,20 @@ __global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __rest
                     acc[a][b][t][1] = mfma_bf16(al, bh_im[b], acc[a][b][t][1]);
                 }
             }
+        }
+        if (PF) {
+#pragma unroll
+            for (int b = 0; b < WJ; ++b) {
+                rbh[b] = nbh[b];
+                rbl[b] = nbl[b];
+            }
+#pragma unroll
+            for (int a = 0; a < WI; ++a)
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    rwh[a][t] = nwh[a][t];
+                    rwl[a][t] = nwl[a][t];
+                }
         }
     }
 
@@ -944,14 +999,14 @@ using PolFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const voi
 using SigFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
                        const char*, int64_t, void*);
 
-template <int WI, int WJ, int T, int PREC>
+template <int WI, int WJ, int T, int PREC, bool PF = false>
 void run_pol(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
              const double* G, void* P) {
     int maxi = 0;
     for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
     const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
     const Order od = make_order(ntG * ntI, ntJ, nq);
-    hipLaunchKernelGGL((k_pol<WI, WJ, T, PREC>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
+    hipLaunchKernelGGL((k_pol<WI, WJ, T, PREC, PF>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
                        (const float2*)M, G, (double2*)P, od, ntI);
     MSGW_HIP(hipGetLastError());
 }
@@ -974,7 +1029,7 @@ void run_sig(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const v
 }
 
 // v3 self-energy: needs the split, transposed M planes (uses the `mt` arguments)
-template <int WI, int WJ, int T>
+template <int WI, int WJ, int T, bool PF = false>
 void run_sig3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
               void* Sig) {
@@ -987,7 +1042,7 @@ void run_sig3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     static_assert(16 * WI <= PAD, "row tiles must fit in the padded W~ planes");
     const int ntI = ceil_div(maxi, 16 * WI), ntC = ceil_div(maxc, 16 * WJ), ntG = ceil_div(h.ntau, T);
     const Order od = make_order(ntG * ntI, h.nk * ntC, nq);
-    hipLaunchKernelGGL((k_sig3<WI, WJ, T>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
+    hipLaunchKernelGGL((k_sig3<WI, WJ, T, PF>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
                        (const float2*)M, G, wsc, plane, mt, mtplane, (double*)Sig, od, ntI, ntC);
     MSGW_HIP(hipGetLastError());
 }
@@ -1028,6 +1083,11 @@ const PolVariant kPolBF16[] = {
     {"4 waves shared-B WI2 WJ2 T4", run_pol3<2, 2, 4>},
     {"4 waves shared-B WI1 WJ2 T8", run_pol3<1, 2, 8>},
     {"4 waves shared-B WI2 WJ4 T2", run_pol3<2, 4, 2>},
+    {"prefetch WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3, true>},
+    {"prefetch WI2 WJ2 T4", run_pol<2, 2, 4, PREC_BF16X3, true>},
+    {"prefetch WI4 WJ1 T4", run_pol<4, 1, 4, PREC_BF16X3, true>},
+    {"prefetch WI4 WJ1 T2", run_pol<4, 1, 2, PREC_BF16X3, true>},
+    {"prefetch WI4 WJ2 T2", run_pol<4, 2, 2, PREC_BF16X3, true>},
 };
 const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
@@ -1044,6 +1104,11 @@ const SigVariant kSigBF16[] = {
     {"split-M WI4 WJ4 T2", nullptr, run_sig3<4, 4, 2>},
     {"split-M WI2 WJ4 T4", nullptr, run_sig3<2, 4, 4>},
     {"split-M WI4 WJ2 T4", nullptr, run_sig3<4, 2, 4>},
+    {"split-M prefetch WI2 WJ4 T2", nullptr, run_sig3<2, 4, 2, true>},
+    {"split-M prefetch WI1 WJ8 T2", nullptr, run_sig3<1, 8, 2, true>},
+    {"split-M prefetch WI2 WJ2 T4", nullptr, run_sig3<2, 2, 4, true>},
+    {"split-M prefetch WI4 WJ2 T2", nullptr, run_sig3<4, 2, 2, true>},
+    {"split-M prefetch WI2 WJ2 T2", nullptr, run_sig3<2, 2, 2, true>},
 };
 const SigVariant kSigFP32[] = {
     {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>, nullptr},
