@@ -60,6 +60,10 @@ __device__ __forceinline__ void split2(float re, float im, uint32_t& h, uint32_t
 __device__ __forceinline__ uint32_t rot_neg(uint32_t p) {
     return __builtin_amdgcn_alignbit(p, p, 16) ^ 0x80000000u;
 }
+// (re, im) -> (-im, re): rotate by 16 bits, flip the sign of the new low half
+__device__ __forceinline__ uint32_t rot_pos(uint32_t p) {
+    return __builtin_amdgcn_alignbit(p, p, 16) ^ 0x00008000u;
+}
 // (re, im) -> (re, -im)
 __device__ __forceinline__ uint32_t conj_pk(uint32_t p) { return p ^ 0x80000000u; }
 // (re, im) -> (im, re)
@@ -993,6 +997,221 @@ __global__ __launch_bounds__(256) void k_pol3(Dev d, int q0, const float2* __res
 }
 
 // =================================================================================================
+// polarization, v5: tau-parallel waves over one LDS-staged (I, J) tile
+// =================================================================================================
+// Work-group = 4 waves; wave w owns tau points t0 + w TW + j (j < TW) of the work-group's tau group
+// and the whole (16 WI) x (16 WJ) output tile for them.  Per K-step of 16 complex elements the
+// work-group stages once, in a double-buffered LDS area and in the MFMA lane layout:
+//   A: the bf16 hi/lo split of the I rows (shared by every wave and tau), and
+//   B: the raw FP32 J rows, which each wave scales by its own g(tau) and splits in registers.
+// The next step's global loads are issued before the current step's MFMAs, so the load latency
+// overlaps the arithmetic; global traffic per MFMA is 4 TW times lower than with one wave per tile.
+template <int WI, int WJ, int TW>
+__global__ __launch_bounds__(256) void k_pol5(Dev d, int q0, const float2* __restrict__ M,
+                                              const double* __restrict__ G,
+                                              double2* __restrict__ P, Order od, int ntI) {
+    constexpr int NW = 4, TG = NW * TW;
+    constexpr int AP = (WI + NW - 1) / NW, BP = (WJ + NW - 1) / NW;  // tiles staged per wave
+    __shared__ float Ga[NB_LDS * TG];
+    __shared__ float Gb[NB_LDS * TG];
+    __shared__ u32x4 Ah[2][WI][64], Al[2][WI][64];
+    __shared__ float4 Braw[2][WJ][2][64];
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, g4 = lane >> 4;
+    const int q = q0 + qrel;
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int NI = d.ni[q];
+    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
+    const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * TG;
+    if (i0 >= NI || j0 >= NI) return;  // uniform over the work-group
+
+    floatx4 acc[WI][WJ][TW][2];
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int t = 0; t < TW; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+
+    const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
+    double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
+    const double sc = d.scale;
+    bool first = true;
+    int since = 0;
+    auto flush = [&]() {
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+            const int it = t0 + wave * TW + t;
+#pragma unroll
+            for (int a = 0; a < WI; ++a)
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const int I = i0 + 16 * a + 4 * g4 + rr, J = j0 + 16 * b + r16;
+                        if (it < ntau && I < NI && J < NI) {
+                            double2* p = &Pq[int64_t(it) * NI * NI + int64_t(I) * NI + J];
+                            double re = sc * double(acc[a][b][t][0][rr]);
+                            double im = sc * double(acc[a][b][t][1][rr]);
+                            if (!first) {
+                                double2 o = *p;
+                                re += o.x;
+                                im += o.y;
+                            }
+                            *p = make_double2(re, im);
+                        }
+                    }
+                    acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
+                }
+        }
+        first = false;
+        since = 0;
+    };
+
+    for (int k = 0; k < nk; ++k) {
+        const int kq = d.kmq[q * nk + k];
+        const int nn = d.nb[k], nm = d.nb[kq];
+        const int Kk = nn * nm;
+        const float2* A = Mq + d.moff[q * nk + k];
+        const bool vec = (Kk & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 31) == 0;
+        __syncthreads();  // the previous k's last step has finished reading LDS
+        for (int e = threadIdx.x; e < nn * TG; e += 256) {
+            const int n = e / TG, t = e - n * TG;
+            Ga[e] = float(G[(int64_t(k) * nbmax + n) * ntau + min(t0 + t, ntau - 1)]);
+        }
+        for (int e = threadIdx.x; e < nm * TG; e += 256) {
+            const int m = e / TG, t = e - m * TG;
+            Gb[e] = float(G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - min(t0 + t, ntau - 1))]);
+        }
+        const int nsteps = (Kk + 15) / 16;
+        // raw values of row `row` (4 complex) this lane stages for step s; zero outside
+        auto load4 = [&](int row, bool ok, int s, float4& u, float4& v) {
+            const int kb = s * 16 + 4 * g4;
+            if (vec && s * 16 + 16 <= Kk && ok) {
+                const float4* p = reinterpret_cast<const float4*>(A + int64_t(row) * Kk + kb);
+                u = p[0];
+                v = p[1];
+            } else {
+                float2 x[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    x[e] = (ok && kb + e < Kk) ? A[int64_t(row) * Kk + kb + e] : make_float2(0.f, 0.f);
+                u = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
+                v = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
+            }
+        };
+        float4 ra[AP][2], rb[BP][2];  // raw staging registers (this wave's share of step s)
+        auto fetch = [&](int s) {
+#pragma unroll
+            for (int p = 0; p < AP; ++p) {
+                const int a = wave + NW * p;
+                const int I = i0 + 16 * a + r16;
+                if (a < WI) load4(min(I, NI - 1), I < NI, s, ra[p][0], ra[p][1]);
+            }
+#pragma unroll
+            for (int p = 0; p < BP; ++p) {
+                const int b = wave + NW * p;
+                const int J = j0 + 16 * b + r16;
+                if (b < WJ) load4(min(J, NI - 1), J < NI, s, rb[p][0], rb[p][1]);
+            }
+        };
+        auto stage = [&](int buf) {
+#pragma unroll
+            for (int p = 0; p < AP; ++p) {
+                const int a = wave + NW * p;
+                if (a < WI) {
+                    const float4 u = ra[p][0], v = ra[p][1];
+                    uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
+                    split2(u.x, u.y, h0, l0);
+                    split2(u.z, u.w, h1, l1);
+                    split2(v.x, v.y, h2, l2);
+                    split2(v.z, v.w, h3, l3);
+                    Ah[buf][a][lane] = u32x4{h0, h1, h2, h3};
+                    Al[buf][a][lane] = u32x4{l0, l1, l2, l3};
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < BP; ++p) {
+                const int b = wave + NW * p;
+                if (b < WJ) {
+                    Braw[buf][b][0][lane] = rb[p][0];
+                    Braw[buf][b][1][lane] = rb[p][1];
+                }
+            }
+        };
+        fetch(0);
+        stage(0);
+        __syncthreads();
+        for (int s = 0; s < nsteps; ++s) {
+            const int buf = s & 1;
+            if (s + 1 < nsteps) fetch(s + 1);
+            // g indices of this lane's 4 K values in step s
+            int gi[4], gj[4];
+            {
+                const int K0 = s * 16 + 4 * g4;
+                int nx = K0 / nm, mm = K0 - nx * nm;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    gi[e] = min(nx, nn - 1) * TG + wave * TW;
+                    gj[e] = min(mm, nm - 1) * TG + wave * TW;
+                    if (++mm == nm) {
+                        mm = 0;
+                        ++nx;
+                    }
+                }
+            }
+            // Re(x conj y) = [xr, xi].[yr, yi] and Im(x conj y) = [xr, xi].[-yi, yr]: the rotation
+            // is applied to the per-tau B fragment, so A needs only its hi/lo parts in registers
+            u32x4 xh[WI], xl[WI];
+#pragma unroll
+            for (int a = 0; a < WI; ++a) {
+                xh[a] = Ah[buf][a][lane];
+                xl[a] = Al[buf][a][lane];
+            }
+#pragma unroll
+            for (int b = 0; b < WJ; ++b) {
+                const float4 u = Braw[buf][b][0][lane], v = Braw[buf][b][1][lane];
+                const float yr[4] = {u.x, u.z, v.x, v.z}, yi[4] = {u.y, u.w, v.y, v.w};
+#pragma unroll
+                for (int t = 0; t < TW; ++t) {
+                    u32x4 yh, yl, yh2, yl2;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float g = Ga[gi[e] + t] * Gb[gj[e] + t];
+                        uint32_t h, l;
+                        split2(g * yr[e], g * yi[e], h, l);
+                        yh[e] = h;
+                        yl[e] = l;
+                        yh2[e] = rot_pos(h);
+                        yl2[e] = rot_pos(l);
+                    }
+#pragma unroll
+                    for (int a = 0; a < WI; ++a) {
+                        acc[a][b][t][0] = mfma_bf16(xh[a], yh, acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma_bf16(xh[a], yh2, acc[a][b][t][1]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < WI; ++a) {
+                        acc[a][b][t][0] = mfma_bf16(xh[a], yl, acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma_bf16(xh[a], yl2, acc[a][b][t][1]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < WI; ++a) {
+                        acc[a][b][t][0] = mfma_bf16(xl[a], yh, acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma_bf16(xl[a], yh2, acc[a][b][t][1]);
+                    }
+                }
+            }
+            if (s + 1 < nsteps) stage(buf ^ 1);
+            if (++since == FLUSH_STEPS) flush();
+            __syncthreads();
+        }
+    }
+    if (since > 0 || first) flush();
+}
+
+// =================================================================================================
 // variants (tile shapes) and dispatch
 // =================================================================================================
 using PolFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*, void*);
@@ -1059,6 +1278,19 @@ void run_pol3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     MSGW_HIP(hipGetLastError());
 }
 
+template <int WI, int WJ, int TW>
+void run_pol5(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+              const double* G, void* P) {
+    int maxi = 0;
+    for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
+    const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ);
+    const int ntG = ceil_div(h.ntau, 4 * TW);
+    const Order od = make_order(ntG * ntI, ntJ, nq, 32);
+    hipLaunchKernelGGL((k_pol5<WI, WJ, TW>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
+                       (const float2*)M, G, (double2*)P, od, ntI);
+    MSGW_HIP(hipGetLastError());
+}
+
 using Sig3Fn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
                         const char*, int64_t, const uint32_t*, int64_t, void*);
 
@@ -1088,6 +1320,11 @@ const PolVariant kPolBF16[] = {
     {"prefetch WI4 WJ1 T4", run_pol<4, 1, 4, PREC_BF16X3, true>},
     {"prefetch WI4 WJ1 T2", run_pol<4, 1, 2, PREC_BF16X3, true>},
     {"prefetch WI4 WJ2 T2", run_pol<4, 2, 2, PREC_BF16X3, true>},
+    {"tau-waves LDS WI5 WJ5 TW1", run_pol5<5, 5, 1>},
+    {"tau-waves LDS WI4 WJ4 TW1", run_pol5<4, 4, 1>},
+    {"tau-waves LDS WI4 WJ4 TW2", run_pol5<4, 4, 2>},
+    {"tau-waves LDS WI5 WJ3 TW1", run_pol5<5, 3, 1>},
+    {"tau-waves LDS WI2 WJ2 TW4", run_pol5<2, 2, 4>},
 };
 const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
