@@ -49,13 +49,13 @@ def tune(run, M_source, reps=2, cache_path=None, log=None):
             ms = []
             for r in range(reps + 1):
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
+                a.record(st) if st is not None else a.record()
                 if op == L.OP_POLARIZATION:
                     ctx.polarization(q0, nq, M, run.m_dtype, run.G_tau, run.precision, run.P_tau, stream=st)
                 else:
                     ctx.self_energy(q0, nq, M, run.m_dtype, run.G_tau, run.Wt_tau, run.precision,
                                     run.sig_tau, stream=st)
-                b.record()
+                b.record(st) if st is not None else b.record()
                 torch.cuda.synchronize()
                 if r > 0:
                     ms.append(a.elapsed_time(b))

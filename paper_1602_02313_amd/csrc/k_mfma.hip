@@ -145,7 +145,7 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
     const int NI = d.ni[q];
     const int tg = r / ntI, ti = r - tg * ntI, tj = c;
     const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
-    if (i0 >= NI || j0 >= NI) return;
+    if (i0 >= NI || j0 >= NI || j0 + 16 * WJ <= i0) return;  // below the diagonal: mirrored later
 
     floatx4 acc[WI][WJ][T][2];
 #pragma unroll
@@ -385,25 +385,79 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
 // W~(q,tau) converted once per call into zero-padded planes [ntau][NIp][NIp], NIp = NI rounded up
 // to PAD: FP32 -> one complex64 plane; BF16X3 -> hi and lo planes of packed (re, im) bf16 pairs.
 // q blocks are packed over the call's q range (wq[q] = offset in elements of each plane).
-__global__ void k_convert_w(const double2* __restrict__ W, int NI, int NIp, int ntau, int prec,
-                            float2* __restrict__ w32, uint32_t* __restrict__ whi,
-                            uint32_t* __restrict__ wlo) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t n = int64_t(ntau) * NIp * NIp;
-    if (i >= n) return;
-    const int J = int(i % NIp);
-    const int I = int((i / NIp) % NIp);
-    const int it = int(i / (int64_t(NIp) * NIp));
-    double2 v = make_double2(0.0, 0.0);
-    if (I < NI && J < NI) v = W[(int64_t(it) * NI + I) * NI + J];
-    const float re = float(v.x), im = float(v.y);
-    if (prec == PREC_FP32) {
-        w32[i] = make_float2(re, im);
-    } else {
-        uint32_t h, l;
-        split2(re, im, h, l);
-        whi[i] = h;
-        wlo[i] = l;
+//
+// The diagonal self-energy needs only Re sum_IJ conj(a_I) W_IJ a_J for the columns a of M.  The
+// anti-Hermitian part of W contributes a purely imaginary amount to that sum, and the Hermitian part
+// H = (W + W^H) / 2 splits into its diagonal and two mirrored triangles, so
+//     Re sum_IJ conj(a_I) W_IJ a_J = 2 Re sum_{I <= J} conj(a_I) U_IJ a_J,
+// with U_IJ = H_IJ above the diagonal, H_II / 2 on it and 0 below.  The planes hold U; the kernels
+// start each row tile's reduction at its diagonal and double the result.  This holds for any W~,
+// Hermitian or not.
+constexpr int CW_TILE = 32;
+__global__ __launch_bounds__(256) void k_convert_w(const double2* __restrict__ W, int NI, int NIp,
+                                                   int prec, float2* __restrict__ w32,
+                                                   uint32_t* __restrict__ whi,
+                                                   uint32_t* __restrict__ wlo) {
+    __shared__ double2 tt[CW_TILE][CW_TILE + 1];  // W^T tile: tt[j][i] = W[J0 + i][I0 + j]
+    const int nt = NIp / CW_TILE;
+    const int bi = blockIdx.x / nt, bj = blockIdx.x - bi * nt, it = blockIdx.y;
+    const int I0 = bi * CW_TILE, J0 = bj * CW_TILE;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const double2* Wt = W + int64_t(it) * NI * NI;
+    const bool upper = bj >= bi;
+    if (upper) {
+        for (int r = ty; r < CW_TILE; r += 8) {
+            const int I = J0 + r, J = I0 + tx;  // coalesced read of the mirrored tile
+            tt[tx][r] = (I < NI && J < NI) ? Wt[int64_t(I) * NI + J] : make_double2(0.0, 0.0);
+        }
+    }
+    __syncthreads();
+    for (int r = ty; r < CW_TILE; r += 8) {
+        const int I = I0 + r, J = J0 + tx;
+        double re = 0.0, im = 0.0;
+        if (upper && I < NI && J < NI && J >= I) {
+            const double2 w = Wt[int64_t(I) * NI + J];
+            const double2 m = tt[r][tx];  // W[J][I]
+            re = 0.5 * (w.x + m.x);
+            im = 0.5 * (w.y - m.y);
+            if (J == I) {
+                re *= 0.5;
+                im = 0.0;
+            }
+        }
+        const int64_t o = (int64_t(it) * NIp + I) * NIp + J;
+        if (prec == PREC_FP32) {
+            w32[o] = make_float2(float(re), float(im));
+        } else {
+            uint32_t h, l;
+            split2(float(re), float(im), h, l);
+            whi[o] = h;
+            wlo[o] = l;
+        }
+    }
+}
+
+// Polarization is Hermitian in (I, J): the contraction kernels skip tiles that lie wholly below the
+// diagonal, and this kernel then sets every entry below the diagonal to the conjugate of its mirror.
+__global__ __launch_bounds__(256) void k_herm_fill(double2* __restrict__ P, int NI) {
+    __shared__ double2 tt[CW_TILE][CW_TILE + 1];
+    const int nt = (NI + CW_TILE - 1) / CW_TILE;
+    const int bi = blockIdx.x / nt, bj = blockIdx.x - bi * nt;  // target tile: rows bi, cols bj
+    if (bj > bi) return;
+    const int I0 = bi * CW_TILE, J0 = bj * CW_TILE;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double2* Pt = P + int64_t(blockIdx.y) * NI * NI;
+    for (int r = ty; r < CW_TILE; r += 8) {
+        const int I = J0 + r, J = I0 + tx;  // source: the mirrored tile (rows J0.., cols I0..)
+        if (I < NI && J < NI) tt[tx][r] = Pt[int64_t(I) * NI + J];
+    }
+    __syncthreads();
+    for (int r = ty; r < CW_TILE; r += 8) {
+        const int I = I0 + r, J = J0 + tx;
+        if (I < NI && J < I) {
+            const double2 v = tt[r][tx];
+            Pt[int64_t(I) * NI + J] = make_double2(v.x, -v.y);
+        }
     }
 }
 
@@ -451,7 +505,7 @@ __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restr
     for (int t = 0; t < T; ++t) tau_[t] = min(t0 + t, ntau - 1);
 
     const int nsteps = (NI + 15) / 16;
-    for (int s = 0; s < nsteps; ++s) {
+    for (int s = i0 / 16; s < nsteps; ++s) {
         const int jb = s * 16;
         float2 mb[WJ][NE];
 #pragma unroll
@@ -525,7 +579,7 @@ __global__ __launch_bounds__(64) void k_sig(Dev d, int q0, const float2* __restr
     }
 
     // epilogue: Re(conj(M) Y) over this tile's rows, weighted by G_m, summed per band n
-    const double sc = d.scale;
+    const double sc = 2.0 * d.scale;  // both triangles of U
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int it = t0 + t;
@@ -687,8 +741,8 @@ __global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __rest
             }
     };
     u32x4 rbh[WJ], rbl[WJ], rwh[WI][T], rwl[WI][T];
-    if (PF) load_raw(0, rbh, rbl, rwh, rwl);
-    for (int s = 0; s < nsteps; ++s) {
+    if (PF) load_raw(i0 / 16, rbh, rbl, rwh, rwl);
+    for (int s = i0 / 16; s < nsteps; ++s) {
         u32x4 nbh[WJ], nbl[WJ], nwh[WI][T], nwl[WI][T];
         if (PF) {
             if (s + 1 < nsteps) load_raw(s + 1, nbh, nbl, nwh, nwl);
@@ -746,7 +800,7 @@ __global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __rest
         }
     }
 
-    const double sc = d.scale;
+    const double sc = 2.0 * d.scale;  // both triangles of U
 #pragma unroll
     for (int t = 0; t < T; ++t) {
         const int it = t0 + t;
@@ -817,7 +871,7 @@ __global__ __launch_bounds__(256) void k_pol3(Dev d, int q0, const float2* __res
     const int tg = r / ntI, ti = r - tg * ntI, tj = c;
     const int ib = ti * NW * 16 * WI;
     const int i0 = ib + wave * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
-    if (ib >= NI || j0 >= NI) return;  // uniform over the work-group
+    if (ib >= NI || j0 >= NI || j0 + 16 * WJ <= ib) return;  // uniform over the work-group
     const bool active = i0 < NI;
 
     floatx4 acc[WI][WJ][T][2];
@@ -1024,7 +1078,7 @@ __global__ __launch_bounds__(256) void k_pol5(Dev d, int q0, const float2* __res
     const int NI = d.ni[q];
     const int tg = r / ntI, ti = r - tg * ntI, tj = c;
     const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * TG;
-    if (i0 >= NI || j0 >= NI) return;  // uniform over the work-group
+    if (i0 >= NI || j0 >= NI || j0 + 16 * WJ <= i0) return;  // uniform over the work-group
 
     floatx4 acc[WI][WJ][TW][2];
 #pragma unroll
@@ -1212,6 +1266,418 @@ __global__ __launch_bounds__(256) void k_pol5(Dev d, int q0, const float2* __res
 }
 
 // =================================================================================================
+// v6: 32x32x16 MFMA tiles (polarization and split-M self-energy)
+// =================================================================================================
+// v_mfma_f32_32x32x16_bf16 sustains close to the BF16 peak on gfx950 where the 16x16x32 shape
+// reaches about half of it, so these kernels use 32 x 32 output tiles and a K-step of 8 complex
+// elements.  Operand layout (lane l, 64 lanes): A row l % 32, B column l % 32, each with the 8
+// consecutive bf16 of K = 4 (l / 32) + e, e < 4 complex elements; the 16 accumulators of lane l hold
+// rows 8 g + 4 (l / 32) + r (acc index 4 g + r) of column l % 32.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ floatx16 mfma32(u32x4 a, u32x4 b, floatx16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ void zero16(floatx16& x) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) x[i] = 0.f;
+}
+constexpr int FLUSH_STEPS8 = 512;  // K-steps of 8 complex between FP64 flushes (4096 terms)
+
+// Polarization.  Work-group = 4 waves in a 2 x 2 grid over a (64 WI) x (64 WJ) (I, J) tile and
+// T tau points; each wave owns (32 WI) x (32 WJ) x T and loads its rows directly (rows shared by
+// two waves of the work-group are served by the CU's L1).
+template <int WI, int WJ, int T, bool PF>
+__global__ __launch_bounds__(256) void k_pol6(Dev d, int q0, const float2* __restrict__ M,
+                                              const double* __restrict__ G,
+                                              double2* __restrict__ P, Order od, int ntI) {
+    __shared__ float Ga[NB_LDS * T];
+    __shared__ float Gb[NB_LDS * T];
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r32 = lane & 31, h2 = lane >> 5;
+    const int q = q0 + qrel;
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int NI = d.ni[q];
+    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
+    const int ib = ti * 64 * WI, jbb = tj * 64 * WJ;
+    const int i0 = ib + (wave & 1) * 32 * WI, j0 = jbb + (wave >> 1) * 32 * WJ, t0 = tg * T;
+    if (ib >= NI || jbb >= NI || jbb + 64 * WJ <= ib) return;  // uniform over the work-group
+    const bool active = i0 < NI && j0 < NI;
+
+    floatx16 acc[WI][WJ][T][2];
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                zero16(acc[a][b][t][0]);
+                zero16(acc[a][b][t][1]);
+            }
+    const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
+    double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
+    const double sc = d.scale;
+    bool first = true;
+    int since = 0;
+    auto flush = [&]() {
+        // an opaque zero keeps the compiler from hoisting the 16 T WI WJ output addresses out of
+        // the k loop, where they would stay live across the whole contraction
+        int z = 0;
+        asm volatile("" : "+v"(z));
+        double2* Pz = Pq + z;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int it = t0 + t;
+#pragma unroll
+            for (int a = 0; a < WI; ++a)
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+                    const int J = j0 + 32 * b + r32 + z;
+#pragma unroll
+                    for (int x = 0; x < 16; ++x) {
+                        const int I = i0 + 32 * a + 8 * (x >> 2) + 4 * h2 + (x & 3) + z;
+                        if (it < ntau && I < NI && J < NI) {
+                            double2* p = &Pz[(int64_t(it) * NI + I) * NI + J];
+                            double re = sc * double(acc[a][b][t][0][x]);
+                            double im = sc * double(acc[a][b][t][1][x]);
+                            if (!first) {
+                                double2 o = *p;
+                                re += o.x;
+                                im += o.y;
+                            }
+                            *p = make_double2(re, im);
+                        }
+                    }
+                    zero16(acc[a][b][t][0]);
+                    zero16(acc[a][b][t][1]);
+                }
+        }
+        first = false;
+        since = 0;
+    };
+
+    int rowI[WI], rowJ[WJ];
+    float keepI[WI], keepJ[WJ];
+#pragma unroll
+    for (int a = 0; a < WI; ++a) {
+        const int I = i0 + 32 * a + r32;
+        rowI[a] = min(I, NI - 1);
+        keepI[a] = I < NI ? 1.f : 0.f;
+    }
+#pragma unroll
+    for (int b = 0; b < WJ; ++b) {
+        const int J = j0 + 32 * b + r32;
+        rowJ[b] = min(J, NI - 1);
+        keepJ[b] = J < NI ? 1.f : 0.f;
+    }
+
+    for (int k = 0; k < nk; ++k) {
+        const int kq = d.kmq[q * nk + k];
+        const int nn = d.nb[k], nm = d.nb[kq];
+        const int Kk = nn * nm;
+        const float2* A = Mq + d.moff[q * nk + k];
+        const bool vec = (Kk & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 31) == 0;
+        __syncthreads();
+        for (int e = threadIdx.x; e < nn * T; e += 256) {
+            const int n = e / T, t = e - n * T;
+            Ga[e] = float(G[(int64_t(k) * nbmax + n) * ntau + min(t0 + t, ntau - 1)]);
+        }
+        for (int e = threadIdx.x; e < nm * T; e += 256) {
+            const int m = e / T, t = e - m * T;
+            Gb[e] = float(G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - min(t0 + t, ntau - 1))]);
+        }
+        __syncthreads();
+        if (!active) continue;
+        const int nsteps = (Kk + 7) / 8;
+        auto load4 = [&](int row, float keepv, int s, float2 v[4]) {
+            const int kb = s * 8 + 4 * h2;
+            if (vec && s * 8 + 8 <= Kk) {
+                const float4* p = reinterpret_cast<const float4*>(A + int64_t(row) * Kk + kb);
+                const float4 u = p[0], w = p[1];
+                v[0] = make_float2(keepv * u.x, keepv * u.y);
+                v[1] = make_float2(keepv * u.z, keepv * u.w);
+                v[2] = make_float2(keepv * w.x, keepv * w.y);
+                v[3] = make_float2(keepv * w.z, keepv * w.w);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[e] = (kb + e < Kk && keepv != 0.f) ? A[int64_t(row) * Kk + kb + e]
+                                                        : make_float2(0.f, 0.f);
+            }
+        };
+        auto load_raw = [&](int s, float2 (&xa)[WI][4], float2 (&yb)[WJ][4]) {
+#pragma unroll
+            for (int a = 0; a < WI; ++a) load4(rowI[a], keepI[a], s, xa[a]);
+#pragma unroll
+            for (int b = 0; b < WJ; ++b) load4(rowJ[b], keepJ[b], s, yb[b]);
+        };
+        int K0 = 4 * h2;
+        int n0 = K0 / nm, m0 = K0 - n0 * nm;  // (n, m) of this lane's first element
+        float2 xa[WI][4], yb[WJ][4];
+        if (PF) load_raw(0, xa, yb);
+        for (int s = 0; s < nsteps; ++s) {
+            float2 xn[WI][4], yn[WJ][4];
+            if (PF) {
+                if (s + 1 < nsteps) load_raw(s + 1, xn, yn);
+            } else {
+                load_raw(s, xa, yb);
+            }
+            int gi[4], gj[4];
+            {
+                int nx = n0, mm = m0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    gi[e] = min(nx, nn - 1) * T;
+                    gj[e] = mm * T;
+                    if (++mm == nm) {
+                        mm = 0;
+                        ++nx;
+                    }
+                }
+            }
+            u32x4 xh[WI], xl[WI];
+#pragma unroll
+            for (int a = 0; a < WI; ++a)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t h, l;
+                    split2(xa[a][e].x, xa[a][e].y, h, l);
+                    xh[a][e] = h;
+                    xl[a][e] = l;
+                }
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                float g[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) g[e] = Ga[gi[e] + t] * Gb[gj[e] + t];
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+                    u32x4 yh, yl, yh2, yl2;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        uint32_t h, l;
+                        split2(g[e] * yb[b][e].x, g[e] * yb[b][e].y, h, l);
+                        yh[e] = h;
+                        yl[e] = l;
+                        yh2[e] = rot_pos(h);
+                        yl2[e] = rot_pos(l);
+                    }
+#pragma unroll
+                    for (int a = 0; a < WI; ++a) {
+                        acc[a][b][t][0] = mfma32(xh[a], yh, acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma32(xh[a], yh2, acc[a][b][t][1]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < WI; ++a) {
+                        acc[a][b][t][0] = mfma32(xh[a], yl, acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma32(xh[a], yl2, acc[a][b][t][1]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < WI; ++a) {
+                        acc[a][b][t][0] = mfma32(xl[a], yh, acc[a][b][t][0]);
+                        acc[a][b][t][1] = mfma32(xl[a], yh2, acc[a][b][t][1]);
+                    }
+                }
+            }
+            if (PF) {
+#pragma unroll
+                for (int a = 0; a < WI; ++a)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) xa[a][e] = xn[a][e];
+#pragma unroll
+                for (int b = 0; b < WJ; ++b)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) yb[b][e] = yn[b][e];
+            }
+            m0 += 8;
+            while (m0 >= nm) {
+                m0 -= nm;
+                ++n0;
+            }
+            if (++since == FLUSH_STEPS8) flush();
+        }
+    }
+    if (active && (since > 0 || first)) flush();
+}
+
+// Self-energy on split-M planes.  Work-group = 4 waves over adjacent column strips (32 WJ columns
+// each) sharing the same W~ rows (32 WI) and T tau points.
+template <int WI, int WJ, int T, bool PF>
+__global__ __launch_bounds__(256) void k_sig6(Dev d, int q0, const float2* __restrict__ M,
+                                              const double* __restrict__ G,
+                                              const char* __restrict__ wsc, int64_t plane,
+                                              const uint32_t* __restrict__ mt, int64_t mtplane,
+                                              double* __restrict__ Sig, Order od, int ntI, int ntC) {
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r32 = lane & 31, h2 = lane >> 5;
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int q = q0 + qrel;
+    const int tg = r / ntI, ti = r - tg * ntI;
+    const int k = c / ntC, tc = c - k * ntC;
+    const int kq = d.kmq[q * nk + k];
+    const int nm = d.nb[kq], NI = d.ni[q];
+    const int Kk = d.nb[k] * nm;
+    const int i0 = ti * 32 * WI, c0 = tc * 4 * 32 * WJ + wave * 32 * WJ, t0 = tg * T;
+    if (i0 >= NI || c0 >= Kk) return;  // no barriers below: waves may leave independently
+    const int NIp = (NI + PAD - 1) / PAD * PAD, NIp16 = (NI + 15) / 16 * 16;
+    int64_t wq = 0;
+    for (int qq = q0; qq < q; ++qq) {
+        const int np = (d.ni[qq] + PAD - 1) / PAD * PAD;
+        wq += int64_t(ntau) * np * np;
+    }
+    const uint32_t* whi = reinterpret_cast<const uint32_t*>(wsc) + wq;
+    const uint32_t* wlo = reinterpret_cast<const uint32_t*>(wsc) + plane + wq;
+    const int64_t mb0 = mt_qbase(d, q0, q) + d.moff[q * nk + k] / NI * NIp16;
+    const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
+
+    int colr[WJ];
+    uint32_t keep[WJ];
+#pragma unroll
+    for (int b = 0; b < WJ; ++b) {
+        const int col = c0 + 32 * b + r32;
+        colr[b] = min(col, Kk - 1);
+        keep[b] = col < Kk ? 0xffffffffu : 0u;
+    }
+    floatx16 acc[WI][WJ][T][2];
+#pragma unroll
+    for (int a = 0; a < WI; ++a)
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                zero16(acc[a][b][t][0]);
+                zero16(acc[a][b][t][1]);
+            }
+    int tau_[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) tau_[t] = min(t0 + t, ntau - 1);
+
+    const int nsteps = NIp16 / 8;
+    auto load_raw = [&](int s, u32x4 (&bh)[WJ], u32x4 (&bl)[WJ], u32x4 (&wh)[WI][T], u32x4 (&wl)[WI][T]) {
+        const int jb = s * 8 + 4 * h2;
+#pragma unroll
+        for (int b = 0; b < WJ; ++b) {
+            const int64_t at = mb0 + int64_t(colr[b]) * NIp16 + jb;
+            bh[b] = *reinterpret_cast<const u32x4*>(mt + at);
+            bl[b] = *reinterpret_cast<const u32x4*>(mt + mtplane + at);
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int a = 0; a < WI; ++a) {
+                const int64_t at = (int64_t(tau_[t]) * NIp + i0 + 32 * a + r32) * NIp + jb;
+                wh[a][t] = *reinterpret_cast<const u32x4*>(whi + at);
+                wl[a][t] = *reinterpret_cast<const u32x4*>(wlo + at);
+            }
+    };
+    u32x4 rbh[WJ], rbl[WJ], rwh[WI][T], rwl[WI][T];
+    if (PF) load_raw(i0 / 8, rbh, rbl, rwh, rwl);
+    for (int s = i0 / 8; s < nsteps; ++s) {
+        u32x4 nbh[WJ], nbl[WJ], nwh[WI][T], nwl[WI][T];
+        if (PF) {
+            if (s + 1 < nsteps) load_raw(s + 1, nbh, nbl, nwh, nwl);
+        } else {
+            load_raw(s, rbh, rbl, rwh, rwl);
+        }
+        u32x4 bh_re[WJ], bl_re[WJ], bh_im[WJ], bl_im[WJ];
+#pragma unroll
+        for (int b = 0; b < WJ; ++b)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t he = rbh[b][e] & keep[b], le = rbl[b][e] & keep[b];
+                bh_re[b][e] = conj_pk(he);
+                bl_re[b][e] = conj_pk(le);
+                bh_im[b][e] = swap_pk(he);
+                bl_im[b][e] = swap_pk(le);
+            }
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int a = 0; a < WI; ++a) {
+                const u32x4 ah = rwh[a][t], al = rwl[a][t];
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+                    acc[a][b][t][0] = mfma32(ah, bh_re[b], acc[a][b][t][0]);
+                    acc[a][b][t][1] = mfma32(ah, bh_im[b], acc[a][b][t][1]);
+                }
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+                    acc[a][b][t][0] = mfma32(ah, bl_re[b], acc[a][b][t][0]);
+                    acc[a][b][t][1] = mfma32(ah, bl_im[b], acc[a][b][t][1]);
+                }
+#pragma unroll
+                for (int b = 0; b < WJ; ++b) {
+                    acc[a][b][t][0] = mfma32(al, bh_re[b], acc[a][b][t][0]);
+                    acc[a][b][t][1] = mfma32(al, bh_im[b], acc[a][b][t][1]);
+                }
+            }
+        if (PF) {
+#pragma unroll
+            for (int b = 0; b < WJ; ++b) {
+                rbh[b] = nbh[b];
+                rbl[b] = nbl[b];
+            }
+#pragma unroll
+            for (int a = 0; a < WI; ++a)
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    rwh[a][t] = nwh[a][t];
+                    rwl[a][t] = nwl[a][t];
+                }
+        }
+    }
+
+    // epilogue: Re(conj(M) Y) over this tile's rows, weighted by G_m, summed per band n
+    const double sc = 2.0 * d.scale;  // both triangles of U
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int it = t0 + t;
+        if (it >= ntau) break;
+        double part[WJ];
+#pragma unroll
+        for (int b = 0; b < WJ; ++b) {
+            const int col = c0 + 32 * b + r32;
+            float s = 0.f;
+            if (col < Kk) {
+#pragma unroll
+                for (int a = 0; a < WI; ++a)
+#pragma unroll
+                    for (int x = 0; x < 16; ++x) {
+                        const int I = i0 + 32 * a + 8 * (x >> 2) + 4 * h2 + (x & 3);
+                        if (I < NI) {
+                            const float2 m = A[int64_t(I) * Kk + col];
+                            s += m.x * acc[a][b][t][0][x] + m.y * acc[a][b][t][1][x];
+                        }
+                    }
+            }
+            double v = s;
+            v += __shfl_xor(v, 32);
+            if (col < Kk) {
+                const int m = col - (col / nm) * nm;
+                v *= G[(int64_t(kq) * nbmax + m) * ntau + it];
+            }
+            part[b] = v;
+        }
+        const int cl = min(c0 + 32 * WJ, Kk) - 1;
+        const int nlo = c0 / nm, nhi = cl / nm;
+        for (int nx = nlo; nx <= nhi; ++nx) {
+            double v = 0.0;
+#pragma unroll
+            for (int b = 0; b < WJ; ++b) {
+                const int col = c0 + 32 * b + r32;
+                if (col < Kk && col / nm == nx) v += part[b];
+            }
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], sc * v);
+        }
+    }
+}
+
+// =================================================================================================
 // variants (tile shapes) and dispatch
 // =================================================================================================
 using PolFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*, void*);
@@ -1294,6 +1760,36 @@ void run_pol5(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
 using Sig3Fn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
                         const char*, int64_t, const uint32_t*, int64_t, void*);
 
+template <int WI, int WJ, int T, bool PF = false>
+void run_pol6(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+              const double* G, void* P) {
+    int maxi = 0;
+    for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
+    const int ntI = ceil_div(maxi, 64 * WI), ntJ = ceil_div(maxi, 64 * WJ), ntG = ceil_div(h.ntau, T);
+    const Order od = make_order(ntG * ntI, ntJ, nq, 32);
+    hipLaunchKernelGGL((k_pol6<WI, WJ, T, PF>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
+                       (const float2*)M, G, (double2*)P, od, ntI);
+    MSGW_HIP(hipGetLastError());
+}
+
+template <int WI, int WJ, int T, bool PF = false>
+void run_sig6(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+              const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
+              void* Sig) {
+    int maxi = 0, maxc = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        maxi = std::max(maxi, h.ni[q]);
+        for (int k = 0; k < h.nk; ++k)
+            maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
+    }
+    static_assert(32 * WI <= PAD, "row tiles must fit in the padded W~ planes");
+    const int ntI = ceil_div(maxi, 32 * WI), ntC = ceil_div(maxc, 4 * 32 * WJ), ntG = ceil_div(h.ntau, T);
+    const Order od = make_order(ntG * ntI, h.nk * ntC, nq, 32);
+    hipLaunchKernelGGL((k_sig6<WI, WJ, T, PF>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
+                       (const float2*)M, G, wsc, plane, mt, mtplane, (double*)Sig, od, ntI, ntC);
+    MSGW_HIP(hipGetLastError());
+}
+
 struct PolVariant {
     const char* name;
     PolFn fn;
@@ -1325,6 +1821,14 @@ const PolVariant kPolBF16[] = {
     {"tau-waves LDS WI4 WJ4 TW2", run_pol5<4, 4, 2>},
     {"tau-waves LDS WI5 WJ3 TW1", run_pol5<5, 3, 1>},
     {"tau-waves LDS WI2 WJ2 TW4", run_pol5<2, 2, 4>},
+    {"32x32 WI1 WJ1 T4", run_pol6<1, 1, 4>},
+    {"32x32 WI1 WJ1 T6", run_pol6<1, 1, 6>},
+    {"32x32 WI1 WJ2 T3", run_pol6<1, 2, 3>},
+    {"32x32 WI2 WJ1 T3", run_pol6<2, 1, 3>},
+    {"32x32 WI1 WJ1 T3", run_pol6<1, 1, 3>},
+    {"32x32 prefetch WI1 WJ1 T4", run_pol6<1, 1, 4, true>},
+    {"32x32 prefetch WI1 WJ2 T3", run_pol6<1, 2, 3, true>},
+    {"32x32 prefetch WI1 WJ1 T6", run_pol6<1, 1, 6, true>},
 };
 const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
@@ -1346,6 +1850,14 @@ const SigVariant kSigBF16[] = {
     {"split-M prefetch WI2 WJ2 T4", nullptr, run_sig3<2, 2, 4, true>},
     {"split-M prefetch WI4 WJ2 T2", nullptr, run_sig3<4, 2, 2, true>},
     {"split-M prefetch WI2 WJ2 T2", nullptr, run_sig3<2, 2, 2, true>},
+    {"32x32 split-M WI1 WJ1 T4", nullptr, run_sig6<1, 1, 4>},
+    {"32x32 split-M WI1 WJ1 T6", nullptr, run_sig6<1, 1, 6>},
+    {"32x32 split-M WI1 WJ2 T3", nullptr, run_sig6<1, 2, 3>},
+    {"32x32 split-M WI2 WJ1 T3", nullptr, run_sig6<2, 1, 3>},
+    {"32x32 split-M WI1 WJ2 T4", nullptr, run_sig6<1, 2, 4>},
+    {"32x32 split-M WI2 WJ2 T2", nullptr, run_sig6<2, 2, 2>},
+    {"32x32 split-M prefetch WI1 WJ2 T3", nullptr, run_sig6<1, 2, 3, true>},
+    {"32x32 split-M prefetch WI1 WJ1 T6", nullptr, run_sig6<1, 1, 6, true>},
 };
 const SigVariant kSigFP32[] = {
     {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>, nullptr},
@@ -1405,6 +1917,12 @@ int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
     const int n = mfma_variant_count(MSGW_OP_POLARIZATION, precision);
     if (variant < 0 || variant >= n) return MSGW_EINVAL;
     (precision == MSGW_BF16X3 ? kPolBF16 : kPolFP32)[variant].fn(d, h, s, q0, nq, M, G, P);
+    for (int q = q0; q < q0 + nq; ++q) {
+        const int nt = ceil_div(h.ni[q], CW_TILE);
+        hipLaunchKernelGGL(k_herm_fill, dim3(nt * nt, h.ntau), dim3(256), 0, s,
+                           (double2*)P + (h.ppre[q] - h.ppre[q0]), h.ni[q]);
+        MSGW_HIP(hipGetLastError());
+    }
     return MSGW_OK;
 }
 
@@ -1423,7 +1941,9 @@ int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
         const int NI = h.ni[q], NIp = round_up(NI, PAD);
         const int64_t n = int64_t(h.ntau) * NIp * NIp;
         const double2* Wq = (const double2*)W + (h.ppre[q] - h.ppre[q0]);
-        hipLaunchKernelGGL(k_convert_w, dim3(ceil_div(n, 256)), dim3(256), 0, s, Wq, NI, NIp, h.ntau,
+        static_assert(PAD % CW_TILE == 0, "conversion tiles must divide the padded planes");
+        const int nt = NIp / CW_TILE;
+        hipLaunchKernelGGL(k_convert_w, dim3(nt * nt, h.ntau), dim3(256), 0, s, Wq, NI, NIp,
                            precision, reinterpret_cast<float2*>(sc) + off,
                            reinterpret_cast<uint32_t*>(sc) + off,
                            reinterpret_cast<uint32_t*>(sc) + plane + off);
