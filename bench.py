@@ -91,11 +91,19 @@ def main():
                     help="q points on which the FP64 GPU path is timed for comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--variant-p", type=int, default=None,
+                    help="polarization tile variant (skips the autotuner for P)")
+    ap.add_argument("--variant-s", type=int, default=None,
+                    help="self-energy tile variant (skips the autotuner for Sigma)")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="counter runs: a plain device copy of --copy-mb MB, then one q batch of the path, "
+                         "no timing and no JSON line")
+    ap.add_argument("--copy-mb", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for --gpus "
-              f"{args.gpus}); the q axis would be sharded across GPUs with one all-reduce of "
-              f"Sigma, which is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): there is no "
+              f"multi-GPU path; it would shard the q axis over GPUs with one all-reduce of Sigma "
+              f"per iteration, which is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -120,10 +128,31 @@ def main():
     t_gen = time.perf_counter() - t0
     log(f"[bench] M resident: {M.numel() * M.element_size() / 1e9:.1f} GB generated in {t_gen:.2f} s")
     src = amd.ResidentM(M, run.mpre)
+    fixed = {amd.OP_POLARIZATION: args.variant_p, amd.OP_SELF_ENERGY: args.variant_s}
+    for op, v in fixed.items():
+        if v is not None:
+            run.ctx.set_variant(op, prec, v)
+    if args.profile_batch:
+        # a plain copy of known size calibrates the HBM byte counters, then one batch of the path
+        n = args.copy_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        run.green0(0.0)
+        run.sig_tau.zero_()
+        run.sig_x.zero_()
+        run.q_block(src, 0, min(args.q_batch, cfg.nk))
+        torch.cuda.synchronize()
+        log(f"[bench] profile batch done: copy of {args.copy_mb} MB, q 0..{args.q_batch - 1}, variants "
+            f"P {run.ctx.get_variant(amd.OP_POLARIZATION, prec)} S {run.ctx.get_variant(amd.OP_SELF_ENERGY, prec)}")
+        return
     tuned = {}
-    if not args.no_autotune:
+    if not args.no_autotune and None in fixed.values():
         from paper_1602_02313_amd import autotune
-        for op, (v, name, times) in autotune.tune(run, src, reps=1, log=log).items():
+        ops = [op for op, v in fixed.items() if v is None]
+        for op, (v, name, times) in autotune.tune(run, src, reps=1, log=log, ops=ops).items():
             tuned[["polarization", "self_energy"][op]] = {"variant": v, "tile": name, "ms": times}
 
     def step():

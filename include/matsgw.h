@@ -229,6 +229,8 @@ int msgw_variant_count(int op, int precision);
 const char* msgw_variant_name(int op, int precision, int variant);
 /* Select the variant used by subsequent calls on c (default 0). */
 int msgw_set_variant(msgw_ctx* c, int op, int precision, int variant);
+/* The variant currently selected on c for (op, precision), written to *variant (host int). */
+int msgw_get_variant(const msgw_ctx* c, int op, int precision, int* variant);
 
 /* ---- input generation (not part of the method) ---------------------------------------------- */
 

@@ -5,5 +5,6 @@
 G0W0 / GW0 / scGW run on one GPU.
 """
 from ._lib import (BF16X3, BOSON, C64, C128, EXPORTS, FERMION, FP32, FP64, LIB_PATH,  # noqa: F401
-                   MU_FIXED, MU_SEARCH, SIGMA_DIAG, SIGMA_FULL, Context, MsgwError, load_library)
+                   MU_FIXED, MU_SEARCH, OP_POLARIZATION, OP_SELF_ENERGY, SIGMA_DIAG, SIGMA_FULL,
+                   Context, MsgwError, load_library)
 from .driver import GWRun, HostM, ResidentM, SynthM  # noqa: F401

@@ -30,7 +30,7 @@ EXPORTS = [
     "msgw_workspace_size", "msgw_set_workspace", "msgw_m_layout", "msgw_green0",
     "msgw_polarization", "msgw_tau_to_iw", "msgw_iw_to_tau", "msgw_screen",
     "msgw_screened_tau", "msgw_self_energy", "msgw_sigma_x", "msgw_dyson", "msgw_gap",
-    "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant",
+    "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant", "msgw_get_variant",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 
@@ -98,6 +98,8 @@ def load_library():
     lib.msgw_variant_name.restype = ctypes.c_char_p
     lib.msgw_set_variant.argtypes = [P, I, I, I]
     lib.msgw_set_variant.restype = ctypes.c_int
+    lib.msgw_get_variant.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_int)]
+    lib.msgw_get_variant.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -240,6 +242,13 @@ class Context:
 
     def set_variant(self, op, precision, variant):
         self._check(self.lib.msgw_set_variant(self._c, int(op), int(precision), int(variant)))
+
+    def get_variant(self, op, precision):
+        out = ctypes.c_int(-1)
+        rc = self.lib.msgw_get_variant(self._c, int(op), int(precision), ctypes.byref(out))
+        if rc != 0:
+            raise MsgwError(rc, "bad op or precision")
+        return out.value
 
     def synth_M(self, seed, q0, nq, symmetric, m_dtype, M, stream=None):
         self._check(self.lib.msgw_synth_M(self._c, _stream(stream), int(seed), q0, nq,

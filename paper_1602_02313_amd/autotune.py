@@ -17,7 +17,7 @@ def _key(run, op):
                                      run.ntau, run.q_batch))
 
 
-def tune(run, M_source, reps=2, cache_path=None, log=None):
+def tune(run, M_source, reps=2, cache_path=None, log=None, ops=None):
     """Pick the fastest variant of each MFMA op for `run`; returns {op: (index, name, ms list)}."""
     import torch
     if run.precision not in (L.FP32, L.BF16X3):
@@ -35,7 +35,7 @@ def tune(run, M_source, reps=2, cache_path=None, log=None):
     run.sig_tau.zero_()
     run.sig_x.zero_()
     run.q_block(M_source, q0, nq)
-    for op in (L.OP_POLARIZATION, L.OP_SELF_ENERGY):
+    for op in (ops if ops is not None else (L.OP_POLARIZATION, L.OP_SELF_ENERGY)):
         names = ctx.variants(op, run.precision)
         key = _key(run, op)
         if key in cache and cache[key] < len(names):

@@ -527,6 +527,13 @@ int msgw_set_variant(msgw_ctx* c, int op, int precision, int variant) {
     });
 }
 
+int msgw_get_variant(const msgw_ctx* c, int op, int precision, int* variant) {
+    if (!c || !variant) return MSGW_EINVAL;
+    if (msgw_variant_count(op, precision) <= 0) return MSGW_EINVAL;
+    *variant = c->variant[op][precision];
+    return MSGW_OK;
+}
+
 int msgw_gap(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
              const void* Sigma_c_iw, const double* mu, int n_index, double* gap) {
     return guarded(c, [&] {

@@ -95,13 +95,33 @@ struct Order {
     int total;     // nq * per_q
 };
 
-// window: work items resident at once on one XCD (waves or work-groups)
+// window: work items resident at once on one XCD (waves or work-groups); window <= 0 gives plain
+// row-major order (each row of C items consecutive)
 Order make_order(int R, int C, int nq, int window = 128) {
     Order o;
     o.R = R;
     o.C = C;
-    o.SC = C <= 32 ? std::min(C, window) : std::min(16, window);
-    o.SR = std::max(1, window / o.SC);
+    if (window <= 0) {
+        o.SC = C;
+        o.SR = 1;
+    } else {
+        o.SC = C <= 32 ? std::min(C, window) : std::min(16, window);
+        o.SR = std::max(1, window / o.SC);
+    }
+    o.nSC = (C + o.SC - 1) / o.SC;
+    const int nSR = (R + o.SR - 1) / o.SR;
+    o.per_q = nSR * o.nSC * o.SR * o.SC;
+    o.total = nq * o.per_q;
+    return o;
+}
+
+// explicit super-tile of SR x SC items (rows x columns)
+Order make_order_st(int R, int C, int nq, int SR, int SC) {
+    Order o;
+    o.R = R;
+    o.C = C;
+    o.SR = std::max(1, std::min(SR, R));
+    o.SC = std::max(1, std::min(SC, C));
     o.nSC = (C + o.SC - 1) / o.SC;
     const int nSR = (R + o.SR - 1) / o.SR;
     o.per_q = nSR * o.nSC * o.SR * o.SC;
@@ -132,7 +152,7 @@ __device__ __forceinline__ bool work_item(const Order& o, int& qrel, int& r, int
 template <int WI, int WJ, int T, int PREC, bool PF>
 __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restrict__ M,
                                             const double* __restrict__ G,
-                                            double2* __restrict__ P, Order od, int ntI) {
+                                            double2* __restrict__ P, Order od, int ntJ) {
     using LY = Lay<PREC>;
     constexpr int NE = LY::NE;
     __shared__ float Ga[NB_LDS * T];
@@ -143,7 +163,7 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
     const int q = q0 + qrel;
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int NI = d.ni[q];
-    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
+    const int tg = c, ti = r / ntJ, tj = r - ti * ntJ;  // tau groups of one tile run together
     const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
     if (i0 >= NI || j0 >= NI || j0 + 16 * WJ <= i0) return;  // below the diagonal: mirrored later
 
@@ -857,7 +877,7 @@ __global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __rest
 template <int WI, int WJ, int T>
 __global__ __launch_bounds__(256) void k_pol3(Dev d, int q0, const float2* __restrict__ M,
                                               const double* __restrict__ G,
-                                              double2* __restrict__ P, Order od, int ntI) {
+                                              double2* __restrict__ P, Order od, int ntJ) {
     constexpr int NW = 4, NP = WJ * T;
     __shared__ float Ga[NB_LDS * T];
     __shared__ float Gb[NB_LDS * T];
@@ -868,7 +888,7 @@ __global__ __launch_bounds__(256) void k_pol3(Dev d, int q0, const float2* __res
     const int q = q0 + qrel;
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int NI = d.ni[q];
-    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
+    const int tg = c, ti = r / ntJ, tj = r - ti * ntJ;  // tau groups of one tile run together
     const int ib = ti * NW * 16 * WI;
     const int i0 = ib + wave * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
     if (ib >= NI || j0 >= NI || j0 + 16 * WJ <= ib) return;  // uniform over the work-group
@@ -1063,7 +1083,7 @@ __global__ __launch_bounds__(256) void k_pol3(Dev d, int q0, const float2* __res
 template <int WI, int WJ, int TW>
 __global__ __launch_bounds__(256) void k_pol5(Dev d, int q0, const float2* __restrict__ M,
                                               const double* __restrict__ G,
-                                              double2* __restrict__ P, Order od, int ntI) {
+                                              double2* __restrict__ P, Order od, int ntJ) {
     constexpr int NW = 4, TG = NW * TW;
     constexpr int AP = (WI + NW - 1) / NW, BP = (WJ + NW - 1) / NW;  // tiles staged per wave
     __shared__ float Ga[NB_LDS * TG];
@@ -1076,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_pol5(Dev d, int q0, const float2* __res
     const int q = q0 + qrel;
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int NI = d.ni[q];
-    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
+    const int tg = c, ti = r / ntJ, tj = r - ti * ntJ;  // tau groups of one tile run together
     const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * TG;
     if (i0 >= NI || j0 >= NI || j0 + 16 * WJ <= i0) return;  // uniform over the work-group
 
@@ -1291,7 +1311,7 @@ constexpr int FLUSH_STEPS8 = 512;  // K-steps of 8 complex between FP64 flushes 
 template <int WI, int WJ, int T, bool PF>
 __global__ __launch_bounds__(256) void k_pol6(Dev d, int q0, const float2* __restrict__ M,
                                               const double* __restrict__ G,
-                                              double2* __restrict__ P, Order od, int ntI) {
+                                              double2* __restrict__ P, Order od, int ntJ) {
     __shared__ float Ga[NB_LDS * T];
     __shared__ float Gb[NB_LDS * T];
     int qrel, r, c;
@@ -1300,7 +1320,7 @@ __global__ __launch_bounds__(256) void k_pol6(Dev d, int q0, const float2* __res
     const int q = q0 + qrel;
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int NI = d.ni[q];
-    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
+    const int tg = c, ti = r / ntJ, tj = r - ti * ntJ;  // tau groups of one tile run together
     const int ib = ti * 64 * WI, jbb = tj * 64 * WJ;
     const int i0 = ib + (wave & 1) * 32 * WI, j0 = jbb + (wave >> 1) * 32 * WJ, t0 = tg * T;
     if (ib >= NI || jbb >= NI || jbb + 64 * WJ <= ib) return;  // uniform over the work-group
@@ -1678,6 +1698,205 @@ __global__ __launch_bounds__(256) void k_sig6(Dev d, int q0, const float2* __res
 }
 
 // =================================================================================================
+// v7 self-energy: LDS double-buffered 32x32x16 contraction
+// =================================================================================================
+// Work-group = 4 waves in a 2 x 2 grid over 64 rows I and 128 columns c = (n, m) of one k block,
+// for T tau points.  The reduction over J advances in stages of 16; each stage of the U planes
+// (T x 64 rows x 16 J, hi and lo) and of the split, transposed M (128 columns x 16 J, hi and lo)
+// is loaded once per work-group into registers while the previous stage is multiplied out of
+// LDS, then written to the other LDS buffer: one barrier per stage, and the global latency hides
+// behind 96 MFMAs per wave.
+constexpr int S7_KS = 16;         // J per stage
+constexpr int S7_RS = S7_KS + 4;  // LDS row stride in u32 (80 B: conflict-free 16-B reads)
+
+template <int T>
+__global__ __launch_bounds__(256) void k_sig7(Dev d, int q0, const float2* __restrict__ M,
+                                              const double* __restrict__ G,
+                                              const char* __restrict__ wsc, int64_t plane,
+                                              const uint32_t* __restrict__ mt, int64_t mtplane,
+                                              double* __restrict__ Sig, Order od, int ntI, int ntC) {
+    __shared__ uint32_t As[2][2][T][64][S7_RS];  // [buffer][hi, lo][tau][row][J]
+    __shared__ uint32_t Bs[2][2][128][S7_RS];    // [buffer][hi, lo][column][J]
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h2 = lane >> 5;
+    const int wi = wave & 1, wc = wave >> 1;
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int q = q0 + qrel;
+    const int tg = r / ntI, ti = r - tg * ntI;
+    const int k = c / ntC, tc = c - k * ntC;
+    const int kq = d.kmq[q * nk + k];
+    const int nm = d.nb[kq], NI = d.ni[q];
+    const int Kk = d.nb[k] * nm;
+    const int i0 = ti * 64, c0 = tc * 128, t0 = tg * T;
+    if (i0 >= NI || c0 >= Kk) return;  // uniform over the work-group
+    const int NIp = (NI + PAD - 1) / PAD * PAD, NIp16 = (NI + 15) / 16 * 16;
+    int64_t wq = 0;
+    for (int qq = q0; qq < q; ++qq) {
+        const int np = (d.ni[qq] + PAD - 1) / PAD * PAD;
+        wq += int64_t(ntau) * np * np;
+    }
+    // one base pointer per operand (the lo planes are at fixed offsets), so that every load is a
+    // plain global load
+    const uint32_t* wbase = reinterpret_cast<const uint32_t*>(wsc) + wq;
+    const uint32_t* mbase = mt + mt_qbase(d, q0, q) + d.moff[q * nk + k] / NI * NIp16;
+
+    // this thread's share of a stage: 2T chunks of the U planes, 4 of the M planes (16 B each)
+    constexpr int NA = 2 * T, NB = 4;
+    int64_t aoff[NA];
+    int alds[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int id = tid + 256 * i;
+        const int aq = id & 3, ar = (id >> 2) & 63, tp = id >> 8;
+        const int at = tp % T, ap = tp / T;
+        const int tau = min(t0 + at, ntau - 1);
+        aoff[i] = ap * plane + (int64_t(tau) * NIp + i0 + ar) * NIp + 4 * aq;
+        alds[i] = ((ap * T + at) * 64 + ar) * S7_RS + 4 * aq;  // within one buffer of As
+    }
+    int64_t boff[NB];
+    int blds[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int id = tid + 256 * i;
+        const int bq = id & 3, bc = (id >> 2) & 127, bp = id >> 9;
+        boff[i] = bp * mtplane + int64_t(min(c0 + bc, Kk - 1)) * NIp16 + 4 * bq;
+        blds[i] = (bp * 128 + bc) * S7_RS + 4 * bq;
+    }
+    u32x4 ra[NA], rb[NB];
+    auto gload = [&](int J0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) ra[i] = *reinterpret_cast<const u32x4*>(wbase + aoff[i] + J0);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) rb[i] = *reinterpret_cast<const u32x4*>(mbase + boff[i] + J0);
+    };
+    auto lstore = [&](int buf) {
+        uint32_t* a = &As[buf][0][0][0][0];
+        uint32_t* b = &Bs[buf][0][0][0];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) *reinterpret_cast<u32x4*>(a + alds[i]) = ra[i];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) *reinterpret_cast<u32x4*>(b + blds[i]) = rb[i];
+    };
+    // fragments of one 8-J step: A for every tau (hi, lo), B for both column tiles (hi, lo)
+    auto lread = [&](int buf, int kk, u32x4 (&fa)[T][2], u32x4 (&fb)[2][2]) {
+        const int jo = 8 * kk + 4 * h2;
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+                fb[b][p] = *reinterpret_cast<const u32x4*>(&Bs[buf][p][64 * wc + 32 * b + r32][jo]);
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+                fa[t][p] = *reinterpret_cast<const u32x4*>(&As[buf][p][t][32 * wi + r32][jo]);
+    };
+
+    floatx16 acc[2][T][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            zero16(acc[b][t][0]);
+            zero16(acc[b][t][1]);
+        }
+    auto compute = [&](const u32x4 (&fa)[T][2], const u32x4 (&fb)[2][2]) {
+        u32x4 bre[2][2], bim[2][2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    bre[b][p][e] = conj_pk(fb[b][p][e]);
+                    bim[b][p][e] = swap_pk(fb[b][p][e]);
+                }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc[b][t][0] = mfma32(fa[t][0], bre[b][0], acc[b][t][0]);
+                acc[b][t][1] = mfma32(fa[t][0], bim[b][0], acc[b][t][1]);
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc[b][t][0] = mfma32(fa[t][0], bre[b][1], acc[b][t][0]);
+                acc[b][t][1] = mfma32(fa[t][0], bim[b][1], acc[b][t][1]);
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                acc[b][t][0] = mfma32(fa[t][1], bre[b][0], acc[b][t][0]);
+                acc[b][t][1] = mfma32(fa[t][1], bim[b][0], acc[b][t][1]);
+            }
+        }
+    };
+
+    // U is zero below the diagonal: the reduction starts at the work-group's first row
+    const int ns = (NIp16 - i0) / S7_KS;
+    gload(i0);
+    lstore(0);
+    __syncthreads();
+    for (int s = 0; s < ns; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < ns) gload(i0 + (s + 1) * S7_KS);
+        u32x4 fa0[T][2], fb0[2][2], fa1[T][2], fb1[2][2];
+        lread(buf, 0, fa0, fb0);
+        lread(buf, 1, fa1, fb1);  // in flight while step 0 multiplies
+        // keep the compiler from sinking the step-1 reads next to their use
+        __builtin_amdgcn_sched_barrier(0);
+        compute(fa0, fb0);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(fa1, fb1);
+        if (s + 1 < ns) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: Re(conj(M) Y) over this wave's rows, weighted by G_m, summed per band n
+    const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
+    const double sc = 2.0 * d.scale;  // both triangles of U
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int it = t0 + t;
+        if (it >= ntau) break;
+        double part[2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int col = c0 + 64 * wc + 32 * b + r32;
+            float s = 0.f;
+            if (col < Kk) {
+#pragma unroll
+                for (int x = 0; x < 16; ++x) {
+                    const int I = i0 + 32 * wi + 8 * (x >> 2) + 4 * h2 + (x & 3);
+                    if (I < NI) {
+                        const float2 m = A[int64_t(I) * Kk + col];
+                        s += m.x * acc[b][t][0][x] + m.y * acc[b][t][1][x];
+                    }
+                }
+            }
+            double v = s;
+            v += __shfl_xor(v, 32);
+            if (col < Kk) v *= G[(int64_t(kq) * nbmax + (col - (col / nm) * nm)) * ntau + it];
+            part[b] = v;
+        }
+        const int cb = c0 + 64 * wc;
+        if (cb >= Kk) continue;
+        const int nlo = cb / nm, nhi = (min(cb + 64, Kk) - 1) / nm;
+        for (int nx = nlo; nx <= nhi; ++nx) {
+            double v = 0.0;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int col = cb + 32 * b + r32;
+                if (col < Kk && col / nm == nx) v += part[b];
+            }
+#pragma unroll
+            for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0) atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], sc * v);
+        }
+    }
+}
+
+// =================================================================================================
 // variants (tile shapes) and dispatch
 // =================================================================================================
 using PolFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*, void*);
@@ -1690,9 +1909,9 @@ void run_pol(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const v
     int maxi = 0;
     for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
     const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
-    const Order od = make_order(ntG * ntI, ntJ, nq);
+    const Order od = make_order(ntI * ntJ, ntG, nq, 0);
     hipLaunchKernelGGL((k_pol<WI, WJ, T, PREC, PF>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntI);
+                       (const float2*)M, G, (double2*)P, od, ntJ);
     MSGW_HIP(hipGetLastError());
 }
 
@@ -1738,9 +1957,9 @@ void run_pol3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     int maxi = 0;
     for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
     const int ntI = ceil_div(maxi, 4 * 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
-    const Order od = make_order(ntG * ntI, ntJ, nq, 32);
+    const Order od = make_order(ntI * ntJ, ntG, nq, 0);
     hipLaunchKernelGGL((k_pol3<WI, WJ, T>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntI);
+                       (const float2*)M, G, (double2*)P, od, ntJ);
     MSGW_HIP(hipGetLastError());
 }
 
@@ -1751,14 +1970,32 @@ void run_pol5(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
     const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ);
     const int ntG = ceil_div(h.ntau, 4 * TW);
-    const Order od = make_order(ntG * ntI, ntJ, nq, 32);
+    const Order od = make_order(ntI * ntJ, ntG, nq, 0);
     hipLaunchKernelGGL((k_pol5<WI, WJ, TW>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntI);
+                       (const float2*)M, G, (double2*)P, od, ntJ);
     MSGW_HIP(hipGetLastError());
 }
 
 using Sig3Fn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
                         const char*, int64_t, const uint32_t*, int64_t, void*);
+
+template <int T, int SR = 4, int SC = 8>
+void run_sig7(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+              const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
+              void* Sig) {
+    int maxi = 0, maxc = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        maxi = std::max(maxi, h.ni[q]);
+        for (int k = 0; k < h.nk; ++k)
+            maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
+    }
+    static_assert(64 <= PAD, "row tiles must fit in the padded W~ planes");
+    const int ntI = ceil_div(maxi, 64), ntC = ceil_div(maxc, 128), ntG = ceil_div(h.ntau, T);
+    const Order od = make_order_st(ntG * ntI, h.nk * ntC, nq, SR, SC);
+    hipLaunchKernelGGL((k_sig7<T>), dim3(grid_of(od)), dim3(256), 0, s, d, q0, (const float2*)M, G,
+                       wsc, plane, mt, mtplane, (double*)Sig, od, ntI, ntC);
+    MSGW_HIP(hipGetLastError());
+}
 
 template <int WI, int WJ, int T, bool PF = false>
 void run_pol6(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
@@ -1766,9 +2003,9 @@ void run_pol6(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     int maxi = 0;
     for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
     const int ntI = ceil_div(maxi, 64 * WI), ntJ = ceil_div(maxi, 64 * WJ), ntG = ceil_div(h.ntau, T);
-    const Order od = make_order(ntG * ntI, ntJ, nq, 32);
+    const Order od = make_order(ntI * ntJ, ntG, nq, 0);
     hipLaunchKernelGGL((k_pol6<WI, WJ, T, PF>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntI);
+                       (const float2*)M, G, (double2*)P, od, ntJ);
     MSGW_HIP(hipGetLastError());
 }
 
@@ -1858,6 +2095,10 @@ const SigVariant kSigBF16[] = {
     {"32x32 split-M WI2 WJ2 T2", nullptr, run_sig6<2, 2, 2>},
     {"32x32 split-M prefetch WI1 WJ2 T3", nullptr, run_sig6<1, 2, 3, true>},
     {"32x32 split-M prefetch WI1 WJ1 T6", nullptr, run_sig6<1, 1, 6, true>},
+    {"LDS 2-stage 64x128 T4", nullptr, run_sig7<4>},
+    {"LDS 2-stage 64x128 T3", nullptr, run_sig7<3>},
+    {"LDS 2-stage 64x128 T4 st2x16", nullptr, run_sig7<4, 2, 16>},
+    {"LDS 2-stage 64x128 T4 st8x4", nullptr, run_sig7<4, 8, 4>},
 };
 const SigVariant kSigFP32[] = {
     {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>, nullptr},
