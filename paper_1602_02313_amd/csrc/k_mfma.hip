@@ -18,8 +18,10 @@
 // The FP32 accumulators of the polarization are flushed into the FP64 output every FLUSH_STEPS
 // K-steps, so an FP32 sum never runs over more than 4096 complex terms.
 //
-// One wave (64 lanes) per work-group.  Each wave owns a (16 WI) x (16 WJ) x T output tile and
-// streams its operands from global memory; reuse between waves is served by L2.  To make that
+// Polarization: one wave (64 lanes) per work-group.  Each wave owns a (16 WI) x (16 WJ) x T output
+// tile and streams its operands from global memory; reuse between waves is served by L2.
+// Self-energy: besides one-wave variants of the same kind, a 4-wave variant (v7) stages its
+// operands through LDS and runs on v_mfma_f32_32x32x16_bf16.  To make that
 // reuse happen, work-groups are ordered XCD-aware: the hardware deals consecutive work-group ids
 // round-robin to the 8 XCDs, so id b is mapped to work item (b % 8) * per + b / 8 -- each XCD
 // walks a contiguous slice of the work -- and the work space (rows x columns) is cut into
@@ -152,7 +154,7 @@ __device__ __forceinline__ bool work_item(const Order& o, int& qrel, int& r, int
 template <int WI, int WJ, int T, int PREC, bool PF>
 __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restrict__ M,
                                             const double* __restrict__ G,
-                                            double2* __restrict__ P, Order od, int ntJ) {
+                                            double2* __restrict__ P, Order od, int ntI) {
     using LY = Lay<PREC>;
     constexpr int NE = LY::NE;
     __shared__ float Ga[NB_LDS * T];
@@ -163,7 +165,7 @@ __global__ __launch_bounds__(64) void k_pol(Dev d, int q0, const float2* __restr
     const int q = q0 + qrel;
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int NI = d.ni[q];
-    const int tg = c, ti = r / ntJ, tj = r - ti * ntJ;  // tau groups of one tile run together
+    const int tg = r / ntI, ti = r - tg * ntI, tj = c;
     const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
     if (i0 >= NI || j0 >= NI || j0 + 16 * WJ <= i0) return;  // below the diagonal: mirrored later
 
@@ -868,425 +870,7 @@ __global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __rest
 }
 
 // =================================================================================================
-// polarization, v3: four waves share the scaled and split J-side operand through LDS
-// =================================================================================================
-// Work-group = 4 waves stacked along I (wave w owns rows i0 + 16 WI w ...), all sharing the same J
-// columns and tau group.  Per K-step the (J tile b, tau t) fragments split(g(tau) M^J) are computed
-// once per work-group -- each wave takes every 4th (b, t) pair -- into a double-buffered LDS area,
-// so the per-tau scaling and splitting is amortised over 4 WI row tiles instead of WI.
-template <int WI, int WJ, int T>
-__global__ __launch_bounds__(256) void k_pol3(Dev d, int q0, const float2* __restrict__ M,
-                                              const double* __restrict__ G,
-                                              double2* __restrict__ P, Order od, int ntJ) {
-    constexpr int NW = 4, NP = WJ * T;
-    __shared__ float Ga[NB_LDS * T];
-    __shared__ float Gb[NB_LDS * T];
-    __shared__ u32x4 Bs[2][NP][2][64];
-    int qrel, r, c;
-    if (!work_item(od, qrel, r, c)) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, g4 = lane >> 4;
-    const int q = q0 + qrel;
-    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
-    const int NI = d.ni[q];
-    const int tg = c, ti = r / ntJ, tj = r - ti * ntJ;  // tau groups of one tile run together
-    const int ib = ti * NW * 16 * WI;
-    const int i0 = ib + wave * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * T;
-    if (ib >= NI || j0 >= NI || j0 + 16 * WJ <= ib) return;  // uniform over the work-group
-    const bool active = i0 < NI;
-
-    floatx4 acc[WI][WJ][T][2];
-#pragma unroll
-    for (int a = 0; a < WI; ++a)
-#pragma unroll
-        for (int b = 0; b < WJ; ++b)
-#pragma unroll
-            for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
-
-    const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
-    double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
-    const double sc = d.scale;
-    bool first = true;
-    int since = 0;
-    auto flush = [&]() {
-        if (active) {
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const int it = t0 + t;
-#pragma unroll
-                for (int a = 0; a < WI; ++a)
-#pragma unroll
-                    for (int b = 0; b < WJ; ++b)
-#pragma unroll
-                        for (int rr = 0; rr < 4; ++rr) {
-                            const int I = i0 + 16 * a + 4 * g4 + rr, J = j0 + 16 * b + r16;
-                            if (it < ntau && I < NI && J < NI) {
-                                double2* p = &Pq[int64_t(it) * NI * NI + int64_t(I) * NI + J];
-                                double re = sc * double(acc[a][b][t][0][rr]);
-                                double im = sc * double(acc[a][b][t][1][rr]);
-                                if (!first) {
-                                    double2 o = *p;
-                                    re += o.x;
-                                    im += o.y;
-                                }
-                                *p = make_double2(re, im);
-                            }
-                        }
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < WI; ++a)
-#pragma unroll
-            for (int b = 0; b < WJ; ++b)
-#pragma unroll
-                for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
-        first = false;
-        since = 0;
-    };
-
-    int rowI[WI];
-    float keepI[WI];
-#pragma unroll
-    for (int a = 0; a < WI; ++a) {
-        const int I = i0 + 16 * a + r16;
-        rowI[a] = min(I, NI - 1);
-        keepI[a] = I < NI ? 1.f : 0.f;
-    }
-
-    for (int k = 0; k < nk; ++k) {
-        const int kq = d.kmq[q * nk + k];
-        const int nn = d.nb[k], nm = d.nb[kq];
-        const int Kk = nn * nm;
-        const float2* A = Mq + d.moff[q * nk + k];
-        const bool vec = (Kk & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 31) == 0;
-        __syncthreads();
-        for (int e = threadIdx.x; e < nn * T; e += 256) {
-            const int n = e / T, t = e - n * T;
-            Ga[e] = float(G[(int64_t(k) * nbmax + n) * ntau + min(t0 + t, ntau - 1)]);
-        }
-        for (int e = threadIdx.x; e < nm * T; e += 256) {
-            const int m = e / T, t = e - m * T;
-            Gb[e] = float(G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - min(t0 + t, ntau - 1))]);
-        }
-        __syncthreads();
-        const int nsteps = (Kk + 15) / 16;
-
-        // load the 4 complex values of row `row` this lane holds in step s (zero outside)
-        auto load4 = [&](int row, float keepv, int s, float2 v[4]) {
-            const int kb = s * 16 + 4 * g4;
-            if (vec && s * 16 + 16 <= Kk) {
-                const float4* p = reinterpret_cast<const float4*>(A + int64_t(row) * Kk + kb);
-                const float4 u = p[0], w = p[1];
-                v[0] = make_float2(keepv * u.x, keepv * u.y);
-                v[1] = make_float2(keepv * u.z, keepv * u.w);
-                v[2] = make_float2(keepv * w.x, keepv * w.y);
-                v[3] = make_float2(keepv * w.z, keepv * w.w);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    v[e] = (kb + e < Kk && keepv != 0.f) ? A[int64_t(row) * Kk + kb + e] : make_float2(0.f, 0.f);
-            }
-        };
-        // the J-side fragments of step s owned by this wave -> Bs[buf]
-        auto make_B = [&](int s, int buf) {
-            int gi[4], gj[4];
-            const int K0 = s * 16 + 4 * g4;
-            int nx = K0 / nm, mm = K0 - nx * nm;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                gi[e] = min(nx, nn - 1) * T;
-                gj[e] = mm * T;
-                if (++mm == nm) {
-                    mm = 0;
-                    ++nx;
-                }
-            }
-            for (int p = wave; p < NP; p += NW) {
-                const int b = p / T, t = p - b * T;
-                const int J = j0 + 16 * b + r16;
-                float2 y[4];
-                load4(min(J, NI - 1), J < NI ? 1.f : 0.f, s, y);
-                u32x4 yh, yl;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const float g = Ga[gi[e] + t] * Gb[gj[e] + t];
-                    uint32_t h, l;
-                    split2(g * y[e].x, g * y[e].y, h, l);
-                    yh[e] = h;
-                    yl[e] = l;
-                }
-                Bs[buf][p][0][lane] = yh;
-                Bs[buf][p][1][lane] = yl;
-            }
-        };
-
-        make_B(0, 0);
-        __syncthreads();
-        for (int s = 0; s < nsteps; ++s) {
-            const int buf = s & 1;
-            u32x4 xh[WI], xl[WI], xh2[WI], xl2[WI];
-#pragma unroll
-            for (int a = 0; a < WI; ++a) {
-                float2 x[4];
-                load4(rowI[a], keepI[a], s, x);
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    uint32_t h, l;
-                    split2(x[e].x, x[e].y, h, l);
-                    xh[a][e] = h;
-                    xl[a][e] = l;
-                    xh2[a][e] = rot_neg(h);
-                    xl2[a][e] = rot_neg(l);
-                }
-            }
-            if (s + 1 < nsteps) make_B(s + 1, buf ^ 1);
-            if (active) {
-#pragma unroll
-                for (int t = 0; t < T; ++t)
-#pragma unroll
-                    for (int b = 0; b < WJ; ++b) {
-                        const u32x4 yh = Bs[buf][b * T + t][0][lane];
-                        const u32x4 yl = Bs[buf][b * T + t][1][lane];
-#pragma unroll
-                        for (int a = 0; a < WI; ++a) {
-                            acc[a][b][t][0] = mfma_bf16(xh[a], yh, acc[a][b][t][0]);
-                            acc[a][b][t][1] = mfma_bf16(xh2[a], yh, acc[a][b][t][1]);
-                        }
-#pragma unroll
-                        for (int a = 0; a < WI; ++a) {
-                            acc[a][b][t][0] = mfma_bf16(xh[a], yl, acc[a][b][t][0]);
-                            acc[a][b][t][1] = mfma_bf16(xh2[a], yl, acc[a][b][t][1]);
-                        }
-#pragma unroll
-                        for (int a = 0; a < WI; ++a) {
-                            acc[a][b][t][0] = mfma_bf16(xl[a], yh, acc[a][b][t][0]);
-                            acc[a][b][t][1] = mfma_bf16(xl2[a], yh, acc[a][b][t][1]);
-                        }
-                    }
-            }
-            if (++since == FLUSH_STEPS) flush();
-            __syncthreads();
-        }
-    }
-    if (since > 0 || first) flush();
-}
-
-// =================================================================================================
-// polarization, v5: tau-parallel waves over one LDS-staged (I, J) tile
-// =================================================================================================
-// Work-group = 4 waves; wave w owns tau points t0 + w TW + j (j < TW) of the work-group's tau group
-// and the whole (16 WI) x (16 WJ) output tile for them.  Per K-step of 16 complex elements the
-// work-group stages once, in a double-buffered LDS area and in the MFMA lane layout:
-//   A: the bf16 hi/lo split of the I rows (shared by every wave and tau), and
-//   B: the raw FP32 J rows, which each wave scales by its own g(tau) and splits in registers.
-// The next step's global loads are issued before the current step's MFMAs, so the load latency
-// overlaps the arithmetic; global traffic per MFMA is 4 TW times lower than with one wave per tile.
-template <int WI, int WJ, int TW>
-__global__ __launch_bounds__(256) void k_pol5(Dev d, int q0, const float2* __restrict__ M,
-                                              const double* __restrict__ G,
-                                              double2* __restrict__ P, Order od, int ntJ) {
-    constexpr int NW = 4, TG = NW * TW;
-    constexpr int AP = (WI + NW - 1) / NW, BP = (WJ + NW - 1) / NW;  // tiles staged per wave
-    __shared__ float Ga[NB_LDS * TG];
-    __shared__ float Gb[NB_LDS * TG];
-    __shared__ u32x4 Ah[2][WI][64], Al[2][WI][64];
-    __shared__ float4 Braw[2][WJ][2][64];
-    int qrel, r, c;
-    if (!work_item(od, qrel, r, c)) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r16 = lane & 15, g4 = lane >> 4;
-    const int q = q0 + qrel;
-    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
-    const int NI = d.ni[q];
-    const int tg = c, ti = r / ntJ, tj = r - ti * ntJ;  // tau groups of one tile run together
-    const int i0 = ti * 16 * WI, j0 = tj * 16 * WJ, t0 = tg * TG;
-    if (i0 >= NI || j0 >= NI || j0 + 16 * WJ <= i0) return;  // uniform over the work-group
-
-    floatx4 acc[WI][WJ][TW][2];
-#pragma unroll
-    for (int a = 0; a < WI; ++a)
-#pragma unroll
-        for (int b = 0; b < WJ; ++b)
-#pragma unroll
-            for (int t = 0; t < TW; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
-
-    const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
-    double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
-    const double sc = d.scale;
-    bool first = true;
-    int since = 0;
-    auto flush = [&]() {
-#pragma unroll
-        for (int t = 0; t < TW; ++t) {
-            const int it = t0 + wave * TW + t;
-#pragma unroll
-            for (int a = 0; a < WI; ++a)
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const int I = i0 + 16 * a + 4 * g4 + rr, J = j0 + 16 * b + r16;
-                        if (it < ntau && I < NI && J < NI) {
-                            double2* p = &Pq[int64_t(it) * NI * NI + int64_t(I) * NI + J];
-                            double re = sc * double(acc[a][b][t][0][rr]);
-                            double im = sc * double(acc[a][b][t][1][rr]);
-                            if (!first) {
-                                double2 o = *p;
-                                re += o.x;
-                                im += o.y;
-                            }
-                            *p = make_double2(re, im);
-                        }
-                    }
-                    acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
-                }
-        }
-        first = false;
-        since = 0;
-    };
-
-    for (int k = 0; k < nk; ++k) {
-        const int kq = d.kmq[q * nk + k];
-        const int nn = d.nb[k], nm = d.nb[kq];
-        const int Kk = nn * nm;
-        const float2* A = Mq + d.moff[q * nk + k];
-        const bool vec = (Kk & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 31) == 0;
-        __syncthreads();  // the previous k's last step has finished reading LDS
-        for (int e = threadIdx.x; e < nn * TG; e += 256) {
-            const int n = e / TG, t = e - n * TG;
-            Ga[e] = float(G[(int64_t(k) * nbmax + n) * ntau + min(t0 + t, ntau - 1)]);
-        }
-        for (int e = threadIdx.x; e < nm * TG; e += 256) {
-            const int m = e / TG, t = e - m * TG;
-            Gb[e] = float(G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - min(t0 + t, ntau - 1))]);
-        }
-        const int nsteps = (Kk + 15) / 16;
-        // raw values of row `row` (4 complex) this lane stages for step s; zero outside
-        auto load4 = [&](int row, bool ok, int s, float4& u, float4& v) {
-            const int kb = s * 16 + 4 * g4;
-            if (vec && s * 16 + 16 <= Kk && ok) {
-                const float4* p = reinterpret_cast<const float4*>(A + int64_t(row) * Kk + kb);
-                u = p[0];
-                v = p[1];
-            } else {
-                float2 x[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    x[e] = (ok && kb + e < Kk) ? A[int64_t(row) * Kk + kb + e] : make_float2(0.f, 0.f);
-                u = make_float4(x[0].x, x[0].y, x[1].x, x[1].y);
-                v = make_float4(x[2].x, x[2].y, x[3].x, x[3].y);
-            }
-        };
-        float4 ra[AP][2], rb[BP][2];  // raw staging registers (this wave's share of step s)
-        auto fetch = [&](int s) {
-#pragma unroll
-            for (int p = 0; p < AP; ++p) {
-                const int a = wave + NW * p;
-                const int I = i0 + 16 * a + r16;
-                if (a < WI) load4(min(I, NI - 1), I < NI, s, ra[p][0], ra[p][1]);
-            }
-#pragma unroll
-            for (int p = 0; p < BP; ++p) {
-                const int b = wave + NW * p;
-                const int J = j0 + 16 * b + r16;
-                if (b < WJ) load4(min(J, NI - 1), J < NI, s, rb[p][0], rb[p][1]);
-            }
-        };
-        auto stage = [&](int buf) {
-#pragma unroll
-            for (int p = 0; p < AP; ++p) {
-                const int a = wave + NW * p;
-                if (a < WI) {
-                    const float4 u = ra[p][0], v = ra[p][1];
-                    uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
-                    split2(u.x, u.y, h0, l0);
-                    split2(u.z, u.w, h1, l1);
-                    split2(v.x, v.y, h2, l2);
-                    split2(v.z, v.w, h3, l3);
-                    Ah[buf][a][lane] = u32x4{h0, h1, h2, h3};
-                    Al[buf][a][lane] = u32x4{l0, l1, l2, l3};
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < BP; ++p) {
-                const int b = wave + NW * p;
-                if (b < WJ) {
-                    Braw[buf][b][0][lane] = rb[p][0];
-                    Braw[buf][b][1][lane] = rb[p][1];
-                }
-            }
-        };
-        fetch(0);
-        stage(0);
-        __syncthreads();
-        for (int s = 0; s < nsteps; ++s) {
-            const int buf = s & 1;
-            if (s + 1 < nsteps) fetch(s + 1);
-            // g indices of this lane's 4 K values in step s
-            int gi[4], gj[4];
-            {
-                const int K0 = s * 16 + 4 * g4;
-                int nx = K0 / nm, mm = K0 - nx * nm;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    gi[e] = min(nx, nn - 1) * TG + wave * TW;
-                    gj[e] = min(mm, nm - 1) * TG + wave * TW;
-                    if (++mm == nm) {
-                        mm = 0;
-                        ++nx;
-                    }
-                }
-            }
-            // Re(x conj y) = [xr, xi].[yr, yi] and Im(x conj y) = [xr, xi].[-yi, yr]: the rotation
-            // is applied to the per-tau B fragment, so A needs only its hi/lo parts in registers
-            u32x4 xh[WI], xl[WI];
-#pragma unroll
-            for (int a = 0; a < WI; ++a) {
-                xh[a] = Ah[buf][a][lane];
-                xl[a] = Al[buf][a][lane];
-            }
-#pragma unroll
-            for (int b = 0; b < WJ; ++b) {
-                const float4 u = Braw[buf][b][0][lane], v = Braw[buf][b][1][lane];
-                const float yr[4] = {u.x, u.z, v.x, v.z}, yi[4] = {u.y, u.w, v.y, v.w};
-#pragma unroll
-                for (int t = 0; t < TW; ++t) {
-                    u32x4 yh, yl, yh2, yl2;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const float g = Ga[gi[e] + t] * Gb[gj[e] + t];
-                        uint32_t h, l;
-                        split2(g * yr[e], g * yi[e], h, l);
-                        yh[e] = h;
-                        yl[e] = l;
-                        yh2[e] = rot_pos(h);
-                        yl2[e] = rot_pos(l);
-                    }
-#pragma unroll
-                    for (int a = 0; a < WI; ++a) {
-                        acc[a][b][t][0] = mfma_bf16(xh[a], yh, acc[a][b][t][0]);
-                        acc[a][b][t][1] = mfma_bf16(xh[a], yh2, acc[a][b][t][1]);
-                    }
-#pragma unroll
-                    for (int a = 0; a < WI; ++a) {
-                        acc[a][b][t][0] = mfma_bf16(xh[a], yl, acc[a][b][t][0]);
-                        acc[a][b][t][1] = mfma_bf16(xh[a], yl2, acc[a][b][t][1]);
-                    }
-#pragma unroll
-                    for (int a = 0; a < WI; ++a) {
-                        acc[a][b][t][0] = mfma_bf16(xl[a], yh, acc[a][b][t][0]);
-                        acc[a][b][t][1] = mfma_bf16(xl[a], yh2, acc[a][b][t][1]);
-                    }
-                }
-            }
-            if (s + 1 < nsteps) stage(buf ^ 1);
-            if (++since == FLUSH_STEPS) flush();
-            __syncthreads();
-        }
-    }
-    if (since > 0 || first) flush();
-}
-
-// =================================================================================================
-// v6: 32x32x16 MFMA tiles (polarization and split-M self-energy)
+// 32x32x16 MFMA helpers
 // =================================================================================================
 // v_mfma_f32_32x32x16_bf16 sustains close to the BF16 peak on gfx950 where the 16x16x32 shape
 // reaches about half of it, so these kernels use 32 x 32 output tiles and a K-step of 8 complex
@@ -1303,400 +887,6 @@ __device__ __forceinline__ void zero16(floatx16& x) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) x[i] = 0.f;
 }
-constexpr int FLUSH_STEPS8 = 512;  // K-steps of 8 complex between FP64 flushes (4096 terms)
-
-// Polarization.  Work-group = 4 waves in a 2 x 2 grid over a (64 WI) x (64 WJ) (I, J) tile and
-// T tau points; each wave owns (32 WI) x (32 WJ) x T and loads its rows directly (rows shared by
-// two waves of the work-group are served by the CU's L1).
-template <int WI, int WJ, int T, bool PF>
-__global__ __launch_bounds__(256) void k_pol6(Dev d, int q0, const float2* __restrict__ M,
-                                              const double* __restrict__ G,
-                                              double2* __restrict__ P, Order od, int ntJ) {
-    __shared__ float Ga[NB_LDS * T];
-    __shared__ float Gb[NB_LDS * T];
-    int qrel, r, c;
-    if (!work_item(od, qrel, r, c)) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r32 = lane & 31, h2 = lane >> 5;
-    const int q = q0 + qrel;
-    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
-    const int NI = d.ni[q];
-    const int tg = c, ti = r / ntJ, tj = r - ti * ntJ;  // tau groups of one tile run together
-    const int ib = ti * 64 * WI, jbb = tj * 64 * WJ;
-    const int i0 = ib + (wave & 1) * 32 * WI, j0 = jbb + (wave >> 1) * 32 * WJ, t0 = tg * T;
-    if (ib >= NI || jbb >= NI || jbb + 64 * WJ <= ib) return;  // uniform over the work-group
-    const bool active = i0 < NI && j0 < NI;
-
-    floatx16 acc[WI][WJ][T][2];
-#pragma unroll
-    for (int a = 0; a < WI; ++a)
-#pragma unroll
-        for (int b = 0; b < WJ; ++b)
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                zero16(acc[a][b][t][0]);
-                zero16(acc[a][b][t][1]);
-            }
-    const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
-    double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
-    const double sc = d.scale;
-    bool first = true;
-    int since = 0;
-    auto flush = [&]() {
-        // an opaque zero keeps the compiler from hoisting the 16 T WI WJ output addresses out of
-        // the k loop, where they would stay live across the whole contraction
-        int z = 0;
-        asm volatile("" : "+v"(z));
-        double2* Pz = Pq + z;
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const int it = t0 + t;
-#pragma unroll
-            for (int a = 0; a < WI; ++a)
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-                    const int J = j0 + 32 * b + r32 + z;
-#pragma unroll
-                    for (int x = 0; x < 16; ++x) {
-                        const int I = i0 + 32 * a + 8 * (x >> 2) + 4 * h2 + (x & 3) + z;
-                        if (it < ntau && I < NI && J < NI) {
-                            double2* p = &Pz[(int64_t(it) * NI + I) * NI + J];
-                            double re = sc * double(acc[a][b][t][0][x]);
-                            double im = sc * double(acc[a][b][t][1][x]);
-                            if (!first) {
-                                double2 o = *p;
-                                re += o.x;
-                                im += o.y;
-                            }
-                            *p = make_double2(re, im);
-                        }
-                    }
-                    zero16(acc[a][b][t][0]);
-                    zero16(acc[a][b][t][1]);
-                }
-        }
-        first = false;
-        since = 0;
-    };
-
-    int rowI[WI], rowJ[WJ];
-    float keepI[WI], keepJ[WJ];
-#pragma unroll
-    for (int a = 0; a < WI; ++a) {
-        const int I = i0 + 32 * a + r32;
-        rowI[a] = min(I, NI - 1);
-        keepI[a] = I < NI ? 1.f : 0.f;
-    }
-#pragma unroll
-    for (int b = 0; b < WJ; ++b) {
-        const int J = j0 + 32 * b + r32;
-        rowJ[b] = min(J, NI - 1);
-        keepJ[b] = J < NI ? 1.f : 0.f;
-    }
-
-    for (int k = 0; k < nk; ++k) {
-        const int kq = d.kmq[q * nk + k];
-        const int nn = d.nb[k], nm = d.nb[kq];
-        const int Kk = nn * nm;
-        const float2* A = Mq + d.moff[q * nk + k];
-        const bool vec = (Kk & 3) == 0 && (reinterpret_cast<uintptr_t>(A) & 31) == 0;
-        __syncthreads();
-        for (int e = threadIdx.x; e < nn * T; e += 256) {
-            const int n = e / T, t = e - n * T;
-            Ga[e] = float(G[(int64_t(k) * nbmax + n) * ntau + min(t0 + t, ntau - 1)]);
-        }
-        for (int e = threadIdx.x; e < nm * T; e += 256) {
-            const int m = e / T, t = e - m * T;
-            Gb[e] = float(G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - min(t0 + t, ntau - 1))]);
-        }
-        __syncthreads();
-        if (!active) continue;
-        const int nsteps = (Kk + 7) / 8;
-        auto load4 = [&](int row, float keepv, int s, float2 v[4]) {
-            const int kb = s * 8 + 4 * h2;
-            if (vec && s * 8 + 8 <= Kk) {
-                const float4* p = reinterpret_cast<const float4*>(A + int64_t(row) * Kk + kb);
-                const float4 u = p[0], w = p[1];
-                v[0] = make_float2(keepv * u.x, keepv * u.y);
-                v[1] = make_float2(keepv * u.z, keepv * u.w);
-                v[2] = make_float2(keepv * w.x, keepv * w.y);
-                v[3] = make_float2(keepv * w.z, keepv * w.w);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    v[e] = (kb + e < Kk && keepv != 0.f) ? A[int64_t(row) * Kk + kb + e]
-                                                        : make_float2(0.f, 0.f);
-            }
-        };
-        auto load_raw = [&](int s, float2 (&xa)[WI][4], float2 (&yb)[WJ][4]) {
-#pragma unroll
-            for (int a = 0; a < WI; ++a) load4(rowI[a], keepI[a], s, xa[a]);
-#pragma unroll
-            for (int b = 0; b < WJ; ++b) load4(rowJ[b], keepJ[b], s, yb[b]);
-        };
-        int K0 = 4 * h2;
-        int n0 = K0 / nm, m0 = K0 - n0 * nm;  // (n, m) of this lane's first element
-        float2 xa[WI][4], yb[WJ][4];
-        if (PF) load_raw(0, xa, yb);
-        for (int s = 0; s < nsteps; ++s) {
-            float2 xn[WI][4], yn[WJ][4];
-            if (PF) {
-                if (s + 1 < nsteps) load_raw(s + 1, xn, yn);
-            } else {
-                load_raw(s, xa, yb);
-            }
-            int gi[4], gj[4];
-            {
-                int nx = n0, mm = m0;
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    gi[e] = min(nx, nn - 1) * T;
-                    gj[e] = mm * T;
-                    if (++mm == nm) {
-                        mm = 0;
-                        ++nx;
-                    }
-                }
-            }
-            u32x4 xh[WI], xl[WI];
-#pragma unroll
-            for (int a = 0; a < WI; ++a)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    uint32_t h, l;
-                    split2(xa[a][e].x, xa[a][e].y, h, l);
-                    xh[a][e] = h;
-                    xl[a][e] = l;
-                }
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                float g[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) g[e] = Ga[gi[e] + t] * Gb[gj[e] + t];
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-                    u32x4 yh, yl, yh2, yl2;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        uint32_t h, l;
-                        split2(g[e] * yb[b][e].x, g[e] * yb[b][e].y, h, l);
-                        yh[e] = h;
-                        yl[e] = l;
-                        yh2[e] = rot_pos(h);
-                        yl2[e] = rot_pos(l);
-                    }
-#pragma unroll
-                    for (int a = 0; a < WI; ++a) {
-                        acc[a][b][t][0] = mfma32(xh[a], yh, acc[a][b][t][0]);
-                        acc[a][b][t][1] = mfma32(xh[a], yh2, acc[a][b][t][1]);
-                    }
-#pragma unroll
-                    for (int a = 0; a < WI; ++a) {
-                        acc[a][b][t][0] = mfma32(xh[a], yl, acc[a][b][t][0]);
-                        acc[a][b][t][1] = mfma32(xh[a], yl2, acc[a][b][t][1]);
-                    }
-#pragma unroll
-                    for (int a = 0; a < WI; ++a) {
-                        acc[a][b][t][0] = mfma32(xl[a], yh, acc[a][b][t][0]);
-                        acc[a][b][t][1] = mfma32(xl[a], yh2, acc[a][b][t][1]);
-                    }
-                }
-            }
-            if (PF) {
-#pragma unroll
-                for (int a = 0; a < WI; ++a)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) xa[a][e] = xn[a][e];
-#pragma unroll
-                for (int b = 0; b < WJ; ++b)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) yb[b][e] = yn[b][e];
-            }
-            m0 += 8;
-            while (m0 >= nm) {
-                m0 -= nm;
-                ++n0;
-            }
-            if (++since == FLUSH_STEPS8) flush();
-        }
-    }
-    if (active && (since > 0 || first)) flush();
-}
-
-// Self-energy on split-M planes.  Work-group = 4 waves over adjacent column strips (32 WJ columns
-// each) sharing the same W~ rows (32 WI) and T tau points.
-template <int WI, int WJ, int T, bool PF>
-__global__ __launch_bounds__(256) void k_sig6(Dev d, int q0, const float2* __restrict__ M,
-                                              const double* __restrict__ G,
-                                              const char* __restrict__ wsc, int64_t plane,
-                                              const uint32_t* __restrict__ mt, int64_t mtplane,
-                                              double* __restrict__ Sig, Order od, int ntI, int ntC) {
-    int qrel, r, c;
-    if (!work_item(od, qrel, r, c)) return;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r32 = lane & 31, h2 = lane >> 5;
-    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
-    const int q = q0 + qrel;
-    const int tg = r / ntI, ti = r - tg * ntI;
-    const int k = c / ntC, tc = c - k * ntC;
-    const int kq = d.kmq[q * nk + k];
-    const int nm = d.nb[kq], NI = d.ni[q];
-    const int Kk = d.nb[k] * nm;
-    const int i0 = ti * 32 * WI, c0 = tc * 4 * 32 * WJ + wave * 32 * WJ, t0 = tg * T;
-    if (i0 >= NI || c0 >= Kk) return;  // no barriers below: waves may leave independently
-    const int NIp = (NI + PAD - 1) / PAD * PAD, NIp16 = (NI + 15) / 16 * 16;
-    int64_t wq = 0;
-    for (int qq = q0; qq < q; ++qq) {
-        const int np = (d.ni[qq] + PAD - 1) / PAD * PAD;
-        wq += int64_t(ntau) * np * np;
-    }
-    const uint32_t* whi = reinterpret_cast<const uint32_t*>(wsc) + wq;
-    const uint32_t* wlo = reinterpret_cast<const uint32_t*>(wsc) + plane + wq;
-    const int64_t mb0 = mt_qbase(d, q0, q) + d.moff[q * nk + k] / NI * NIp16;
-    const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
-
-    int colr[WJ];
-    uint32_t keep[WJ];
-#pragma unroll
-    for (int b = 0; b < WJ; ++b) {
-        const int col = c0 + 32 * b + r32;
-        colr[b] = min(col, Kk - 1);
-        keep[b] = col < Kk ? 0xffffffffu : 0u;
-    }
-    floatx16 acc[WI][WJ][T][2];
-#pragma unroll
-    for (int a = 0; a < WI; ++a)
-#pragma unroll
-        for (int b = 0; b < WJ; ++b)
-#pragma unroll
-            for (int t = 0; t < T; ++t) {
-                zero16(acc[a][b][t][0]);
-                zero16(acc[a][b][t][1]);
-            }
-    int tau_[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) tau_[t] = min(t0 + t, ntau - 1);
-
-    const int nsteps = NIp16 / 8;
-    auto load_raw = [&](int s, u32x4 (&bh)[WJ], u32x4 (&bl)[WJ], u32x4 (&wh)[WI][T], u32x4 (&wl)[WI][T]) {
-        const int jb = s * 8 + 4 * h2;
-#pragma unroll
-        for (int b = 0; b < WJ; ++b) {
-            const int64_t at = mb0 + int64_t(colr[b]) * NIp16 + jb;
-            bh[b] = *reinterpret_cast<const u32x4*>(mt + at);
-            bl[b] = *reinterpret_cast<const u32x4*>(mt + mtplane + at);
-        }
-#pragma unroll
-        for (int t = 0; t < T; ++t)
-#pragma unroll
-            for (int a = 0; a < WI; ++a) {
-                const int64_t at = (int64_t(tau_[t]) * NIp + i0 + 32 * a + r32) * NIp + jb;
-                wh[a][t] = *reinterpret_cast<const u32x4*>(whi + at);
-                wl[a][t] = *reinterpret_cast<const u32x4*>(wlo + at);
-            }
-    };
-    u32x4 rbh[WJ], rbl[WJ], rwh[WI][T], rwl[WI][T];
-    if (PF) load_raw(i0 / 8, rbh, rbl, rwh, rwl);
-    for (int s = i0 / 8; s < nsteps; ++s) {
-        u32x4 nbh[WJ], nbl[WJ], nwh[WI][T], nwl[WI][T];
-        if (PF) {
-            if (s + 1 < nsteps) load_raw(s + 1, nbh, nbl, nwh, nwl);
-        } else {
-            load_raw(s, rbh, rbl, rwh, rwl);
-        }
-        u32x4 bh_re[WJ], bl_re[WJ], bh_im[WJ], bl_im[WJ];
-#pragma unroll
-        for (int b = 0; b < WJ; ++b)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t he = rbh[b][e] & keep[b], le = rbl[b][e] & keep[b];
-                bh_re[b][e] = conj_pk(he);
-                bl_re[b][e] = conj_pk(le);
-                bh_im[b][e] = swap_pk(he);
-                bl_im[b][e] = swap_pk(le);
-            }
-#pragma unroll
-        for (int t = 0; t < T; ++t)
-#pragma unroll
-            for (int a = 0; a < WI; ++a) {
-                const u32x4 ah = rwh[a][t], al = rwl[a][t];
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-                    acc[a][b][t][0] = mfma32(ah, bh_re[b], acc[a][b][t][0]);
-                    acc[a][b][t][1] = mfma32(ah, bh_im[b], acc[a][b][t][1]);
-                }
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-                    acc[a][b][t][0] = mfma32(ah, bl_re[b], acc[a][b][t][0]);
-                    acc[a][b][t][1] = mfma32(ah, bl_im[b], acc[a][b][t][1]);
-                }
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-                    acc[a][b][t][0] = mfma32(al, bh_re[b], acc[a][b][t][0]);
-                    acc[a][b][t][1] = mfma32(al, bh_im[b], acc[a][b][t][1]);
-                }
-            }
-        if (PF) {
-#pragma unroll
-            for (int b = 0; b < WJ; ++b) {
-                rbh[b] = nbh[b];
-                rbl[b] = nbl[b];
-            }
-#pragma unroll
-            for (int a = 0; a < WI; ++a)
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    rwh[a][t] = nwh[a][t];
-                    rwl[a][t] = nwl[a][t];
-                }
-        }
-    }
-
-    // epilogue: Re(conj(M) Y) over this tile's rows, weighted by G_m, summed per band n
-    const double sc = 2.0 * d.scale;  // both triangles of U
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int it = t0 + t;
-        if (it >= ntau) break;
-        double part[WJ];
-#pragma unroll
-        for (int b = 0; b < WJ; ++b) {
-            const int col = c0 + 32 * b + r32;
-            float s = 0.f;
-            if (col < Kk) {
-#pragma unroll
-                for (int a = 0; a < WI; ++a)
-#pragma unroll
-                    for (int x = 0; x < 16; ++x) {
-                        const int I = i0 + 32 * a + 8 * (x >> 2) + 4 * h2 + (x & 3);
-                        if (I < NI) {
-                            const float2 m = A[int64_t(I) * Kk + col];
-                            s += m.x * acc[a][b][t][0][x] + m.y * acc[a][b][t][1][x];
-                        }
-                    }
-            }
-            double v = s;
-            v += __shfl_xor(v, 32);
-            if (col < Kk) {
-                const int m = col - (col / nm) * nm;
-                v *= G[(int64_t(kq) * nbmax + m) * ntau + it];
-            }
-            part[b] = v;
-        }
-        const int cl = min(c0 + 32 * WJ, Kk) - 1;
-        const int nlo = c0 / nm, nhi = cl / nm;
-        for (int nx = nlo; nx <= nhi; ++nx) {
-            double v = 0.0;
-#pragma unroll
-            for (int b = 0; b < WJ; ++b) {
-                const int col = c0 + 32 * b + r32;
-                if (col < Kk && col / nm == nx) v += part[b];
-            }
-#pragma unroll
-            for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            if (lane == 0) atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], sc * v);
-        }
-    }
-}
-
 // =================================================================================================
 // v7 self-energy: LDS double-buffered 32x32x16 contraction
 // =================================================================================================
@@ -1709,8 +899,8 @@ __global__ __launch_bounds__(256) void k_sig6(Dev d, int q0, const float2* __res
 constexpr int S7_KS = 16;         // J per stage
 constexpr int S7_RS = S7_KS + 4;  // LDS row stride in u32 (80 B: conflict-free 16-B reads)
 
-template <int T>
-__global__ __launch_bounds__(256) void k_sig7(Dev d, int q0, const float2* __restrict__ M,
+template <int T, int OCC = 1>
+__global__ __launch_bounds__(256, OCC) void k_sig7(Dev d, int q0, const float2* __restrict__ M,
                                               const double* __restrict__ G,
                                               const char* __restrict__ wsc, int64_t plane,
                                               const uint32_t* __restrict__ mt, int64_t mtplane,
@@ -1840,14 +1030,24 @@ __global__ __launch_bounds__(256) void k_sig7(Dev d, int q0, const float2* __res
     for (int s = 0; s < ns; ++s) {
         const int buf = s & 1;
         if (s + 1 < ns) gload(i0 + (s + 1) * S7_KS);
-        u32x4 fa0[T][2], fb0[2][2], fa1[T][2], fb1[2][2];
-        lread(buf, 0, fa0, fb0);
-        lread(buf, 1, fa1, fb1);  // in flight while step 0 multiplies
-        // keep the compiler from sinking the step-1 reads next to their use
-        __builtin_amdgcn_sched_barrier(0);
-        compute(fa0, fb0);
-        __builtin_amdgcn_sched_barrier(0);
-        compute(fa1, fb1);
+        if constexpr (OCC == 1) {
+            u32x4 fa0[T][2], fb0[2][2], fa1[T][2], fb1[2][2];
+            lread(buf, 0, fa0, fb0);
+            lread(buf, 1, fa1, fb1);  // in flight while step 0 multiplies
+            // keep the compiler from sinking the step-1 reads next to their use
+            __builtin_amdgcn_sched_barrier(0);
+            compute(fa0, fb0);
+            __builtin_amdgcn_sched_barrier(0);
+            compute(fa1, fb1);
+        } else {
+            // two work-groups per CU cover each other's LDS and barrier latency
+#pragma unroll
+            for (int kk = 0; kk < S7_KS / 8; ++kk) {
+                u32x4 fa[T][2], fb[2][2];
+                lread(buf, kk, fa, fb);
+                compute(fa, fb);
+            }
+        }
         if (s + 1 < ns) lstore(buf ^ 1);
         __syncthreads();
     }
@@ -1909,9 +1109,9 @@ void run_pol(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const v
     int maxi = 0;
     for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
     const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
-    const Order od = make_order(ntI * ntJ, ntG, nq, 0);
+    const Order od = make_order(ntG * ntI, ntJ, nq);
     hipLaunchKernelGGL((k_pol<WI, WJ, T, PREC, PF>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntJ);
+                       (const float2*)M, G, (double2*)P, od, ntI);
     MSGW_HIP(hipGetLastError());
 }
 
@@ -1951,35 +1151,10 @@ void run_sig3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     MSGW_HIP(hipGetLastError());
 }
 
-template <int WI, int WJ, int T>
-void run_pol3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-              const double* G, void* P) {
-    int maxi = 0;
-    for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
-    const int ntI = ceil_div(maxi, 4 * 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
-    const Order od = make_order(ntI * ntJ, ntG, nq, 0);
-    hipLaunchKernelGGL((k_pol3<WI, WJ, T>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntJ);
-    MSGW_HIP(hipGetLastError());
-}
-
-template <int WI, int WJ, int TW>
-void run_pol5(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-              const double* G, void* P) {
-    int maxi = 0;
-    for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
-    const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ);
-    const int ntG = ceil_div(h.ntau, 4 * TW);
-    const Order od = make_order(ntI * ntJ, ntG, nq, 0);
-    hipLaunchKernelGGL((k_pol5<WI, WJ, TW>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntJ);
-    MSGW_HIP(hipGetLastError());
-}
-
 using Sig3Fn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
                         const char*, int64_t, const uint32_t*, int64_t, void*);
 
-template <int T, int SR = 4, int SC = 8>
+template <int T, int SR = 4, int SC = 8, int OCC = 1>
 void run_sig7(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
               void* Sig) {
@@ -1992,38 +1167,8 @@ void run_sig7(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     static_assert(64 <= PAD, "row tiles must fit in the padded W~ planes");
     const int ntI = ceil_div(maxi, 64), ntC = ceil_div(maxc, 128), ntG = ceil_div(h.ntau, T);
     const Order od = make_order_st(ntG * ntI, h.nk * ntC, nq, SR, SC);
-    hipLaunchKernelGGL((k_sig7<T>), dim3(grid_of(od)), dim3(256), 0, s, d, q0, (const float2*)M, G,
+    hipLaunchKernelGGL((k_sig7<T, OCC>), dim3(grid_of(od)), dim3(256), 0, s, d, q0, (const float2*)M, G,
                        wsc, plane, mt, mtplane, (double*)Sig, od, ntI, ntC);
-    MSGW_HIP(hipGetLastError());
-}
-
-template <int WI, int WJ, int T, bool PF = false>
-void run_pol6(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-              const double* G, void* P) {
-    int maxi = 0;
-    for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
-    const int ntI = ceil_div(maxi, 64 * WI), ntJ = ceil_div(maxi, 64 * WJ), ntG = ceil_div(h.ntau, T);
-    const Order od = make_order(ntI * ntJ, ntG, nq, 0);
-    hipLaunchKernelGGL((k_pol6<WI, WJ, T, PF>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntJ);
-    MSGW_HIP(hipGetLastError());
-}
-
-template <int WI, int WJ, int T, bool PF = false>
-void run_sig6(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-              const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
-              void* Sig) {
-    int maxi = 0, maxc = 0;
-    for (int q = q0; q < q0 + nq; ++q) {
-        maxi = std::max(maxi, h.ni[q]);
-        for (int k = 0; k < h.nk; ++k)
-            maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
-    }
-    static_assert(32 * WI <= PAD, "row tiles must fit in the padded W~ planes");
-    const int ntI = ceil_div(maxi, 32 * WI), ntC = ceil_div(maxc, 4 * 32 * WJ), ntG = ceil_div(h.ntau, T);
-    const Order od = make_order(ntG * ntI, h.nk * ntC, nq, 32);
-    hipLaunchKernelGGL((k_sig6<WI, WJ, T, PF>), dim3(grid_of(od)), dim3(256), 0, s, d, q0,
-                       (const float2*)M, G, wsc, plane, mt, mtplane, (double*)Sig, od, ntI, ntC);
     MSGW_HIP(hipGetLastError());
 }
 
@@ -2037,68 +1182,32 @@ struct SigVariant {
     Sig3Fn fn3;   // W~ planes + split transposed M
 };
 
+// index 0 of each table is the default (the fastest on the 4x4x4-k, 64-band, NI = 400 shapes)
 const PolVariant kPolBF16[] = {
+    {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3>},
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_BF16X3>},
     {"WI4 WJ1 T4", run_pol<4, 1, 4, PREC_BF16X3>},
     {"WI4 WJ2 T2", run_pol<4, 2, 2, PREC_BF16X3>},
     {"WI2 WJ4 T2", run_pol<2, 4, 2, PREC_BF16X3>},
-    {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3>},
-    {"4 waves shared-B WI1 WJ4 T4", run_pol3<1, 4, 4>},
-    {"4 waves shared-B WI1 WJ5 T3", run_pol3<1, 5, 3>},
-    {"4 waves shared-B WI2 WJ2 T4", run_pol3<2, 2, 4>},
-    {"4 waves shared-B WI1 WJ2 T8", run_pol3<1, 2, 8>},
-    {"4 waves shared-B WI2 WJ4 T2", run_pol3<2, 4, 2>},
     {"prefetch WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3, true>},
     {"prefetch WI2 WJ2 T4", run_pol<2, 2, 4, PREC_BF16X3, true>},
     {"prefetch WI4 WJ1 T4", run_pol<4, 1, 4, PREC_BF16X3, true>},
-    {"prefetch WI4 WJ1 T2", run_pol<4, 1, 2, PREC_BF16X3, true>},
-    {"prefetch WI4 WJ2 T2", run_pol<4, 2, 2, PREC_BF16X3, true>},
-    {"tau-waves LDS WI5 WJ5 TW1", run_pol5<5, 5, 1>},
-    {"tau-waves LDS WI4 WJ4 TW1", run_pol5<4, 4, 1>},
-    {"tau-waves LDS WI4 WJ4 TW2", run_pol5<4, 4, 2>},
-    {"tau-waves LDS WI5 WJ3 TW1", run_pol5<5, 3, 1>},
-    {"tau-waves LDS WI2 WJ2 TW4", run_pol5<2, 2, 4>},
-    {"32x32 WI1 WJ1 T4", run_pol6<1, 1, 4>},
-    {"32x32 WI1 WJ1 T6", run_pol6<1, 1, 6>},
-    {"32x32 WI1 WJ2 T3", run_pol6<1, 2, 3>},
-    {"32x32 WI2 WJ1 T3", run_pol6<2, 1, 3>},
-    {"32x32 WI1 WJ1 T3", run_pol6<1, 1, 3>},
-    {"32x32 prefetch WI1 WJ1 T4", run_pol6<1, 1, 4, true>},
-    {"32x32 prefetch WI1 WJ2 T3", run_pol6<1, 2, 3, true>},
-    {"32x32 prefetch WI1 WJ1 T6", run_pol6<1, 1, 6, true>},
 };
 const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_FP32>},
 };
 const SigVariant kSigBF16[] = {
-    {"WI2 WJ4 T4", run_sig<2, 4, 4, PREC_BF16X3>, nullptr},
-    {"WI4 WJ2 T4", run_sig<4, 2, 4, PREC_BF16X3>, nullptr},
-    {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_BF16X3>, nullptr},
-    {"WI4 WJ4 T2", run_sig<4, 4, 2, PREC_BF16X3>, nullptr},
-    {"WI2 WJ8 T2", run_sig<2, 8, 2, PREC_BF16X3>, nullptr},
-    {"split-M WI1 WJ8 T2", nullptr, run_sig3<1, 8, 2>},
-    {"split-M WI2 WJ4 T2", nullptr, run_sig3<2, 4, 2>},
-    {"split-M WI4 WJ4 T2", nullptr, run_sig3<4, 4, 2>},
-    {"split-M WI2 WJ4 T4", nullptr, run_sig3<2, 4, 4>},
-    {"split-M WI4 WJ2 T4", nullptr, run_sig3<4, 2, 4>},
-    {"split-M prefetch WI2 WJ4 T2", nullptr, run_sig3<2, 4, 2, true>},
-    {"split-M prefetch WI1 WJ8 T2", nullptr, run_sig3<1, 8, 2, true>},
-    {"split-M prefetch WI2 WJ2 T4", nullptr, run_sig3<2, 2, 4, true>},
-    {"split-M prefetch WI4 WJ2 T2", nullptr, run_sig3<4, 2, 2, true>},
-    {"split-M prefetch WI2 WJ2 T2", nullptr, run_sig3<2, 2, 2, true>},
-    {"32x32 split-M WI1 WJ1 T4", nullptr, run_sig6<1, 1, 4>},
-    {"32x32 split-M WI1 WJ1 T6", nullptr, run_sig6<1, 1, 6>},
-    {"32x32 split-M WI1 WJ2 T3", nullptr, run_sig6<1, 2, 3>},
-    {"32x32 split-M WI2 WJ1 T3", nullptr, run_sig6<2, 1, 3>},
-    {"32x32 split-M WI1 WJ2 T4", nullptr, run_sig6<1, 2, 4>},
-    {"32x32 split-M WI2 WJ2 T2", nullptr, run_sig6<2, 2, 2>},
-    {"32x32 split-M prefetch WI1 WJ2 T3", nullptr, run_sig6<1, 2, 3, true>},
-    {"32x32 split-M prefetch WI1 WJ1 T6", nullptr, run_sig6<1, 1, 6, true>},
+    {"LDS 2-stage 64x128 T2 2 WG/CU st8x8", nullptr, run_sig7<2, 8, 8, 2>},
+    {"LDS 2-stage 64x128 T2 2 WG/CU st4x16", nullptr, run_sig7<2, 4, 16, 2>},
     {"LDS 2-stage 64x128 T4", nullptr, run_sig7<4>},
     {"LDS 2-stage 64x128 T3", nullptr, run_sig7<3>},
-    {"LDS 2-stage 64x128 T4 st2x16", nullptr, run_sig7<4, 2, 16>},
     {"LDS 2-stage 64x128 T4 st8x4", nullptr, run_sig7<4, 8, 4>},
+    {"WI2 WJ4 T4", run_sig<2, 4, 4, PREC_BF16X3>, nullptr},
+    {"WI4 WJ4 T2", run_sig<4, 4, 2, PREC_BF16X3>, nullptr},
+    {"WI2 WJ8 T2", run_sig<2, 8, 2, PREC_BF16X3>, nullptr},
+    {"split-M WI2 WJ4 T2", nullptr, run_sig3<2, 4, 2>},
+    {"split-M prefetch WI2 WJ2 T2", nullptr, run_sig3<2, 2, 2, true>},
 };
 const SigVariant kSigFP32[] = {
     {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>, nullptr},
