@@ -17,6 +17,14 @@ def _key(run, op):
                                      run.ntau, run.q_batch))
 
 
+def _launch(op, ctx, run, M, q0, nq, st):
+    if op == L.OP_POLARIZATION:
+        ctx.polarization(q0, nq, M, run.m_dtype, run.G_tau, run.precision, run.P_tau, stream=st)
+    else:
+        ctx.self_energy(q0, nq, M, run.m_dtype, run.G_tau, run.Wt_tau, run.precision, run.sig_tau,
+                        stream=st)
+
+
 def tune(run, M_source, reps=2, cache_path=None, log=None, ops=None):
     """Pick the fastest variant of each MFMA op for `run`; returns {op: (index, name, ms list)}."""
     import torch
@@ -47,18 +55,20 @@ def tune(run, M_source, reps=2, cache_path=None, log=None, ops=None):
         for v in range(len(names)):
             ctx.set_variant(op, run.precision, v)
             ms = []
-            for r in range(reps + 1):
+            try:
+                _launch(op, ctx, run, M, q0, nq, st)
+            except L.MsgwError as e:  # this tile cannot run these shapes
+                times.append(float("inf"))
+                if log:
+                    log(f"[autotune] op={op} variant {v} ({names[v]}): unavailable ({e})")
+                continue
+            for r in range(reps):  # the launch above was the warm-up
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record(st) if st is not None else a.record()
-                if op == L.OP_POLARIZATION:
-                    ctx.polarization(q0, nq, M, run.m_dtype, run.G_tau, run.precision, run.P_tau, stream=st)
-                else:
-                    ctx.self_energy(q0, nq, M, run.m_dtype, run.G_tau, run.Wt_tau, run.precision,
-                                    run.sig_tau, stream=st)
+                _launch(op, ctx, run, M, q0, nq, st)
                 b.record(st) if st is not None else b.record()
                 torch.cuda.synchronize()
-                if r > 0:
-                    ms.append(a.elapsed_time(b))
+                ms.append(a.elapsed_time(b))
             times.append(min(ms))
             if log:
                 log(f"[autotune] op={op} variant {v} ({names[v]}): {min(ms):.2f} ms")

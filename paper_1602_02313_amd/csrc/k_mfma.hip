@@ -1097,6 +1097,296 @@ __global__ __launch_bounds__(256, OCC) void k_sig7(Dev d, int q0, const float2* 
 }
 
 // =================================================================================================
+// pair-space polarization (vZ)
+// =================================================================================================
+// The weight g_K(tau) = G_n(k,tau) G_m(k-q,beta-tau) is real, so with Z_IJ,K = M^I_K conj(M^J_K)
+//     P_IJ(tau) = s sum_k sum_K Z_IJ,K g_K(tau)
+// is a real GEMM per component: rows = pairs (I, J), reduction = K, columns = tau.  Z is formed on
+// the fly from the rows of M (4 FLOP per complex element, shared by every tau), and g is a small
+// table per (q, k) that k_gtab writes once per call as bf16 hi/lo planes [tau][K] -- no operand is
+// rescaled per tau.  Against the complex GEMM this halves the MFMA work (complex x real instead of
+// complex x complex) and the VALU work per MFMA.
+constexpr int GZ_T = 96;   // tau columns per work-group (three 32-wide MFMA tiles)
+constexpr int GZ_KS = 32;  // K per stage (default)
+constexpr int GZ_KPAD = 64;  // the g planes are padded in K to a multiple of the largest stage
+
+// g planes of q0..q0+nq-1: for each (q, k) two bf16 planes [TP][KP], TP = Ntau rounded up to GZ_T,
+// KP = K rounded up to GZ_KPAD
+__device__ __host__ __forceinline__ int gz_tp(int ntau) { return (ntau + GZ_T - 1) / GZ_T * GZ_T; }
+__device__ __forceinline__ int64_t gz_block(const Dev& d, int q0, int q, int k) {
+    int64_t off = 0;
+    for (int qq = q0; qq <= q; ++qq)
+        for (int kk = 0; kk < (qq == q ? k : d.nk); ++kk) {
+            const int K = d.nb[kk] * d.nb[d.kmq[qq * d.nk + kk]];
+            off += int64_t(2) * gz_tp(d.ntau) * ((K + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD);
+        }
+    return off;  // in bf16 elements
+}
+
+// one thread per (tau, K pair): writes hi and lo of g for two consecutive K
+__global__ __launch_bounds__(256) void k_gtab(Dev d, int q0, int q, const double* __restrict__ G,
+                                              uint32_t* __restrict__ gz, int64_t base) {
+    const int k = blockIdx.y, nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int kq = d.kmq[q * nk + k];
+    const int nm = d.nb[kq], Kk = d.nb[k] * nm;
+    const int KP = (Kk + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD;
+    const int64_t off = base + gz_block(d, q0, q, k);  // bf16 elements, even
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    const int npair = KP / 2;
+    const int TP = gz_tp(ntau);
+    if (id >= TP * npair) return;
+    const int t = id / npair, K0 = 2 * (id - t * npair);
+    float g[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int K = K0 + e;
+        g[e] = 0.f;
+        if (t < ntau && K < Kk) {
+            const int n = K / nm, m = K - n * nm;
+            g[e] = float(G[(int64_t(k) * nbmax + n) * ntau + t] *
+                         G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - t)]);
+        }
+    }
+    uint32_t h, l;
+    h = pk_bf16(g[0], g[1]);
+    l = pk_bf16(g[0] - bf_lo(h), g[1] - bf_hi(h));
+    uint32_t* hp = gz + (off >> 1);
+    hp[int64_t(t) * (KP / 2) + K0 / 2] = h;
+    hp[int64_t(TP + t) * (KP / 2) + K0 / 2] = l;
+}
+
+// Work-group = 2 WI waves over a block of 4 WI rows I x 16 rows J (64 WI pairs); wave w owns the 32
+// pairs I = I0 + 4 (w % WI) + p / 8, J = J0 + 8 (w / WI) + p % 8 (p = lane % 32) for all 96 tau
+// columns.  Each stage brings KS K of the block's 4 WI + 16 rows of M and of the g planes through LDS
+// (double buffered); each lane forms Z for its pair and 8 K per MFMA step and splits it into bf16
+// hi/lo.  A larger WI shares every staged g plane among more pairs.
+template <int OCC, int KS, int WI>
+__global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const float2* __restrict__ M,
+                                                        const uint32_t* __restrict__ gz,
+                                                        double2* __restrict__ P, Order od) {
+    constexpr int NT = 128 * WI, XROWS = 4 * WI + 16;
+    static_assert(KS % GZ_KS == 0, "stages hold whole 32-K slabs of the g planes");
+    static_assert((XROWS * KS) % NT == 0 && (2 * GZ_T * KS / 8) % NT == 0, "stage split over threads");
+    constexpr int XR = 2 * KS + 4, GR = KS / 2 + 4, NX = XROWS * KS / NT, NG = 2 * GZ_T * KS / 8 / NT;
+    __shared__ float Xs[2][XROWS][XR];       // [buffer][row: 4 WI rows I then 16 rows J][K re, im]
+    __shared__ uint32_t Gs[2][2][GZ_T][GR];  // [buffer][hi, lo][tau][K pair]
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h2 = lane >> 5;
+    const int q = q0 + qrel, nk = d.nk, ntau = d.ntau;
+    const int NI = d.ni[q];
+    const int ntc = gz_tp(d.ntau) / GZ_T, cj = c / ntc, tc = c - cj * ntc;  // tau chunk tc
+    const int I0 = r * 4 * WI, J0 = cj * 16, TP = ntc * GZ_T;
+    if (I0 >= NI || J0 >= NI || J0 + 16 <= I0) return;  // uniform; below the diagonal: mirrored later
+    const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
+    double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
+    const int64_t gq = gz_block(d, q0, q, 0);
+
+    // staging per thread: NX complex elements of the M rows and NG 16-B chunks of the g planes
+    float2 rx[NX];
+    u32x4 rg[NG];
+    uint32_t okx = 0;  // validity bits of rx, applied when the stage is written to LDS
+    struct Blk {
+        const float2* A;
+        const uint32_t* g;
+        int Kk, KP;
+    };
+    auto block_of = [&](int kx) {
+        Blk b;
+        const int kq = d.kmq[q * nk + kx];
+        b.Kk = d.nb[kx] * d.nb[kq];
+        b.KP = (b.Kk + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD;
+        b.A = Mq + d.moff[q * nk + kx];
+        int64_t off = gq;
+        for (int kk = 0; kk < kx; ++kk) {
+            const int K = d.nb[kk] * d.nb[d.kmq[q * nk + kk]];
+            off += int64_t(2) * gz_tp(d.ntau) * ((K + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD);
+        }
+        b.g = gz + (off >> 1);
+        return b;
+    };
+    auto gload = [&](const Blk& b, int slab) {
+        const int K0 = slab * KS;
+        okx = 0;
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            const int id = tid + NT * i;             // XROWS rows x KS
+            const int row = id / KS, kc = id % KS;
+            const int R = row < 4 * WI ? I0 + row : J0 + row - 4 * WI;
+            const int K = K0 + kc;
+            okx |= (R < NI && K < b.Kk) ? (1u << i) : 0u;
+            rx[i] = b.A[int64_t(min(R, NI - 1)) * b.Kk + min(K, b.Kk - 1)];
+        }
+        constexpr int CH = KS / 8;  // 16-B chunks per g row of a stage
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            const int id = tid + NT * i;             // 2 planes x 96 tau x CH chunks of 4 u32
+            const int pl = id / (GZ_T * CH), rem = id - pl * GZ_T * CH;
+            const int t = rem / CH, ch = rem % CH;
+            rg[i] = *reinterpret_cast<const u32x4*>(b.g + (int64_t(pl * TP + GZ_T * tc + t) * b.KP + K0) / 2 +
+                                                    4 * ch);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            const int id = tid + NT * i;
+            const int row = id / KS, kc = id % KS;
+            *reinterpret_cast<float2*>(&Xs[buf][row][2 * kc]) =
+                (okx >> i) & 1u ? rx[i] : make_float2(0.f, 0.f);
+        }
+        constexpr int CH = KS / 8;
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            const int id = tid + NT * i;
+            const int pl = id / (GZ_T * CH), rem = id - pl * GZ_T * CH;
+            const int t = rem / CH, ch = rem % CH;
+            *reinterpret_cast<u32x4*>(&Gs[buf][pl][t][4 * ch]) = rg[i];
+        }
+    };
+
+    floatx16 acc[3][2];  // [tau tile][re, im]
+#pragma unroll
+    for (int tt = 0; tt < 3; ++tt) {
+        zero16(acc[tt][0]);
+        zero16(acc[tt][1]);
+    }
+    const int ri = 4 * (wave % WI) + (r32 >> 3), rj = 4 * WI + 8 * (wave / WI) + (r32 & 7);
+    // Z = x_I conj(x_J) for this lane's pair and K = 16 kk + 8 h2 + e, e < 8, split into bf16 hi/lo
+    auto zform = [&](int buf, int kk, u32x4 (&z)[4]) {
+        const float* xi = &Xs[buf][ri][2 * (16 * kk + 8 * h2)];
+        const float* xj = &Xs[buf][rj][2 * (16 * kk + 8 * h2)];
+        float zr[8], zi[8];
+#pragma unroll
+        for (int e4 = 0; e4 < 4; ++e4) {
+            const float4 a = *reinterpret_cast<const float4*>(xi + 4 * e4);
+            const float4 b = *reinterpret_cast<const float4*>(xj + 4 * e4);
+            zr[2 * e4] = a.x * b.x + a.y * b.y;
+            zi[2 * e4] = a.y * b.x - a.x * b.y;
+            zr[2 * e4 + 1] = a.z * b.z + a.w * b.w;
+            zi[2 * e4 + 1] = a.w * b.z - a.z * b.w;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            uint32_t h;
+            h = pk_bf16(zr[2 * e], zr[2 * e + 1]);
+            z[0][e] = h;
+            z[1][e] = pk_bf16(zr[2 * e] - bf_lo(h), zr[2 * e + 1] - bf_hi(h));
+            h = pk_bf16(zi[2 * e], zi[2 * e + 1]);
+            z[2][e] = h;
+            z[3][e] = pk_bf16(zi[2 * e] - bf_lo(h), zi[2 * e + 1] - bf_hi(h));
+        }
+    };
+    // the 18 MFMAs of one 16-K step: Z (re hi, re lo, im hi, im lo) against g (hi, lo) of 3 tau tiles
+    auto mmas = [&](int buf, int kk, const u32x4 (&z)[4]) {
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt) {
+            const u32x4* grow = reinterpret_cast<const u32x4*>(&Gs[buf][0][32 * tt + r32][0]);
+            const u32x4* lrow = reinterpret_cast<const u32x4*>(&Gs[buf][1][32 * tt + r32][0]);
+            const u32x4 gh = grow[2 * kk + h2], gl = lrow[2 * kk + h2];
+            acc[tt][0] = mfma32(z[0], gh, acc[tt][0]);
+            acc[tt][1] = mfma32(z[2], gh, acc[tt][1]);
+            acc[tt][0] = mfma32(z[0], gl, acc[tt][0]);
+            acc[tt][1] = mfma32(z[2], gl, acc[tt][1]);
+            acc[tt][0] = mfma32(z[1], gh, acc[tt][0]);
+            acc[tt][1] = mfma32(z[3], gh, acc[tt][1]);
+        }
+    };
+    // software pipeline over the 16-K steps of a stage: the VALU work that forms Z for step kk + 1 is
+    // interleaved with the MFMAs of step kk
+    auto compute_stage = [&](int buf) {
+        u32x4 za[4], zb[4];
+        zform(buf, 0, za);
+#pragma unroll
+        for (int kk = 0; kk < KS / 16; ++kk) {
+            if (kk & 1) {
+                mmas(buf, kk, zb);
+                if (kk + 1 < KS / 16) zform(buf, kk + 1, za);
+            } else {
+                mmas(buf, kk, za);
+                if (kk + 1 < KS / 16) zform(buf, kk + 1, zb);
+            }
+            if (kk + 1 < KS / 16) {
+#pragma unroll
+                for (int i = 0; i < 18; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // then up to six VALU
+                }
+            }
+        }
+    };
+
+    const double sc = d.scale;
+    bool first = true;
+    auto flush = [&]() {
+        int z = 0;  // opaque zero: keeps the output addresses out of the main loop
+        asm volatile("" : "+v"(z));
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt) {
+            const int it = GZ_T * tc + 32 * tt + r32 + z;
+#pragma unroll
+            for (int x = 0; x < 16; ++x) {
+                const int p = 8 * (x >> 2) + 4 * h2 + (x & 3);
+                const int I = I0 + 4 * (wave % WI) + (p >> 3), J = J0 + 8 * (wave / WI) + (p & 7);
+                if (it < ntau && I < NI && J < NI) {
+                    double2* pp = &Pq[(int64_t(it) * NI + I) * NI + J];
+                    double re = sc * double(acc[tt][0][x]);
+                    double im = sc * double(acc[tt][1][x]);
+                    if (!first) {
+                        const double2 o = *pp;
+                        re += o.x;
+                        im += o.y;
+                    }
+                    *pp = make_double2(re, im);
+                }
+            }
+            zero16(acc[tt][0]);
+            zero16(acc[tt][1]);
+        }
+        first = false;
+    };
+
+    // stages run over (k, slab); the FP32 accumulators go to FP64 every 4096 terms
+    int k = 0, slab = 0, since = 0;
+    Blk blk = block_of(0);
+    int nsl = (blk.KP + KS - 1) / KS;
+    while (nsl == 0 && k + 1 < nk) {
+        blk = block_of(++k);
+        nsl = (blk.KP + KS - 1) / KS;
+    }
+    gload(blk, 0);
+    lstore(0);
+    __syncthreads();
+    int buf = 0;
+    while (true) {
+        int k2 = k, s2 = slab + 1, n2 = nsl;
+        Blk b2 = blk;
+        while (s2 >= n2 && k2 + 1 < nk) {
+            ++k2;
+            s2 = 0;
+            b2 = block_of(k2);
+            n2 = (b2.KP + KS - 1) / KS;
+        }
+        const bool more = s2 < n2;
+        if (more) gload(b2, s2);
+        compute_stage(buf);
+        since += KS;
+        if (since >= 4096 || !more) {
+            flush();
+            since = 0;
+        }
+        if (!more) break;
+        lstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+        k = k2;
+        slab = s2;
+        nsl = n2;
+        blk = b2;
+    }
+}
+
+// =================================================================================================
 // variants (tile shapes) and dispatch
 // =================================================================================================
 using PolFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*, void*);
@@ -1154,6 +1444,41 @@ void run_sig3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
 using Sig3Fn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
                         const char*, int64_t, const uint32_t*, int64_t, void*);
 
+// bf16 elements of the g planes of q0..q0+nq-1
+int64_t gz_elems(const Host& h, int q0, int nq) {
+    int64_t n = 0;
+    for (int q = q0; q < q0 + nq; ++q)
+        for (int k = 0; k < h.nk; ++k) {
+            const int K = h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]];
+            n += int64_t(2) * gz_tp(h.ntau) * round_up(K, GZ_KPAD);
+        }
+    return n;
+}
+
+template <int OCC, int SR, int SC, int KS = GZ_KS, int WI = 2>
+void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+              const double* G, void* P) {
+    int maxi = 0, maxk = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        maxi = std::max(maxi, h.ni[q]);
+        for (int k = 0; k < h.nk; ++k)
+            maxk = std::max(maxk, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
+    }
+    if (size_t(gz_elems(h, q0, nq)) * 2 > scratch_mfma_bytes(d, h))
+        throw Error(MSGW_ENOMEM, "workspace too small for the g planes");
+    uint32_t* gz = reinterpret_cast<uint32_t*>(scratch_mfma(d, h));
+    const unsigned gx = unsigned(ceil_div(gz_tp(h.ntau) * round_up(maxk, GZ_KPAD) / 2, 256));
+    for (int q = q0; q < q0 + nq; ++q) {
+        hipLaunchKernelGGL(k_gtab, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, G, gz, int64_t(0));
+        MSGW_HIP(hipGetLastError());
+    }
+    const int ntc = gz_tp(h.ntau) / GZ_T;
+    const Order od = make_order_st(ceil_div(maxi, 4 * WI), ceil_div(maxi, 16) * ntc, nq, SR, SC * ntc);
+    hipLaunchKernelGGL((k_polz<OCC, KS, WI>), dim3(grid_of(od)), dim3(128 * WI), 0, s, d, q0, (const float2*)M,
+                       (const uint32_t*)gz, (double2*)P, od);
+    MSGW_HIP(hipGetLastError());
+}
+
 template <int T, int SR = 4, int SC = 8, int OCC = 1>
 void run_sig7(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
@@ -1184,14 +1509,13 @@ struct SigVariant {
 
 // index 0 of each table is the default (the fastest on the 4x4x4-k, 64-band, NI = 400 shapes)
 const PolVariant kPolBF16[] = {
+    {"pair-space 16x16 pairs K64 st4x8", run_polz<1, 4, 8, 64, 4>},
+    {"pair-space 8x16 pairs 2 WG/CU st4x16 K64", run_polz<2, 4, 16, 64>},
+    {"pair-space 8x16 pairs 2 WG/CU st4x16", run_polz<2, 4, 16>},
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3>},
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_BF16X3>},
     {"WI4 WJ1 T4", run_pol<4, 1, 4, PREC_BF16X3>},
-    {"WI4 WJ2 T2", run_pol<4, 2, 2, PREC_BF16X3>},
-    {"WI2 WJ4 T2", run_pol<2, 4, 2, PREC_BF16X3>},
     {"prefetch WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3, true>},
-    {"prefetch WI2 WJ2 T4", run_pol<2, 2, 4, PREC_BF16X3, true>},
-    {"prefetch WI4 WJ1 T4", run_pol<4, 1, 4, PREC_BF16X3, true>},
 };
 const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
@@ -1253,12 +1577,15 @@ const char* mfma_variant_name(int op, int precision, int v) {
 
 size_t mfma_scratch_bytes(const Host& h, int nq_max) {
     // for the q range of one self_energy call: padded W~ planes and the split, transposed M planes,
-    // 8 bytes per complex element each (complex64 for FP32, hi + lo bf16 pairs for BF16X3)
+    // 8 bytes per complex element each (complex64 for FP32, hi + lo bf16 pairs for BF16X3); for one
+    // polarization call: the bf16 g planes of the pair-space kernel (2 bytes each)
     int64_t best = 0;
-    for (int q = 0; q + nq_max <= h.nk; ++q)
-        best = std::max(best, round_up(int(std::min<int64_t>(plane_elems(h, q, nq_max), 1 << 30)), 64) +
-                                  mt_elems(h, q, nq_max));
-    return size_t(best) * 8;
+    for (int q = 0; q + nq_max <= h.nk; ++q) {
+        best = std::max(best, 8 * (round_up(int(std::min<int64_t>(plane_elems(h, q, nq_max), 1 << 30)), 64) +
+                                   mt_elems(h, q, nq_max)));
+        best = std::max(best, 2 * gz_elems(h, q, nq_max));
+    }
+    return size_t(best);
 }
 
 int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,

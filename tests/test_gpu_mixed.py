@@ -17,6 +17,8 @@ from test_gpu_parity import SMALL, TILES, UNEVEN, _oracle_pw, oracle_G
 pytestmark = pytest.mark.gpu
 
 GATE = {1: 2e-6, 2: 1e-5}
+# more than 96 tau points: the pair-space polarization runs its tau axis in chunks of 96
+LONGTAU = gi.tiny(name="longtau", grid=(2, 1, 1), nocc=3, nemp=3, ni=41, ntau=120, beta=30.0, niw=16)
 
 
 @pytest.fixture(scope="module")
@@ -47,7 +49,7 @@ def _small_cases(op):
 
 
 @pytest.mark.parametrize("prec,variant", _small_cases(0))
-@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES, LONGTAU])
 def test_polarization_mixed(torch, cfg, prec, variant):
     import paper_1602_02313_amd as amd
     prob, run = make_run(cfg, precision=prec, q_batch=cfg.nk)
