@@ -121,6 +121,8 @@ def main():
                     help="counter runs: a plain device copy of --copy-mb MB, then one q batch of the path, "
                          "no timing and no JSON line")
     ap.add_argument("--copy-mb", type=int, default=1024)
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the iteration captured as a HIP graph (no per-kernel times)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): there is no "
@@ -177,12 +179,20 @@ def main():
         for op, (v, name, times) in autotune.tune(run, src, reps=1, log=log, ops=ops).items():
             tuned[["polarization", "self_energy"][op]] = {"variant": v, "tile": name, "ms": times}
 
-    def step():
+    def step_eager():
         run.green0(0.0)
         run.mu.zero_()
-        run.sigma_pass(src)
-        run.dyson(True)
-        run.gap()
+        run.iteration(src)
+
+    step = step_eager
+    if args.graph:
+        # one pass = G0 + the captured iteration (Sigma pass, Dyson with the mu search, gap)
+        graph = run.capture_iteration(src)
+
+        def step():
+            run.green0(0.0)
+            run.mu.zero_()
+            graph.replay()
 
     for w in range(args.warmup):
         t0 = time.perf_counter()
@@ -190,7 +200,7 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f} s")
     timer = EventTimer()
-    run.timer = timer
+    run.timer = None if args.graph else timer
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -200,6 +210,14 @@ def main():
     t_tot = time.perf_counter() - t0
     run.timer = None
     ms_step = 1e3 * t_tot / args.steps
+    kern_steps = args.steps
+    if args.graph:
+        # per-kernel times come from one extra eager pass (kernels cannot be timed inside a replay)
+        run.timer = timer
+        step_eager()
+        torch.cuda.synchronize()
+        run.timer = None
+        kern_steps = 1
     kern = timer.summary()
     fp, fs = flop_model(prob)
     value = (fp + fs) / (ms_step / 1e3) / 1e12
@@ -207,7 +225,7 @@ def main():
 
     # per-kernel times and the dominant contraction's roofline
     nb_q = -(-cfg.nk // args.q_batch)
-    ksum = {k: float(np.sum(v)) / args.steps for k, v in kern.items()}
+    ksum = {k: float(np.sum(v)) / kern_steps for k, v in kern.items()}
     kavg = {k: float(np.mean(v)) for k, v in kern.items()}
     per_launch = {"polarization": fp / nb_q, "self_energy": fs / nb_q}
     dom_op = {"polarization": amd.OP_POLARIZATION, "self_energy": amd.OP_SELF_ENERGY}
@@ -230,7 +248,7 @@ def main():
     if args.precision == "bf16x3":
         roof["peak_basis"] = ("bf16 dense 2516.6 TFLOP/s / 3 products per split product; achieved "
                               "counts the dense complex flop model, executed_* the MFMA work done")
-    kernels = {k: {"ms_per_step": round(ksum[k], 3), "launches_per_step": len(kern[k]) // args.steps}
+    kernels = {k: {"ms_per_step": round(ksum[k], 3), "launches_per_step": len(kern[k]) // kern_steps}
                for k in kern}
     kernels["polarization"]["tflops"] = round(fp / (ksum["polarization"] / 1e3) / 1e12, 2)
     kernels["self_energy"]["tflops"] = round(fs / (ksum["self_energy"] / 1e3) / 1e12, 2)
@@ -283,7 +301,7 @@ def main():
                    "nk": cfg.nk, "nb": int(prob.nb.max()), "ni": int(prob.ni.max()),
                    "ntau": int(prob.tau.size), "niw_f": cfg.niw_f, "niw_b": cfg.niw_b,
                    "beta": cfg.beta, "precision": args.precision, "q_batch": args.q_batch,
-                   "flops_p": fp, "flops_sigma": fs},
+                   "hip_graph": bool(args.graph), "flops_p": fp, "flops_sigma": fs},
         "roofline": roof,
         "kernels": kernels,
         "fp64_gpu_reference": fp64_ref,

@@ -975,12 +975,12 @@ __global__ __launch_bounds__(256, OCC) void k_sig7(Dev d, int q0, const float2* 
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int p = 0; p < 2; ++p)
-                fb[b][p] = *reinterpret_cast<const u32x4*>(&Bs[buf][p][64 * wc + 32 * b + r32][jo]);
+                fb[b][p] = reinterpret_cast<const u32x4*>(&Bs[buf][p][64 * wc + 32 * b + r32][0])[jo / 4];
 #pragma unroll
         for (int t = 0; t < T; ++t)
 #pragma unroll
             for (int p = 0; p < 2; ++p)
-                fa[t][p] = *reinterpret_cast<const u32x4*>(&As[buf][p][t][32 * wi + r32][jo]);
+                fa[t][p] = reinterpret_cast<const u32x4*>(&As[buf][p][t][32 * wi + r32][0])[jo / 4];
     };
 
     floatx16 acc[2][T][2];

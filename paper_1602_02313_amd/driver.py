@@ -52,6 +52,14 @@ class SynthM:
         self.symmetric = symmetric
         self.buf = None
 
+    def reserve(self, run):
+        """Allocate the buffer for the largest q batch of `run` (before a graph capture)."""
+        import torch
+        size = max(int(run.mpre[q0 + nq] - run.mpre[q0]) for q0, nq in run._batches())
+        ct = torch.complex128 if run.m_dtype == L.C128 else torch.complex64
+        if self.buf is None or self.buf.numel() < size or self.buf.dtype != ct:
+            self.buf = torch.empty(size, dtype=ct, device=run.device)
+
     def __call__(self, run, q0, nq):
         import torch
         size = int(run.mpre[q0 + nq] - run.mpre[q0])
@@ -243,17 +251,58 @@ class GWRun:
         self.ctx.gap(self.eps, self.sig_x, self.sig_iw, self.mu, int(round(self.n_target)),
                      self.gap_d, stream=self.stream)
 
-    def run(self, M_source, mode="g0w0", niter=1):
-        """Returns a list of per-iteration dicts (host copies of mu, N, gap, flags)."""
+    def _record(self):
+        return dict(mu=float(self.mu.item()), N=float(self.N.item()),
+                    gap=float(self.gap_d.item()), flags=int(self.flags.item()))
+
+    def iteration(self, M_source, search=True):
+        """One self-consistent iteration: Sigma from the current G, Dyson with the mu search, gap."""
+        self.sigma_pass(M_source)
+        self.dyson(search)
+        self.gap()
+
+    def capture_iteration(self, M_source, search=True):
+        """The scGW iteration recorded once as a HIP graph (torch.cuda.CUDAGraph).
+
+        Every step is a kernel launch or a device fill on the capture stream, so replaying the
+        graph repeats the iteration from the current device state (G, mu) without host work.
+        The M source must live on the device: ResidentM, or SynthM (its buffer is reserved here).
+        """
+        import torch
+        if isinstance(M_source, HostM):
+            raise ValueError("graph capture needs a device-resident M source (ResidentM or SynthM)")
+        if self.stream is not None:
+            raise ValueError("graph capture runs on torch's capture stream; construct GWRun with stream=None")
+        if isinstance(M_source, SynthM):
+            M_source.reserve(self)
+        timer, self.timer = self.timer, None
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.iteration(M_source, search)
+        torch.cuda.synchronize()
+        self.timer = timer
+        return g
+
+    def run(self, M_source, mode="g0w0", niter=1, graph=False):
+        """Returns a list of per-iteration dicts (host copies of mu, N, gap, flags).
+
+        graph=True (scGW only): the iteration is captured once and replayed niter times.
+        """
         self.green0(0.0)
         self.mu.zero_()
         self.W_frozen = None
         hist = []
+        if graph and mode == "scgw":
+            g = self.capture_iteration(M_source)
+            for _ in range(niter):
+                g.replay()
+                hist.append(self._record())
+            return hist
         for it in range(1 if mode == "g0w0" else niter):
             self.sigma_pass(M_source, keep_W=(mode == "gw0" and it == 0))
             if mode != "g0w0":
                 self.dyson(True)
             self.gap()
-            hist.append(dict(mu=float(self.mu.item()), N=float(self.N.item()),
-                             gap=float(self.gap_d.item()), flags=int(self.flags.item())))
+            hist.append(self._record())
         return hist

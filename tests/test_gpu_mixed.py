@@ -224,3 +224,43 @@ def test_gap_physical_scale(torch, c1_phys_oracle, prec):
           f"err {e0 / MEV:.2e} meV; scGW gap errors (meV) {[f'{x / MEV:.2e}' for x in esc]}")
     assert es < GATE[prec]
     assert e0 < MEV and max(esc) < MEV
+
+
+# ---------------------------------------------------------------------------------------------
+# the scGW iteration as a HIP graph: every replay must reproduce the eager iteration
+# ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [0, 2])
+def test_graph_replays_match_eager(torch, prec):
+    import paper_1602_02313_amd as amd
+    cfg = C1_PHYS
+    prob = gi.make_problem(cfg)
+    _, run = make_run(cfg, precision=prec, q_batch=4)
+    mdt = amd.C128 if prec == 0 else amd.C64
+    ct = torch.complex128 if prec == 0 else torch.complex64
+    M = torch.empty(int(run.mpre[-1]), dtype=ct, device="cuda")
+    run.ctx.synth_M(cfg.seed, 0, cfg.nk, 1, mdt, M)
+    src = amd.ResidentM(M, run.mpre)
+    niter = 3
+    eager, eager_G = [], []
+    run.green0(0.0)
+    run.mu.zero_()
+    for _ in range(niter):
+        run.iteration(src)
+        eager.append(run._record())
+        eager_G.append(np_(run.G_tau).copy())
+    run.green0(0.0)
+    run.mu.zero_()
+    g = run.capture_iteration(src)
+    for it in range(niter):
+        # eager work and a synchronization between replays
+        junk = torch.ones(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        rec = run._record()
+        eg = rel(np_(run.G_tau), eager_G[it])
+        print(f"graph prec={prec} replay {it}: gap {rec['gap']:.9f} (eager {eager[it]['gap']:.9f}), "
+              f"G rel {eg:.2e}, flags {rec['flags']}")
+        assert rec["flags"] == eager[it]["flags"] == 0
+        assert abs(rec["gap"] - eager[it]["gap"]) < 1e-9 and abs(rec["N"] - eager[it]["N"]) < 1e-9
+        assert eg < 1e-10
+        del junk
