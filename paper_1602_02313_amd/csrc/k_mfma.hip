@@ -1387,6 +1387,283 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
 }
 
 // =================================================================================================
+// pair-space self-energy (vZ)
+// =================================================================================================
+// With the Hermitian part H of W~ and the pair product Z_K,IJ = M^I_K conj(M^J_K) of the polarization,
+//     Re sum_IJ conj(a_I) W~_IJ a_J = sum_{I <= J} c_IJ (Re H_IJ Re Z_IJ + Im H_IJ Im Z_IJ),
+// with a = column K of M, c_IJ = 2 above the diagonal and 1 on it (conj(a_I) a_J = conj(Z_IJ); the
+// anti-Hermitian part of W~ adds only an imaginary amount).  Hence
+//     Sigma_n(k,tau) = s sum_m G_m(k-q,tau) sum_pairs [Re Z w_re + Im Z w_im](K, tau),  w = c H,
+// a real GEMM with rows = K, reduction = (pair, re/im) and columns = tau.  The weights are cut into
+// blocks of 8 I x 8 J pairs (upper triangle of blocks), stored as bf16 hi/lo planes; a work-group
+// keeps one weight block in LDS at a time and all its waves reuse it for 64 rows K each.
+constexpr int SZ_WR = 64 + 4;  // LDS row stride of a weight block (u32): 8 steps x 8 pairs + pad
+
+__device__ __host__ __forceinline__ int sz_nb8(int ni) { return (ni + 7) / 8; }
+__device__ __host__ __forceinline__ int64_t sz_blocks(int ni) {
+    const int n = sz_nb8(ni);
+    return int64_t(n) * (n + 1) / 2;
+}
+// u32 elements of the weight planes of one q (hi and lo)
+__device__ __host__ __forceinline__ int64_t sz_wq(int ni, int ntau) {
+    return 2 * sz_blocks(ni) * gz_tp(ntau) * 64;
+}
+// fp32 transposed M of q0..q0+nq-1, [k][K][NIp8] complex, NIp8 = NI rounded up to 8
+__device__ __host__ __forceinline__ int sz_np8(int ni) { return (ni + 7) / 8 * 8; }
+
+// transposed FP32 M of one q: mt[k][K][NIp8], zero-padded in I
+__global__ __launch_bounds__(256) void k_trans32(Dev d, int q0, int q, const float2* __restrict__ M,
+                                                 float2* __restrict__ mt) {
+    __shared__ float2 tile[32][33];
+    const int nk = d.nk, k = blockIdx.y;
+    const int NI = d.ni[q], NP = sz_np8(NI);
+    const int Kk = d.nb[k] * d.nb[d.kmq[q * nk + k]];
+    const int nti = (NP + 31) / 32;
+    const int i0 = (blockIdx.x % nti) * 32, c0 = (blockIdx.x / nti) * 32;
+    if (c0 >= Kk) return;
+    const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
+    int64_t ob = 0;
+    for (int qq = q0; qq < q; ++qq) ob += (d.mpre[qq + 1] - d.mpre[qq]) / d.ni[qq] * sz_np8(d.ni[qq]);
+    float2* T = mt + ob + d.moff[q * nk + k] / NI * NP;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) {
+        const int I = i0 + r, col = c0 + tx;
+        tile[r][tx] = (I < NI && col < Kk) ? A[int64_t(I) * Kk + col] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int col = c0 + r, I = i0 + tx;
+        if (col < Kk && I < NP) T[int64_t(col) * NP + I] = tile[tx][r];
+    }
+}
+
+// weight blocks of one q: for block (bi, bj), bj >= bi, tau row t and step s (I = 8 bi + s), the
+// 8 pairs J = 8 bj + j hold (w_re, w_im) = c_IJ (Re H_IJ, Im H_IJ) as packed bf16, hi and lo planes
+__global__ __launch_bounds__(256) void k_wpair(const double2* __restrict__ W, int NI, int ntau,
+                                               uint32_t* __restrict__ wz) {
+    const int TP = gz_tp(ntau), nb = sz_nb8(NI);
+    const int64_t nblk = sz_blocks(NI);
+    const int64_t id = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (id >= nblk * TP * 64) return;
+    const int j = int(id & 7), s = int((id >> 3) & 7);
+    const int64_t bt = id >> 6;
+    const int t = int(bt % TP);
+    int64_t b = bt / TP;
+    int bi = 0;  // block b -> (bi, bj): rows of the upper triangle of blocks, bi ascending
+    while (b >= nb - bi) {
+        b -= nb - bi;
+        ++bi;
+    }
+    const int bj = bi + int(b);
+    const int I = 8 * bi + s, J = 8 * bj + j;
+    float re = 0.f, im = 0.f;
+    if (t < ntau && I < NI && J < NI && J >= I) {
+        const double2* Wt = W + int64_t(t) * NI * NI;
+        const double2 a = Wt[int64_t(I) * NI + J], m = Wt[int64_t(J) * NI + I];
+        const double c = J > I ? 1.0 : 0.5;  // c_IJ H_IJ = c_IJ (W_IJ + conj W_JI) / 2
+        re = float(c * (a.x + m.x));
+        im = J > I ? float(c * (a.y - m.y)) : 0.f;
+    }
+    uint32_t h, l;
+    split2(re, im, h, l);
+    const int64_t blk = id >> 6;  // (block, tau) row of 64 u32
+    wz[blk * 64 + 8 * s + j] = h;
+    wz[nblk * TP * 64 + blk * 64 + 8 * s + j] = l;
+}
+
+// Work-group = 8 waves over 512 rows K of one (q, k) block and one 96-wide tau chunk; wave w owns
+// rows K0 + 64 w .. + 63 as two 32-row MFMA tiles.  The work-group walks the weight blocks in order;
+// each block (48 KB, hi and lo) is staged through LDS (double-buffered) while the previous one is
+// used.  Every lane forms Z for its rows K and 4 pairs per MFMA step from the transposed FP32 M
+// (the 8 values a_I of the block row stay in registers across the block row), splits it into
+// bf16 hi/lo, and the FP32 accumulators go through the epilogue (G_m weight, sum over the m of each
+// band n, FP64 atomic) every 32 blocks.
+template <int OCC>
+__global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* __restrict__ G,
+                                                   const float2* __restrict__ mt,
+                                                   const uint32_t* __restrict__ wz,
+                                                   double* __restrict__ Sig, int nkc) {
+    __shared__ uint32_t Ws[2][2][GZ_T][SZ_WR];  // [buffer][hi, lo][tau][8 s x 8 j]
+    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
+    const int ntc = gz_tp(ntau) / GZ_T, TP = ntc * GZ_T;
+    // work item: (q, k, K chunk of 512, tau chunk)
+    int w = blockIdx.x;
+    const int tc = w % ntc;
+    w /= ntc;
+    const int kc = w % nkc;
+    w /= nkc;
+    const int k = w % nk, qrel = w / nk, q = q0 + qrel;
+    const int kq = d.kmq[q * nk + k];
+    const int nm = d.nb[kq], Kk = d.nb[k] * nm;
+    const int K0 = kc * 512;
+    if (K0 >= Kk) return;  // uniform
+    const int NI = d.ni[q], NP = sz_np8(NI), nb = sz_nb8(NI);
+    const int64_t nblk = sz_blocks(NI);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h2 = lane >> 5;
+
+    int64_t mq = 0, wq = 0;
+    for (int qq = q0; qq < q; ++qq) {
+        mq += (d.mpre[qq + 1] - d.mpre[qq]) / d.ni[qq] * sz_np8(d.ni[qq]);
+        wq += sz_wq(d.ni[qq], ntau);
+    }
+    const float2* T = mt + mq + d.moff[q * nk + k] / NI * NP;
+    const uint32_t* wq0 = wz + wq;  // hi plane of q; the lo plane follows at nblk * TP * 64
+    const int64_t wlo = nblk * TP * 64;
+
+    // this lane's two rows K (one per 32-row tile); rows past Kk read row Kk - 1 and are masked in
+    // the epilogue
+    int Krow[2];
+    const float2* Tr[2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+        Krow[kt] = K0 + 64 * wave + 32 * kt + r32;
+        Tr[kt] = T + int64_t(min(Krow[kt], Kk - 1)) * NP;
+    }
+
+    // staging of one weight block: 2 planes x 96 tau x 16 chunks of 16 B = 3072 chunks, 6 per thread
+    u32x4 rw[6];
+    auto wload = [&](int64_t b) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const int id = tid + 512 * i;
+            const int pl = id / (GZ_T * 16), rem = id - pl * GZ_T * 16;
+            const int t = rem >> 4, ch = rem & 15;
+            const uint32_t* src = wq0 + (pl * wlo + (b * TP + GZ_T * tc + t) * 64 + 4 * ch);
+            rw[i] = *reinterpret_cast<const u32x4*>(src);
+        }
+    };
+    auto wstore = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const int id = tid + 512 * i;
+            const int pl = id / (GZ_T * 16), rem = id - pl * GZ_T * 16;
+            const int t = rem >> 4, ch = rem & 15;
+            *reinterpret_cast<u32x4*>(&Ws[buf][pl][t][4 * ch]) = rw[i];
+        }
+    };
+
+    floatx16 acc[2][3];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt) zero16(acc[kt][tt]);
+
+    const double sc = d.scale;
+    // epilogue on the accumulators: weight each row K = (n, m) by G_m(k-q, tau), sum the rows of
+    // each band n and add to Sigma_n(k, tau)
+    auto flush = [&]() {
+        int z = 0;  // opaque zero: keeps the loop-invariant G loads of this epilogue out of the loop
+        asm volatile("" : "+v"(z));
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            const int kb = K0 + 64 * wave + 32 * kt;  // first row of the tile (wave-uniform)
+            if (kb >= Kk) continue;
+            const int nlo = kb / nm, nhi = (min(kb + 32, Kk) - 1) / nm;
+#pragma unroll
+            for (int tt = 0; tt < 3; ++tt) {
+                const int it = GZ_T * tc + 32 * tt + r32;
+                const int itc = min(it, ntau - 1);
+                for (int nx = nlo; nx <= nhi; ++nx) {
+                    float v = 0.f;  // 16 terms; the run totals are summed in FP64
+#pragma unroll
+                    for (int x = 0; x < 16; ++x) {
+                        const int K = kb + 8 * (x >> 2) + 4 * h2 + (x & 3);
+                        if (K < Kk && K / nm == nx) {
+                            const int m = K - nx * nm;
+                            v += acc[kt][tt][x] * float(G[(int64_t(kq) * nbmax + m) * ntau + itc + z]);
+                        }
+                    }
+                    v += __shfl_xor(v, 32);
+                    if (h2 == 0 && it < ntau)
+                        atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], sc * double(v));
+                }
+                zero16(acc[kt][tt]);
+            }
+        }
+    };
+
+    float4 ai[2][4];   // a_I, I = 8 bi .. 8 bi + 7, for both rows (re, im pairs in float4)
+    float4 aj[2][2];   // a_J, J = 8 bj + 4 h2 .. + 3
+    auto load_ai = [&](int bi) {
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ai[kt][e] = reinterpret_cast<const float4*>(Tr[kt] + 8 * bi)[e];
+    };
+    auto load_aj = [&](int bj, float4 (&dst)[2][2]) {
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int e = 0; e < 2; ++e) dst[kt][e] = reinterpret_cast<const float4*>(Tr[kt] + 8 * bj + 4 * h2)[e];
+    };
+
+    int bi = 0, bj = 0;
+    wload(0);
+    wstore(0);
+    __syncthreads();
+    int buf = 0;
+    int64_t b = 0;
+    // blocks in runs of 32 (4096 terms per FP32 accumulator), each run followed by the epilogue
+    while (b < nblk) {
+        const int64_t bend = b + 32 < nblk ? b + 32 : nblk;
+        for (; b < bend; ++b) {
+            int bi2 = bi, bj2 = bj + 1;
+            if (bj2 >= nb) {
+                ++bi2;
+                bj2 = bi2;
+            }
+            const bool more = b + 1 < nblk;
+            // this block's a_I and a_J (L1 / L2 hits; the other wave on the SIMD covers the wait)
+            load_ai(bi);
+            load_aj(bj, aj);
+            if (more) wload(b + 1);
+            // 8 MFMA steps: step s pairs I = 8 bi + s with J = 8 bj + 4 h2 .. + 3 (this lane's half)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                u32x4 zh[2], zl[2];
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) {
+                    const float4 a4 = ai[kt][s >> 1];
+                    const float ar = (s & 1) ? a4.z : a4.x, aim = (s & 1) ? a4.w : a4.y;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float4 c4 = aj[kt][j >> 1];
+                        const float cr = (j & 1) ? c4.z : c4.x, ci = (j & 1) ? c4.w : c4.y;
+                        const float zr = ar * cr + aim * ci, zi = aim * cr - ar * ci;
+                        uint32_t h, l;
+                        split2(zr, zi, h, l);
+                        zh[kt][j] = h;
+                        zl[kt][j] = l;
+                    }
+                }
+#pragma unroll
+                for (int tt = 0; tt < 3; ++tt) {
+                    const u32x4* hrow = reinterpret_cast<const u32x4*>(&Ws[buf][0][32 * tt + r32][0]);
+                    const u32x4* lrow = reinterpret_cast<const u32x4*>(&Ws[buf][1][32 * tt + r32][0]);
+                    const u32x4 bh = hrow[2 * s + h2], bl = lrow[2 * s + h2];
+#pragma unroll
+                    for (int kt = 0; kt < 2; ++kt) {
+                        acc[kt][tt] = mfma32(zh[kt], bh, acc[kt][tt]);
+                        acc[kt][tt] = mfma32(zh[kt], bl, acc[kt][tt]);
+                        acc[kt][tt] = mfma32(zl[kt], bh, acc[kt][tt]);
+                    }
+                }
+                // keeps the Z of later steps from being formed (and held) ahead of time
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (!more) break;
+            wstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+            bi = bi2;
+            bj = bj2;
+        }
+        flush();
+        if (b + 1 >= nblk && b < bend) break;  // the last block was handled inside the run
+    }
+}
+
+// =================================================================================================
 // variants (tile shapes) and dispatch
 // =================================================================================================
 using PolFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*, void*);
@@ -1479,6 +1756,38 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     MSGW_HIP(hipGetLastError());
 }
 
+// pair-space self-energy: needs only the raw W~ (FP64), so it runs its own conversions
+void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+              const double* G, const void* W, void* Sig) {
+    int64_t nmt = 0, nwz = 0;
+    int maxk = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        nmt += (h.mpre[q + 1] - h.mpre[q]) / h.ni[q] * sz_np8(h.ni[q]);
+        nwz += sz_wq(h.ni[q], h.ntau);
+        for (int k = 0; k < h.nk; ++k) maxk = std::max(maxk, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
+    }
+    if (size_t(nmt) * 8 + size_t(nwz) * 4 > scratch_mfma_bytes(d, h))
+        throw Error(MSGW_ENOMEM, "workspace too small for the pair-space self-energy");
+    float2* mt = reinterpret_cast<float2*>(scratch_mfma(d, h));
+    uint32_t* wz = reinterpret_cast<uint32_t*>(mt + nmt);
+    int64_t woff = 0;
+    for (int q = q0; q < q0 + nq; ++q) {
+        const int NI = h.ni[q];
+        const unsigned gx = ceil_div(sz_np8(NI), 32) * ceil_div(maxk, 32);
+        hipLaunchKernelGGL(k_trans32, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, (const float2*)M, mt);
+        MSGW_HIP(hipGetLastError());
+        const int64_t n = sz_blocks(NI) * gz_tp(h.ntau) * 64;
+        hipLaunchKernelGGL(k_wpair, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
+                           (const double2*)W + (h.ppre[q] - h.ppre[q0]), NI, h.ntau, wz + woff);
+        MSGW_HIP(hipGetLastError());
+        woff += sz_wq(NI, h.ntau);
+    }
+    const int nkc = ceil_div(maxk, 512), ntc = gz_tp(h.ntau) / GZ_T;
+    hipLaunchKernelGGL((k_sigz<1>), dim3(unsigned(nq * h.nk * nkc * ntc)), dim3(512), 0, s, d, q0, G,
+                       (const float2*)mt, (const uint32_t*)wz, (double*)Sig, nkc);
+    MSGW_HIP(hipGetLastError());
+}
+
 template <int T, int SR = 4, int SC = 8, int OCC = 1>
 void run_sig7(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
@@ -1501,10 +1810,13 @@ struct PolVariant {
     const char* name;
     PolFn fn;
 };
+using SigZFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
+                        const void*, void*);
 struct SigVariant {
     const char* name;
-    SigFn fn;     // W~ planes only
-    Sig3Fn fn3;   // W~ planes + split transposed M
+    SigFn fn;      // W~ planes only
+    Sig3Fn fn3;    // W~ planes + split transposed M
+    SigZFn fnz = nullptr;  // raw W~ (runs its own conversions)
 };
 
 // index 0 of each table is the default (the fastest on the 4x4x4-k, 64-band, NI = 400 shapes)
@@ -1522,6 +1834,7 @@ const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_FP32>},
 };
 const SigVariant kSigBF16[] = {
+    {"pair-space 512 K x 8x8-pair blocks", nullptr, nullptr, run_sigz},
     {"LDS 2-stage 64x128 T2 2 WG/CU st8x8", nullptr, run_sig7<2, 8, 8, 2>},
     {"LDS 2-stage 64x128 T2 2 WG/CU st4x16", nullptr, run_sig7<2, 4, 16, 2>},
     {"LDS 2-stage 64x128 T4", nullptr, run_sig7<4>},
@@ -1584,6 +1897,10 @@ size_t mfma_scratch_bytes(const Host& h, int nq_max) {
         best = std::max(best, 8 * (round_up(int(std::min<int64_t>(plane_elems(h, q, nq_max), 1 << 30)), 64) +
                                    mt_elems(h, q, nq_max)));
         best = std::max(best, 2 * gz_elems(h, q, nq_max));
+        int64_t zs = 0;  // pair-space self-energy: FP32 transposed M and the weight blocks
+        for (int qq = q; qq < q + nq_max; ++qq)
+            zs += 8 * ((h.mpre[qq + 1] - h.mpre[qq]) / h.ni[qq] * sz_np8(h.ni[qq])) + 4 * sz_wq(h.ni[qq], h.ntau);
+        best = std::max(best, zs);
     }
     return size_t(best);
 }
@@ -1608,6 +1925,10 @@ int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
     const int nv = mfma_variant_count(MSGW_OP_SELF_ENERGY, precision);
     if (variant < 0 || variant >= nv) return MSGW_EINVAL;
     const SigVariant& V = (precision == MSGW_BF16X3 ? kSigBF16 : kSigFP32)[variant];
+    if (V.fnz) {
+        V.fnz(d, h, s, q0, nq, M, G, W, Sig);
+        return MSGW_OK;
+    }
     const int64_t plane = plane_elems(h, q0, nq);
     const int64_t wsz = round_up(int(std::min<int64_t>(plane, 1 << 30)), 64);  // W~ planes, 256-B aligned
     const int64_t mtp = V.fn3 ? mt_elems(h, q0, nq) : 0;

@@ -71,7 +71,7 @@ def test_polarization_mixed(torch, cfg, prec, variant):
 
 
 @pytest.mark.parametrize("prec,variant", _small_cases(1))
-@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES])
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN, TILES, LONGTAU])
 def test_self_energy_mixed(torch, cfg, prec, variant):
     import paper_1602_02313_amd as amd
     prob, run = make_run(cfg, precision=prec, q_batch=1)
