@@ -25,6 +25,19 @@ struct Error : std::runtime_error {
             throw ::msgw::Error(MSGW_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// A grid dimension holds at most 2^32 - 1 work-items, and y / z at most 65535 work-groups: larger
+// shapes are refused rather than launched truncated.
+inline void check_grid(dim3 g, dim3 b, const char* what) {
+    if (uint64_t(g.x) * b.x > 0xFFFFFFFFull || g.y > 65535u || g.z > 65535u)
+        throw Error(MSGW_ENOTSUP, std::string(what) + ": launch grid exceeds the dispatch limits");
+}
+
+#define MSGW_LAUNCH(kernel, grid, block, shm, stream, ...)               \
+    do {                                                                 \
+        ::msgw::check_grid((grid), (block), #kernel);                    \
+        hipLaunchKernelGGL(kernel, grid, block, shm, stream, __VA_ARGS__); \
+    } while (0)
+
 // Device-resident constant tables (they live in the caller's workspace) plus the
 // sizes every kernel needs.  Passed by value to the launchers.
 struct Dev {

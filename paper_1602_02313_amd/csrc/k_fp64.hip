@@ -8,7 +8,11 @@ namespace {
 constexpr int TT = 64;   // output tile (rows and columns)
 constexpr int KC = 16;   // K chunk staged in LDS
 
-inline unsigned ceil_div(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
+inline unsigned ceil_div(int64_t a, int64_t b) {
+    const int64_t r = (a + b - 1) / b;
+    if (r > int64_t(0xFFFFFFFFu)) throw Error(MSGW_ENOTSUP, "shape too large for one launch");
+    return unsigned(r);
+}
 
 // P_IJ(q,tau) = s sum_k sum_nm M^I_nm g_nm conj(M^J_nm),  g_nm = G_n(k,tau) G_m(k-q,beta-tau)
 // grid: x = I-tile * nt + J-tile, y = tau, z = q - q0.  256 threads, 4x4 complex per thread.
@@ -221,7 +225,7 @@ void launch_pol_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
         int nt = (h.ni[q] + TT - 1) / TT;
         maxt = std::max(maxt, nt * nt);
     }
-    hipLaunchKernelGGL(k_pol_fp64, dim3(maxt, h.ntau, nq), dim3(256), 0, s, d, q0,
+    MSGW_LAUNCH(k_pol_fp64, dim3(maxt, h.ntau, nq), dim3(256), 0, s, d, q0,
                        (const double2*)M, G, (double2*)P);
     MSGW_HIP(hipGetLastError());
 }
@@ -235,7 +239,7 @@ void launch_sig_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
             maxt = std::max(maxt, int(ceil_div(h.ni[q], TT) * ceil_div(Kk, TT)));
         }
     if (int64_t(nq) * h.nk > 65535) throw Error(MSGW_ENOTSUP, "self_energy: nq * nk must be <= 65535");
-    hipLaunchKernelGGL(k_sig_fp64, dim3(maxt, h.ntau, nq * h.nk), dim3(256), 0, s, d, q0,
+    MSGW_LAUNCH(k_sig_fp64, dim3(maxt, h.ntau, nq * h.nk), dim3(256), 0, s, d, q0,
                        (const double2*)M, G, (const double2*)W, (double*)Sig);
     MSGW_HIP(hipGetLastError());
 }
@@ -245,7 +249,7 @@ void launch_sig_full_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, in
     size_t lds = sizeof(double2) * size_t(h.nimax) * h.nbmax;
     if (lds > 65536) throw Error(MSGW_ENOTSUP, "FULL self-energy needs NI * Nb <= 4096");
     if (int64_t(nq) * h.nk > 65535) throw Error(MSGW_ENOTSUP, "self_energy: nq * nk must be <= 65535");
-    hipLaunchKernelGGL(k_sig_full_fp64, dim3(h.nbmax, h.ntau, nq * h.nk), dim3(256), lds, s, d, q0,
+    MSGW_LAUNCH(k_sig_full_fp64, dim3(h.nbmax, h.ntau, nq * h.nk), dim3(256), lds, s, d, q0,
                        (const double2*)M, G, (const double2*)W, (double2*)Sig);
     MSGW_HIP(hipGetLastError());
 }

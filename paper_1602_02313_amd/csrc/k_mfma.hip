@@ -43,7 +43,11 @@ constexpr int NB_LDS = 256;       // band limit of the MFMA path (G slices stage
 constexpr int FLUSH_STEPS = 256;  // K-steps of 16 complex between FP64 flushes
 constexpr int PAD = 64;           // W~ planes are zero-padded to a multiple of PAD
 
-inline unsigned ceil_div(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
+inline unsigned ceil_div(int64_t a, int64_t b) {
+    const int64_t r = (a + b - 1) / b;
+    if (r > int64_t(0xFFFFFFFFu)) throw Error(MSGW_ENOTSUP, "shape too large for one launch");
+    return unsigned(r);
+}
 inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
 
 // ---- bf16 helpers -------------------------------------------------------------------------------
@@ -95,7 +99,18 @@ struct Order {
     int nSC;       // super-tiles per row of super-tiles
     int per_q;     // padded items per q
     int total;     // nq * per_q
+    int off, n;    // items [off, off + n) belong to this launch
 };
+
+// item counts of an order; the work-items of one call must be countable in an int
+inline void order_sizes(Order& o, int nq) {
+    const int64_t per = int64_t((o.R + o.SR - 1) / o.SR) * o.nSC * o.SR * o.SC;
+    if (per * nq >= (int64_t(1) << 31)) throw Error(MSGW_ENOTSUP, "too many work items in one call");
+    o.per_q = int(per);
+    o.total = int(per * nq);
+    o.off = 0;
+    o.n = o.total;
+}
 
 // window: work items resident at once on one XCD (waves or work-groups); window <= 0 gives plain
 // row-major order (each row of C items consecutive)
@@ -111,9 +126,7 @@ Order make_order(int R, int C, int nq, int window = 128) {
         o.SR = std::max(1, window / o.SC);
     }
     o.nSC = (C + o.SC - 1) / o.SC;
-    const int nSR = (R + o.SR - 1) / o.SR;
-    o.per_q = nSR * o.nSC * o.SR * o.SC;
-    o.total = nq * o.per_q;
+    order_sizes(o, nq);
     return o;
 }
 
@@ -125,19 +138,30 @@ Order make_order_st(int R, int C, int nq, int SR, int SC) {
     o.SR = std::max(1, std::min(SR, R));
     o.SC = std::max(1, std::min(SC, C));
     o.nSC = (C + o.SC - 1) / o.SC;
-    const int nSR = (R + o.SR - 1) / o.SR;
-    o.per_q = nSR * o.nSC * o.SR * o.SC;
-    o.total = nq * o.per_q;
+    order_sizes(o, nq);
     return o;
 }
 
-unsigned grid_of(const Order& o) { return unsigned(round_up(o.total, 8)); }
+// launch(grid, order) once per slice of at most 2^32 - 1 work-items, the most one grid dimension
+// holds (grids are multiples of 8)
+template <class F>
+void launch_order(Order o, unsigned threads, F&& launch) {
+    const int64_t cap = (int64_t(0xFFFFFFFFu) / threads) & ~int64_t(7);
+    const int total = o.total;
+    for (int64_t s0 = 0; s0 < total; s0 += cap) {
+        o.off = int(s0);
+        o.n = int(std::min<int64_t>(cap, total - s0));
+        launch(dim3(unsigned(round_up(o.n, 8))), o);
+        MSGW_HIP(hipGetLastError());
+    }
+}
 
-// returns false for padding items
+// consecutive items of a launch go to one XCD; returns false for padding items
 __device__ __forceinline__ bool work_item(const Order& o, int& qrel, int& r, int& c) {
     const int per = gridDim.x >> 3;
     int w = int(blockIdx.x & 7) * per + int(blockIdx.x >> 3);
-    if (w >= o.total) return false;
+    if (w >= o.n) return false;
+    w += o.off;
     qrel = w / o.per_q;
     w -= qrel * o.per_q;
     const int sts = o.SR * o.SC;
@@ -1123,17 +1147,28 @@ __device__ __forceinline__ int64_t gz_block(const Dev& d, int q0, int q, int k) 
     return off;  // in bf16 elements
 }
 
-// one thread per (tau, K pair): writes hi and lo of g for two consecutive K
-__global__ __launch_bounds__(256) void k_gtab(Dev d, int q0, int q, const double* __restrict__ G,
-                                              uint32_t* __restrict__ gz, int64_t base) {
+// one thread per (tau, K pair): writes hi and lo of g for two consecutive K.  gz points at the planes
+// of q; the offset of block k inside them is summed over the k' < k by the whole work-group.
+__global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __restrict__ G,
+                                              uint32_t* __restrict__ gz) {
+    __shared__ int64_t part[4];
     const int k = blockIdx.y, nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int kq = d.kmq[q * nk + k];
     const int nm = d.nb[kq], Kk = d.nb[k] * nm;
     const int KP = (Kk + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD;
-    const int64_t off = base + gz_block(d, q0, q, k);  // bf16 elements, even
+    const int TP = gz_tp(ntau);
+    int64_t o = 0;
+    for (int kk = threadIdx.x; kk < k; kk += 256) {
+        const int K = d.nb[kk] * d.nb[d.kmq[q * nk + kk]];
+        o += int64_t(2) * TP * ((K + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD);
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) o += __shfl_xor(o, m);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = o;
+    __syncthreads();
+    const int64_t off = part[0] + part[1] + part[2] + part[3];  // bf16 elements, even
     const int id = blockIdx.x * 256 + threadIdx.x;
     const int npair = KP / 2;
-    const int TP = gz_tp(ntau);
     if (id >= TP * npair) return;
     const int t = id / npair, K0 = 2 * (id - t * npair);
     float g[2];
@@ -1197,12 +1232,12 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         b.Kk = d.nb[kx] * d.nb[kq];
         b.KP = (b.Kk + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD;
         b.A = Mq + d.moff[q * nk + kx];
-        int64_t off = gq;
-        for (int kk = 0; kk < kx; ++kk) {
-            const int K = d.nb[kk] * d.nb[d.kmq[q * nk + kk]];
-            off += int64_t(2) * gz_tp(d.ntau) * ((K + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD);
-        }
-        b.g = gz + (off >> 1);
+        return b;
+    };
+    // blocks are visited in k order: the g planes of block k follow those of block k - 1
+    auto next_block = [&](const Blk& prev, int kx) {
+        Blk b = block_of(kx);
+        b.g = prev.g + int64_t(TP) * prev.KP;
         return b;
     };
     auto gload = [&](const Blk& b, int slab) {
@@ -1349,9 +1384,10 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     // stages run over (k, slab); the FP32 accumulators go to FP64 every 4096 terms
     int k = 0, slab = 0, since = 0;
     Blk blk = block_of(0);
+    blk.g = gz + (gq >> 1);
     int nsl = (blk.KP + KS - 1) / KS;
     while (nsl == 0 && k + 1 < nk) {
-        blk = block_of(++k);
+        blk = next_block(blk, ++k);
         nsl = (blk.KP + KS - 1) / KS;
     }
     gload(blk, 0);
@@ -1364,7 +1400,7 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         while (s2 >= n2 && k2 + 1 < nk) {
             ++k2;
             s2 = 0;
-            b2 = block_of(k2);
+            b2 = next_block(b2, k2);
             n2 = (b2.KP + KS - 1) / KS;
         }
         const bool more = s2 < n2;
@@ -1677,9 +1713,10 @@ void run_pol(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const v
     for (int q = q0; q < q0 + nq; ++q) maxi = std::max(maxi, h.ni[q]);
     const int ntI = ceil_div(maxi, 16 * WI), ntJ = ceil_div(maxi, 16 * WJ), ntG = ceil_div(h.ntau, T);
     const Order od = make_order(ntG * ntI, ntJ, nq);
-    hipLaunchKernelGGL((k_pol<WI, WJ, T, PREC, PF>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
-                       (const float2*)M, G, (double2*)P, od, ntI);
-    MSGW_HIP(hipGetLastError());
+    launch_order(od, 64, [&](dim3 g, const Order& o) {
+        MSGW_LAUNCH((k_pol<WI, WJ, T, PREC, PF>), g, dim3(64), 0, s, d, q0, (const float2*)M, G,
+                           (double2*)P, o, ntI);
+    });
 }
 
 template <int WI, int WJ, int T, int PREC>
@@ -1694,9 +1731,10 @@ void run_sig(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const v
     static_assert(16 * WI <= PAD, "row tiles must fit in the padded W~ planes");
     const int ntI = ceil_div(maxi, 16 * WI), ntC = ceil_div(maxc, 16 * WJ), ntG = ceil_div(h.ntau, T);
     const Order od = make_order(ntG * ntI, h.nk * ntC, nq);
-    hipLaunchKernelGGL((k_sig<WI, WJ, T, PREC>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
-                       (const float2*)M, G, wsc, plane, (double*)Sig, od, ntI, ntC);
-    MSGW_HIP(hipGetLastError());
+    launch_order(od, 64, [&](dim3 g, const Order& o) {
+        MSGW_LAUNCH((k_sig<WI, WJ, T, PREC>), g, dim3(64), 0, s, d, q0, (const float2*)M, G, wsc,
+                           plane, (double*)Sig, o, ntI, ntC);
+    });
 }
 
 // v3 self-energy: needs the split, transposed M planes (uses the `mt` arguments)
@@ -1713,9 +1751,10 @@ void run_sig3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     static_assert(16 * WI <= PAD, "row tiles must fit in the padded W~ planes");
     const int ntI = ceil_div(maxi, 16 * WI), ntC = ceil_div(maxc, 16 * WJ), ntG = ceil_div(h.ntau, T);
     const Order od = make_order(ntG * ntI, h.nk * ntC, nq);
-    hipLaunchKernelGGL((k_sig3<WI, WJ, T, PF>), dim3(grid_of(od)), dim3(64), 0, s, d, q0,
-                       (const float2*)M, G, wsc, plane, mt, mtplane, (double*)Sig, od, ntI, ntC);
-    MSGW_HIP(hipGetLastError());
+    launch_order(od, 64, [&](dim3 g, const Order& o) {
+        MSGW_LAUNCH((k_sig3<WI, WJ, T, PF>), g, dim3(64), 0, s, d, q0, (const float2*)M, G, wsc,
+                           plane, mt, mtplane, (double*)Sig, o, ntI, ntC);
+    });
 }
 
 using Sig3Fn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
@@ -1746,14 +1785,15 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     uint32_t* gz = reinterpret_cast<uint32_t*>(scratch_mfma(d, h));
     const unsigned gx = unsigned(ceil_div(gz_tp(h.ntau) * round_up(maxk, GZ_KPAD) / 2, 256));
     for (int q = q0; q < q0 + nq; ++q) {
-        hipLaunchKernelGGL(k_gtab, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, G, gz, int64_t(0));
+        MSGW_LAUNCH(k_gtab, dim3(gx, h.nk), dim3(256), 0, s, d, q, G, gz + gz_elems(h, q0, q - q0) / 2);
         MSGW_HIP(hipGetLastError());
     }
     const int ntc = gz_tp(h.ntau) / GZ_T;
     const Order od = make_order_st(ceil_div(maxi, 4 * WI), ceil_div(maxi, 16) * ntc, nq, SR, SC * ntc);
-    hipLaunchKernelGGL((k_polz<OCC, KS, WI>), dim3(grid_of(od)), dim3(128 * WI), 0, s, d, q0, (const float2*)M,
-                       (const uint32_t*)gz, (double2*)P, od);
-    MSGW_HIP(hipGetLastError());
+    launch_order(od, 128 * WI, [&](dim3 g, const Order& o) {
+        MSGW_LAUNCH((k_polz<OCC, KS, WI>), g, dim3(128 * WI), 0, s, d, q0, (const float2*)M,
+                           (const uint32_t*)gz, (double2*)P, o);
+    });
 }
 
 // pair-space self-energy: needs only the raw W~ (FP64), so it runs its own conversions
@@ -1774,16 +1814,16 @@ void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     for (int q = q0; q < q0 + nq; ++q) {
         const int NI = h.ni[q];
         const unsigned gx = ceil_div(sz_np8(NI), 32) * ceil_div(maxk, 32);
-        hipLaunchKernelGGL(k_trans32, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, (const float2*)M, mt);
+        MSGW_LAUNCH(k_trans32, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, (const float2*)M, mt);
         MSGW_HIP(hipGetLastError());
         const int64_t n = sz_blocks(NI) * gz_tp(h.ntau) * 64;
-        hipLaunchKernelGGL(k_wpair, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
+        MSGW_LAUNCH(k_wpair, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
                            (const double2*)W + (h.ppre[q] - h.ppre[q0]), NI, h.ntau, wz + woff);
         MSGW_HIP(hipGetLastError());
         woff += sz_wq(NI, h.ntau);
     }
     const int nkc = ceil_div(maxk, 512), ntc = gz_tp(h.ntau) / GZ_T;
-    hipLaunchKernelGGL((k_sigz<1>), dim3(unsigned(nq * h.nk * nkc * ntc)), dim3(512), 0, s, d, q0, G,
+    MSGW_LAUNCH((k_sigz<1>), dim3(unsigned(nq * h.nk * nkc * ntc)), dim3(512), 0, s, d, q0, G,
                        (const float2*)mt, (const uint32_t*)wz, (double*)Sig, nkc);
     MSGW_HIP(hipGetLastError());
 }
@@ -1801,9 +1841,10 @@ void run_sig7(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     static_assert(64 <= PAD, "row tiles must fit in the padded W~ planes");
     const int ntI = ceil_div(maxi, 64), ntC = ceil_div(maxc, 128), ntG = ceil_div(h.ntau, T);
     const Order od = make_order_st(ntG * ntI, h.nk * ntC, nq, SR, SC);
-    hipLaunchKernelGGL((k_sig7<T, OCC>), dim3(grid_of(od)), dim3(256), 0, s, d, q0, (const float2*)M, G,
-                       wsc, plane, mt, mtplane, (double*)Sig, od, ntI, ntC);
-    MSGW_HIP(hipGetLastError());
+    launch_order(od, 256, [&](dim3 g, const Order& o) {
+        MSGW_LAUNCH((k_sig7<T, OCC>), g, dim3(256), 0, s, d, q0, (const float2*)M, G, wsc, plane, mt,
+                           mtplane, (double*)Sig, o, ntI, ntC);
+    });
 }
 
 struct PolVariant {
@@ -1913,7 +1954,7 @@ int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
     (precision == MSGW_BF16X3 ? kPolBF16 : kPolFP32)[variant].fn(d, h, s, q0, nq, M, G, P);
     for (int q = q0; q < q0 + nq; ++q) {
         const int nt = ceil_div(h.ni[q], CW_TILE);
-        hipLaunchKernelGGL(k_herm_fill, dim3(nt * nt, h.ntau), dim3(256), 0, s,
+        MSGW_LAUNCH(k_herm_fill, dim3(nt * nt, h.ntau), dim3(256), 0, s,
                            (double2*)P + (h.ppre[q] - h.ppre[q0]), h.ni[q]);
         MSGW_HIP(hipGetLastError());
     }
@@ -1941,7 +1982,7 @@ int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
         const double2* Wq = (const double2*)W + (h.ppre[q] - h.ppre[q0]);
         static_assert(PAD % CW_TILE == 0, "conversion tiles must divide the padded planes");
         const int nt = NIp / CW_TILE;
-        hipLaunchKernelGGL(k_convert_w, dim3(nt * nt, h.ntau), dim3(256), 0, s, Wq, NI, NIp,
+        MSGW_LAUNCH(k_convert_w, dim3(nt * nt, h.ntau), dim3(256), 0, s, Wq, NI, NIp,
                            precision, reinterpret_cast<float2*>(sc) + off,
                            reinterpret_cast<uint32_t*>(sc) + off,
                            reinterpret_cast<uint32_t*>(sc) + plane + off);
@@ -1957,7 +1998,7 @@ int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
         int maxc = 0;
         for (int k = 0; k < h.nk; ++k) maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
         const unsigned gx = ceil_div(round_up(h.ni[q], 16), 32) * ceil_div(maxc, 32);
-        hipLaunchKernelGGL(k_split_mt, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, (const float2*)M, mt, mtp);
+        MSGW_LAUNCH(k_split_mt, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, (const float2*)M, mt, mtp);
         MSGW_HIP(hipGetLastError());
     }
     V.fn3(d, h, s, q0, nq, M, G, sc, plane, mt, mtp, Sig);

@@ -8,7 +8,11 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
-inline unsigned ceil_div(int64_t a, int64_t b) { return unsigned((a + b - 1) / b); }
+inline unsigned ceil_div(int64_t a, int64_t b) {
+    const int64_t r = (a + b - 1) / b;
+    if (r > int64_t(0xFFFFFFFFu)) throw Error(MSGW_ENOTSUP, "shape too large for one launch");
+    return unsigned(r);
+}
 
 __device__ __forceinline__ double2 ld_c(const void* p, int64_t i, bool c64) {
     if (c64) {
@@ -568,7 +572,7 @@ void launch_gap(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                 const double* sstat, const void* sigc, const double* mu, int n_index, double* gap) {
     (void)h;
     DysonArgs a{eps, sstat, (const double2*)sigc, d.nb, d.nk, d.nbmax, d.niw_f, d.beta, 0.0};
-    hipLaunchKernelGGL(k_gap, dim3(1), dim3(1024), 0, s, a, mu, n_index, gap);
+    MSGW_LAUNCH(k_gap, dim3(1), dim3(1024), 0, s, a, mu, n_index, gap);
     MSGW_HIP(hipGetLastError());
 }
 
@@ -577,7 +581,7 @@ void launch_gap(const Dev& d, const Host& h, hipStream_t s, const double* eps,
 // ---------------------------------------------------------------------------------------------
 void launch_green0(const Dev& d, hipStream_t s, const double* eps, double mu, double* G) {
     int64_t tot = int64_t(d.nk) * d.nbmax * d.ntau;
-    hipLaunchKernelGGL(k_green0, dim3(ceil_div(tot, 256)), dim3(256), 0, s, eps, mu, d.nb, d.tau, d.nk,
+    MSGW_LAUNCH(k_green0, dim3(ceil_div(tot, 256)), dim3(256), 0, s, eps, mu, d.nb, d.tau, d.nk,
                        d.nbmax, d.ntau, d.beta, G);
     MSGW_HIP(hipGetLastError());
 }
@@ -589,7 +593,7 @@ void launch_synth_M(const Dev& d, const Host& h, hipStream_t s, uint64_t seed, i
         for (int k = 0; k < h.nk; ++k)
             maxblk = std::max<int64_t>(maxblk, int64_t(h.ni[q]) * h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
     if (int64_t(nq) * h.nk > 65535) throw Error(MSGW_ENOTSUP, "synth_M: nq * nk must be <= 65535");
-    hipLaunchKernelGGL(k_synth, dim3(ceil_div(maxblk, 256), nq * h.nk), dim3(256), 0, s, d.kmq, d.nb, d.ni,
+    MSGW_LAUNCH(k_synth, dim3(ceil_div(maxblk, 256), nq * h.nk), dim3(256), 0, s, d.kmq, d.nb, d.ni,
                        d.moff, d.mpre, d.nk, d.nbmax, q0, seed, symmetric, m_dtype == MSGW_C64, M);
     MSGW_HIP(hipGetLastError());
 }
@@ -600,12 +604,11 @@ void launch_fwd(const Dev& d, hipStream_t s, int stat, int64_t nblk, int64_t len
     const int niw = fer ? d.niw_f : d.niw_b;
     const double2* W = fer ? d.wf : d.wb;
     dim3 grid(ceil_div(nblk * len, 256), ceil_div(niw, FCH));
-    if (grid.x > 0x7fffffff) throw Error(MSGW_ENOTSUP, "tau_to_iw: nblk * len too large");
     if (f_cplx)
-        hipLaunchKernelGGL(k_fwd<true>, grid, dim3(256), 0, s, W, niw, d.ntau, nblk, len, f, eref,
+        MSGW_LAUNCH(k_fwd<true>, grid, dim3(256), 0, s, W, niw, d.ntau, nblk, len, f, eref,
                            d.tau, d.beta, int(fer), (double2*)out);
     else
-        hipLaunchKernelGGL(k_fwd<false>, grid, dim3(256), 0, s, W, niw, d.ntau, nblk, len, f, eref,
+        MSGW_LAUNCH(k_fwd<false>, grid, dim3(256), 0, s, W, niw, d.ntau, nblk, len, f, eref,
                            d.tau, d.beta, int(fer), (double2*)out);
     MSGW_HIP(hipGetLastError());
 }
@@ -613,7 +616,7 @@ void launch_fwd(const Dev& d, hipStream_t s, int stat, int64_t nblk, int64_t len
 void launch_inv_fermion(const Dev& d, hipStream_t s, int64_t nblk, int64_t len, const void* F,
                         const double* eref, double* out) {
     dim3 grid(ceil_div(nblk * len, 256), ceil_div(d.ntau, ICH));
-    hipLaunchKernelGGL(k_inv_f, grid, dim3(256), 0, s, d.ef, d.niw_f, d.ntau, nblk, len,
+    MSGW_LAUNCH(k_inv_f, grid, dim3(256), 0, s, d.ef, d.niw_f, d.ntau, nblk, len,
                        (const double2*)F, eref, d.tau, d.beta, out);
     MSGW_HIP(hipGetLastError());
 }
@@ -621,7 +624,7 @@ void launch_inv_fermion(const Dev& d, hipStream_t s, int64_t nblk, int64_t len, 
 void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, const void* F,
                       const void* add, const double* v, void* out) {
     dim3 grid(ceil_div(nblk * int64_t(mat_n) * mat_n, 256), ceil_div(d.ntau, BCH));
-    hipLaunchKernelGGL(k_inv_b, grid, dim3(256), 0, s, d.eb, d.niw_b, d.ntau, nblk, mat_n,
+    MSGW_LAUNCH(k_inv_b, grid, dim3(256), 0, s, d.eb, d.niw_b, d.ntau, nblk, mat_n,
                        (const double2*)F, (const double2*)add, v, d.beta, (double2*)out);
     MSGW_HIP(hipGetLastError());
 }
@@ -630,10 +633,10 @@ void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
                     int m_dtype, const double* occ, const double* v, void* out, int full) {
     dim3 grid(h.nbmax, h.nk, nq);
     if (full)
-        hipLaunchKernelGGL(k_sigx_full, grid, dim3(64), 0, s, d, q0, M, m_dtype == MSGW_C64, occ, v,
+        MSGW_LAUNCH(k_sigx_full, grid, dim3(64), 0, s, d, q0, M, m_dtype == MSGW_C64, occ, v,
                            (double2*)out);
     else
-        hipLaunchKernelGGL(k_sigx_diag, grid, dim3(256), 0, s, d, q0, M, m_dtype == MSGW_C64, occ, v,
+        MSGW_LAUNCH(k_sigx_diag, grid, dim3(256), 0, s, d, q0, M, m_dtype == MSGW_C64, occ, v,
                            (double*)out);
     MSGW_HIP(hipGetLastError());
 }
@@ -643,10 +646,10 @@ void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                   void* G_iw, double* G_tau, double* n_out, int* flags) {
     DysonArgs a{eps, sstat, (const double2*)sigc, d.nb, d.nk, d.nbmax, d.niw_f, d.beta, n_target};
     double* E = scratch_E(d);
-    hipLaunchKernelGGL(k_dyson_mu, dim3(1), dim3(1024), 0, s, a, search, mu, n_out, flags, E);
+    MSGW_LAUNCH(k_dyson_mu, dim3(1), dim3(1024), 0, s, a, search, mu, n_out, flags, E);
     MSGW_HIP(hipGetLastError());
     int64_t nstate = int64_t(h.nk) * h.nbmax;
-    hipLaunchKernelGGL(k_dyson_g, dim3(ceil_div(nstate, 128), ceil_div(h.ntau, ICH)), dim3(128), 0, s, d.ef,
+    MSGW_LAUNCH(k_dyson_g, dim3(ceil_div(nstate, 128), ceil_div(h.ntau, ICH)), dim3(128), 0, s, d.ef,
                        d.tau, a, d.ntau, E, (double2*)G_iw, G_tau);
     MSGW_HIP(hipGetLastError());
 }

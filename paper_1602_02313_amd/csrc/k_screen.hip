@@ -206,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __r
 
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
                    const double* v, void* Wt_iw, void* R_iw, int* info) {
-    hipLaunchKernelGGL(k_screen, dim3(nq * h.niw_b), dim3(NT), 0, s, d, q0, (const double2*)P_iw, v,
+    MSGW_LAUNCH(k_screen, dim3(nq * h.niw_b), dim3(NT), 0, s, d, q0, (const double2*)P_iw, v,
                        (double2*)Wt_iw, (double2*)R_iw, info);
     MSGW_HIP(hipGetLastError());
 }
