@@ -2,7 +2,7 @@
 
 Each compiled variant (msgw_variant_name) of the polarization and self-energy kernels is
 launched on the run's own shapes (the first q batch), timed with HIP events, and the fastest is
-selected on the context.  Results can be cached in a JSON file keyed by the problem shape.
+selected on the context (variants within 2% of the fastest count as ties, won by the lower index).  Results can be cached in a JSON file keyed by the problem shape.
 """
 from __future__ import annotations
 
@@ -10,6 +10,16 @@ import json
 import os
 
 from . import _lib as L
+
+TIE = 0.02  # relative time difference below which the earlier (default-order) variant is kept
+
+
+def pick(times, tie=TIE):
+    """Index of the lowest-index variant within `tie` (relative) of the fastest finite time."""
+    fastest = min(times)
+    if fastest == float("inf"):
+        raise RuntimeError("no tile variant can run these shapes")
+    return next(v for v, t in enumerate(times) if t <= fastest * (1.0 + tie))
 
 
 def _key(run, op):
@@ -72,7 +82,7 @@ def tune(run, M_source, reps=2, cache_path=None, log=None, ops=None):
             times.append(min(ms))
             if log:
                 log(f"[autotune] op={op} variant {v} ({names[v]}): {min(ms):.2f} ms")
-        best = min(range(len(names)), key=lambda v: times[v])
+        best = pick(times)
         ctx.set_variant(op, run.precision, best)
         out[op] = (best, names[best], times)
         cache[key] = best

@@ -56,6 +56,11 @@ __device__ __forceinline__ uint32_t pk_bf16(float a, float b) {
     return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float bf_lo(uint32_t p) { return __uint_as_float(p << 16); }
+// the same by one byte permute (bytes 1:0 of p to 3:2, zeros below): where the compiler would rewrite
+// the shift of a fresh conversion into a second conversion of the low element
+__device__ __forceinline__ float bf_lo_perm(uint32_t p) {
+    return __uint_as_float(__builtin_amdgcn_perm(0u, p, 0x01000c0cu));
+}
 __device__ __forceinline__ float bf_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
 // split a complex pair (re, im) into packed hi and lo bf16 pairs
 __device__ __forceinline__ void split2(float re, float im, uint32_t& h, uint32_t& l) {
@@ -1306,10 +1311,10 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             uint32_t h;
             h = pk_bf16(zr[2 * e], zr[2 * e + 1]);
             z[0][e] = h;
-            z[1][e] = pk_bf16(zr[2 * e] - bf_lo(h), zr[2 * e + 1] - bf_hi(h));
+            z[1][e] = pk_bf16(zr[2 * e] - bf_lo_perm(h), zr[2 * e + 1] - bf_hi(h));
             h = pk_bf16(zi[2 * e], zi[2 * e + 1]);
             z[2][e] = h;
-            z[3][e] = pk_bf16(zi[2 * e] - bf_lo(h), zi[2 * e + 1] - bf_hi(h));
+            z[3][e] = pk_bf16(zi[2 * e] - bf_lo_perm(h), zi[2 * e + 1] - bf_hi(h));
         }
     };
     // the 18 MFMAs of one 16-K step: Z (re hi, re lo, im hi, im lo) against g (hi, lo) of 3 tau tiles
@@ -1548,32 +1553,28 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
 
     // this lane's two rows K (one per 32-row tile); rows past Kk read row Kk - 1 and are masked in
     // the epilogue
-    int Krow[2];
-    const float2* Tr[2];
+    // byte offsets of the rows from the work-group's base T (uniform base + 32-bit lane offset)
+    uint32_t trow[2];
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt) {
-        Krow[kt] = K0 + 64 * wave + 32 * kt + r32;
-        Tr[kt] = T + int64_t(min(Krow[kt], Kk - 1)) * NP;
-    }
+    for (int kt = 0; kt < 2; ++kt)
+        trow[kt] = uint32_t(min(K0 + 64 * wave + 32 * kt + r32, Kk - 1)) * uint32_t(NP * sizeof(float2));
+    const char* Tb = reinterpret_cast<const char*>(T);
 
-    // staging of one weight block: 2 planes x 96 tau x 16 chunks of 16 B = 3072 chunks, 6 per thread
-    u32x4 rw[6];
-    auto wload = [&](int64_t b) {
+    // staging of one plane (hi or lo) of a weight block: 96 tau x 16 chunks of 16 B, 3 per thread;
+    // the two planes of the next block are loaded in the two halves of the current one
+    u32x4 rw[3];
+    auto wload = [&](int64_t b, int pl) {
+        // the plane's 96 tau rows of 64 u32 are contiguous: chunk id sits at 16 id bytes
+        const char* src = reinterpret_cast<const char*>(wq0 + (pl * wlo + (b * TP + GZ_T * tc) * 64));
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            const int id = tid + 512 * i;
-            const int pl = id / (GZ_T * 16), rem = id - pl * GZ_T * 16;
-            const int t = rem >> 4, ch = rem & 15;
-            const uint32_t* src = wq0 + (pl * wlo + (b * TP + GZ_T * tc + t) * 64 + 4 * ch);
-            rw[i] = *reinterpret_cast<const u32x4*>(src);
-        }
+        for (int i = 0; i < 3; ++i)
+            rw[i] = *reinterpret_cast<const u32x4*>(src + (uint32_t(16 * tid) + uint32_t(8192 * i)));
     };
-    auto wstore = [&](int buf) {
+    auto wstore = [&](int buf, int pl) {
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < 3; ++i) {
             const int id = tid + 512 * i;
-            const int pl = id / (GZ_T * 16), rem = id - pl * GZ_T * 16;
-            const int t = rem >> 4, ch = rem & 15;
+            const int t = id >> 4, ch = id & 15;
             *reinterpret_cast<u32x4*>(&Ws[buf][pl][t][4 * ch]) = rw[i];
         }
     };
@@ -1624,18 +1625,26 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) ai[kt][e] = reinterpret_cast<const float4*>(Tr[kt] + 8 * bi)[e];
+            for (int e = 0; e < 4; ++e)
+                ai[kt][e] = *reinterpret_cast<const float4*>(Tb + (trow[kt] + uint32_t(64 * bi + 16 * e)));
     };
     auto load_aj = [&](int bj, float4 (&dst)[2][2]) {
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-            for (int e = 0; e < 2; ++e) dst[kt][e] = reinterpret_cast<const float4*>(Tr[kt] + 8 * bj + 4 * h2)[e];
+            for (int e = 0; e < 2; ++e)
+                dst[kt][e] =
+                    *reinterpret_cast<const float4*>(Tb + (trow[kt] + uint32_t(64 * bj + 32 * h2 + 16 * e)));
     };
 
     int bi = 0, bj = 0;
-    wload(0);
-    wstore(0);
+    float4 ajn[2][2];  // a_J of the next block, loaded one block ahead
+    load_ai(0);
+    load_aj(0, aj);
+    wload(0, 0);
+    wstore(0, 0);
+    wload(0, 1);
+    wstore(0, 1);
     __syncthreads();
     int buf = 0;
     int64_t b = 0;
@@ -1649,13 +1658,18 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
                 bj2 = bi2;
             }
             const bool more = b + 1 < nblk;
-            // this block's a_I and a_J (L1 / L2 hits; the other wave on the SIMD covers the wait)
-            load_ai(bi);
-            load_aj(bj, aj);
-            if (more) wload(b + 1);
+            // the next block's a_J and weights are in flight while this block computes
+            if (more) {
+                load_aj(bj2, ajn);
+                wload(b + 1, 0);
+            }
             // 8 MFMA steps: step s pairs I = 8 bi + s with J = 8 bj + 4 h2 .. + 3 (this lane's half)
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
+                if (s == 4 && more) {  // the other buffer is not read in this block
+                    wstore(buf ^ 1, 0);
+                    wload(b + 1, 1);
+                }
                 u32x4 zh[2], zl[2];
 #pragma unroll
                 for (int kt = 0; kt < 2; ++kt) {
@@ -1688,7 +1702,13 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (!more) break;
-            wstore(buf ^ 1);
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt) {
+                aj[kt][0] = ajn[kt][0];
+                aj[kt][1] = ajn[kt][1];
+            }
+            if (bi2 != bi) load_ai(bi2);  // once per row of blocks
+            wstore(buf ^ 1, 1);
             __syncthreads();
             buf ^= 1;
             bi = bi2;

@@ -225,51 +225,100 @@ __global__ void k_inv_f(const double2* __restrict__ ef, int niw, int ntau, int64
 // inverse bosonic transform of Hermitian-pair matrices, with an optional exact-in-tau term
 // add (scaled v_I add_IJ v_J when v is given)
 // ---------------------------------------------------------------------------------------------
-constexpr int BCH = 8;
+constexpr int BT = 16;    // matrix tile edge
+constexpr int BTAU = 16;  // most tau points per work-group
 
-__global__ void k_inv_b(const double2* __restrict__ eb, int niw, int ntau, int64_t nblk, int n,
-                        const double2* __restrict__ F, const double2* __restrict__ add,
-                        const double* __restrict__ v, double beta, double2* __restrict__ out) {
-    int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t nn = int64_t(n) * n;
-    if (idx >= nblk * nn) return;
-    int64_t b = idx / nn, e = idx % nn;
-    int I = int(e / n), J = int(e % n);
-    int i0 = blockIdx.y * BCH;
-    double2 acc[BCH];
-#pragma unroll
-    for (int j = 0; j < BCH; ++j) acc[j] = make_double2(0.0, 0.0);
+// One work-group per (tile pair, tau chunk, block b): the tiles (ti, tj) and (tj, ti), ti <= tj, are
+// produced together, so R(J, I) for the conjugate-pair term comes from the mirror tile through LDS and
+// every element of R is read once per tau chunk.  With p = e^{-i nu tau}, S = R(I,J) + conj R(J,I)
+// and D = R(I,J) - conj R(J,I), the pair p R(I,J) + conj(p) conj R(J,I) equals Re(p) S + i Im(p) D.
+__global__ __launch_bounds__(256) void k_inv_b(const double2* __restrict__ eb, int niw, int ntau, int n,
+                                               int nch, const double2* __restrict__ F,
+                                               const double2* __restrict__ add, const double* __restrict__ v,
+                                               double beta, double2* __restrict__ out) {
+    __shared__ double2 ta[BT][BT + 1], tb[BT][BT + 1];
+    extern __shared__ double2 ph[];  // [niw][BTAU] phases of this tau chunk
+    const int nt = (n + BT - 1) / BT;
+    int p = blockIdx.x, ti = 0;      // tile pair -> (ti, tj), rows of the upper triangle of tiles
+    while (p >= nt - ti) {
+        p -= nt - ti;
+        ++ti;
+    }
+    const int tj = ti + p;
+    const int c = blockIdx.y;
+    const int i0 = int(int64_t(c) * ntau / nch), i1 = int(int64_t(c + 1) * ntau / nch);  // <= BTAU points
+    const int64_t b = blockIdx.z, nn = int64_t(n) * n;
+    const int tid = threadIdx.x, ty = tid / BT, tx = tid % BT;
+    for (int e = tid; e < niw * BTAU; e += 256) {
+        const int w = e / BTAU, j = e % BTAU;
+        ph[e] = eb[int64_t(min(i0 + j, ntau - 1)) * niw + w];
+    }
+    const int IA = BT * ti + ty, JA = BT * tj + tx;  // element of tile A owned by this thread
+    const int IB = BT * tj + ty, JB = BT * ti + tx;  // element of tile B
+    const bool okA = IA < n && JA < n, okB = IB < n && JB < n;
+    const bool two = ti != tj;
     const double2* Fb = F + b * niw * nn;
+    const double2 z0 = make_double2(0.0, 0.0);
+    double2 accA[BTAU], accB[BTAU];
     {
-        double2 a = Fb[e];
+        const double2 a0 = okA ? Fb[int64_t(IA) * n + JA] : z0;
+        const double2 b0 = okB && two ? Fb[int64_t(IB) * n + JB] : z0;
 #pragma unroll
-        for (int j = 0; j < BCH; ++j) acc[j] = a;
+        for (int j = 0; j < BTAU; ++j) {
+            accA[j] = a0;
+            accB[j] = b0;
+        }
     }
+    __syncthreads();  // phases staged
     for (int w = 1; w < niw; ++w) {
-        double2 a = Fb[int64_t(w) * nn + e];
-        double2 t = Fb[int64_t(w) * nn + int64_t(J) * n + I];
-        // e^{-i nu tau} a + e^{+i nu tau} conj(t)
+        const double2* Fw = Fb + int64_t(w) * nn;
+        const double2 a = okA ? Fw[int64_t(IA) * n + JA] : z0;
+        const double2 bb = okB && two ? Fw[int64_t(IB) * n + JB] : z0;
+        ta[ty][tx] = a;
+        tb[ty][tx] = bb;
+        __syncthreads();
+        const double2 tA = two ? tb[tx][ty] : ta[tx][ty];  // R(JA, IA)
+        const double2 tB = ta[tx][ty];                     // R(JB, IB)
+        __syncthreads();
+        const double SAx = a.x + tA.x, SAy = a.y - tA.y, DAx = a.x - tA.x, DAy = a.y + tA.y;
+        const double SBx = bb.x + tB.x, SBy = bb.y - tB.y, DBx = bb.x - tB.x, DBy = bb.y + tB.y;
+        const double2* pw = ph + w * BTAU;
 #pragma unroll
-        for (int j = 0; j < BCH; ++j) {
-            int i = min(i0 + j, ntau - 1);
-            double2 p = eb[int64_t(i) * niw + w];
-            acc[j].x += (p.x * a.x - p.y * a.y) + (p.x * t.x - p.y * t.y);
-            acc[j].y += (p.x * a.y + p.y * a.x) - (p.x * t.y + p.y * t.x);
+        for (int j = 0; j < BTAU; ++j) {
+            const double2 q = pw[j];
+            accA[j].x += q.x * SAx - q.y * DAy;
+            accA[j].y += q.x * SAy + q.y * DAx;
+            accB[j].x += q.x * SBx - q.y * DBy;
+            accB[j].y += q.x * SBy + q.y * DBx;
         }
     }
-    double vv = v ? v[I] * v[J] : 1.0;
+    const double ib = 1.0 / beta;
+    const double vA = okA && v ? v[IA] * v[JA] : 1.0, vB = okB && v ? v[IB] * v[JB] : 1.0;
 #pragma unroll
-    for (int j = 0; j < BCH; ++j) {
-        int i = i0 + j;
-        if (i >= ntau) break;
-        int64_t at = (b * ntau + i) * nn + e;
-        double2 r = make_double2(acc[j].x / beta, acc[j].y / beta);
-        if (add) {
-            double2 a = add[at];
-            r.x += vv * a.x;
-            r.y += vv * a.y;
+    for (int j = 0; j < BTAU; ++j) {
+        const int i = i0 + j;
+        if (i >= i1) break;
+        const int64_t base = (b * ntau + i) * nn;
+        if (okA) {
+            const int64_t at = base + int64_t(IA) * n + JA;
+            double2 r = make_double2(accA[j].x * ib, accA[j].y * ib);
+            if (add) {
+                const double2 x = add[at];
+                r.x += vA * x.x;
+                r.y += vA * x.y;
+            }
+            out[at] = r;
         }
-        out[at] = r;
+        if (okB && two) {
+            const int64_t at = base + int64_t(IB) * n + JB;
+            double2 r = make_double2(accB[j].x * ib, accB[j].y * ib);
+            if (add) {
+                const double2 x = add[at];
+                r.x += vB * x.x;
+                r.y += vB * x.y;
+            }
+            out[at] = r;
+        }
     }
 }
 
@@ -623,9 +672,14 @@ void launch_inv_fermion(const Dev& d, hipStream_t s, int64_t nblk, int64_t len, 
 
 void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, const void* F,
                       const void* add, const double* v, void* out) {
-    dim3 grid(ceil_div(nblk * int64_t(mat_n) * mat_n, 256), ceil_div(d.ntau, BCH));
-    MSGW_LAUNCH(k_inv_b, grid, dim3(256), 0, s, d.eb, d.niw_b, d.ntau, nblk, mat_n,
-                       (const double2*)F, (const double2*)add, v, d.beta, (double2*)out);
+    const int64_t nt = ceil_div(mat_n, BT);
+    const int nch = int(ceil_div(d.ntau, BTAU));
+    const size_t lds = sizeof(double2) * size_t(d.niw_b) * BTAU;
+    if (lds > 48 * 1024) throw Error(MSGW_ENOTSUP, "iw_to_tau: niw_b must be <= 192 for BOSON matrices");
+    if (nblk > 65535) throw Error(MSGW_ENOTSUP, "iw_to_tau: at most 65535 BOSON matrices per call");
+    dim3 grid(ceil_div(nt * (nt + 1) / 2, 1), nch, unsigned(nblk));
+    MSGW_LAUNCH(k_inv_b, grid, dim3(256), lds, s, d.eb, d.niw_b, d.ntau, mat_n, nch, (const double2*)F,
+                (const double2*)add, v, d.beta, (double2*)out);
     MSGW_HIP(hipGetLastError());
 }
 
