@@ -169,8 +169,11 @@ def main():
         run.sig_x.zero_()
         run.q_block(src, 0, min(args.q_batch, cfg.nk))
         torch.cuda.synchronize()
+        vp = run.ctx.get_variant(amd.OP_POLARIZATION, prec)
+        vs = run.ctx.get_variant(amd.OP_SELF_ENERGY, prec)
         log(f"[bench] profile batch done: copy of {args.copy_mb} MB, q 0..{args.q_batch - 1}, variants "
-            f"P {run.ctx.get_variant(amd.OP_POLARIZATION, prec)} S {run.ctx.get_variant(amd.OP_SELF_ENERGY, prec)}")
+            f"P {vp} ({run.ctx.variants(amd.OP_POLARIZATION, prec)[vp]}) "
+            f"S {vs} ({run.ctx.variants(amd.OP_SELF_ENERGY, prec)[vs]})")
         return
     tuned = {}
     if not args.no_autotune and None in fixed.values():
