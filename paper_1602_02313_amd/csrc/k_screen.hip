@@ -4,7 +4,7 @@
 // partial (row) pivoting, then W~ = v^1/2 (A^-1 - 1) v^1/2 and R = W~ - v P v.  This is the
 // W~ Dyson equation W~ = v P v + v P W~ after the tau convolution becomes a product on i nu.
 //
-// One work-group of 1024 threads owns one matrix (n <= 1024).  Panel of SB columns:
+// One work-group of NT = 1024 threads owns one matrix (n <= 1024).  Panel of SB = 16 columns:
 //   1. for each panel column j: pick the pivot row (max |re| + |im| over rows >= j), swap the
 //      full rows, scale the pivot row and eliminate column j from every other row -- on the
 //      panel columns only.  The panel then holds the columns J of T = E_last ... E_first.
@@ -16,9 +16,8 @@
 namespace msgw {
 namespace {
 
-constexpr int SB = 16;      // panel width
 constexpr int RCH = 64;     // rows of the panel staged in LDS per chunk of the update
-constexpr int NT = 1024;
+constexpr int UR = 3;       // rows of a column updated per group of loads
 
 __device__ __forceinline__ double2 cmuls(double2 a, double2 b) { return cmul(a, b); }
 
@@ -29,6 +28,7 @@ __device__ __forceinline__ double2 crecip(double2 a) {
     return make_double2(ax / den, -ay / den);
 }
 
+template <int NT, int SB>
 __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __restrict__ Piw,
                                                const double* __restrict__ v,
                                                double2* __restrict__ Wt, double2* __restrict__ R,
@@ -38,8 +38,8 @@ __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __r
     __shared__ int idx[MSGW_MAX_NI];
     __shared__ double2 buf[MSGW_MAX_NI];        // pivot column multipliers / row buffer
     __shared__ double2 tch[RCH][SB];
-    __shared__ double rv[16];
-    __shared__ int ri[16];
+    __shared__ double rv[NT / 64];
+    __shared__ int ri[NT / 64];
     __shared__ int s_info;
 
     const int mi = blockIdx.x;
@@ -138,9 +138,10 @@ __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __r
             }
             __syncthreads();
         }
-        // ---- update of the columns outside the panel: c <- c + (T[:,J] - I[:,J]) c[J]
-        const int c = tid;
-        const bool own = (c < n) && (c < j0 || c >= j0 + jb);
+        // ---- update of the columns outside the panel: c <- c + (T[:,J] - I[:,J]) c[J]; NT / n threads
+        // share a column, each taking every tpc-th group of UR rows
+        const int tpc = NT / n, c = tid % n, sub = tid / n;
+        const bool own = sub < tpc && (c < j0 || c >= j0 + jb);
         double2 cj[SB];
 #pragma unroll
         for (int t = 0; t < SB; ++t)
@@ -155,17 +156,27 @@ __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __r
             __syncthreads();
             if (own) {
                 const int rmax = min(RCH, n - i0);
-                for (int r = 0; r < rmax; ++r) {
-                    const int i = i0 + r;
-                    double2 s = (i >= j0 && i < j0 + jb) ? make_double2(0.0, 0.0)
-                                                          : A[int64_t(i) * n + c];
+                // UR rows at a time: their loads are in flight together
+                for (int r0 = sub * UR; r0 < rmax; r0 += tpc * UR) {
+                    double2 sr[UR];
 #pragma unroll
-                    for (int t = 0; t < SB; ++t) {
-                        const double2 tv = tch[r][t];
-                        s.x += tv.x * cj[t].x - tv.y * cj[t].y;
-                        s.y += tv.x * cj[t].y + tv.y * cj[t].x;
+                    for (int u = 0; u < UR; ++u) {
+                        const int i = i0 + r0 + u;
+                        sr[u] = (r0 + u >= rmax || (i >= j0 && i < j0 + jb)) ? make_double2(0.0, 0.0)
+                                                                             : A[int64_t(i) * n + c];
                     }
-                    A[int64_t(i) * n + c] = s;
+#pragma unroll
+                    for (int u = 0; u < UR; ++u) {
+                        if (r0 + u >= rmax) break;
+                        double2 s = sr[u];
+#pragma unroll
+                        for (int t = 0; t < SB; ++t) {
+                            const double2 tv = tch[r0 + u][t];
+                            s.x += tv.x * cj[t].x - tv.y * cj[t].y;
+                            s.y += tv.x * cj[t].y + tv.y * cj[t].x;
+                        }
+                        A[int64_t(i0 + r0 + u) * n + c] = s;
+                    }
                 }
             }
         }
@@ -206,8 +217,8 @@ __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __r
 
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
                    const double* v, void* Wt_iw, void* R_iw, int* info) {
-    MSGW_LAUNCH(k_screen, dim3(nq * h.niw_b), dim3(NT), 0, s, d, q0, (const double2*)P_iw, v,
-                       (double2*)Wt_iw, (double2*)R_iw, info);
+    MSGW_LAUNCH((k_screen<1024, 16>), dim3(nq * h.niw_b), dim3(1024), 0, s, d, q0, (const double2*)P_iw, v,
+                (double2*)Wt_iw, (double2*)R_iw, info);
     MSGW_HIP(hipGetLastError());
 }
 
