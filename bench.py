@@ -101,6 +101,92 @@ def cpu_baseline(cfg, prob, budget_s=12.0):
                       f"{cores} BLAS threads"}
 
 
+def batching_study(args):
+    """One launch over all (k, tau) blocks of a q against one launch per k block, on one q.
+
+    The uneven 6x6x6-k workload (Nb_k in [96, 160], NI_q in [500, 900], 121 tau points) by default,
+    on its q with the largest NI; split-BF16 pair-space kernels, M resident in HBM.  Prints one JSON
+    line with both times for the polarization and the self-energy and the relative difference of the
+    two results (they differ only in where the FP32 partial sums are flushed to FP64).
+    """
+    import torch
+    import gwinputs as gi
+    import paper_1602_02313_amd as amd
+
+    cfg = gi.CONFIGS[args.config]
+    prob = gi.make_problem(cfg)
+    q = int(np.argmax(prob.ni))
+    run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
+                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=amd.BF16X3, q_batch=1)
+    M = torch.empty(int(run.mpre[q + 1] - run.mpre[q]), dtype=torch.complex64, device="cuda")
+    run.ctx.synth_M(cfg.seed, q, 1, 1, amd.C64, M)
+    run.green0(0.0)
+    NI, ntau = int(prob.ni[q]), int(prob.tau.size)
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    W = run.Wt_tau[:ntau * NI * NI]
+    W.copy_(torch.randn(W.shape, dtype=torch.complex128, device="cuda", generator=gen) * 1e-3)
+    ctx, B = run.ctx, amd.BF16X3
+    fp, fs = 0.0, 0.0
+    for k in range(cfg.nk):
+        kk = int(prob.nb[k]) * int(prob.nb[prob.kmq[q, k]])
+        fp += 8.0 * NI * NI * kk * ntau
+        fs += 8.0 * NI * NI * kk * ntau + 8.0 * NI * kk * ntau
+    log(f"[batching] {cfg.name} q={q} NI={NI}: M {M.numel() * 8 / 1e9:.1f} GB")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    def p_one():
+        ctx.polarization(q, 1, M, amd.C64, run.G_tau, B, run.P_tau)
+
+    P2 = torch.empty(ntau * NI * NI, dtype=torch.complex128, device="cuda")
+
+    def p_loop():
+        for k in range(cfg.nk):
+            ctx.set_k_range(k, k + 1, reuse_prepared=k > 0)
+            ctx.polarization(q, 1, M, amd.C64, run.G_tau, B, P2)
+        ctx.set_k_range()
+
+    def s_one():
+        run.sig_tau.zero_()
+        ctx.self_energy(q, 1, M, amd.C64, run.G_tau, run.Wt_tau, B, run.sig_tau)
+
+    sig_loop = torch.zeros_like(run.sig_tau)
+
+    def s_loop():
+        sig_loop.zero_()
+        for k in range(cfg.nk):
+            ctx.set_k_range(k, k + 1, reuse_prepared=k > 0)
+            ctx.self_energy(q, 1, M, amd.C64, run.G_tau, run.Wt_tau, B, sig_loop)
+        ctx.set_k_range()
+
+    res = {}
+    for name, one, loop, nfl in (("polarization", p_one, p_loop, fp), ("self_energy", s_one, s_loop, fs)):
+        one()
+        t1 = min(timed(one) for _ in range(2))
+        loop()
+        tl = min(timed(loop) for _ in range(2))
+        log(f"[batching] {name}: one launch {t1:.1f} ms, {cfg.nk} launches {tl:.1f} ms")
+        res[name] = {"one_launch_ms": round(t1, 2), "per_k_loop_ms": round(tl, 2),
+                     "launches_in_loop": cfg.nk, "loop_over_one": round(tl / t1, 3),
+                     "one_launch_tflops": round(nfl / (t1 / 1e3) / 1e12, 1)}
+    n = ntau * NI * NI
+    a, b = run.P_tau[:n], P2
+    res["polarization"]["loop_vs_one_rel"] = float((a - b).abs().norm() / a.abs().norm())
+    a, b = run.sig_tau, sig_loop
+    res["self_energy"]["loop_vs_one_rel"] = float((a - b).norm() / a.norm())
+    print(json.dumps({"study": "batching: all (k, tau) blocks of a q in one launch vs one launch per k",
+                      "workload": f"{cfg.name}, q = {q} (NI = {NI}), {cfg.nk} k blocks with uneven band "
+                                  f"counts, {ntau} tau points, split-BF16 pair-space kernels",
+                      "unit": "ms", **res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,12 +209,20 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=1024)
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the iteration captured as a HIP graph (no per-kernel times)")
+    ap.add_argument("--batching", action="store_true",
+                    help="instead of the pass: one launch vs a per-k launch loop on one q of --config "
+                         "(default c4, the uneven workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): there is no "
               f"multi-GPU path; it would shard the q axis over GPUs with one all-reduce of Sigma "
               f"per iteration, which is not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.batching:
+        if args.config == "c2":
+            args.config = "c4"
+        batching_study(args)
+        return
 
     import torch
     import gwinputs as gi

@@ -232,6 +232,15 @@ int msgw_set_variant(msgw_ctx* c, int op, int precision, int variant);
 /* The variant currently selected on c for (op, precision), written to *variant (host int). */
 int msgw_get_variant(const msgw_ctx* c, int op, int precision, int* variant);
 
+/* Harness-only (the batching study): restrict the following MSGW_BF16X3 pair-space polarization and
+ * self-energy calls on c to the k blocks k0 <= k < k1, so that a loop over k reproduces one full call
+ * launch by launch.  A polarization with k0 > 0 ADDS its blocks to P_tau (k0 == 0 overwrites); the
+ * self-energy accumulates as always.  reuse_prepared != 0 skips the per-q preparations (the g planes
+ * of the polarization, the weight blocks of the self-energy) and reuses what the previous call of the
+ * same op and q batch left in the workspace.  k1 <= 0 restores the full range.  While a partial range
+ * is set, the other tile variants and precisions return MSGW_ENOTSUP. */
+int msgw_set_k_range(msgw_ctx* c, int k0, int k1, int reuse_prepared);
+
 /* ---- input generation (not part of the method) ---------------------------------------------- */
 
 /* Synthetic M for q0..q0+nq-1 in the layout above (c128 or c64): complex Gaussian with

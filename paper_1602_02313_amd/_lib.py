@@ -31,6 +31,7 @@ EXPORTS = [
     "msgw_polarization", "msgw_tau_to_iw", "msgw_iw_to_tau", "msgw_screen",
     "msgw_screened_tau", "msgw_self_energy", "msgw_sigma_x", "msgw_dyson", "msgw_gap",
     "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant", "msgw_get_variant",
+    "msgw_set_k_range",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 
@@ -100,6 +101,8 @@ def load_library():
     lib.msgw_set_variant.restype = ctypes.c_int
     lib.msgw_get_variant.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_int)]
     lib.msgw_get_variant.restype = ctypes.c_int
+    lib.msgw_set_k_range.argtypes = [P, I, I, I]
+    lib.msgw_set_k_range.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -249,6 +252,10 @@ class Context:
         if rc != 0:
             raise MsgwError(rc, "bad op or precision")
         return out.value
+
+    def set_k_range(self, k0=0, k1=0, reuse_prepared=False):
+        """Harness only: restrict the pair-space contractions to k blocks [k0, k1) (k1 <= 0: all)."""
+        self._check(self.lib.msgw_set_k_range(self._c, int(k0), int(k1), int(bool(reuse_prepared))))
 
     def synth_M(self, seed, q0, nq, symmetric, m_dtype, M, stream=None):
         self._check(self.lib.msgw_synth_M(self._c, _stream(stream), int(seed), q0, nq,

@@ -333,6 +333,8 @@ int msgw_set_workspace(msgw_ctx* c, void* dptr, size_t bytes) {
         need(off == tb, MSGW_EINVAL, "internal: table size mismatch");
         d.scratch = base + off;
         d.scratch_bytes = bytes - off;
+        d.kb0 = 0;
+        d.kb1 = h.nk;
         c->d = d;
         c->ws = base;
         c->ws_bytes = bytes;
@@ -372,12 +374,16 @@ int msgw_synth_M(msgw_ctx* c, void* stream, uint64_t seed, int q0, int nq, int s
     });
 }
 
+static bool full_k_range(const msgw_ctx* c) { return c->d.kb0 == 0 && c->d.kb1 == c->h.nk; }
+
 int msgw_polarization(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
                       const double* G_tau, int precision, void* P_tau) {
     return guarded(c, [&] {
         require_ready(c);
         check_qrange(c, q0, nq);
         need(M && G_tau && P_tau, MSGW_EINVAL, "null pointer");
+        need(full_k_range(c) || precision == MSGW_BF16X3, MSGW_ENOTSUP,
+             "a partial k range is supported by the MSGW_BF16X3 pair-space kernels only");
         if (precision == MSGW_FP64) {
             need(m_dtype == MSGW_C128, MSGW_EINVAL, "MSGW_FP64 needs MSGW_C128 M");
             launch_pol_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, P_tau);
@@ -462,6 +468,8 @@ int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, i
         require_ready(c);
         check_qrange(c, q0, nq);
         need(M && G_tau && Wt_tau && Sigma_tau, MSGW_EINVAL, "null pointer");
+        need(full_k_range(c) || (precision == MSGW_BF16X3 && c->h.sigma_mode != MSGW_SIGMA_FULL), MSGW_ENOTSUP,
+             "a partial k range is supported by the MSGW_BF16X3 pair-space kernels only");
         if (c->h.sigma_mode == MSGW_SIGMA_FULL) {
             need(precision == MSGW_FP64 && m_dtype == MSGW_C128, MSGW_ENOTSUP,
                  "MSGW_SIGMA_FULL runs in MSGW_FP64 with MSGW_C128 M");
@@ -524,6 +532,21 @@ int msgw_set_variant(msgw_ctx* c, int op, int precision, int variant) {
         need(n > 0, MSGW_EINVAL, "bad op or precision");
         need(variant >= 0 && variant < n, MSGW_EINVAL, "variant out of range");
         c->variant[op][precision] = variant;
+    });
+}
+
+int msgw_set_k_range(msgw_ctx* c, int k0, int k1, int reuse_prepared) {
+    return guarded(c, [&] {
+        require_ready(c);
+        if (k1 <= 0) {
+            k0 = 0;
+            k1 = c->h.nk;
+            reuse_prepared = 0;
+        }
+        need(k0 >= 0 && k0 < k1 && k1 <= c->h.nk, MSGW_EINVAL, "k range outside [0, nk]");
+        c->d.kb0 = k0;
+        c->d.kb1 = k1;
+        c->d.kreuse = reuse_prepared ? 1 : 0;
     });
 }
 

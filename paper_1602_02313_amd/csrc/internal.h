@@ -58,6 +58,8 @@ struct Dev {
     const int64_t* vpre = nullptr;    // [nk+1]  prefix over q of NI_q
     char* scratch = nullptr;          // per-call scratch
     size_t scratch_bytes = 0;
+    int kb0 = 0, kb1 = 0;             // k blocks [kb0, kb1) of the pair-space contractions
+    int kreuse = 0;                   // 1: the per-q operands prepared by the previous call are reused
 };
 
 // Host mirror of the problem (used for launch shapes and validation).

@@ -724,180 +724,6 @@ __global__ __launch_bounds__(256) void k_split_mt(Dev d, int q0, int q, const fl
     }
 }
 
-template <int WI, int WJ, int T, bool PF>
-__global__ __launch_bounds__(64) void k_sig3(Dev d, int q0, const float2* __restrict__ M,
-                                             const double* __restrict__ G,
-                                             const char* __restrict__ wsc, int64_t plane,
-                                             const uint32_t* __restrict__ mt, int64_t mtplane,
-                                             double* __restrict__ Sig, Order od, int ntI, int ntC) {
-    int qrel, r, c;
-    if (!work_item(od, qrel, r, c)) return;
-    const int lane = threadIdx.x, r16 = lane & 15, g4 = lane >> 4;
-    const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
-    const int q = q0 + qrel;
-    const int tg = r / ntI, ti = r - tg * ntI;
-    const int k = c / ntC, tc = c - k * ntC;
-    const int kq = d.kmq[q * nk + k];
-    const int nm = d.nb[kq], NI = d.ni[q];
-    const int Kk = d.nb[k] * nm;
-    const int i0 = ti * 16 * WI, c0 = tc * 16 * WJ, t0 = tg * T;
-    if (i0 >= NI || c0 >= Kk) return;
-    const int NIp = (NI + PAD - 1) / PAD * PAD, NIp16 = (NI + 15) / 16 * 16;
-    int64_t wq = 0;
-    for (int qq = q0; qq < q; ++qq) {
-        const int np = (d.ni[qq] + PAD - 1) / PAD * PAD;
-        wq += int64_t(ntau) * np * np;
-    }
-    const uint32_t* whi = reinterpret_cast<const uint32_t*>(wsc) + wq;
-    const uint32_t* wlo = reinterpret_cast<const uint32_t*>(wsc) + plane + wq;
-    const int64_t mb0 = mt_qbase(d, q0, q) + d.moff[q * nk + k] / NI * NIp16;
-    const float2* A = M + (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
-
-    int colr[WJ];
-    uint32_t keep[WJ];
-#pragma unroll
-    for (int b = 0; b < WJ; ++b) {
-        const int col = c0 + 16 * b + r16;
-        colr[b] = min(col, Kk - 1);
-        keep[b] = col < Kk ? 0xffffffffu : 0u;
-    }
-    floatx4 acc[WI][WJ][T][2];
-#pragma unroll
-    for (int a = 0; a < WI; ++a)
-#pragma unroll
-        for (int b = 0; b < WJ; ++b)
-#pragma unroll
-            for (int t = 0; t < T; ++t) acc[a][b][t][0] = acc[a][b][t][1] = floatx4{0, 0, 0, 0};
-    int tau_[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) tau_[t] = min(t0 + t, ntau - 1);
-
-    const int nsteps = NIp16 / 16;
-    // raw bf16 operands of step s (B: split M columns; A: W~ rows for each tau)
-    auto load_raw = [&](int s, u32x4 (&bh)[WJ], u32x4 (&bl)[WJ], u32x4 (&wh)[WI][T], u32x4 (&wl)[WI][T]) {
-        const int jb = s * 16;
-#pragma unroll
-        for (int b = 0; b < WJ; ++b) {
-            const int64_t at = mb0 + int64_t(colr[b]) * NIp16 + jb + 4 * g4;
-            bh[b] = *reinterpret_cast<const u32x4*>(mt + at);
-            bl[b] = *reinterpret_cast<const u32x4*>(mt + mtplane + at);
-        }
-#pragma unroll
-        for (int t = 0; t < T; ++t)
-#pragma unroll
-            for (int a = 0; a < WI; ++a) {
-                const int64_t at = (int64_t(tau_[t]) * NIp + i0 + 16 * a + r16) * NIp + jb + 4 * g4;
-                wh[a][t] = *reinterpret_cast<const u32x4*>(whi + at);
-                wl[a][t] = *reinterpret_cast<const u32x4*>(wlo + at);
-            }
-    };
-    u32x4 rbh[WJ], rbl[WJ], rwh[WI][T], rwl[WI][T];
-    if (PF) load_raw(i0 / 16, rbh, rbl, rwh, rwl);
-    for (int s = i0 / 16; s < nsteps; ++s) {
-        u32x4 nbh[WJ], nbl[WJ], nwh[WI][T], nwl[WI][T];
-        if (PF) {
-            if (s + 1 < nsteps) load_raw(s + 1, nbh, nbl, nwh, nwl);
-        } else {
-            load_raw(s, rbh, rbl, rwh, rwl);
-        }
-        u32x4 bh_re[WJ], bl_re[WJ], bh_im[WJ], bl_im[WJ];
-#pragma unroll
-        for (int b = 0; b < WJ; ++b) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t he = rbh[b][e] & keep[b], le = rbl[b][e] & keep[b];
-                bh_re[b][e] = conj_pk(he);
-                bl_re[b][e] = conj_pk(le);
-                bh_im[b][e] = swap_pk(he);
-                bl_im[b][e] = swap_pk(le);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-#pragma unroll
-            for (int a = 0; a < WI; ++a) {
-                const u32x4 ah = rwh[a][t];
-                const u32x4 al = rwl[a][t];
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-                    acc[a][b][t][0] = mfma_bf16(ah, bh_re[b], acc[a][b][t][0]);
-                    acc[a][b][t][1] = mfma_bf16(ah, bh_im[b], acc[a][b][t][1]);
-                }
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-                    acc[a][b][t][0] = mfma_bf16(ah, bl_re[b], acc[a][b][t][0]);
-                    acc[a][b][t][1] = mfma_bf16(ah, bl_im[b], acc[a][b][t][1]);
-                }
-#pragma unroll
-                for (int b = 0; b < WJ; ++b) {
-                    acc[a][b][t][0] = mfma_bf16(al, bh_re[b], acc[a][b][t][0]);
-                    acc[a][b][t][1] = mfma_bf16(al, bh_im[b], acc[a][b][t][1]);
-                }
-            }
-        }
-        if (PF) {
-#pragma unroll
-            for (int b = 0; b < WJ; ++b) {
-                rbh[b] = nbh[b];
-                rbl[b] = nbl[b];
-            }
-#pragma unroll
-            for (int a = 0; a < WI; ++a)
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    rwh[a][t] = nwh[a][t];
-                    rwl[a][t] = nwl[a][t];
-                }
-        }
-    }
-
-    const double sc = 2.0 * d.scale;  // both triangles of U
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int it = t0 + t;
-        if (it >= ntau) break;
-        double part[WJ];
-#pragma unroll
-        for (int b = 0; b < WJ; ++b) {
-            const int col = c0 + 16 * b + r16;
-            float s = 0.f;
-            if (col < Kk) {
-#pragma unroll
-                for (int a = 0; a < WI; ++a)
-#pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) {
-                        const int I = i0 + 16 * a + 4 * g4 + rr;
-                        if (I < NI) {
-                            const float2 m = A[int64_t(I) * Kk + col];
-                            s += m.x * acc[a][b][t][0][rr] + m.y * acc[a][b][t][1][rr];
-                        }
-                    }
-            }
-            double v = s;
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            if (col < Kk) {
-                const int m = col - (col / nm) * nm;
-                v *= G[(int64_t(kq) * nbmax + m) * ntau + it];
-            }
-            part[b] = v;
-        }
-        const int cl = min(c0 + 16 * WJ, Kk) - 1;
-        const int nlo = c0 / nm, nhi = cl / nm;
-        for (int nx = nlo; nx <= nhi; ++nx) {
-            double v = 0.0;
-#pragma unroll
-            for (int b = 0; b < WJ; ++b) {
-                const int col = c0 + 16 * b + r16;
-                if (col < Kk && col / nm == nx) v += part[b];
-            }
-#pragma unroll
-            for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o);
-            if (lane == 0) atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], sc * v);
-        }
-    }
-}
-
 // =================================================================================================
 // 32x32x16 MFMA helpers
 // =================================================================================================
@@ -1387,11 +1213,15 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     };
 
     // stages run over (k, slab); the FP32 accumulators go to FP64 every 4096 terms
-    int k = 0, slab = 0, since = 0;
-    Blk blk = block_of(0);
-    blk.g = gz + (gq >> 1);
+    // k blocks [kb0, kb1) (all of them unless a partial range is set); a range that starts past k = 0
+    // adds to P
+    const int kend = d.kb1;
+    int k = d.kb0, slab = 0, since = 0;
+    first = k == 0;
+    Blk blk = block_of(k);
+    blk.g = gz + (gz_block(d, q0, q, k) >> 1);
     int nsl = (blk.KP + KS - 1) / KS;
-    while (nsl == 0 && k + 1 < nk) {
+    while (nsl == 0 && k + 1 < kend) {
         blk = next_block(blk, ++k);
         nsl = (blk.KP + KS - 1) / KS;
     }
@@ -1402,7 +1232,7 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     while (true) {
         int k2 = k, s2 = slab + 1, n2 = nsl;
         Blk b2 = blk;
-        while (s2 >= n2 && k2 + 1 < nk) {
+        while (s2 >= n2 && k2 + 1 < kend) {
             ++k2;
             s2 = 0;
             b2 = next_block(b2, k2);
@@ -1456,7 +1286,7 @@ __device__ __host__ __forceinline__ int sz_np8(int ni) { return (ni + 7) / 8 * 8
 __global__ __launch_bounds__(256) void k_trans32(Dev d, int q0, int q, const float2* __restrict__ M,
                                                  float2* __restrict__ mt) {
     __shared__ float2 tile[32][33];
-    const int nk = d.nk, k = blockIdx.y;
+    const int nk = d.nk, k = d.kb0 + int(blockIdx.y);
     const int NI = d.ni[q], NP = sz_np8(NI);
     const int Kk = d.nb[k] * d.nb[d.kmq[q * nk + k]];
     const int nti = (NP + 31) / 32;
@@ -1533,7 +1363,8 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
     w /= ntc;
     const int kc = w % nkc;
     w /= nkc;
-    const int k = w % nk, qrel = w / nk, q = q0 + qrel;
+    const int nkr = d.kb1 - d.kb0;
+    const int k = d.kb0 + w % nkr, qrel = w / nkr, q = q0 + qrel;
     const int kq = d.kmq[q * nk + k];
     const int nm = d.nb[kq], Kk = d.nb[k] * nm;
     const int K0 = kc * 512;
@@ -1757,26 +1588,6 @@ void run_sig(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const v
     });
 }
 
-// v3 self-energy: needs the split, transposed M planes (uses the `mt` arguments)
-template <int WI, int WJ, int T, bool PF = false>
-void run_sig3(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
-              const double* G, const char* wsc, int64_t plane, const uint32_t* mt, int64_t mtplane,
-              void* Sig) {
-    int maxi = 0, maxc = 0;
-    for (int q = q0; q < q0 + nq; ++q) {
-        maxi = std::max(maxi, h.ni[q]);
-        for (int k = 0; k < h.nk; ++k)
-            maxc = std::max(maxc, h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]]);
-    }
-    static_assert(16 * WI <= PAD, "row tiles must fit in the padded W~ planes");
-    const int ntI = ceil_div(maxi, 16 * WI), ntC = ceil_div(maxc, 16 * WJ), ntG = ceil_div(h.ntau, T);
-    const Order od = make_order(ntG * ntI, h.nk * ntC, nq);
-    launch_order(od, 64, [&](dim3 g, const Order& o) {
-        MSGW_LAUNCH((k_sig3<WI, WJ, T, PF>), g, dim3(64), 0, s, d, q0, (const float2*)M, G, wsc,
-                           plane, mt, mtplane, (double*)Sig, o, ntI, ntC);
-    });
-}
-
 using Sig3Fn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
                         const char*, int64_t, const uint32_t*, int64_t, void*);
 
@@ -1804,7 +1615,7 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
         throw Error(MSGW_ENOMEM, "workspace too small for the g planes");
     uint32_t* gz = reinterpret_cast<uint32_t*>(scratch_mfma(d, h));
     const unsigned gx = unsigned(ceil_div(gz_tp(h.ntau) * round_up(maxk, GZ_KPAD) / 2, 256));
-    for (int q = q0; q < q0 + nq; ++q) {
+    for (int q = q0; q < q0 + nq && !d.kreuse; ++q) {
         MSGW_LAUNCH(k_gtab, dim3(gx, h.nk), dim3(256), 0, s, d, q, G, gz + gz_elems(h, q0, q - q0) / 2);
         MSGW_HIP(hipGetLastError());
     }
@@ -1834,16 +1645,18 @@ void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     for (int q = q0; q < q0 + nq; ++q) {
         const int NI = h.ni[q];
         const unsigned gx = ceil_div(sz_np8(NI), 32) * ceil_div(maxk, 32);
-        MSGW_LAUNCH(k_trans32, dim3(gx, h.nk), dim3(256), 0, s, d, q0, q, (const float2*)M, mt);
+        MSGW_LAUNCH(k_trans32, dim3(gx, d.kb1 - d.kb0), dim3(256), 0, s, d, q0, q, (const float2*)M, mt);
         MSGW_HIP(hipGetLastError());
         const int64_t n = sz_blocks(NI) * gz_tp(h.ntau) * 64;
-        MSGW_LAUNCH(k_wpair, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
-                           (const double2*)W + (h.ppre[q] - h.ppre[q0]), NI, h.ntau, wz + woff);
-        MSGW_HIP(hipGetLastError());
+        if (!d.kreuse) {
+            MSGW_LAUNCH(k_wpair, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
+                        (const double2*)W + (h.ppre[q] - h.ppre[q0]), NI, h.ntau, wz + woff);
+            MSGW_HIP(hipGetLastError());
+        }
         woff += sz_wq(NI, h.ntau);
     }
     const int nkc = ceil_div(maxk, 512), ntc = gz_tp(h.ntau) / GZ_T;
-    MSGW_LAUNCH((k_sigz<1>), dim3(unsigned(nq * h.nk * nkc * ntc)), dim3(512), 0, s, d, q0, G,
+    MSGW_LAUNCH((k_sigz<1>), dim3(unsigned(nq * (d.kb1 - d.kb0) * nkc * ntc)), dim3(512), 0, s, d, q0, G,
                        (const float2*)mt, (const uint32_t*)wz, (double*)Sig, nkc);
     MSGW_HIP(hipGetLastError());
 }
@@ -1870,6 +1683,7 @@ void run_sig7(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
 struct PolVariant {
     const char* name;
     PolFn fn;
+    bool ranged = false;  // honours a partial k range (pair space)
 };
 using SigZFn = void (*)(const Dev&, const Host&, hipStream_t, int, int, const void*, const double*,
                         const void*, void*);
@@ -1882,13 +1696,10 @@ struct SigVariant {
 
 // index 0 of each table is the default (the fastest on the 4x4x4-k, 64-band, NI = 400 shapes)
 const PolVariant kPolBF16[] = {
-    {"pair-space 16x16 pairs K64 st4x8", run_polz<1, 4, 8, 64, 4>},
-    {"pair-space 8x16 pairs 2 WG/CU st4x16 K64", run_polz<2, 4, 16, 64>},
-    {"pair-space 8x16 pairs 2 WG/CU st4x16", run_polz<2, 4, 16>},
+    {"pair-space 16x16 pairs K64 st4x8", run_polz<1, 4, 8, 64, 4>, true},
+    {"pair-space 8x16 pairs 2 WG/CU st4x16 K64", run_polz<2, 4, 16, 64>, true},
+    {"pair-space 8x16 pairs 2 WG/CU st4x16", run_polz<2, 4, 16>, true},
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3>},
-    {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_BF16X3>},
-    {"WI4 WJ1 T4", run_pol<4, 1, 4, PREC_BF16X3>},
-    {"prefetch WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3, true>},
 };
 const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
@@ -1897,15 +1708,7 @@ const PolVariant kPolFP32[] = {
 const SigVariant kSigBF16[] = {
     {"pair-space 512 K x 8x8-pair blocks", nullptr, nullptr, run_sigz},
     {"LDS 2-stage 64x128 T2 2 WG/CU st8x8", nullptr, run_sig7<2, 8, 8, 2>},
-    {"LDS 2-stage 64x128 T2 2 WG/CU st4x16", nullptr, run_sig7<2, 4, 16, 2>},
-    {"LDS 2-stage 64x128 T4", nullptr, run_sig7<4>},
-    {"LDS 2-stage 64x128 T3", nullptr, run_sig7<3>},
-    {"LDS 2-stage 64x128 T4 st8x4", nullptr, run_sig7<4, 8, 4>},
     {"WI2 WJ4 T4", run_sig<2, 4, 4, PREC_BF16X3>, nullptr},
-    {"WI4 WJ4 T2", run_sig<4, 4, 2, PREC_BF16X3>, nullptr},
-    {"WI2 WJ8 T2", run_sig<2, 8, 2, PREC_BF16X3>, nullptr},
-    {"split-M WI2 WJ4 T2", nullptr, run_sig3<2, 4, 2>},
-    {"split-M prefetch WI2 WJ2 T2", nullptr, run_sig3<2, 2, 2, true>},
 };
 const SigVariant kSigFP32[] = {
     {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>, nullptr},
@@ -1971,7 +1774,9 @@ int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
     if (h.nbmax > NB_LDS) return MSGW_ENOTSUP;
     const int n = mfma_variant_count(MSGW_OP_POLARIZATION, precision);
     if (variant < 0 || variant >= n) return MSGW_EINVAL;
-    (precision == MSGW_BF16X3 ? kPolBF16 : kPolFP32)[variant].fn(d, h, s, q0, nq, M, G, P);
+    const PolVariant& V = (precision == MSGW_BF16X3 ? kPolBF16 : kPolFP32)[variant];
+    if ((d.kb0 != 0 || d.kb1 != h.nk) && !V.ranged) return MSGW_ENOTSUP;
+    V.fn(d, h, s, q0, nq, M, G, P);
     for (int q = q0; q < q0 + nq; ++q) {
         const int nt = ceil_div(h.ni[q], CW_TILE);
         MSGW_LAUNCH(k_herm_fill, dim3(nt * nt, h.ntau), dim3(256), 0, s,
@@ -1986,6 +1791,7 @@ int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
     const int nv = mfma_variant_count(MSGW_OP_SELF_ENERGY, precision);
     if (variant < 0 || variant >= nv) return MSGW_EINVAL;
     const SigVariant& V = (precision == MSGW_BF16X3 ? kSigBF16 : kSigFP32)[variant];
+    if ((d.kb0 != 0 || d.kb1 != h.nk) && !V.fnz) return MSGW_ENOTSUP;
     if (V.fnz) {
         V.fnz(d, h, s, q0, nq, M, G, W, Sig);
         return MSGW_OK;
