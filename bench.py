@@ -174,7 +174,7 @@ def batching_study(args):
         tl = min(timed(loop) for _ in range(2))
         log(f"[batching] {name}: one launch {t1:.1f} ms, {cfg.nk} launches {tl:.1f} ms")
         res[name] = {"one_launch_ms": round(t1, 2), "per_k_loop_ms": round(tl, 2),
-                     "launches_in_loop": cfg.nk, "loop_over_one": round(tl / t1, 3),
+                     "calls_in_loop": cfg.nk, "loop_over_one": round(tl / t1, 3),
                      "one_launch_tflops": round(nfl / (t1 / 1e3) / 1e12, 1)}
     n = ntau * NI * NI
     a, b = run.P_tau[:n], P2

@@ -1026,23 +1026,25 @@ __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __rest
 // columns.  Each stage brings KS K of the block's 4 WI + 16 rows of M and of the g planes through LDS
 // (double buffered); each lane forms Z for its pair and 8 K per MFMA step and splits it into bf16
 // hi/lo.  A larger WI shares every staged g plane among more pairs.
-template <int OCC, int KS, int WI>
+// NTT 32-wide tau tiles per work item (a chunk of CW = 32 NTT tau columns): three for the chunks of 96,
+// one or two for a tail chunk; the launch covers ntc chunks starting at tau t0.
+template <int OCC, int KS, int WI, int NTT>
 __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const float2* __restrict__ M,
                                                         const uint32_t* __restrict__ gz,
-                                                        double2* __restrict__ P, Order od) {
-    constexpr int NT = 128 * WI, XROWS = 4 * WI + 16;
+                                                        double2* __restrict__ P, Order od, int t0, int ntc) {
+    constexpr int NT = 128 * WI, XROWS = 4 * WI + 16, CW = 32 * NTT;
     static_assert(KS % GZ_KS == 0, "stages hold whole 32-K slabs of the g planes");
-    static_assert((XROWS * KS) % NT == 0 && (2 * GZ_T * KS / 8) % NT == 0, "stage split over threads");
-    constexpr int XR = 2 * KS + 4, GR = KS / 2 + 4, NX = XROWS * KS / NT, NG = 2 * GZ_T * KS / 8 / NT;
-    __shared__ float Xs[2][XROWS][XR];       // [buffer][row: 4 WI rows I then 16 rows J][K re, im]
-    __shared__ uint32_t Gs[2][2][GZ_T][GR];  // [buffer][hi, lo][tau][K pair]
+    static_assert((XROWS * KS) % NT == 0 && (2 * CW * KS / 8) % NT == 0, "stage split over threads");
+    constexpr int XR = 2 * KS + 4, GR = KS / 2 + 4, NX = XROWS * KS / NT, NG = 2 * CW * KS / 8 / NT;
+    __shared__ float Xs[2][XROWS][XR];     // [buffer][row: 4 WI rows I then 16 rows J][K re, im]
+    __shared__ uint32_t Gs[2][2][CW][GR];  // [buffer][hi, lo][tau][K pair]
     int qrel, r, c;
     if (!work_item(od, qrel, r, c)) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h2 = lane >> 5;
     const int q = q0 + qrel, nk = d.nk, ntau = d.ntau;
     const int NI = d.ni[q];
-    const int ntc = gz_tp(d.ntau) / GZ_T, cj = c / ntc, tc = c - cj * ntc;  // tau chunk tc
-    const int I0 = r * 4 * WI, J0 = cj * 16, TP = ntc * GZ_T;
+    const int cj = c / ntc, tc = c - cj * ntc;  // tau chunk tc of this launch
+    const int I0 = r * 4 * WI, J0 = cj * 16, TP = gz_tp(ntau), tb = t0 + CW * tc;
     if (I0 >= NI || J0 >= NI || J0 + 16 <= I0) return;  // uniform; below the diagonal: mirrored later
     const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
     double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
@@ -1086,11 +1088,10 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         constexpr int CH = KS / 8;  // 16-B chunks per g row of a stage
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
-            const int id = tid + NT * i;             // 2 planes x 96 tau x CH chunks of 4 u32
-            const int pl = id / (GZ_T * CH), rem = id - pl * GZ_T * CH;
+            const int id = tid + NT * i;             // 2 planes x CW tau x CH chunks of 4 u32
+            const int pl = id / (CW * CH), rem = id - pl * CW * CH;
             const int t = rem / CH, ch = rem % CH;
-            rg[i] = *reinterpret_cast<const u32x4*>(b.g + (int64_t(pl * TP + GZ_T * tc + t) * b.KP + K0) / 2 +
-                                                    4 * ch);
+            rg[i] = *reinterpret_cast<const u32x4*>(b.g + (int64_t(pl * TP + tb + t) * b.KP + K0) / 2 + 4 * ch);
         }
     };
     auto lstore = [&](int buf) {
@@ -1105,15 +1106,15 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
             const int id = tid + NT * i;
-            const int pl = id / (GZ_T * CH), rem = id - pl * GZ_T * CH;
+            const int pl = id / (CW * CH), rem = id - pl * CW * CH;
             const int t = rem / CH, ch = rem % CH;
             *reinterpret_cast<u32x4*>(&Gs[buf][pl][t][4 * ch]) = rg[i];
         }
     };
 
-    floatx16 acc[3][2];  // [tau tile][re, im]
+    floatx16 acc[NTT][2];  // [tau tile][re, im]
 #pragma unroll
-    for (int tt = 0; tt < 3; ++tt) {
+    for (int tt = 0; tt < NTT; ++tt) {
         zero16(acc[tt][0]);
         zero16(acc[tt][1]);
     }
@@ -1143,10 +1144,10 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             z[3][e] = pk_bf16(zi[2 * e] - bf_lo_perm(h), zi[2 * e + 1] - bf_hi(h));
         }
     };
-    // the 18 MFMAs of one 16-K step: Z (re hi, re lo, im hi, im lo) against g (hi, lo) of 3 tau tiles
+    // the 6 NTT MFMAs of one 16-K step: Z (re hi, re lo, im hi, im lo) against g (hi, lo) per tau tile
     auto mmas = [&](int buf, int kk, const u32x4 (&z)[4]) {
 #pragma unroll
-        for (int tt = 0; tt < 3; ++tt) {
+        for (int tt = 0; tt < NTT; ++tt) {
             const u32x4* grow = reinterpret_cast<const u32x4*>(&Gs[buf][0][32 * tt + r32][0]);
             const u32x4* lrow = reinterpret_cast<const u32x4*>(&Gs[buf][1][32 * tt + r32][0]);
             const u32x4 gh = grow[2 * kk + h2], gl = lrow[2 * kk + h2];
@@ -1174,9 +1175,9 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             }
             if (kk + 1 < KS / 16) {
 #pragma unroll
-                for (int i = 0; i < 18; ++i) {
+                for (int i = 0; i < 6 * NTT; ++i) {
                     __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
-                    __builtin_amdgcn_sched_group_barrier(0x002, 6, 0);  // then up to six VALU
+                    __builtin_amdgcn_sched_group_barrier(0x002, 18 / NTT, 0);  // then the VALU share
                 }
             }
         }
@@ -1188,8 +1189,8 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         int z = 0;  // opaque zero: keeps the output addresses out of the main loop
         asm volatile("" : "+v"(z));
 #pragma unroll
-        for (int tt = 0; tt < 3; ++tt) {
-            const int it = GZ_T * tc + 32 * tt + r32 + z;
+        for (int tt = 0; tt < NTT; ++tt) {
+            const int it = tb + 32 * tt + r32 + z;
 #pragma unroll
             for (int x = 0; x < 16; ++x) {
                 const int p = 8 * (x >> 2) + 4 * h2 + (x & 3);
@@ -1342,21 +1343,23 @@ __global__ __launch_bounds__(256) void k_wpair(const double2* __restrict__ W, in
     wz[nblk * TP * 64 + blk * 64 + 8 * s + j] = l;
 }
 
-// Work-group = 8 waves over 512 rows K of one (q, k) block and one 96-wide tau chunk; wave w owns
+// Work-group = 8 waves over 512 rows K of one (q, k) block and one tau chunk of NTT 32-wide tiles
+// (three, or one or two for a tail chunk; the launch covers ntc chunks from tau t0); wave w owns
 // rows K0 + 64 w .. + 63 as two 32-row MFMA tiles.  The work-group walks the weight blocks in order;
 // each block (48 KB, hi and lo) is staged through LDS (double-buffered) while the previous one is
 // used.  Every lane forms Z for its rows K and 4 pairs per MFMA step from the transposed FP32 M
 // (the 8 values a_I of the block row stay in registers across the block row), splits it into
 // bf16 hi/lo, and the FP32 accumulators go through the epilogue (G_m weight, sum over the m of each
 // band n, FP64 atomic) every 32 blocks.
-template <int OCC>
+template <int OCC, int NTT>
 __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* __restrict__ G,
                                                    const float2* __restrict__ mt,
                                                    const uint32_t* __restrict__ wz,
-                                                   double* __restrict__ Sig, int nkc) {
-    __shared__ uint32_t Ws[2][2][GZ_T][SZ_WR];  // [buffer][hi, lo][tau][8 s x 8 j]
+                                                   double* __restrict__ Sig, int nkc, int t0, int ntc) {
+    constexpr int CW = 32 * NTT;
+    __shared__ uint32_t Ws[2][2][CW][SZ_WR];  // [buffer][hi, lo][tau][8 s x 8 j]
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
-    const int ntc = gz_tp(ntau) / GZ_T, TP = ntc * GZ_T;
+    const int TP = gz_tp(ntau);
     // work item: (q, k, K chunk of 512, tau chunk)
     int w = blockIdx.x;
     const int tc = w % ntc;
@@ -1372,6 +1375,7 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
     const int NI = d.ni[q], NP = sz_np8(NI), nb = sz_nb8(NI);
     const int64_t nblk = sz_blocks(NI);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h2 = lane >> 5;
+    const int tb = t0 + CW * tc;  // first tau of the chunk
 
     int64_t mq = 0, wq = 0;
     for (int qq = q0; qq < q; ++qq) {
@@ -1391,30 +1395,30 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
         trow[kt] = uint32_t(min(K0 + 64 * wave + 32 * kt + r32, Kk - 1)) * uint32_t(NP * sizeof(float2));
     const char* Tb = reinterpret_cast<const char*>(T);
 
-    // staging of one plane (hi or lo) of a weight block: 96 tau x 16 chunks of 16 B, 3 per thread;
+    // staging of one plane (hi or lo) of a weight block: CW tau x 16 chunks of 16 B, NTT per thread;
     // the two planes of the next block are loaded in the two halves of the current one
-    u32x4 rw[3];
+    u32x4 rw[NTT];
     auto wload = [&](int64_t b, int pl) {
-        // the plane's 96 tau rows of 64 u32 are contiguous: chunk id sits at 16 id bytes
-        const char* src = reinterpret_cast<const char*>(wq0 + (pl * wlo + (b * TP + GZ_T * tc) * 64));
+        // the chunk's CW tau rows of 64 u32 are contiguous: chunk id sits at 16 id bytes
+        const char* src = reinterpret_cast<const char*>(wq0 + (pl * wlo + (b * TP + tb) * 64));
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+        for (int i = 0; i < NTT; ++i)
             rw[i] = *reinterpret_cast<const u32x4*>(src + (uint32_t(16 * tid) + uint32_t(8192 * i)));
     };
     auto wstore = [&](int buf, int pl) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
+        for (int i = 0; i < NTT; ++i) {
             const int id = tid + 512 * i;
             const int t = id >> 4, ch = id & 15;
             *reinterpret_cast<u32x4*>(&Ws[buf][pl][t][4 * ch]) = rw[i];
         }
     };
 
-    floatx16 acc[2][3];
+    floatx16 acc[2][NTT];
 #pragma unroll
     for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-        for (int tt = 0; tt < 3; ++tt) zero16(acc[kt][tt]);
+        for (int tt = 0; tt < NTT; ++tt) zero16(acc[kt][tt]);
 
     const double sc = d.scale;
     // epilogue on the accumulators: weight each row K = (n, m) by G_m(k-q, tau), sum the rows of
@@ -1428,8 +1432,8 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
             if (kb >= Kk) continue;
             const int nlo = kb / nm, nhi = (min(kb + 32, Kk) - 1) / nm;
 #pragma unroll
-            for (int tt = 0; tt < 3; ++tt) {
-                const int it = GZ_T * tc + 32 * tt + r32;
+            for (int tt = 0; tt < NTT; ++tt) {
+                const int it = tb + 32 * tt + r32;
                 const int itc = min(it, ntau - 1);
                 for (int nx = nlo; nx <= nhi; ++nx) {
                     float v = 0.f;  // 16 terms; the run totals are summed in FP64
@@ -1518,7 +1522,7 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
                     }
                 }
 #pragma unroll
-                for (int tt = 0; tt < 3; ++tt) {
+                for (int tt = 0; tt < NTT; ++tt) {
                     const u32x4* hrow = reinterpret_cast<const u32x4*>(&Ws[buf][0][32 * tt + r32][0]);
                     const u32x4* lrow = reinterpret_cast<const u32x4*>(&Ws[buf][1][32 * tt + r32][0]);
                     const u32x4 bh = hrow[2 * s + h2], bl = lrow[2 * s + h2];
@@ -1619,12 +1623,18 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
         MSGW_LAUNCH(k_gtab, dim3(gx, h.nk), dim3(256), 0, s, d, q, G, gz + gz_elems(h, q0, q - q0) / 2);
         MSGW_HIP(hipGetLastError());
     }
-    const int ntc = gz_tp(h.ntau) / GZ_T;
-    const Order od = make_order_st(ceil_div(maxi, 4 * WI), ceil_div(maxi, 16) * ntc, nq, SR, SC * ntc);
-    launch_order(od, 128 * WI, [&](dim3 g, const Order& o) {
-        MSGW_LAUNCH((k_polz<OCC, KS, WI>), g, dim3(128 * WI), 0, s, d, q0, (const float2*)M,
-                           (const uint32_t*)gz, (double2*)P, o);
-    });
+    // tau in chunks of three 32-wide tiles, the last chunk with the one or two tiles left
+    const int ntiles = ceil_div(h.ntau, 32), n3 = ntiles / 3, rest = ntiles % 3;
+    auto launch = [&](auto kern, int t0, int ntc) {
+        const Order od = make_order_st(ceil_div(maxi, 4 * WI), ceil_div(maxi, 16) * ntc, nq, SR, SC * ntc);
+        launch_order(od, 128 * WI, [&](dim3 g, const Order& o) {
+            MSGW_LAUNCH(kern, g, dim3(128 * WI), 0, s, d, q0, (const float2*)M, (const uint32_t*)gz, (double2*)P, o,
+                        t0, ntc);
+        });
+    };
+    if (n3 > 0) launch(k_polz<OCC, KS, WI, 3>, 0, n3);
+    if (rest == 1) launch(k_polz<OCC, KS, WI, 1>, 96 * n3, 1);
+    if (rest == 2) launch(k_polz<OCC, KS, WI, 2>, 96 * n3, 1);
 }
 
 // pair-space self-energy: needs only the raw W~ (FP64), so it runs its own conversions
@@ -1655,10 +1665,16 @@ void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
         }
         woff += sz_wq(NI, h.ntau);
     }
-    const int nkc = ceil_div(maxk, 512), ntc = gz_tp(h.ntau) / GZ_T;
-    MSGW_LAUNCH((k_sigz<1>), dim3(unsigned(nq * (d.kb1 - d.kb0) * nkc * ntc)), dim3(512), 0, s, d, q0, G,
-                       (const float2*)mt, (const uint32_t*)wz, (double*)Sig, nkc);
-    MSGW_HIP(hipGetLastError());
+    // tau in chunks of three 32-wide tiles, the last chunk with the one or two tiles left
+    const int nkc = ceil_div(maxk, 512), ntiles = ceil_div(h.ntau, 32), n3 = ntiles / 3, rest = ntiles % 3;
+    auto launch = [&](auto kern, int t0, int ntc) {
+        MSGW_LAUNCH(kern, dim3(ceil_div(int64_t(nq) * (d.kb1 - d.kb0) * nkc * ntc, 1)), dim3(512), 0, s, d, q0, G,
+                    (const float2*)mt, (const uint32_t*)wz, (double*)Sig, nkc, t0, ntc);
+        MSGW_HIP(hipGetLastError());
+    };
+    if (n3 > 0) launch(k_sigz<1, 3>, 0, n3);
+    if (rest == 1) launch(k_sigz<1, 1>, 96 * n3, 1);
+    if (rest == 2) launch(k_sigz<1, 2>, 96 * n3, 1);
 }
 
 template <int T, int SR = 4, int SC = 8, int OCC = 1>
