@@ -199,8 +199,9 @@ int msgw_sigma_x(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m
 /* a8. Dyson update of the diagonal G on the fermionic axis and the chemical potential:
  * E = eps + sigma_static - mu;  G(i w_n) = 1/(i w_n - E - Sigma^c(i w_n));
  * N(mu) = sum_nk [n_F(E) + (2/beta) sum_{n<niw_f} Re(G - 1/(i w_n - E))];
- * MSGW_MU_SEARCH: mu by 200 fixed bisection steps on [min(eps+sigma_static) - 50/beta,
- * max(...) + 50/beta] so that N(mu) = n_target (device-side, graph-capturable);
+ * MSGW_MU_SEARCH: mu so that N(mu) = n_target, on the bracket [min(eps+sigma_static) - 50/beta,
+ * max(...) + 50/beta], by 8 fixed rounds of 256-section (N at 257 points of the bracket per round,
+ * the bracket shrinks by 2^64 in all; device-side, a fixed number of launches, graph-capturable);
  * MSGW_MU_FIXED: mu is read from *mu.  Then G(tau) by the FERMION inverse transform with
  * e_ref = E.  mu, n_out: device f64 scalars (mu in/out); flags: device int (MSGW_FLAG_*).
  * G_iw may be NULL. */

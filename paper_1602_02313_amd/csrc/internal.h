@@ -105,11 +105,16 @@ int mfma_variant_count(int op, int precision);
 const char* mfma_variant_name(int op, int precision, int variant);
 size_t mfma_scratch_bytes(const Host& h, int nq_max);
 
-// Scratch layout: [E array of msgw_dyson: nk*nbmax doubles][MFMA conversion buffers].
+// Scratch layout: [E array of msgw_dyson: nk*nbmax doubles][mu search state: 8 KB][MFMA conversion
+// buffers].
+constexpr size_t kMuSearchBytes = 8192;
 inline size_t scratch_E_bytes(const Host& h) {
-    return (sizeof(double) * size_t(h.nk) * h.nbmax + 255) & ~size_t(255);
+    return ((sizeof(double) * size_t(h.nk) * h.nbmax + 255) & ~size_t(255)) + kMuSearchBytes;
 }
 inline double* scratch_E(const Dev& d) { return reinterpret_cast<double*>(d.scratch); }
+inline double* scratch_mu_search(const Dev& d, const Host& h) {
+    return reinterpret_cast<double*>(d.scratch + scratch_E_bytes(h) - kMuSearchBytes);
+}
 inline char* scratch_mfma(const Dev& d, const Host& h) { return d.scratch + scratch_E_bytes(h); }
 inline size_t scratch_mfma_bytes(const Dev& d, const Host& h) {
     return d.scratch_bytes > scratch_E_bytes(h) ? d.scratch_bytes - scratch_E_bytes(h) : 0;

@@ -430,11 +430,36 @@ __device__ double number_partial(const DysonArgs& a, const double* E0, double mu
     return part;
 }
 
-__global__ __launch_bounds__(1024) void k_dyson_mu(DysonArgs a, int search, double* mu_io,
-                                                   double* n_out, int* flags, double* Eout) {
-    __shared__ double red[16];
+// ---- chemical potential: multisection on N(mu) = n_target ------------------------------------------
+// Each round evaluates N at MS_S + 2 equally spaced points of the bracket [lo, hi] (ends included), one
+// work-group per point, and the next round (or the final kernel) narrows the bracket to the cell where
+// N - n_target changes sign: a factor MS_S + 1 = 256 per round, 2^64 after MS_ROUNDS rounds.  The
+// number of launches is fixed, so the search can be captured in a graph.  Search state in scratch
+// (doubles): br[2][2] (bracket of the round, ping-pong), Nv[2][MS_S + 2], flags (as a double).
+constexpr int MS_S = 255;
+constexpr int MS_ROUNDS = 8;
+constexpr int MS_NV = MS_S + 2;
+__device__ __forceinline__ double* ms_br(double* st, int r) { return st + 2 * (r & 1); }
+__device__ __forceinline__ double* ms_nv(double* st, int r) { return st + 4 + MS_NV * (r & 1); }
+__device__ __forceinline__ double* ms_fl(double* st) { return st + 4 + 2 * MS_NV; }
+
+// the bracket after round r: the cell [mu_j, mu_j+1] of round r's points that holds the sign change
+// (the end of the old bracket where every point is on one side)
+__device__ void ms_narrow(double* st, int r, double target, double& lo, double& hi) {
+    const double* br = ms_br(st, r);
+    const double* N = ms_nv(st, r);
+    const double l0 = br[0], h0 = br[1];
+    int jl = -1;
+    for (int j = 0; j < MS_NV; ++j)
+        if (N[j] < target) jl = j;
+    auto at = [&](int j) { return l0 + (h0 - l0) * (double(j) / double(MS_S + 1)); };
+    lo = jl >= 0 ? at(jl) : l0;
+    hi = jl + 1 < MS_NV ? at(jl + 1) : h0;
+}
+
+// E0 = eps + Sigma_static (written to Eout), NaN check, initial bracket
+__global__ __launch_bounds__(1024) void k_dyson_prep(DysonArgs a, double* Eout, double* st) {
     const int64_t nstate = int64_t(a.nk) * a.nbmax;
-    // E0 = eps + sstat, written to Eout as scratch first
     double lo = 1e300, hi = -1e300;
     int bad = 0;
     for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
@@ -453,7 +478,6 @@ __global__ __launch_bounds__(1024) void k_dyson_mu(DysonArgs a, int search, doub
             if (!isfinite(s.x) || !isfinite(s.y)) bad = 1;
         }
     }
-    // min / max / or via shuffles + LDS
     for (int o = 32; o > 0; o >>= 1) {
         lo = fmin(lo, __shfl_xor(lo, o));
         hi = fmax(hi, __shfl_xor(hi, o));
@@ -468,34 +492,65 @@ __global__ __launch_bounds__(1024) void k_dyson_mu(DysonArgs a, int search, doub
         rbad[w] = bad;
     }
     __syncthreads();
-    lo = 1e300;
-    hi = -1e300;
-    bad = 0;
-    for (int i = 0; i < nw; ++i) {
-        lo = fmin(lo, rlo[i]);
-        hi = fmax(hi, rhi[i]);
-        bad |= rbad[i];
+    if (threadIdx.x == 0) {
+        lo = 1e300;
+        hi = -1e300;
+        bad = 0;
+        for (int i = 0; i < nw; ++i) {
+            lo = fmin(lo, rlo[i]);
+            hi = fmax(hi, rhi[i]);
+            bad |= rbad[i];
+        }
+        double* br = ms_br(st, 0);
+        br[0] = lo - 50.0 / a.beta;
+        br[1] = hi + 50.0 / a.beta;
+        *ms_fl(st) = bad ? double(MSGW_FLAG_NAN) : 0.0;
     }
-    int fl = bad ? MSGW_FLAG_NAN : 0;
+}
+
+// round r: narrow the bracket of round r - 1 (r > 0), then N at point blockIdx.x of the new bracket
+__global__ __launch_bounds__(1024) void k_dyson_round(DysonArgs a, const double* __restrict__ E, double* st,
+                                                      int r) {
+    __shared__ double red[16];
+    double lo, hi;
+    if (r == 0) {
+        lo = ms_br(st, 0)[0];
+        hi = ms_br(st, 0)[1];
+    } else {
+        ms_narrow(st, r - 1, a.n_target, lo, hi);
+    }
+    const int j = blockIdx.x;
+    const double mu = lo + (hi - lo) * (double(j) / double(MS_S + 1));
+    const double N = block_sum(number_partial(a, E, mu), red);
+    if (threadIdx.x == 0) {
+        ms_nv(st, r)[j] = N;
+        if (j == 0) {
+            ms_br(st, r)[0] = lo;
+            ms_br(st, r)[1] = hi;
+        }
+        if (r == 1 && j == 0) {  // the ends of the first bracket were points 0 and MS_S + 1 of round 0
+            const double* N0 = ms_nv(st, 0);
+            if (!(N0[0] <= a.n_target && a.n_target <= N0[MS_NV - 1]))
+                *ms_fl(st) = double(int(*ms_fl(st)) | MSGW_FLAG_NOBRACKET);
+        }
+    }
+}
+
+// final: mu (the middle of the last bracket, or the given one), N(mu), flags, E0 - mu
+__global__ __launch_bounds__(1024) void k_dyson_mu(DysonArgs a, int search, double* mu_io, double* n_out,
+                                                   int* flags, double* Eout, double* st) {
+    __shared__ double red[16];
+    const int64_t nstate = int64_t(a.nk) * a.nbmax;
     double mu;
     if (search) {
-        lo -= 50.0 / a.beta;
-        hi += 50.0 / a.beta;
-        double Nlo = block_sum(number_partial(a, Eout, lo), red);
-        double Nhi = block_sum(number_partial(a, Eout, hi), red);
-        if (!(Nlo <= a.n_target && a.n_target <= Nhi)) fl |= MSGW_FLAG_NOBRACKET;
-        for (int s = 0; s < 200; ++s) {
-            double mid = 0.5 * (lo + hi);
-            double N = block_sum(number_partial(a, Eout, mid), red);
-            if (N < a.n_target)
-                lo = mid;
-            else
-                hi = mid;
-        }
+        double lo, hi;
+        ms_narrow(st, MS_ROUNDS - 1, a.n_target, lo, hi);
         mu = 0.5 * (lo + hi);
     } else {
         mu = *mu_io;
     }
+    int fl = int(*ms_fl(st));
+    if (!search) fl &= ~MSGW_FLAG_NOBRACKET;
     double N = block_sum(number_partial(a, Eout, mu), red);
     if (!isfinite(N)) fl |= MSGW_FLAG_NAN;
     __syncthreads();
@@ -700,7 +755,15 @@ void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                   void* G_iw, double* G_tau, double* n_out, int* flags) {
     DysonArgs a{eps, sstat, (const double2*)sigc, d.nb, d.nk, d.nbmax, d.niw_f, d.beta, n_target};
     double* E = scratch_E(d);
-    MSGW_LAUNCH(k_dyson_mu, dim3(1), dim3(1024), 0, s, a, search, mu, n_out, flags, E);
+    double* st = scratch_mu_search(d, h);
+    static_assert(sizeof(double) * (5 + 2 * MS_NV) <= kMuSearchBytes, "mu search state fits its scratch");
+    MSGW_LAUNCH(k_dyson_prep, dim3(1), dim3(1024), 0, s, a, E, st);
+    MSGW_HIP(hipGetLastError());
+    for (int r = 0; search && r < MS_ROUNDS; ++r) {
+        MSGW_LAUNCH(k_dyson_round, dim3(MS_NV), dim3(1024), 0, s, a, E, st, r);
+        MSGW_HIP(hipGetLastError());
+    }
+    MSGW_LAUNCH(k_dyson_mu, dim3(1), dim3(1024), 0, s, a, search, mu, n_out, flags, E, st);
     MSGW_HIP(hipGetLastError());
     int64_t nstate = int64_t(h.nk) * h.nbmax;
     MSGW_LAUNCH(k_dyson_g, dim3(ceil_div(nstate, 128), ceil_div(h.ntau, ICH)), dim3(128), 0, s, d.ef,
