@@ -9,3 +9,4 @@ Every function follows a passage of Chu et al., "All-electron self-consistent
 GW in the Matsubara-time domain" (arXiv:1602.02313), cited in its docstring.
 """
 from .gw import *  # noqa: F401,F403
+from .continuation import *  # noqa: F401,F403

@@ -527,3 +527,103 @@ def test_planted_polarization_mistakes_are_caught(toy, kind):
         got = bad(toy.M[q], Gb, toy.kmq[q], toy.s)
         worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
     assert worst > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# analytic continuation (Pade) and quasiparticle energies
+# ---------------------------------------------------------------------------
+_POLES = np.array([-0.7, 0.2, 1.1])
+_RES = np.array([0.05, 0.1, 0.03])
+
+
+def _rational(z):
+    """A causal three-pole self-energy sum_i r_i / (z - p_i) (r_i > 0)."""
+    return np.sum(_RES / (np.asarray(z)[..., None] - _POLES), axis=-1)
+
+
+@pytest.mark.parametrize("n_pade", [6, 7, 10, 24])
+def test_pade_reproduces_a_rational_self_energy(n_pade):
+    """Three poles make a [2/3] rational function: six Matsubara points determine it, and the
+    continued fraction through them (or more) reproduces it on the real axis."""
+    beta = 50.0
+    z = o.matsubara_points(n_pade, beta)
+    a = o.pade_coefficients(z, _rational(z)[None])
+    w = np.linspace(-2.0, 2.0, 81) + 0.01j
+    c = o.pade_eval(z, a, w[None])[0]
+    assert np.max(np.abs(c - _rational(w)) / np.abs(_rational(w))) < 1e-8
+    # interpolation property at the data points themselves
+    assert np.allclose(o.pade_eval(z, a, z[None])[0], _rational(z), rtol=1e-12, atol=0)
+
+
+def test_pade_derivative_matches_closed_form():
+    beta, n = 50.0, 10
+    z = o.matsubara_points(n, beta)
+    a = o.pade_coefficients(z, _rational(z)[None])
+    w = np.linspace(-1.5, 1.5, 7) + 0.05j
+    c, dc = o.pade_eval_and_derivative(z, a, w[None])
+    exact = -np.sum(_RES / (w[:, None] - _POLES) ** 2, axis=-1)
+    assert np.allclose(dc[0], exact, rtol=1e-7, atol=0)
+
+
+def test_qp_energy_one_pole_closed_form():
+    """Sigma(z) = r / (z - p): x = e0 + r / (x - p) is a quadratic; Newton from e0 reaches the root
+    nearest e0."""
+    beta, p, r = 50.0, 0.8, 0.04
+    e0 = np.array([[-0.5, 0.3, 1.5, 0.9]])
+    w = (2 * np.arange(32) + 1) * np.pi / beta
+    sig = np.broadcast_to(r / (1j * w - p), (1, 4, 32))
+    E, ok = o.qp_energies(e0, [4], np.zeros_like(e0), sig, 0.0, beta, 8, 0.0)
+    assert ok.all()
+    for x, e in zip(E[0], e0[0]):
+        roots = np.roots([1.0, -(e + p), e * p - r])
+        assert abs(x - roots[np.argmin(np.abs(roots - e))]) < 1e-12
+    # mu shifts the energies rigidly
+    E2, _ = o.qp_energies(e0 + 0.25, [4], np.zeros_like(e0), sig, 0.25, beta, 8, 0.0)
+    assert np.allclose(E2, E + 0.25, rtol=0, atol=1e-12)
+
+
+def test_spectral_function_sum_rule_and_peak():
+    """A(w) of a causal self-energy integrates to one; a static self-energy gives a Lorentzian of
+    half-width eta at e0 + Sigma."""
+    beta, eta = 50.0, 0.02
+    w = (2 * np.arange(32) + 1) * np.pi / beta
+    sig = (0.04 / (1j * w - 0.8))[None, None, :]
+    om = np.linspace(-40.0, 40.0, 400001)
+    A = o.spectral(np.array([[0.3]]), np.zeros((1, 1)), sig, 0.0, beta, 8, eta, om)[0, 0]
+    assert abs(np.trapezoid(A, om) - 1.0) < 2e-3
+    static = np.full((1, 1, 8), 0.1 + 0j)
+    A0 = o.spectral(np.array([[0.3]]), np.zeros((1, 1)), static, 0.0, beta, 1, eta, om)[0, 0]
+    lor = eta / np.pi / ((om - 0.4) ** 2 + eta ** 2)
+    assert np.max(np.abs(A0 - lor)) < 1e-12 * lor.max()
+
+
+def test_qp_gap_orders_states():
+    E = np.array([[0.3, -0.2, 9.0], [0.1, -0.5, 0.7]])
+    assert o.qp_gap(E, [2, 3], 2) == pytest.approx(0.1 - (-0.2))
+    assert o.qp_gap(E, [2, 3], 3) == pytest.approx(0.3 - 0.1)
+
+
+@pytest.mark.parametrize("kind", ["sign", "index", "conj"])
+def test_planted_pade_mistakes_are_caught(kind):
+    """The rational pin rejects plausible slips in the continued-fraction recursion."""
+    beta, n = 50.0, 10
+    z = o.matsubara_points(n, beta)
+    u = _rational(z)
+    g = u.astype(np.complex128).copy()
+    a = np.empty_like(g)
+    a[0] = g[0]
+    for p in range(1, n):
+        prev = g[p - 1]
+        dz = z[p:] - z[p - 1]
+        if kind == "sign":
+            dz = -dz
+        if kind == "conj":
+            prev = np.conj(prev)
+        nxt = (prev - g[p:]) / (dz * g[p:])
+        if kind == "index":
+            nxt = (prev - g[p:]) / (dz * g[p - 1])
+        g[p:] = nxt
+        a[p] = g[p]
+    w = np.linspace(-2.0, 2.0, 81) + 0.01j
+    c = o.pade_eval(z, a[None], w[None])[0]
+    assert np.max(np.abs(c - _rational(w)) / np.abs(_rational(w))) > 1e-3
