@@ -87,6 +87,7 @@ extern "C" {
 /* bits of the device flag word written by msgw_dyson */
 #define MSGW_FLAG_NAN        1   /* a non-finite value in Sigma or G   */
 #define MSGW_FLAG_NOBRACKET  2   /* n_target outside [N(lo), N(hi)]     */
+#define MSGW_FLAG_NOCONV     4   /* a quasiparticle equation did not converge */
 
 /* hard limits (checked by set_problem / the calls) */
 #define MSGW_MAX_NI   1024   /* product-basis size per q (screen keeps a row per thread) */
@@ -216,6 +217,29 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
  * continuation.  Sigma_c_iw: device c128 [nk][nbmax][niw_f]; mu: device scalar; gap: device f64. */
 int msgw_gap(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
              const void* Sigma_c_iw, const double* mu, int n_index, double* gap);
+
+/* ---- after the path: analytic continuation ---------------------------------------------------- */
+
+/* Analytic continuation of Sigma^c to the real axis by a Pade approximant (the route the paper
+ * compares with its continuous-pole expansion, analytic continuation subsection of Sec. III.B):
+ * for every state (n < Nb_k, k) the continued fraction of Vidberg and Serene through the n_pade
+ * lowest positive Matsubara points, C(z) = a_0 / (1 + a_1 (z - z_0) / (1 + ...)), z_j = i w_j; then
+ *   E_qp = x + mu with x the root of x = e0 + Re C(x + i eta), e0 = eps + sigma_static - mu, reached
+ *          by Newton's method from x = e0 (at most 100 steps, |step| <= 1e-12 (1 + |x|));
+ *   A[state][j] = -(1/pi) Im 1 / (omega_j + i eta - e0 - C(omega_j + i eta)) when A is not NULL.
+ * eps, sigma_static: device f64 [nk][nbmax]; Sigma_c_iw: device c128 [nk][nbmax][niw_f]; mu: device
+ * scalar; omega: device f64 [n_omega], energies from mu (NULL when n_omega == 0); A: device f64
+ * [nk][nbmax][n_omega] or NULL; E_qp: device f64 [nk][nbmax] (NaN for n >= Nb_k); flags: device int,
+ * set to 0 then MSGW_FLAG_NOCONV if some state's iteration did not converge.
+ * 1 <= n_pade <= min(niw_f, 128); eta >= 0.  Pade coefficients of noisy data can be ill-conditioned:
+ * the usual n_pade is a few tens. */
+int msgw_continue_pade(msgw_ctx* c, void* stream, int n_pade, double eta, const double* eps,
+                       const double* sigma_static, const void* Sigma_c_iw, const double* mu, int n_omega,
+                       const double* omega, double* A, double* E_qp, int* flags);
+
+/* Gap of given energies: *gap = E_(N+1) - E_(N) over the states n < Nb_k in ascending order
+ * (N = n_index, 1 <= N < number of states).  E: device f64 [nk][nbmax]; gap: device f64. */
+int msgw_gap_of(msgw_ctx* c, void* stream, const double* E, int n_index, double* gap);
 
 /* ---- tile shapes of the MFMA paths (used by the autotuner) ---------------------------------- */
 

@@ -31,7 +31,7 @@ EXPORTS = [
     "msgw_polarization", "msgw_tau_to_iw", "msgw_iw_to_tau", "msgw_screen",
     "msgw_screened_tau", "msgw_self_energy", "msgw_sigma_x", "msgw_dyson", "msgw_gap",
     "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant", "msgw_get_variant",
-    "msgw_set_k_range",
+    "msgw_set_k_range", "msgw_continue_pade", "msgw_gap_of",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 
@@ -103,6 +103,10 @@ def load_library():
     lib.msgw_get_variant.restype = ctypes.c_int
     lib.msgw_set_k_range.argtypes = [P, I, I, I]
     lib.msgw_set_k_range.restype = ctypes.c_int
+    lib.msgw_continue_pade.argtypes = [P, P, I, ctypes.c_double, P, P, P, P, I, P, P, P, P]
+    lib.msgw_continue_pade.restype = ctypes.c_int
+    lib.msgw_gap_of.argtypes = [P, P, P, I, P]
+    lib.msgw_gap_of.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -252,6 +256,16 @@ class Context:
         if rc != 0:
             raise MsgwError(rc, "bad op or precision")
         return out.value
+
+    def continue_pade(self, n_pade, eta, eps, sigma_static, Sigma_c_iw, mu, omega, A, E_qp, flags,
+                      stream=None):
+        n_omega = 0 if omega is None else int(omega.numel())
+        self._check(self.lib.msgw_continue_pade(self._c, _stream(stream), int(n_pade), float(eta), _ptr(eps),
+                                                _ptr(sigma_static), _ptr(Sigma_c_iw), _ptr(mu), n_omega,
+                                                _ptr(omega), _ptr(A), _ptr(E_qp), _ptr(flags)))
+
+    def gap_of(self, E, n_index, gap, stream=None):
+        self._check(self.lib.msgw_gap_of(self._c, _stream(stream), _ptr(E), int(n_index), _ptr(gap)))
 
     def set_k_range(self, k0=0, k1=0, reuse_prepared=False):
         """Harness only: restrict the pair-space contractions to k blocks [k0, k1) (k1 <= 0: all)."""

@@ -516,6 +516,33 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
     });
 }
 
+int msgw_continue_pade(msgw_ctx* c, void* stream, int n_pade, double eta, const double* eps,
+                       const double* sigma_static, const void* Sigma_c_iw, const double* mu, int n_omega,
+                       const double* omega, double* A, double* E_qp, int* flags) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(eps && sigma_static && Sigma_c_iw && mu && E_qp && flags, MSGW_EINVAL, "null pointer");
+        need(n_pade >= 1 && n_pade <= c->h.niw_f && n_pade <= 128, MSGW_EINVAL,
+             "n_pade outside [1, min(niw_f, 128)]");
+        need(std::isfinite(eta) && eta >= 0.0, MSGW_EINVAL, "eta must be finite and >= 0");
+        need(n_omega >= 0, MSGW_EINVAL, "negative n_omega");
+        need(n_omega == 0 || (omega && A), MSGW_EINVAL, "n_omega > 0 needs omega and A");
+        launch_pade(c->d, c->h, S(stream), n_pade, eta, eps, sigma_static, Sigma_c_iw, mu, n_omega,
+                    n_omega ? omega : nullptr, n_omega ? A : nullptr, E_qp, flags);
+    });
+}
+
+int msgw_gap_of(msgw_ctx* c, void* stream, const double* E, int n_index, double* gap) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(E && gap, MSGW_EINVAL, "null pointer");
+        int64_t nstate = 0;
+        for (int k = 0; k < c->h.nk; ++k) nstate += c->h.nb[k];
+        need(n_index >= 1 && n_index < nstate, MSGW_EINVAL, "n_index outside [1, number of states)");
+        launch_gap_given(c->d, c->h, S(stream), E, n_index, gap);
+    });
+}
+
 int msgw_variant_count(int op, int precision) {
     if (op != MSGW_OP_POLARIZATION && op != MSGW_OP_SELF_ENERGY) return MSGW_EINVAL;
     if (precision != MSGW_FP32 && precision != MSGW_BF16X3) return MSGW_EINVAL;

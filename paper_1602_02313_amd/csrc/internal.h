@@ -90,6 +90,10 @@ void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                   void* G_iw, double* G_tau, double* n_out, int* flags);
 void launch_gap(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                 const double* sstat, const void* sigc, const double* mu, int n_index, double* gap);
+void launch_gap_given(const Dev& d, const Host& h, hipStream_t s, const double* E, int n_index, double* gap);
+void launch_pade(const Dev& d, const Host& h, hipStream_t s, int n_pade, double eta, const double* eps,
+                 const double* sstat, const void* sigc, const double* mu, int n_omega, const double* omega,
+                 double* A, double* Eqp, int* flags);
 // contractions
 void launch_pol_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
                      const double* G, void* P);

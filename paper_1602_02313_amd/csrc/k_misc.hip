@@ -623,15 +623,17 @@ __device__ double eqp(const DysonArgs& a, double mu, int64_t b) {
     return a.eps[b] + a.sstat[b] + a.sigc[b * a.niw].x - mu;
 }
 
-// value of the N-th smallest E^QP (1-based)
-__device__ double select_nth(const DysonArgs& a, double mu, int N, double lo, double hi, double* red) {
-    const int64_t nstate = int64_t(a.nk) * a.nbmax;
+// value of the N-th smallest energy (1-based) over the states n < Nb_k; energy(b) for state b
+template <class EF>
+__device__ double select_nth(EF energy, int nk, int nbmax, const int* nb, int N, double lo, double hi,
+                             double* red) {
+    const int64_t nstate = int64_t(nk) * nbmax;
     for (int s = 0; s < 200; ++s) {
         double mid = 0.5 * (lo + hi);
         double cnt = 0.0;
         for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
-            int k = int(b / a.nbmax), n = int(b % a.nbmax);
-            if (n < a.nb[k] && eqp(a, mu, b) <= mid) cnt += 1.0;
+            int k = int(b / nbmax), n = int(b % nbmax);
+            if (n < nb[k] && energy(b) <= mid) cnt += 1.0;
         }
         cnt = block_sum(cnt, red);
         if (cnt >= N)
@@ -641,36 +643,53 @@ __device__ double select_nth(const DysonArgs& a, double mu, int N, double lo, do
     }
     double best = -INFINITY;
     for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
-        int k = int(b / a.nbmax), n = int(b % a.nbmax);
-        if (n < a.nb[k]) {
-            double e = eqp(a, mu, b);
+        int k = int(b / nbmax), n = int(b % nbmax);
+        if (n < nb[k]) {
+            double e = energy(b);
             if (e <= hi) best = fmax(best, e);
         }
     }
     return block_max(best, red);
 }
 
-__global__ __launch_bounds__(1024) void k_gap(DysonArgs a, const double* mu_p, int N, double* gap) {
+// gap E_(N+1) - E_(N) of the energies energy(b) over the states n < Nb_k
+template <class EF>
+__device__ void gap_of(EF energy, int nk, int nbmax, const int* nb, int N, double* gap) {
     __shared__ double red[16];
-    const double mu = *mu_p;
-    const int64_t nstate = int64_t(a.nk) * a.nbmax;
+    const int64_t nstate = int64_t(nk) * nbmax;
     double lo = INFINITY, hi = -INFINITY;
     for (int64_t b = threadIdx.x; b < nstate; b += blockDim.x) {
-        int k = int(b / a.nbmax), n = int(b % a.nbmax);
-        if (n >= a.nb[k]) continue;
-        double e = eqp(a, mu, b);
+        int k = int(b / nbmax), n = int(b % nbmax);
+        if (n >= nb[k]) continue;
+        double e = energy(b);
         lo = fmin(lo, e);
         hi = fmax(hi, e);
     }
     hi = block_max(hi, red);
     lo = -block_max(-lo, red);
     const double start = lo - (1.0 + fabs(lo));
-    const double eN = select_nth(a, mu, N, start, hi, red);
-    const double eN1 = select_nth(a, mu, N + 1, start, hi, red);
+    const double eN = select_nth(energy, nk, nbmax, nb, N, start, hi, red);
+    const double eN1 = select_nth(energy, nk, nbmax, nb, N + 1, start, hi, red);
     if (threadIdx.x == 0) *gap = eN1 - eN;
 }
 
+__global__ __launch_bounds__(1024) void k_gap(DysonArgs a, const double* mu_p, int N, double* gap) {
+    const double mu = *mu_p;
+    gap_of([&](int64_t b) { return eqp(a, mu, b); }, a.nk, a.nbmax, a.nb, N, gap);
+}
+
+// the same over given energies (quasiparticle energies of the continuation)
+__global__ __launch_bounds__(1024) void k_gap_given(const double* __restrict__ E, int nk, int nbmax,
+                                                    const int* __restrict__ nb, int N, double* gap) {
+    gap_of([&](int64_t b) { return E[b]; }, nk, nbmax, nb, N, gap);
+}
+
 }  // namespace
+
+void launch_gap_given(const Dev& d, const Host& h, hipStream_t s, const double* E, int n_index, double* gap) {
+    MSGW_LAUNCH(k_gap_given, dim3(1), dim3(1024), 0, s, E, h.nk, h.nbmax, d.nb, n_index, gap);
+    MSGW_HIP(hipGetLastError());
+}
 
 void launch_gap(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                 const double* sstat, const void* sigc, const double* mu, int n_index, double* gap) {

@@ -251,6 +251,23 @@ class GWRun:
         self.ctx.gap(self.eps, self.sig_x, self.sig_iw, self.mu, int(round(self.n_target)),
                      self.gap_d, stream=self.stream)
 
+    def continue_pade(self, n_pade=16, eta=0.0, omega=None):
+        """Pade continuation of the current Sigma^c(i w) (after the path): quasiparticle energies,
+        their gap, and A(w) on the real grid omega (energies from mu) when given.
+
+        Returns (E_qp [nk, nbmax], A [nk, nbmax, n_omega] or None, gap, flags)."""
+        import torch
+        dev, f64 = self.device, torch.float64
+        E = torch.empty((self.nk, self.nbmax), dtype=f64, device=dev)
+        om = None if omega is None else torch.as_tensor(omega, dtype=f64).to(dev).contiguous()
+        A = None if om is None else torch.empty((self.nk, self.nbmax, om.numel()), dtype=f64, device=dev)
+        flags = torch.zeros(1, dtype=torch.int32, device=dev)
+        gap = torch.zeros(1, dtype=f64, device=dev)
+        self.ctx.continue_pade(n_pade, eta, self.eps, self.sig_x, self.sig_iw, self.mu, om, A, E, flags,
+                               stream=self.stream)
+        self.ctx.gap_of(E, int(round(self.n_target)), gap, stream=self.stream)
+        return E, A, gap, flags
+
     def _record(self):
         return dict(mu=float(self.mu.item()), N=float(self.N.item()),
                     gap=float(self.gap_d.item()), flags=int(self.flags.item()))
