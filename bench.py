@@ -209,6 +209,9 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=1024)
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the iteration captured as a HIP graph (no per-kernel times)")
+    ap.add_argument("--tau-mirror", action="store_true",
+                    help="use P(tau) = P(beta - tau) of the symmetric inputs (the dense flop count of the "
+                         "metric is unchanged; the saving is reported as tau_mirror in config)")
     ap.add_argument("--batching", action="store_true",
                     help="instead of the pass: one launch vs a per-k launch loop on one q of --config "
                          "(default c4, the uneven workload)")
@@ -236,7 +239,7 @@ def main():
         f"ntau={prob.tau.size} niw={cfg.niw_f} precision={args.precision}")
     run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
                     cfg.scale, prob.eps, prob.v, prob.n_target, precision=prec,
-                    q_batch=args.q_batch)
+                    q_batch=args.q_batch, tau_mirror=args.tau_mirror)
     ct = torch.complex128 if run.m_dtype == amd.C128 else torch.complex64
     M = torch.empty(int(run.mpre[-1]), dtype=ct, device="cuda")
     torch.cuda.synchronize()
@@ -398,7 +401,8 @@ def main():
                    "nk": cfg.nk, "nb": int(prob.nb.max()), "ni": int(prob.ni.max()),
                    "ntau": int(prob.tau.size), "niw_f": cfg.niw_f, "niw_b": cfg.niw_b,
                    "beta": cfg.beta, "precision": args.precision, "q_batch": args.q_batch,
-                   "hip_graph": bool(args.graph), "flops_p": fp, "flops_sigma": fs},
+                   "hip_graph": bool(args.graph), "tau_mirror": bool(args.tau_mirror),
+                   "flops_p": fp, "flops_sigma": fs},
         "roofline": roof,
         "kernels": kernels,
         "fp64_gpu_reference": fp64_ref,

@@ -218,6 +218,16 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
 int msgw_gap(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
              const void* Sigma_c_iw, const double* mu, int n_index, double* gap);
 
+/* ---- symmetry ------------------------------------------------------------------------------ */
+
+/* The caller asserts (on != 0) that its inputs give P(q, tau_{N-1-i}) = P(q, tau_i), i.e. P(tau) =
+ * P(beta - tau) on the mirror-symmetric mesh: time-reversal symmetry of the matrix elements, as in
+ * crystals without spin-orbit coupling and for msgw_synth_M's symmetric generator (the tau-mirror
+ * saving of the paper's use of symmetry, Sec. III.C).  The split-BF16 pair-space polarization then
+ * computes the points i <= (N - 1) / 2 and copies the others; the other paths compute every point.
+ * With inputs that lack the symmetry the copied points are wrong.  Default off. */
+int msgw_set_tau_mirror(msgw_ctx* c, int on);
+
 /* ---- after the path: analytic continuation ---------------------------------------------------- */
 
 /* Analytic continuation of Sigma^c to the real axis by a Pade approximant (the route the paper

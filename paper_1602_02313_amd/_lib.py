@@ -31,7 +31,7 @@ EXPORTS = [
     "msgw_polarization", "msgw_tau_to_iw", "msgw_iw_to_tau", "msgw_screen",
     "msgw_screened_tau", "msgw_self_energy", "msgw_sigma_x", "msgw_dyson", "msgw_gap",
     "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant", "msgw_get_variant",
-    "msgw_set_k_range", "msgw_continue_pade", "msgw_gap_of",
+    "msgw_set_k_range", "msgw_continue_pade", "msgw_gap_of", "msgw_set_tau_mirror",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 
@@ -107,6 +107,8 @@ def load_library():
     lib.msgw_continue_pade.restype = ctypes.c_int
     lib.msgw_gap_of.argtypes = [P, P, P, I, P]
     lib.msgw_gap_of.restype = ctypes.c_int
+    lib.msgw_set_tau_mirror.argtypes = [P, I]
+    lib.msgw_set_tau_mirror.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -263,6 +265,10 @@ class Context:
         self._check(self.lib.msgw_continue_pade(self._c, _stream(stream), int(n_pade), float(eta), _ptr(eps),
                                                 _ptr(sigma_static), _ptr(Sigma_c_iw), _ptr(mu), n_omega,
                                                 _ptr(omega), _ptr(A), _ptr(E_qp), _ptr(flags)))
+
+    def set_tau_mirror(self, on=True):
+        """Assert P(tau) = P(beta - tau) for the inputs (time-reversal symmetry); see matsgw.h."""
+        self._check(self.lib.msgw_set_tau_mirror(self._c, int(bool(on))))
 
     def gap_of(self, E, n_index, gap, stream=None):
         self._check(self.lib.msgw_gap_of(self._c, _stream(stream), _ptr(E), int(n_index), _ptr(gap)))

@@ -516,6 +516,13 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
     });
 }
 
+int msgw_set_tau_mirror(msgw_ctx* c, int on) {
+    return guarded(c, [&] {
+        require_ready(c);
+        c->d.tau_mirror = on ? 1 : 0;
+    });
+}
+
 int msgw_continue_pade(msgw_ctx* c, void* stream, int n_pade, double eta, const double* eps,
                        const double* sigma_static, const void* Sigma_c_iw, const double* mu, int n_omega,
                        const double* omega, double* A, double* E_qp, int* flags) {

@@ -60,6 +60,7 @@ struct Dev {
     size_t scratch_bytes = 0;
     int kb0 = 0, kb1 = 0;             // k blocks [kb0, kb1) of the pair-space contractions
     int kreuse = 0;                   // 1: the per-q operands prepared by the previous call are reused
+    int tau_mirror = 0;               // 1: P(q, tau_{N-1-i}) = P(q, tau_i) may be used (caller's assertion)
 };
 
 // Host mirror of the problem (used for launch shapes and validation).

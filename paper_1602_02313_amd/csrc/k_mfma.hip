@@ -978,6 +978,17 @@ __device__ __forceinline__ int64_t gz_block(const Dev& d, int q0, int q, int k) 
     return off;  // in bf16 elements
 }
 
+// tau points the pair-space polarization computes: all of them, or i <= (N - 1) / 2 with the mirror
+int tau_points_computed(const Dev& d, const Host& h) { return d.tau_mirror ? (h.ntau + 1) / 2 : h.ntau; }
+
+// P(tau_i) = P(tau_{N-1-i}) for the points i >= nt_eff (whole planes, after the mirror below the diagonal)
+__global__ __launch_bounds__(256) void k_tau_mirror(double2* __restrict__ P, int NI, int ntau, int nt_eff) {
+    const int64_t nn = int64_t(NI) * NI;
+    const int i = nt_eff + int(blockIdx.y);
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e < nn) P[int64_t(i) * nn + e] = P[int64_t(ntau - 1 - i) * nn + e];
+}
+
 // one thread per (tau, K pair): writes hi and lo of g for two consecutive K.  gz points at the planes
 // of q; the offset of block k inside them is summed over the k' < k by the whole work-group.
 __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __restrict__ G,
@@ -1031,7 +1042,8 @@ __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __rest
 template <int OCC, int KS, int WI, int NTT>
 __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const float2* __restrict__ M,
                                                         const uint32_t* __restrict__ gz,
-                                                        double2* __restrict__ P, Order od, int t0, int ntc) {
+                                                        double2* __restrict__ P, Order od, int t0, int ntc,
+                                                        int nt_eff) {
     constexpr int NT = 128 * WI, XROWS = 4 * WI + 16, CW = 32 * NTT;
     static_assert(KS % GZ_KS == 0, "stages hold whole 32-K slabs of the g planes");
     static_assert((XROWS * KS) % NT == 0 && (2 * CW * KS / 8) % NT == 0, "stage split over threads");
@@ -1195,7 +1207,7 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             for (int x = 0; x < 16; ++x) {
                 const int p = 8 * (x >> 2) + 4 * h2 + (x & 3);
                 const int I = I0 + 4 * (wave % WI) + (p >> 3), J = J0 + 8 * (wave / WI) + (p & 7);
-                if (it < ntau && I < NI && J < NI) {
+                if (it < nt_eff && I < NI && J < NI) {
                     double2* pp = &Pq[(int64_t(it) * NI + I) * NI + J];
                     double re = sc * double(acc[tt][0][x]);
                     double im = sc * double(acc[tt][1][x]);
@@ -1623,13 +1635,15 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
         MSGW_LAUNCH(k_gtab, dim3(gx, h.nk), dim3(256), 0, s, d, q, G, gz + gz_elems(h, q0, q - q0) / 2);
         MSGW_HIP(hipGetLastError());
     }
-    // tau in chunks of three 32-wide tiles, the last chunk with the one or two tiles left
-    const int ntiles = ceil_div(h.ntau, 32), n3 = ntiles / 3, rest = ntiles % 3;
+    // tau in chunks of three 32-wide tiles, the last chunk with the one or two tiles left; with the
+    // tau mirror only the points i <= (N - 1) / 2 (the others are copied afterwards)
+    const int nt_eff = tau_points_computed(d, h);
+    const int ntiles = ceil_div(nt_eff, 32), n3 = ntiles / 3, rest = ntiles % 3;
     auto launch = [&](auto kern, int t0, int ntc) {
         const Order od = make_order_st(ceil_div(maxi, 4 * WI), ceil_div(maxi, 16) * ntc, nq, SR, SC * ntc);
         launch_order(od, 128 * WI, [&](dim3 g, const Order& o) {
             MSGW_LAUNCH(kern, g, dim3(128 * WI), 0, s, d, q0, (const float2*)M, (const uint32_t*)gz, (double2*)P, o,
-                        t0, ntc);
+                        t0, ntc, nt_eff);
         });
     };
     if (n3 > 0) launch(k_polz<OCC, KS, WI, 3>, 0, n3);
@@ -1793,11 +1807,17 @@ int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
     const PolVariant& V = (precision == MSGW_BF16X3 ? kPolBF16 : kPolFP32)[variant];
     if ((d.kb0 != 0 || d.kb1 != h.nk) && !V.ranged) return MSGW_ENOTSUP;
     V.fn(d, h, s, q0, nq, M, G, P);
+    const int nt_eff = V.ranged ? tau_points_computed(d, h) : h.ntau;  // only the pair-space kernels mirror
     for (int q = q0; q < q0 + nq; ++q) {
         const int nt = ceil_div(h.ni[q], CW_TILE);
-        MSGW_LAUNCH(k_herm_fill, dim3(nt * nt, h.ntau), dim3(256), 0, s,
-                           (double2*)P + (h.ppre[q] - h.ppre[q0]), h.ni[q]);
+        double2* Pq = (double2*)P + (h.ppre[q] - h.ppre[q0]);
+        MSGW_LAUNCH(k_herm_fill, dim3(nt * nt, nt_eff), dim3(256), 0, s, Pq, h.ni[q]);
         MSGW_HIP(hipGetLastError());
+        if (nt_eff < h.ntau) {
+            MSGW_LAUNCH(k_tau_mirror, dim3(ceil_div(int64_t(h.ni[q]) * h.ni[q], 256), h.ntau - nt_eff), dim3(256), 0,
+                        s, Pq, h.ni[q], h.ntau, nt_eff);
+            MSGW_HIP(hipGetLastError());
+        }
     }
     return MSGW_OK;
 }

@@ -103,7 +103,8 @@ class GWRun:
     """State of one run: problem tables, workspace, G, Sigma and per-q-batch buffers."""
 
     def __init__(self, nk, kmq, nb, ni, tau, beta, niw_f, niw_b, scale, eps, v, n_target,
-                 precision=L.FP64, sigma_mode=L.SIGMA_DIAG, q_batch=1, device=0, stream=None):
+                 precision=L.FP64, sigma_mode=L.SIGMA_DIAG, q_batch=1, device=0, stream=None,
+                 tau_mirror=False):
         import torch
         self.torch = torch
         self.device = torch.device("cuda", device)
@@ -128,6 +129,8 @@ class GWRun:
         ws_bytes = self.ctx.workspace_size(self.q_batch)
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         self.ctx.set_workspace(self.ws)
+        if tau_mirror:  # the caller asserts P(tau) = P(beta - tau) for its inputs
+            self.ctx.set_tau_mirror(True)
         # prefixes of the packed per-q arrays
         nk = self.nk
         self.mpre = np.zeros(nk + 1, dtype=np.int64)
