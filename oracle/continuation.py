@@ -112,3 +112,101 @@ def qp_gap(E, nb, n_index):
     mask = np.arange(E.shape[1])[None, :] < np.asarray(nb)[:, None]
     e = np.sort(E[mask])
     return float(e[n_index] - e[n_index - 1])
+
+
+# ---------------------------------------------------------------------------
+# continuous-pole expansion (CPE)
+# ---------------------------------------------------------------------------
+# The paper's own continuation (after Staar et al.): Im Sigma(w + i0) <= 0 (causality) is expanded in
+# piecewise-linear functions of w with coefficients a_l >= 0, so that
+#     Sigma(z) = (1/pi) int dw Im Sigma(w) / (w - z) = -(1/pi) sum_l a_l Phi_l(z),
+#     Phi_l(z) = int dw h_l(w) / (w - z)                     (h_l: hat function at grid point w_l),
+# and the a_l minimise the squared misfit to Sigma(i w_n) over the positive Matsubara points under
+# a_l >= 0.  Readings: the hats sit at the interior points of a uniform real grid on [w_min, w_max]
+# (Im Sigma vanishes at both ends); the spectral prefactor is 1/pi (the one that reproduces a pole
+# r / (z - p) from Im Sigma = -pi r delta(w - p)); a ridge term ridge * max_l (B^T B)_ll * |a|^2 makes
+# the non-negative least-squares problem strictly convex, so that its minimiser is unique.
+
+def cpe_grid(w_min, w_max, n_real):
+    """Uniform real grid w_0 .. w_{n_real-1}; the hats sit at w_1 .. w_{n_real-2}."""
+    return np.linspace(float(w_min), float(w_max), int(n_real))
+
+
+def cpe_phi(wgrid, z, derivative=False):
+    """Phi_l(z) for the interior hats (last axis, n_real - 2), z complex (Im z > 0) broadcast in front.
+
+    With F(a, b, c) = int_a^b (w - c) / (w - z) dw = (b - a) + (z - c) [ln(b - z) - ln(a - z)]:
+    Phi_l = [F(w_{l-1}, w_l, w_{l-1}) - F(w_l, w_{l+1}, w_{l+1})] / (w_l - w_{l-1})."""
+    w = np.asarray(wgrid, dtype=np.float64)
+    z = np.asarray(z, dtype=np.complex128)[..., None]
+    lo, mid, hi = w[:-2], w[1:-1], w[2:]
+    dw = mid - lo
+
+    def F(a, b, c):
+        L = np.log(b - z) - np.log(a - z)
+        val = (b - a) + (z - c) * L
+        if not derivative:
+            return val, None
+        return val, L + (z - c) * (1.0 / (a - z) - 1.0 / (b - z))
+
+    f1, d1 = F(lo, mid, lo)
+    f2, d2 = F(mid, hi, hi)
+    phi = (f1 - f2) / dw
+    return (phi, (d1 - d2) / dw) if derivative else phi
+
+
+def cpe_basis(wgrid, beta, n_iw):
+    """Real design matrix [2 n_iw, n_real - 2]: rows Re then Im of -Phi_l(i w_n) / pi."""
+    z = matsubara_points(n_iw, beta)
+    B = -cpe_phi(wgrid, z) / np.pi
+    return np.concatenate([B.real, B.imag], axis=0)
+
+
+def cpe_fit(wgrid, beta, sigc_iw, ridge):
+    """a_l >= 0 minimising |B a - y|^2 + lam |a|^2, lam = ridge * max_l (B^T B)_ll, per state.
+
+    sigc_iw: complex [..., n_iw]; returns [..., n_real - 2]."""
+    from scipy.optimize import nnls
+    y = np.asarray(sigc_iw)
+    n_iw = y.shape[-1]
+    B = cpe_basis(wgrid, beta, n_iw)
+    lam = ridge * np.max(np.sum(B * B, axis=0))
+    Baug = np.concatenate([B, np.sqrt(lam) * np.eye(B.shape[1])], axis=0)
+    flat = y.reshape(-1, n_iw)
+    out = np.empty((flat.shape[0], B.shape[1]))
+    for s in range(flat.shape[0]):
+        rhs = np.concatenate([flat[s].real, flat[s].imag, np.zeros(B.shape[1])])
+        out[s] = nnls(Baug, rhs, maxiter=50 * B.shape[1])[0]
+    return out.reshape(y.shape[:-1] + (B.shape[1],))
+
+
+def cpe_sigma(wgrid, a, z, derivative=False):
+    """Sigma(z) = -(1/pi) sum_l a_l Phi_l(z) (and dSigma/dz); a: [..., n_real - 2], z: [...] complex."""
+    if derivative:
+        phi, dphi = cpe_phi(wgrid, z, derivative=True)
+        return -np.sum(a * phi, axis=-1) / np.pi, -np.sum(a * dphi, axis=-1) / np.pi
+    return -np.sum(a * cpe_phi(wgrid, z), axis=-1) / np.pi
+
+
+def qp_energies_cpe(eps, nb, sig_static, sigc_iw, mu, beta, wgrid, ridge, eta, iters=100, tol=1e-12):
+    """Quasiparticle energies from the CPE continuation: x = e0 + Re Sigma(x + i eta) by Newton from
+    x = e0 (eta > 0).  Returns (E [nk, nbmax] with NaN for n >= Nb_k, converged, coefficients)."""
+    a = cpe_fit(wgrid, beta, sigc_iw, ridge)
+    e0 = eps + sig_static - mu
+    x = e0.copy()
+    done = np.zeros_like(x, dtype=bool)
+    for _ in range(iters):
+        s, ds = cpe_sigma(wgrid, a, x + 1j * eta, derivative=True)
+        step = (x - e0 - s.real) / (1.0 - ds.real)
+        x = np.where(done, x, x - step)
+        done |= np.abs(step) <= tol * (1.0 + np.abs(x))
+    mask = np.arange(eps.shape[1])[None, :] < np.asarray(nb)[:, None]
+    return np.where(mask, x + mu, np.nan), done | ~mask, a
+
+
+def spectral_cpe(eps, sig_static, a, mu, wgrid, eta, omega):
+    """A(w) = -(1/pi) Im 1 / (w + i eta - e0 - Sigma(w + i eta)) with the CPE coefficients a."""
+    e0 = eps + sig_static - mu
+    w = np.asarray(omega, dtype=np.float64)
+    s = cpe_sigma(wgrid, a[..., None, :], w + 1j * eta)
+    return -np.imag(1.0 / (w + 1j * eta - e0[..., None] - s)) / np.pi

@@ -627,3 +627,73 @@ def test_planted_pade_mistakes_are_caught(kind):
     w = np.linspace(-2.0, 2.0, 81) + 0.01j
     c = o.pade_eval(z, a[None], w[None])[0]
     assert np.max(np.abs(c - _rational(w)) / np.abs(_rational(w))) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# continuous-pole expansion
+# ---------------------------------------------------------------------------
+def test_cpe_basis_matches_quadrature():
+    """The closed form of Phi_l(z) = int h_l(w) / (w - z) dw against numerical quadrature."""
+    wg = o.cpe_grid(-3.0, 3.0, 41)
+    z = np.array([0.3 + 0.2j, -1.0 + 0.05j, 2.0 + 1.0j, 0.0 + 0.8j])
+    phi, dphi = o.cpe_phi(wg, z, derivative=True)
+    for l in (0, 17, 38):
+        def h(w):
+            return np.interp(w, wg[l:l + 3], [0.0, 1.0, 0.0])
+        for i, zz in enumerate(z):
+            den = lambda w: (w - zz.real) ** 2 + zz.imag ** 2  # noqa: E731
+            re = quad(lambda w: h(w) * (w - zz.real) / den(w), wg[l], wg[l + 2], points=[wg[l + 1]])[0]
+            im = quad(lambda w: h(w) * zz.imag / den(w), wg[l], wg[l + 2], points=[wg[l + 1]])[0]
+            assert abs(phi[i, l] - (re + 1j * im)) < 1e-10
+            # derivative: int h / (w - z)^2
+            d2 = lambda w: (w - zz) ** 2  # noqa: E731
+            dre = quad(lambda w: (h(w) / d2(w)).real, wg[l], wg[l + 2], points=[wg[l + 1]])[0]
+            dim = quad(lambda w: (h(w) / d2(w)).imag, wg[l], wg[l + 2], points=[wg[l + 1]])[0]
+            assert abs(dphi[i, l] - (dre + 1j * dim)) < 1e-8
+
+
+def test_cpe_recovers_an_exact_expansion():
+    """Data generated by non-negative coefficients are fitted back; the continued self-energy is the
+    spectral integral of the piecewise-linear Im Sigma."""
+    beta = 50.0
+    wg = o.cpe_grid(-3.0, 3.0, 41)
+    a_true = np.zeros(39)
+    a_true[[10, 11, 12, 25, 26]] = [0.02, 0.05, 0.02, 0.03, 0.01]
+    B = o.cpe_basis(wg, beta, 64)
+    y = B @ a_true
+    a = o.cpe_fit(wg, beta, (y[:64] + 1j * y[64:])[None], 1e-14)[0]
+    assert np.all(a >= 0)
+    assert np.linalg.norm(a - a_true) < 1e-6 * np.linalg.norm(a_true)
+    z = 0.4 + 0.05j
+    im_sig = lambda w: -np.interp(w, wg[1:-1], a_true, left=0.0, right=0.0)  # noqa: E731
+    d = lambda w: (w - z.real) ** 2 + z.imag ** 2  # noqa: E731
+    re = quad(lambda w: im_sig(w) * (w - z.real) / d(w), -3, 3, points=list(wg[9:14]) + list(wg[24:28]),
+              limit=200)[0] / np.pi
+    im = quad(lambda w: im_sig(w) * z.imag / d(w), -3, 3, points=list(wg[9:14]) + list(wg[24:28]),
+              limit=200)[0] / np.pi
+    assert abs(o.cpe_sigma(wg, a, np.array(z)) - (re + 1j * im)) < 1e-8
+
+
+def test_cpe_one_pole_weight_causality_and_qp():
+    """Sigma = r / (z - p): the fit is causal (a >= 0, Im Sigma(w) <= 0), carries the pole's weight r,
+    satisfies the optimality conditions of the constrained problem, and gives the quasiparticle
+    energy of the exact self-energy to the resolution of the grid."""
+    beta, r, p, ridge = 50.0, 0.04, 0.8, 1e-10
+    wg = o.cpe_grid(-3.0, 3.0, 61)
+    w = (2 * np.arange(64) + 1) * np.pi / beta
+    sig = (r / (1j * w - p))[None, None, :]
+    a = o.cpe_fit(wg, beta, sig, ridge)[0, 0]
+    assert np.all(a >= 0)
+    dw = wg[1] - wg[0]
+    assert abs(np.sum(a) * dw / np.pi - r) < 0.03 * r
+    B = o.cpe_basis(wg, beta, 64)
+    lam = ridge * np.max(np.sum(B * B, axis=0))
+    g = B.T @ (B @ a - np.concatenate([sig[0, 0].real, sig[0, 0].imag])) + lam * a
+    scale = np.linalg.norm(B.T @ np.concatenate([sig[0, 0].real, sig[0, 0].imag]))
+    assert np.all(g[a > 0] < 1e-6 * scale) and np.all(g[a > 0] > -1e-6 * scale)
+    assert np.all(g[a == 0] > -1e-6 * scale)
+    e0 = np.array([[0.3]])
+    E, ok, _ = o.qp_energies_cpe(e0, [1], np.zeros_like(e0), sig, 0.0, beta, wg, ridge, 0.02)
+    roots = np.roots([1.0, -(0.3 + p), 0.3 * p - r])
+    exact = roots[np.argmin(np.abs(roots - 0.3))]
+    assert ok.all() and abs(E[0, 0] - exact) < 2e-3
