@@ -247,6 +247,20 @@ int msgw_continue_pade(msgw_ctx* c, void* stream, int n_pade, double eta, const 
                        const double* sigma_static, const void* Sigma_c_iw, const double* mu, int n_omega,
                        const double* omega, double* A, double* E_qp, int* flags);
 
+/* Analytic continuation by the continuous-pole expansion, the paper's own route (analytic continuation
+ * subsection of Sec. III.B): Im Sigma^c(w) <= 0 is expanded in hat functions h_l at the interior
+ * points of the uniform grid of n_real points on [w_min, w_max] (energies from mu),
+ *   Sigma^c(z) = -(1/pi) sum_l a_l int h_l(w) / (w - z) dw,  a_l >= 0,
+ * with the a_l minimising sum_n |Sigma^c(i w_n) - Sigma(i w_n)|^2 + lam |a|^2 over all niw_f positive
+ * Matsubara points, lam = ridge * max_l of the diagonal of the normal matrix (the ridge makes the
+ * minimiser unique).  Then, as for msgw_continue_pade, E_qp = x + mu with x = e0 + Re Sigma(x + i eta)
+ * (Newton from e0) and, when A is not NULL, A on the omega grid.  coef: device f64
+ * [nk][nbmax][n_real - 2] (the a_l) or NULL.  4 <= n_real <= 98, eta > 0, ridge >= 0.  flags gets
+ * MSGW_FLAG_NOCONV if a fit or a quasiparticle iteration did not finish.  Uses the workspace. */
+int msgw_continue_cpe(msgw_ctx* c, void* stream, int n_real, double w_min, double w_max, double ridge, double eta,
+                      const double* eps, const double* sigma_static, const void* Sigma_c_iw, const double* mu,
+                      int n_omega, const double* omega, double* A, double* E_qp, double* coef, int* flags);
+
 /* Gap of given energies: *gap = E_(N+1) - E_(N) over the states n < Nb_k in ascending order
  * (N = n_index, 1 <= N < number of states).  E: device f64 [nk][nbmax]; gap: device f64. */
 int msgw_gap_of(msgw_ctx* c, void* stream, const double* E, int n_index, double* gap);

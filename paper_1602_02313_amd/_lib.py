@@ -32,6 +32,7 @@ EXPORTS = [
     "msgw_screened_tau", "msgw_self_energy", "msgw_sigma_x", "msgw_dyson", "msgw_gap",
     "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant", "msgw_get_variant",
     "msgw_set_k_range", "msgw_continue_pade", "msgw_gap_of", "msgw_set_tau_mirror",
+    "msgw_continue_cpe",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 
@@ -107,6 +108,9 @@ def load_library():
     lib.msgw_continue_pade.restype = ctypes.c_int
     lib.msgw_gap_of.argtypes = [P, P, P, I, P]
     lib.msgw_gap_of.restype = ctypes.c_int
+    lib.msgw_continue_cpe.argtypes = [P, P, I, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      P, P, P, P, I, P, P, P, P, P]
+    lib.msgw_continue_cpe.restype = ctypes.c_int
     lib.msgw_set_tau_mirror.argtypes = [P, I]
     lib.msgw_set_tau_mirror.restype = ctypes.c_int
     _lib = lib
@@ -269,6 +273,14 @@ class Context:
     def set_tau_mirror(self, on=True):
         """Assert P(tau) = P(beta - tau) for the inputs (time-reversal symmetry); see matsgw.h."""
         self._check(self.lib.msgw_set_tau_mirror(self._c, int(bool(on))))
+
+    def continue_cpe(self, n_real, w_min, w_max, ridge, eta, eps, sigma_static, Sigma_c_iw, mu, omega, A, E_qp,
+                     coef, flags, stream=None):
+        n_omega = 0 if omega is None else int(omega.numel())
+        self._check(self.lib.msgw_continue_cpe(self._c, _stream(stream), int(n_real), float(w_min), float(w_max),
+                                               float(ridge), float(eta), _ptr(eps), _ptr(sigma_static),
+                                               _ptr(Sigma_c_iw), _ptr(mu), n_omega, _ptr(omega), _ptr(A),
+                                               _ptr(E_qp), _ptr(coef), _ptr(flags)))
 
     def gap_of(self, E, n_index, gap, stream=None):
         self._check(self.lib.msgw_gap_of(self._c, _stream(stream), _ptr(E), int(n_index), _ptr(gap)))

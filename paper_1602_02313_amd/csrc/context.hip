@@ -279,7 +279,7 @@ static size_t tables_bytes(const Host& h) {
 }
 
 static size_t scratch_needed(const Host& h, int nq_max) {
-    return scratch_E_bytes(h) + align_up(mfma_scratch_bytes(h, nq_max));
+    return scratch_E_bytes(h) + align_up(std::max(mfma_scratch_bytes(h, nq_max), cpe_scratch_bytes(h, 98)));
 }
 
 int msgw_workspace_size(msgw_ctx* c, int nq_max, size_t* bytes) {
@@ -536,6 +536,23 @@ int msgw_continue_pade(msgw_ctx* c, void* stream, int n_pade, double eta, const 
         need(n_omega == 0 || (omega && A), MSGW_EINVAL, "n_omega > 0 needs omega and A");
         launch_pade(c->d, c->h, S(stream), n_pade, eta, eps, sigma_static, Sigma_c_iw, mu, n_omega,
                     n_omega ? omega : nullptr, n_omega ? A : nullptr, E_qp, flags);
+    });
+}
+
+int msgw_continue_cpe(msgw_ctx* c, void* stream, int n_real, double w_min, double w_max, double ridge, double eta,
+                      const double* eps, const double* sigma_static, const void* Sigma_c_iw, const double* mu,
+                      int n_omega, const double* omega, double* A, double* E_qp, double* coef, int* flags) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(eps && sigma_static && Sigma_c_iw && mu && E_qp && flags, MSGW_EINVAL, "null pointer");
+        need(n_real >= 4 && n_real <= 98, MSGW_EINVAL, "n_real outside [4, 98]");
+        need(std::isfinite(w_min) && std::isfinite(w_max) && w_min < w_max, MSGW_EINVAL, "need w_min < w_max");
+        need(std::isfinite(ridge) && ridge >= 0.0, MSGW_EINVAL, "ridge must be finite and >= 0");
+        need(std::isfinite(eta) && eta > 0.0, MSGW_EINVAL, "eta must be finite and > 0");
+        need(n_omega >= 0, MSGW_EINVAL, "negative n_omega");
+        need(n_omega == 0 || (omega && A), MSGW_EINVAL, "n_omega > 0 needs omega and A");
+        launch_cpe(c->d, c->h, S(stream), n_real, w_min, w_max, ridge, eta, eps, sigma_static, Sigma_c_iw, mu,
+                   n_omega, n_omega ? omega : nullptr, n_omega ? A : nullptr, E_qp, coef, flags);
     });
 }
 

@@ -92,6 +92,10 @@ void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
 void launch_gap(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                 const double* sstat, const void* sigc, const double* mu, int n_index, double* gap);
 void launch_gap_given(const Dev& d, const Host& h, hipStream_t s, const double* E, int n_index, double* gap);
+size_t cpe_scratch_bytes(const Host& h, int n_real);
+void launch_cpe(const Dev& d, const Host& h, hipStream_t s, int n_real, double w_min, double w_max, double ridge,
+                double eta, const double* eps, const double* sstat, const void* sigc, const double* mu,
+                int n_omega, const double* omega, double* A, double* Eqp, double* coef, int* flags);
 void launch_pade(const Dev& d, const Host& h, hipStream_t s, int n_pade, double eta, const double* eps,
                  const double* sstat, const void* sigc, const double* mu, int n_omega, const double* omega,
                  double* A, double* Eqp, int* flags);

@@ -271,6 +271,22 @@ class GWRun:
         self.ctx.gap_of(E, int(round(self.n_target)), gap, stream=self.stream)
         return E, A, gap, flags
 
+    def continue_cpe(self, n_real=61, w_min=-3.0, w_max=3.0, ridge=1e-10, eta=0.02, omega=None):
+        """CPE continuation of the current Sigma^c(i w): quasiparticle energies, their gap, the fitted
+        coefficients, and A(w) on omega when given.  Returns (E_qp, A or None, gap, coef, flags)."""
+        import torch
+        dev, f64 = self.device, torch.float64
+        E = torch.empty((self.nk, self.nbmax), dtype=f64, device=dev)
+        coef = torch.empty((self.nk, self.nbmax, n_real - 2), dtype=f64, device=dev)
+        om = None if omega is None else torch.as_tensor(omega, dtype=f64).to(dev).contiguous()
+        A = None if om is None else torch.empty((self.nk, self.nbmax, om.numel()), dtype=f64, device=dev)
+        flags = torch.zeros(1, dtype=torch.int32, device=dev)
+        gap = torch.zeros(1, dtype=f64, device=dev)
+        self.ctx.continue_cpe(n_real, w_min, w_max, ridge, eta, self.eps, self.sig_x, self.sig_iw, self.mu, om, A,
+                              E, coef, flags, stream=self.stream)
+        self.ctx.gap_of(E, int(round(self.n_target)), gap, stream=self.stream)
+        return E, A, gap, coef, flags
+
     def _record(self):
         return dict(mu=float(self.mu.item()), N=float(self.N.item()),
                     gap=float(self.gap_d.item()), flags=int(self.flags.item()))

@@ -124,3 +124,63 @@ def test_continuation_validation(torch):
     with pytest.raises(amd.MsgwError):
         run.ctx.gap_of(E, 0, gap)
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------------------------
+# continuous-pole expansion
+# ---------------------------------------------------------------------------------------------
+CPE = dict(n_real=41, w_min=-3.0, w_max=3.0, ridge=1e-8)
+
+
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN])
+def test_cpe_two_pole_matches_oracle(torch, cfg):
+    """The non-negative fit, quasiparticle energies, A(w) and gap against the oracle (scipy's
+    active-set NNLS on the augmented system; the GPU solves the normal equations)."""
+    prob, run = make_run(cfg)
+    sig, sstat = _two_pole(cfg, prob, 13)
+    run.sig_iw.copy_(torch.from_numpy(sig))
+    run.sig_x.copy_(torch.from_numpy(sstat))
+    run.mu.fill_(0.0123)
+    omega = np.linspace(-1.5, 1.5, 31)
+    eta = 0.02
+    E, A, gap, coef, flags = run.continue_cpe(eta=eta, omega=omega, **CPE)
+    torch.cuda.synchronize()
+    wg = o.cpe_grid(CPE["w_min"], CPE["w_max"], CPE["n_real"])
+    Eo, ok, ao = o.qp_energies_cpe(prob.eps, prob.nb, sstat, sig, 0.0123, cfg.beta, wg, CPE["ridge"], eta)
+    Ao = o.spectral_cpe(prob.eps, sstat, ao, 0.0123, wg, eta, omega)
+    mask = np.arange(prob.eps.shape[1])[None, :] < np.asarray(prob.nb)[:, None]
+    cg = np_(coef)
+    e_coef = rel(cg[mask], ao[mask])
+    dE = np.max(np.abs(np_(E)[mask] - Eo[mask]))
+    e_A = rel(np_(A)[mask], Ao[mask])
+    go = o.qp_gap(Eo, prob.nb, int(round(prob.n_target)))
+    print(f"{cfg.name}: coef rel {e_coef:.2e}, max |dE| {dE:.2e}, A rel {e_A:.2e}, "
+          f"gap {go:.6f} vs {float(gap.item()):.6f}")
+    assert int(flags.item()) == 0 and ok.all()
+    assert np.all(cg >= 0)
+    assert e_coef < 1e-6 and dE < 1e-8 and e_A < 1e-6
+    assert abs(float(gap.item()) - go) < 1e-8
+
+
+@pytest.mark.parametrize("prec", [0, 2])
+def test_cpe_qp_gap_physical_scale_g0w0(torch, c1_phys, prec):
+    """The paper's continuation on the physical-scale G0W0 pass: the CPE fit tolerates the split
+    path's ~1e-6 differences (it is a regularised least-squares fit, not an interpolation)."""
+    import paper_1602_02313_amd as amd
+    cfg, prob, g, ref = c1_phys
+    _, run = make_run(cfg, precision=prec, q_batch=8)
+    src = amd.HostM(lambda q: g.q_packed(q), amd.C128 if prec == 0 else amd.C64)
+    run.run(src, "g0w0", 1)
+    kw = dict(n_real=61, w_min=-2.0, w_max=2.0, ridge=1e-8)
+    E, _, gap, _, flags = run.continue_cpe(eta=0.01, **kw)
+    torch.cuda.synchronize()
+    wg = o.cpe_grid(kw["w_min"], kw["w_max"], kw["n_real"])
+    Eo, ok, _ = o.qp_energies_cpe(prob.eps, prob.nb, ref["sigx"], ref["sigc_iw"], ref["mu"], cfg.beta, wg,
+                                  kw["ridge"], 0.01)
+    go = o.qp_gap(Eo, prob.nb, int(round(prob.n_target)))
+    mask = np.arange(prob.eps.shape[1])[None, :] < np.asarray(prob.nb)[:, None]
+    dE = np.max(np.abs(np_(E)[mask] - Eo[mask]))
+    dg = abs(float(gap.item()) - go)
+    print(f"CPE prec={prec}: QP gap {go * 1e3:.4f} mHa, max |dE| {dE:.2e} Ha, gap error {dg / MEV:.2e} meV")
+    assert int(flags.item()) == 0 and ok.all()
+    assert dg < MEV
