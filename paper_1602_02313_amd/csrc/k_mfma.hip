@@ -26,7 +26,9 @@
 // round-robin to the 8 XCDs, so id b is mapped to work item (b % 8) * per + b / 8 -- each XCD
 // walks a contiguous slice of the work -- and the work space (rows x columns) is cut into
 // super-tiles of SR x SC items (about the number of waves resident on one XCD), so the waves
-// running together on an XCD share SR row panels and SC column panels in its L2.
+// running together on an XCD share SR row panels and SC column panels in its L2.  Where only part of
+// the item space holds work (the upper triangle of the Hermitian polarization), the slices are cut
+// so that every XCD gets the same number of working items, not the same number of indices.
 #include "internal.h"
 
 namespace msgw {
@@ -105,6 +107,7 @@ struct Order {
     int per_q;     // padded items per q
     int total;     // nq * per_q
     int off, n;    // items [off, off + n) belong to this launch
+    int xs[9];     // XCD x takes the launch's items [xs[x], xs[x + 1]) (offsets from off)
 };
 
 // item counts of an order; the work-items of one call must be countable in an int
@@ -147,25 +150,98 @@ Order make_order_st(int R, int C, int nq, int SR, int SC) {
     return o;
 }
 
+// the item at index w of an order (q relative to the call, row, column; r, c may lie in the padding)
+inline void order_item(const Order& o, int w, int& qrel, int& r, int& c) {
+    qrel = w / o.per_q;
+    w -= qrel * o.per_q;
+    const int sts = o.SR * o.SC;
+    const int st = w / sts, in = w - st * sts;
+    const int sr = st / o.nSC, sc = st - sr * o.nSC;
+    r = sr * o.SR + in / o.SC;
+    c = sc * o.SC + in % o.SC;
+}
+
+// Working items among [w0, w1) of an order whose row r of q holds work in the columns [lo, hi) that
+// rows(qrel, r, lo, hi) returns.  Whole super-tiles are counted row by row, partial ones item by item.
+template <class RR>
+int64_t order_count(const Order& o, int64_t w0, int64_t w1, RR&& rows) {
+    const int sts = o.SR * o.SC;
+    int64_t n = 0;
+    int64_t w = w0;
+    while (w < w1) {
+        const int64_t st0 = w / sts * sts;
+        if (w == st0 && st0 + sts <= w1) {  // a whole super-tile
+            int qrel, r, c;
+            order_item(o, int(w), qrel, r, c);
+            for (int rr = r; rr < std::min(r + o.SR, o.R); ++rr) {
+                int lo, hi;
+                rows(qrel, rr, lo, hi);
+                lo = std::max(lo, c);
+                hi = std::min({hi, c + o.SC, o.C});
+                n += std::max(0, hi - lo);
+            }
+            w += sts;
+        } else {
+            int qrel, r, c;
+            order_item(o, int(w), qrel, r, c);
+            if (r < o.R && c < o.C) {
+                int lo, hi;
+                rows(qrel, r, lo, hi);
+                n += (c >= lo && c < hi) ? 1 : 0;
+            }
+            ++w;
+        }
+    }
+    return n;
+}
+
 // launch(grid, order) once per slice of at most 2^32 - 1 work-items, the most one grid dimension
-// holds (grids are multiples of 8)
-template <class F>
-void launch_order(Order o, unsigned threads, F&& launch) {
+// holds.  Each XCD takes a contiguous part of the slice: of equal length, or, given rows (see
+// order_count), holding equal numbers of working items; the grid is 8 times the longest part.
+template <class F, class RR = std::nullptr_t>
+void launch_order(Order o, unsigned threads, F&& launch, RR&& rows = nullptr) {
     const int64_t cap = (int64_t(0xFFFFFFFFu) / threads) & ~int64_t(7);
     const int total = o.total;
     for (int64_t s0 = 0; s0 < total; s0 += cap) {
         o.off = int(s0);
         o.n = int(std::min<int64_t>(cap, total - s0));
-        launch(dim3(unsigned(round_up(o.n, 8))), o);
+        const int per = (o.n + 7) / 8;
+        for (int x = 0; x <= 8; ++x) o.xs[x] = std::min(x * per, o.n);
+        if constexpr (!std::is_same_v<std::decay_t<RR>, std::nullptr_t>) {
+            // cut where the running count of working items reaches x/8 of them
+            const int64_t nw = order_count(o, o.off, int64_t(o.off) + o.n, rows);
+            int64_t w = o.off, seen = 0;
+            const int sts = o.SR * o.SC;
+            for (int x = 1; x < 8; ++x) {
+                const int64_t want = nw * x / 8;
+                while (seen < want) {  // whole super-tiles while they fit, then single items
+                    const int64_t st_end = std::min<int64_t>((w / sts + 1) * sts, int64_t(o.off) + o.n);
+                    const int64_t m = order_count(o, w, st_end, rows);
+                    if (seen + m <= want && w % sts == 0) {
+                        seen += m;
+                        w = st_end;
+                    } else {
+                        seen += order_count(o, w, w + 1, rows);
+                        ++w;
+                    }
+                }
+                o.xs[x] = int(w - o.off);
+            }
+            o.xs[8] = o.n;
+        }
+        int longest = 0;
+        for (int x = 0; x < 8; ++x) longest = std::max(longest, o.xs[x + 1] - o.xs[x]);
+        launch(dim3(unsigned(8 * std::max(longest, 1))), o);
         MSGW_HIP(hipGetLastError());
     }
 }
 
-// consecutive items of a launch go to one XCD; returns false for padding items
+// the hardware deals work-group ids round-robin to the 8 XCDs: XCD b % 8 takes item xs[b % 8] + b / 8
+// of its part; returns false past the part and for padding items
 __device__ __forceinline__ bool work_item(const Order& o, int& qrel, int& r, int& c) {
-    const int per = gridDim.x >> 3;
-    int w = int(blockIdx.x & 7) * per + int(blockIdx.x >> 3);
-    if (w >= o.n) return false;
+    const int x = int(blockIdx.x & 7);
+    int w = o.xs[x] + int(blockIdx.x >> 3);
+    if (w >= o.xs[x + 1]) return false;
     w += o.off;
     qrel = w / o.per_q;
     w -= qrel * o.per_q;
@@ -1197,26 +1273,65 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
 
     const double sc = d.scale;
     bool first = true;
+    // P += s acc for this lane's 16 pairs per tau tile.  With one work-group per CU the partial sums
+    // already in P are read in batches of 8 from clamped (always valid) addresses before any store,
+    // so a batch costs one memory round trip; only the valid elements are written.  With two the
+    // registers for that are lacking and each element is read and written in turn.
+    constexpr int FB = 8;
     auto flush = [&]() {
         int z = 0;  // opaque zero: keeps the output addresses out of the main loop
         asm volatile("" : "+v"(z));
+        if constexpr (OCC > 1) {
+#pragma unroll
+            for (int tt = 0; tt < NTT; ++tt) {
+                const int it = tb + 32 * tt + r32 + z;
+#pragma unroll
+                for (int x = 0; x < 16; ++x) {
+                    const int p = 8 * (x >> 2) + 4 * h2 + (x & 3);
+                    const int I = I0 + 4 * (wave % WI) + (p >> 3), J = J0 + 8 * (wave / WI) + (p & 7);
+                    if (it < nt_eff && I < NI && J < NI) {
+                        double2* pp = &Pq[(int64_t(it) * NI + I) * NI + J];
+                        double re = sc * double(acc[tt][0][x]);
+                        double im = sc * double(acc[tt][1][x]);
+                        if (!first) {
+                            const double2 o = *pp;
+                            re += o.x;
+                            im += o.y;
+                        }
+                        *pp = make_double2(re, im);
+                    }
+                }
+                zero16(acc[tt][0]);
+                zero16(acc[tt][1]);
+            }
+            first = false;
+            return;
+        }
 #pragma unroll
         for (int tt = 0; tt < NTT; ++tt) {
             const int it = tb + 32 * tt + r32 + z;
+            const int itc = min(it, nt_eff - 1);
 #pragma unroll
-            for (int x = 0; x < 16; ++x) {
-                const int p = 8 * (x >> 2) + 4 * h2 + (x & 3);
-                const int I = I0 + 4 * (wave % WI) + (p >> 3), J = J0 + 8 * (wave / WI) + (p & 7);
-                if (it < nt_eff && I < NI && J < NI) {
-                    double2* pp = &Pq[(int64_t(it) * NI + I) * NI + J];
-                    double re = sc * double(acc[tt][0][x]);
-                    double im = sc * double(acc[tt][1][x]);
-                    if (!first) {
-                        const double2 o = *pp;
-                        re += o.x;
-                        im += o.y;
+            for (int x0 = 0; x0 < 16; x0 += FB) {
+                double2 o[FB];
+#pragma unroll
+                for (int x = 0; x < FB; ++x) o[x] = make_double2(0.0, 0.0);
+                if (!first) {
+#pragma unroll
+                    for (int x = 0; x < FB; ++x) {
+                        const int p = 8 * ((x0 + x) >> 2) + 4 * h2 + ((x0 + x) & 3);
+                        const int I = I0 + 4 * (wave % WI) + (p >> 3), J = J0 + 8 * (wave / WI) + (p & 7);
+                        o[x] = Pq[(int64_t(itc) * NI + min(I, NI - 1)) * NI + min(J, NI - 1)];
                     }
-                    *pp = make_double2(re, im);
+                }
+#pragma unroll
+                for (int x = 0; x < FB; ++x) {
+                    const int p = 8 * ((x0 + x) >> 2) + 4 * h2 + ((x0 + x) & 3);
+                    const int I = I0 + 4 * (wave % WI) + (p >> 3), J = J0 + 8 * (wave / WI) + (p & 7);
+                    if (it < nt_eff && I < NI && J < NI)
+                        Pq[(int64_t(it) * NI + I) * NI + J] =
+                            make_double2(o[x].x + sc * double(acc[tt][0][x0 + x]),
+                                         o[x].y + sc * double(acc[tt][1][x0 + x]));
                 }
             }
             zero16(acc[tt][0]);
@@ -1641,10 +1756,16 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     const int ntiles = ceil_div(nt_eff, 32), n3 = ntiles / 3, rest = ntiles % 3;
     auto launch = [&](auto kern, int t0, int ntc) {
         const Order od = make_order_st(ceil_div(maxi, 4 * WI), ceil_div(maxi, 16) * ntc, nq, SR, SC * ntc);
+        // row r (4 WI rows I from I0) works on the 16-wide column blocks cj with J0 < NI and J0 + 16 > I0
+        auto rows = [&](int qrel, int r, int& lo, int& hi) {
+            const int NI = h.ni[q0 + qrel], I0 = r * 4 * WI;
+            lo = I0 / 16 * ntc;
+            hi = I0 < NI ? ceil_div(NI, 16) * ntc : lo;
+        };
         launch_order(od, 128 * WI, [&](dim3 g, const Order& o) {
             MSGW_LAUNCH(kern, g, dim3(128 * WI), 0, s, d, q0, (const float2*)M, (const uint32_t*)gz, (double2*)P, o,
                         t0, ntc, nt_eff);
-        });
+        }, rows);
     };
     if (n3 > 0) launch(k_polz<OCC, KS, WI, 3>, 0, n3);
     if (rest == 1) launch(k_polz<OCC, KS, WI, 1>, 96 * n3, 1);
