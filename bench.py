@@ -53,16 +53,19 @@ def flop_model(prob):
 def measured_record(kernel, tile, precision, cfg_name, q_batch):
     """Counter record of one launch of `kernel` (HBM bytes, executed MFMA work), or None.
 
-    The record (profiles/traffic_c2_bf16x3.json) holds FETCH_SIZE and WRITE_SIZE of one 4-q launch,
-    scaled by a plain copy of known size, together with the SHA-256 of the kernel source it was taken
-    on; it is used only for the same workload, precision, tile and unchanged source.
+    The record (profiles/traffic_c2_bf16x3.json) holds FETCH_SIZE and WRITE_SIZE of one launch over
+    its q_batch q, scaled by a plain copy of known size, together with the SHA-256 of the kernel source
+    it was taken on; it is used only for the same workload, precision, q batch, tile and unchanged
+    source.
     """
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_c2_bf16x3.json")
-    if precision != "bf16x3" or q_batch != 4 or not cfg_name.startswith("c2_") or not os.path.exists(path):
+    if precision != "bf16x3" or not cfg_name.startswith("c2_") or not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
+    if rec.get("q_batch") != q_batch:
+        return None
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
             return None
@@ -194,7 +197,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
-    ap.add_argument("--q-batch", type=int, default=4)
+    ap.add_argument("--q-batch", type=int, default=16)
     ap.add_argument("--fp64-ref-q", type=int, default=1,
                     help="q points on which the FP64 GPU path is timed for comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

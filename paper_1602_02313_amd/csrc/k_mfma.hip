@@ -1115,7 +1115,11 @@ __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __rest
 // hi/lo.  A larger WI shares every staged g plane among more pairs.
 // NTT 32-wide tau tiles per work item (a chunk of CW = 32 NTT tau columns): three for the chunks of 96,
 // one or two for a tail chunk; the launch covers ntc chunks starting at tau t0.
-template <int OCC, int KS, int WI, int NTT>
+// NBUF = 2: stage s + 1 is loaded into registers during stage s and written to the other LDS buffer
+// after it.  NBUF = 3: the buffer written after stage s is the one for stage s + 2, so stage s + 1 is
+// already in LDS while stage s runs and the Z of its first step is formed during the last MFMAs of
+// stage s (one barrier per stage either way).
+template <int OCC, int KS, int WI, int NTT, int NBUF = 2>
 __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const float2* __restrict__ M,
                                                         const uint32_t* __restrict__ gz,
                                                         double2* __restrict__ P, Order od, int t0, int ntc,
@@ -1124,8 +1128,9 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     static_assert(KS % GZ_KS == 0, "stages hold whole 32-K slabs of the g planes");
     static_assert((XROWS * KS) % NT == 0 && (2 * CW * KS / 8) % NT == 0, "stage split over threads");
     constexpr int XR = 2 * KS + 4, GR = KS / 2 + 4, NX = XROWS * KS / NT, NG = 2 * CW * KS / 8 / NT;
-    __shared__ float Xs[2][XROWS][XR];     // [buffer][row: 4 WI rows I then 16 rows J][K re, im]
-    __shared__ uint32_t Gs[2][2][CW][GR];  // [buffer][hi, lo][tau][K pair]
+    static_assert(NBUF == 2 || (NBUF == 3 && (KS / 16) % 2 == 0), "three buffers need an even step count");
+    __shared__ float Xs[NBUF][XROWS][XR];     // [buffer][row: 4 WI rows I then 16 rows J][K re, im]
+    __shared__ uint32_t Gs[NBUF][2][CW][GR];  // [buffer][hi, lo][tau][K pair]
     int qrel, r, c;
     if (!work_item(od, qrel, r, c)) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h2 = lane >> 5;
@@ -1270,6 +1275,32 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             }
         }
     };
+    // three buffers: z holds the Z of step 0 on entry and that of step 0 of the stage in nbuf on exit
+    // (formed during the last step; when no stage follows it is formed from stale LDS and not used)
+    auto compute_stage3 = [&](int buf, int nbuf, u32x4 (&za)[4]) {
+        u32x4 zb[4];
+#pragma unroll
+        for (int kk = 0; kk < KS / 16; ++kk) {
+            if (kk & 1) {
+                mmas(buf, kk, zb);
+                zform(kk + 1 < KS / 16 ? buf : nbuf, (kk + 1) % (KS / 16), za);
+            } else {
+                mmas(buf, kk, za);
+                zform(buf, kk + 1, zb);
+            }
+#pragma unroll
+            for (int i = 0; i < 6 * NTT; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x002, 18 / NTT, 0);  // then the VALU share
+            }
+        }
+        // pin the next stage's Z here, so that its forming is not moved behind the loop's branches and
+        // stays interleaved with the last MFMAs
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) asm volatile("" : "+v"(za[i][j]));
+    };
 
     const double sc = d.scale;
     bool first = true;
@@ -1352,6 +1383,50 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     while (nsl == 0 && k + 1 < kend) {
         blk = next_block(blk, ++k);
         nsl = (blk.KP + KS - 1) / KS;
+    }
+    if constexpr (NBUF == 3) {
+        // (k, slab, blk, nsl) is the load cursor, two stages ahead of the stage computed
+        auto advance = [&]() {
+            ++slab;
+            while (slab >= nsl && k + 1 < kend) {
+                blk = next_block(blk, ++k);
+                slab = 0;
+                nsl = (blk.KP + KS - 1) / KS;
+            }
+        };
+        gload(blk, 0);
+        lstore(0);
+        advance();
+        bool e1 = slab < nsl;  // stage s + 1 exists
+        if (e1) {
+            gload(blk, slab);
+            lstore(1);
+            advance();
+        }
+        __syncthreads();
+        u32x4 z0[4];
+        zform(0, 0, z0);
+        int buf = 0;
+        while (true) {
+            const bool e2 = e1 && slab < nsl;  // stage s + 2 exists
+            if (e2) gload(blk, slab);
+            const int nb1 = buf == NBUF - 1 ? 0 : buf + 1, nb2 = nb1 == NBUF - 1 ? 0 : nb1 + 1;
+            compute_stage3(buf, nb1, z0);
+            since += KS;
+            if (since >= 4096 || !e1) {
+                flush();
+                since = 0;
+            }
+            if (!e1) break;
+            if (e2) {
+                lstore(nb2);
+                advance();
+            }
+            __syncthreads();
+            buf = nb1;
+            e1 = e2;
+        }
+        return;
     }
     gload(blk, 0);
     lstore(0);
@@ -1733,7 +1808,7 @@ int64_t gz_elems(const Host& h, int q0, int nq) {
     return n;
 }
 
-template <int OCC, int SR, int SC, int KS = GZ_KS, int WI = 2>
+template <int OCC, int SR, int SC, int KS = GZ_KS, int WI = 2, int NBUF = 2>
 void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, void* P) {
     int maxi = 0, maxk = 0;
@@ -1767,9 +1842,9 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
                         t0, ntc, nt_eff);
         }, rows);
     };
-    if (n3 > 0) launch(k_polz<OCC, KS, WI, 3>, 0, n3);
-    if (rest == 1) launch(k_polz<OCC, KS, WI, 1>, 96 * n3, 1);
-    if (rest == 2) launch(k_polz<OCC, KS, WI, 2>, 96 * n3, 1);
+    if (n3 > 0) launch(k_polz<OCC, KS, WI, 3, NBUF>, 0, n3);
+    if (rest == 1) launch(k_polz<OCC, KS, WI, 1, NBUF>, 96 * n3, 1);
+    if (rest == 2) launch(k_polz<OCC, KS, WI, 2, NBUF>, 96 * n3, 1);
 }
 
 // pair-space self-energy: needs only the raw W~ (FP64), so it runs its own conversions
@@ -1847,6 +1922,7 @@ struct SigVariant {
 
 // index 0 of each table is the default (the fastest on the 4x4x4-k, 64-band, NI = 400 shapes)
 const PolVariant kPolBF16[] = {
+    {"pair-space 16x16 pairs K64 st4x8 3-buffer", run_polz<1, 4, 8, 64, 4, 3>, true},
     {"pair-space 16x16 pairs K64 st4x8", run_polz<1, 4, 8, 64, 4>, true},
     {"pair-space 8x16 pairs 2 WG/CU st4x16 K64", run_polz<2, 4, 16, 64>, true},
     {"pair-space 8x16 pairs 2 WG/CU st4x16", run_polz<2, 4, 16>, true},
