@@ -1150,10 +1150,11 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     struct Blk {
         const float2* A;
         const uint32_t* g;
-        int Kk, KP;
+        int Kk, KP, k;
     };
     auto block_of = [&](int kx) {
         Blk b;
+        b.k = kx;
         const int kq = d.kmq[q * nk + kx];
         b.Kk = d.nb[kx] * d.nb[kq];
         b.KP = (b.Kk + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD;
@@ -1166,27 +1167,57 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         b.g = prev.g + int64_t(TP) * prev.KP;
         return b;
     };
-    auto gload = [&](const Blk& b, int slab) {
-        const int K0 = slab * KS;
-        okx = 0;
+    // Byte offsets of this thread's staged elements from the block's base pointers, 32-bit (the host
+    // checks that a block's M rows and g planes fit), recomputed when the block changes: a stage then
+    // needs only a uniform base per block and slab.
+    uint32_t xo[NX], go[NG], rowok = 0;
+    int offk = -1;
+    constexpr int CH = KS / 8;  // 16-B chunks per g row of a stage
+    auto set_offsets = [&](const Blk& b) {
+        rowok = 0;
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
             const int id = tid + NT * i;             // XROWS rows x KS
             const int row = id / KS, kc = id % KS;
             const int R = row < 4 * WI ? I0 + row : J0 + row - 4 * WI;
-            const int K = K0 + kc;
-            okx |= (R < NI && K < b.Kk) ? (1u << i) : 0u;
-            rx[i] = b.A[int64_t(min(R, NI - 1)) * b.Kk + min(K, b.Kk - 1)];
+            rowok |= R < NI ? (1u << i) : 0u;
+            xo[i] = uint32_t(min(R, NI - 1) * b.Kk + kc) * uint32_t(sizeof(float2));
         }
-        constexpr int CH = KS / 8;  // 16-B chunks per g row of a stage
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
             const int id = tid + NT * i;             // 2 planes x CW tau x CH chunks of 4 u32
             const int pl = id / (CW * CH), rem = id - pl * CW * CH;
             const int t = rem / CH, ch = rem % CH;
-            rg[i] = *reinterpret_cast<const u32x4*>(b.g + (int64_t(pl * TP + tb + t) * b.KP + K0) / 2 + 4 * ch);
+            go[i] = uint32_t((pl * TP + tb + t) * b.KP) * 2u + 16u * uint32_t(ch);
+        }
+        offk = b.k;
+    };
+    auto gload = [&](const Blk& b, int slab) {
+        const int K0 = slab * KS;
+        if (b.k != offk) set_offsets(b);
+        const char* gb = reinterpret_cast<const char*>(b.g) + 2 * int64_t(K0);
+#pragma unroll
+        for (int i = 0; i < NG; ++i) rg[i] = *reinterpret_cast<const u32x4*>(gb + go[i]);
+        if (K0 + KS <= b.Kk) {
+            const char* xb = reinterpret_cast<const char*>(b.A + K0);
+#pragma unroll
+            for (int i = 0; i < NX; ++i) rx[i] = *reinterpret_cast<const float2*>(xb + xo[i]);
+            okx = rowok;
+        } else {  // the last slab of a block whose K is not a multiple of KS
+            okx = 0;
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                const int id = tid + NT * i;
+                const int row = id / KS, kc = id % KS;
+                const int R = row < 4 * WI ? I0 + row : J0 + row - 4 * WI;
+                const int K = K0 + kc;
+                okx |= (R < NI && K < b.Kk) ? (1u << i) : 0u;
+                rx[i] = b.A[int64_t(min(R, NI - 1)) * b.Kk + min(K, b.Kk - 1)];
+            }
         }
     };
+    // (a uniform branch around an unmasked copy for whole stages upsets the MFMA/VALU interleaving of
+    // the compute steps, so the mask is always applied)
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
@@ -1195,7 +1226,6 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             *reinterpret_cast<float2*>(&Xs[buf][row][2 * kc]) =
                 (okx >> i) & 1u ? rx[i] : make_float2(0.f, 0.f);
         }
-        constexpr int CH = KS / 8;
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
             const int id = tid + NT * i;
@@ -1625,6 +1655,7 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
     const double sc = d.scale;
     // epilogue on the accumulators: weight each row K = (n, m) by G_m(k-q, tau), sum the rows of
     // each band n and add to Sigma_n(k, tau)
+    const double* Gq = G + int64_t(kq) * nbmax * ntau;  // G_m(k - q, tau) = Gq[m * ntau + tau]
     auto flush = [&]() {
         int z = 0;  // opaque zero: keeps the loop-invariant G loads of this epilogue out of the loop
         asm volatile("" : "+v"(z));
@@ -1638,14 +1669,20 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
                 const int it = tb + 32 * tt + r32;
                 const int itc = min(it, ntau - 1);
                 for (int nx = nlo; nx <= nhi; ++nx) {
+                    // the 16 weights are loaded together from clamped (always valid) rows m, so the
+                    // epilogue waits once per band instead of once per element
+                    float gw[16];
+#pragma unroll
+                    for (int x = 0; x < 16; ++x) {
+                        const int K = kb + 8 * (x >> 2) + 4 * h2 + (x & 3);
+                        const int m = min(max(K - nx * nm, 0), nm - 1);
+                        gw[x] = float(Gq[m * ntau + itc + z]);
+                    }
                     float v = 0.f;  // 16 terms; the run totals are summed in FP64
 #pragma unroll
                     for (int x = 0; x < 16; ++x) {
                         const int K = kb + 8 * (x >> 2) + 4 * h2 + (x & 3);
-                        if (K < Kk && K / nm == nx) {
-                            const int m = K - nx * nm;
-                            v += acc[kt][tt][x] * float(G[(int64_t(kq) * nbmax + m) * ntau + itc + z]);
-                        }
+                        if (K < Kk && K / nm == nx) v += acc[kt][tt][x] * gw[x];
                     }
                     v += __shfl_xor(v, 32);
                     if (h2 == 0 && it < ntau)
@@ -1819,6 +1856,10 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     }
     if (size_t(gz_elems(h, q0, nq)) * 2 > scratch_mfma_bytes(d, h))
         throw Error(MSGW_ENOMEM, "workspace too small for the g planes");
+    // the kernel addresses one block's M rows and g planes with 32-bit byte offsets
+    if (int64_t(maxi) * maxk * 8 >= (int64_t(1) << 32) ||
+        int64_t(2) * gz_tp(h.ntau) * round_up(maxk, GZ_KPAD) * 2 >= (int64_t(1) << 31))
+        throw Error(MSGW_ENOTSUP, "a (q, k) block too large for the pair-space polarization");
     uint32_t* gz = reinterpret_cast<uint32_t*>(scratch_mfma(d, h));
     const unsigned gx = unsigned(ceil_div(gz_tp(h.ntau) * round_up(maxk, GZ_KPAD) / 2, 256));
     for (int q = q0; q < q0 + nq && !d.kreuse; ++q) {
