@@ -181,3 +181,37 @@ def test_screen_full_ni(torch, big):
     e_t = rel(got_t, Wt_ref)
     print(f"[{cfg.name}] screen NI={NI}: W(i nu) rel {e_w:.2e}, W(tau) rel {e_t:.2e}")
     assert e_w < 1e-10 and e_t < 1e-10
+
+
+@pytest.mark.parametrize("ni", [400, 512, 513])
+def test_screen_panel_sizes(torch, ni):
+    """The FP64 screen at C2's product-basis size (400), at a multiple of the 16-column panel (512)
+    and one past it (513, a last panel of one column), against the oracle on sampled frequencies of
+    a synthetic negative-definite P(i nu) with a non-Hermitian part."""
+    import paper_1602_02313_amd as amd
+    cfg = gi.C2.replace(ni=ni, name=f"c2_ni{ni}")
+    prob = gi.make_problem(cfg)
+    run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
+                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=amd.FP64, q_batch=1)
+    q, niw = 2, cfg.niw_b
+    rng = np.random.default_rng(ni)
+    d = 1.0 / (1.0 + np.arange(ni) / 16.0)
+    B = (rng.normal(size=(ni, ni)) + 1j * rng.normal(size=(ni, ni))) * np.sqrt(d)[:, None]
+    P0 = -(B @ B.conj().T) / ni * 0.02
+    C = rng.normal(size=(ni, ni)) + 1j * rng.normal(size=(ni, ni))
+    P1 = (C - C.T) * 1e-3                                # a non-Hermitian part as well
+    nu = o.matsubara(o.BOSON, niw, cfg.beta)
+    lor = 1.0 / (1.0 + (nu / 0.5) ** 2)
+    Piw = lor[:, None, None] * P0[None] + (lor ** 2)[:, None, None] * P1[None]
+    run.P_iw[:Piw.size].copy_(torch.from_numpy(Piw.ravel()))
+    vq = torch.from_numpy(np.asarray(prob.v[q], dtype=np.float64)).to("cuda")
+    run.ctx.screen(q, 1, run.P_iw, vq, run.Wt_iw, run.R_iw, run.info)
+    torch.cuda.synchronize()
+    assert int(run.info[:niw].abs().max()) == 0
+    nus = [0, 1, niw // 2, niw - 1]
+    W, R = o.screen(Piw[nus], prob.v[q])
+    Wg = np_(run.Wt_iw[:Piw.size].view(niw, ni, ni)[nus])
+    Rg = np_(run.R_iw[:Piw.size].view(niw, ni, ni)[nus])
+    e_w, e_r = rel(Wg, W), rel(Rg, R)
+    print(f"screen NI={ni}: W(i nu) rel {e_w:.2e}, R rel {e_r:.2e}")
+    assert e_w < 1e-10 and e_r < 1e-10
