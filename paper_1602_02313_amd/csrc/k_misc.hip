@@ -336,7 +336,7 @@ __device__ double block_sum(double x, double* red) {
     return t;
 }
 
-// DIAG: block per (q, k, n); threads over m
+// DIAG: block per (q, k, n); threads over m and slices of I
 __global__ void k_sigx_diag(Dev d, int q0, const void* __restrict__ M, int c64,
                             const double* __restrict__ occ, const double* __restrict__ v,
                             double* __restrict__ out) {
@@ -349,14 +349,20 @@ __global__ void k_sigx_diag(Dev d, int q0, const void* __restrict__ M, int c64,
     if (n >= nn) return;
     const int64_t base = (d.mpre[q] - d.mpre[q0]) + d.moff[q * nk + k];
     const double* vq = v + (d.vpre[q] - d.vpre[q0]);
+    // the threads cover mw >= nm columns m (whole waves, coalesced rows of M) times S slices of I
+    const int mw = min(int(blockDim.x), (nm + 63) / 64 * 64), S = int(blockDim.x) / mw;
+    const int sl = threadIdx.x / mw;
     double part = 0.0;
-    for (int m = threadIdx.x; m < nm; m += blockDim.x) {
-        double s = 0.0;
-        for (int I = 0; I < nI; ++I) {
-            double2 x = ld_c(M, base + (int64_t(I) * nn + n) * nm + m, c64);
-            s += vq[I] * (x.x * x.x + x.y * x.y);
+    if (sl < S) {
+        for (int m = threadIdx.x % mw; m < nm; m += mw) {
+            double s = 0.0;
+#pragma unroll 4
+            for (int I = sl; I < nI; I += S) {
+                const double2 x = ld_c(M, base + (int64_t(I) * nn + n) * nm + m, c64);
+                s += vq[I] * (x.x * x.x + x.y * x.y);
+            }
+            part += (-occ[(int64_t(kq) * d.nbmax + m) * d.ntau + d.ntau - 1]) * s;
         }
-        part += (-occ[(int64_t(kq) * d.nbmax + m) * d.ntau + d.ntau - 1]) * s;
     }
     double tot = block_sum(part, red);
     if (threadIdx.x == 0) atomicAdd(&out[int64_t(k) * d.nbmax + n], d.scale * tot);
