@@ -232,11 +232,13 @@ constexpr int BTAU = 16;  // most tau points per work-group
 // produced together, so R(J, I) for the conjugate-pair term comes from the mirror tile through LDS and
 // every element of R is read once per tau chunk.  With p = e^{-i nu tau}, S = R(I,J) + conj R(J,I)
 // and D = R(I,J) - conj R(J,I), the pair p R(I,J) + conj(p) conj R(J,I) equals Re(p) S + i Im(p) D.
+// The elements of the next frequency are loaded while the current one is combined, and the two tiles
+// alternate between two LDS buffers, so one barrier per frequency suffices.
 __global__ __launch_bounds__(256) void k_inv_b(const double2* __restrict__ eb, int niw, int ntau, int n,
                                                int nch, const double2* __restrict__ F,
                                                const double2* __restrict__ add, const double* __restrict__ v,
                                                double beta, double2* __restrict__ out) {
-    __shared__ double2 ta[BT][BT + 1], tb[BT][BT + 1];
+    __shared__ double2 ta[2][BT][BT + 1], tb[2][BT][BT + 1];
     extern __shared__ double2 ph[];  // [niw][BTAU] phases of this tau chunk
     const int nt = (n + BT - 1) / BT;
     int p = blockIdx.x, ti = 0;      // tile pair -> (ti, tj), rows of the upper triangle of tiles
@@ -270,16 +272,25 @@ __global__ __launch_bounds__(256) void k_inv_b(const double2* __restrict__ eb, i
         }
     }
     __syncthreads();  // phases staged
+    const int64_t offA = int64_t(IA) * n + JA, offB = int64_t(IB) * n + JB;
+    double2 an = z0, bn = z0;  // the elements of frequency w + 1
+    if (niw > 1) {
+        an = okA ? Fb[nn + offA] : z0;
+        bn = okB && two ? Fb[nn + offB] : z0;
+    }
     for (int w = 1; w < niw; ++w) {
-        const double2* Fw = Fb + int64_t(w) * nn;
-        const double2 a = okA ? Fw[int64_t(IA) * n + JA] : z0;
-        const double2 bb = okB && two ? Fw[int64_t(IB) * n + JB] : z0;
-        ta[ty][tx] = a;
-        tb[ty][tx] = bb;
+        const double2 a = an, bb = bn;
+        if (w + 1 < niw) {
+            const double2* Fn = Fb + int64_t(w + 1) * nn;
+            an = okA ? Fn[offA] : z0;
+            bn = okB && two ? Fn[offB] : z0;
+        }
+        const int buf = w & 1;  // written here, read after the barrier; rewritten two frequencies later
+        ta[buf][ty][tx] = a;
+        tb[buf][ty][tx] = bb;
         __syncthreads();
-        const double2 tA = two ? tb[tx][ty] : ta[tx][ty];  // R(JA, IA)
-        const double2 tB = ta[tx][ty];                     // R(JB, IB)
-        __syncthreads();
+        const double2 tA = two ? tb[buf][tx][ty] : ta[buf][tx][ty];  // R(JA, IA)
+        const double2 tB = ta[buf][tx][ty];                          // R(JB, IB)
         const double SAx = a.x + tA.x, SAy = a.y - tA.y, DAx = a.x - tA.x, DAy = a.y + tA.y;
         const double SBx = bb.x + tB.x, SBy = bb.y - tB.y, DBx = bb.x - tB.x, DBy = bb.y + tB.y;
         const double2* pw = ph + w * BTAU;
