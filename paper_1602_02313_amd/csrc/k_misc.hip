@@ -151,13 +151,15 @@ __global__ void k_fwd(const double2* __restrict__ W, int niw, int ntau, int64_t 
     double2 acc[FCH];
 #pragma unroll
     for (int j = 0; j < FCH; ++j) acc[j] = make_double2(0.0, 0.0);
+    auto load = [&](int i) {
+        const int64_t at = (b * ntau + i) * len + e;
+        return CPLX ? reinterpret_cast<const double2*>(f)[at]
+                    : make_double2(reinterpret_cast<const double*>(f)[at], 0.0);
+    };
+    double2 fn = load(0);  // the next point's value is loaded while this one is accumulated
     for (int i = 0; i < ntau; ++i) {
-        int64_t at = (b * ntau + i) * len + e;
-        double2 fi;
-        if (CPLX)
-            fi = reinterpret_cast<const double2*>(f)[at];
-        else
-            fi = make_double2(reinterpret_cast<const double*>(f)[at], 0.0);
+        double2 fi = fn;
+        if (i + 1 < ntau) fn = load(i + 1);
         if (eref) fi.x -= g0_tau(E, tau[i], beta);
 #pragma unroll
         for (int j = 0; j < FCH; ++j) {
