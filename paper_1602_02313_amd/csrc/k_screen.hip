@@ -38,6 +38,7 @@ __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __r
     __shared__ int idx[MSGW_MAX_NI];
     __shared__ double2 buf[MSGW_MAX_NI];        // pivot column multipliers / row buffer
     __shared__ double2 tch[RCH][SB];
+    __shared__ double2 prow[SB];               // the scaled pivot row within the panel
     __shared__ double rv[NT / 64];
     __shared__ int ri[NT / 64];
     __shared__ int s_info;
@@ -117,23 +118,38 @@ __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __r
             if (tid < jb) {
                 const int c = j0 + tid;
                 double2* a = &A[int64_t(j) * n + c];
-                *a = (c == j) ? inv : cmuls(*a, inv);
+                const double2 val = (c == j) ? inv : cmuls(*a, inv);
+                *a = val;
+                prow[tid] = val;
             }
             __syncthreads();
-            for (int e = tid; e < n * jb; e += NT) {
-                const int i = e / jb, c = j0 + e % jb;
-                if (i == j) continue;
-                const double2 f = buf[i];
-                double2* a = &A[int64_t(i) * n + c];
-                if (c == j) {
-                    double2 t = cmuls(f, inv);
-                    *a = make_double2(-t.x, -t.y);
-                } else {
-                    double2 r = A[int64_t(j) * n + c];
-                    double2 x = *a;
-                    x.x -= f.x * r.x - f.y * r.y;
-                    x.y -= f.x * r.y + f.y * r.x;
-                    *a = x;
+            // eliminate column j from the other rows of the panel: each thread loads its EB elements
+            // together (one memory round trip), then updates them
+            constexpr int EB = 8;
+            for (int e0 = tid; e0 < n * jb; e0 += NT * EB) {
+                double2 x[EB];
+#pragma unroll
+                for (int u = 0; u < EB; ++u) {
+                    const int e = e0 + u * NT;
+                    const int i = e / jb, c = j0 + e % jb;
+                    x[u] = (e < n * jb && i != j && c != j) ? A[int64_t(i) * n + c] : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int u = 0; u < EB; ++u) {
+                    const int e = e0 + u * NT;
+                    const int i = e / jb, t = e % jb, c = j0 + t;
+                    if (e >= n * jb || i == j) continue;
+                    const double2 f = buf[i];
+                    if (c == j) {
+                        const double2 w = cmuls(f, inv);
+                        A[int64_t(i) * n + c] = make_double2(-w.x, -w.y);
+                    } else {
+                        const double2 r = prow[t];
+                        double2 y = x[u];
+                        y.x -= f.x * r.x - f.y * r.y;
+                        y.y -= f.x * r.y + f.y * r.x;
+                        A[int64_t(i) * n + c] = y;
+                    }
                 }
             }
             __syncthreads();
