@@ -1146,7 +1146,6 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     // staging per thread: NX complex elements of the M rows and NG 16-B chunks of the g planes
     float2 rx[NX];
     u32x4 rg[NG];
-    uint32_t okx = 0;  // validity bits of rx, applied when the stage is written to LDS
     struct Blk {
         const float2* A;
         const uint32_t* g;
@@ -1169,18 +1168,18 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     };
     // Byte offsets of this thread's staged elements from the block's base pointers, 32-bit (the host
     // checks that a block's M rows and g planes fit), recomputed when the block changes: a stage then
-    // needs only a uniform base per block and slab.
-    uint32_t xo[NX], go[NG], rowok = 0;
+    // needs only a uniform base per block and slab.  Rows past NI and K past the block's K read the
+    // nearest valid element instead of zeros: such rows only form pairs that are never stored, and the
+    // g planes are zero for K past the block's K, so those terms add exact zeros.
+    uint32_t xo[NX], go[NG];
     int offk = -1;
     constexpr int CH = KS / 8;  // 16-B chunks per g row of a stage
     auto set_offsets = [&](const Blk& b) {
-        rowok = 0;
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
             const int id = tid + NT * i;             // XROWS rows x KS
             const int row = id / KS, kc = id % KS;
             const int R = row < 4 * WI ? I0 + row : J0 + row - 4 * WI;
-            rowok |= R < NI ? (1u << i) : 0u;
             xo[i] = uint32_t(min(R, NI - 1) * b.Kk + kc) * uint32_t(sizeof(float2));
         }
 #pragma unroll
@@ -1202,29 +1201,22 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             const char* xb = reinterpret_cast<const char*>(b.A + K0);
 #pragma unroll
             for (int i = 0; i < NX; ++i) rx[i] = *reinterpret_cast<const float2*>(xb + xo[i]);
-            okx = rowok;
         } else {  // the last slab of a block whose K is not a multiple of KS
-            okx = 0;
 #pragma unroll
             for (int i = 0; i < NX; ++i) {
                 const int id = tid + NT * i;
                 const int row = id / KS, kc = id % KS;
                 const int R = row < 4 * WI ? I0 + row : J0 + row - 4 * WI;
-                const int K = K0 + kc;
-                okx |= (R < NI && K < b.Kk) ? (1u << i) : 0u;
-                rx[i] = b.A[int64_t(min(R, NI - 1)) * b.Kk + min(K, b.Kk - 1)];
+                rx[i] = b.A[int64_t(min(R, NI - 1)) * b.Kk + min(K0 + kc, b.Kk - 1)];
             }
         }
     };
-    // (a uniform branch around an unmasked copy for whole stages upsets the MFMA/VALU interleaving of
-    // the compute steps, so the mask is always applied)
     auto lstore = [&](int buf) {
 #pragma unroll
         for (int i = 0; i < NX; ++i) {
             const int id = tid + NT * i;
             const int row = id / KS, kc = id % KS;
-            *reinterpret_cast<float2*>(&Xs[buf][row][2 * kc]) =
-                (okx >> i) & 1u ? rx[i] : make_float2(0.f, 0.f);
+            *reinterpret_cast<float2*>(&Xs[buf][row][2 * kc]) = rx[i];
         }
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
