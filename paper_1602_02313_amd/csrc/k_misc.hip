@@ -228,7 +228,7 @@ __global__ void k_inv_f(const double2* __restrict__ ef, int niw, int ntau, int64
 // add (scaled v_I add_IJ v_J when v is given)
 // ---------------------------------------------------------------------------------------------
 constexpr int BT = 16;    // matrix tile edge
-constexpr int BTAU = 16;  // most tau points per work-group
+constexpr int BTAU = 21;  // most tau points per work-group
 
 // One work-group per (tile pair, tau chunk, block b): the tiles (ti, tj) and (tj, ti), ti <= tj, are
 // produced together, so R(J, I) for the conjugate-pair term comes from the mirror tile through LDS and
