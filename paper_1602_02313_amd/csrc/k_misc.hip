@@ -768,7 +768,9 @@ void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, cons
     const int64_t nt = ceil_div(mat_n, BT);
     const int nch = int(ceil_div(d.ntau, BTAU));
     const size_t lds = sizeof(double2) * size_t(d.niw_b) * BTAU;
-    if (lds > 48 * 1024) throw Error(MSGW_ENOTSUP, "iw_to_tau: niw_b must be <= 192 for BOSON matrices");
+    if (lds > 48 * 1024)
+        throw Error(MSGW_ENOTSUP, "iw_to_tau: niw_b must be <= " + std::to_string(48 * 1024 / (16 * BTAU)) +
+                                      " for BOSON matrices");
     if (nblk > 65535) throw Error(MSGW_ENOTSUP, "iw_to_tau: at most 65535 BOSON matrices per call");
     dim3 grid(ceil_div(nt * (nt + 1) / 2, 1), nch, unsigned(nblk));
     MSGW_LAUNCH(k_inv_b, grid, dim3(256), lds, s, d.eb, d.niw_b, d.ntau, mat_n, nch, (const double2*)F,
