@@ -165,7 +165,9 @@ int msgw_tau_to_iw(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t le
  *     (e_ref may be NULL: no reference term).
  *   BOSON (mat_n > 0, len == mat_n^2, Hermitian pair f(-i nu) = f(i nu)^H, c128 output):
  *     f(tau_i) = add(tau_i) + (1/beta)[f_0 + sum_{n>=1}(e^{-i nu_n tau_i} f_n + e^{i nu_n tau_i} f_n^H)]
- *     add_tau (device c128 [nblk][ntau][len] or NULL). */
+ *     add_tau (device c128 [nblk][ntau][len] or NULL).
+ *     MSGW_ENOTSUP for BOSON when niw_b > 146 (the phases of a chunk of tau points are kept in LDS) or
+ *     nblk > 65535. */
 int msgw_iw_to_tau(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t len, int mat_n,
                    const void* f_iw, const void* add_tau, const double* e_ref, void* f_tau);
 
