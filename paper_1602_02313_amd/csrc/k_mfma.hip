@@ -18,13 +18,15 @@
 // The FP32 accumulators of the polarization are flushed into the FP64 output every FLUSH_STEPS
 // K-steps, so an FP32 sum never runs over more than 4096 complex terms.
 //
-// Polarization: one wave (64 lanes) per work-group.  Each wave owns a (16 WI) x (16 WJ) x T output
-// tile and streams its operands from global memory; reuse between waves is served by L2.
-// Self-energy: besides one-wave variants of the same kind, a 4-wave variant (v7) stages its
-// operands through LDS and runs on v_mfma_f32_32x32x16_bf16.  To make that
-// reuse happen, work-groups are ordered XCD-aware: the hardware deals consecutive work-group ids
-// round-robin to the 8 XCDs, so id b is mapped to work item (b % 8) * per + b / 8 -- each XCD
-// walks a contiguous slice of the work -- and the work space (rows x columns) is cut into
+// The split-BF16 defaults are the pair-space kernels (k_polz, k_sigz; 32x32x16 MFMA, operands staged
+// through LDS by 8-wave work-groups; see their sections below).  The tile forms: polarization, one
+// wave (64 lanes) per work-group owning a (16 WI) x (16 WJ) x T output tile and streaming its operands
+// from global memory (reuse between waves served by L2); self-energy, one-wave variants of the same
+// kind and a 4-wave variant (v7) that stages its operands through LDS and runs on
+// v_mfma_f32_32x32x16_bf16.  To make the reuse happen, work-groups are ordered XCD-aware: the
+// hardware deals consecutive work-group ids round-robin to the 8 XCDs, so id b is mapped to item
+// b / 8 of the slice of XCD b % 8 -- each XCD walks a contiguous slice of the work -- and the work
+// space (rows x columns) is cut into
 // super-tiles of SR x SC items (about the number of waves resident on one XCD), so the waves
 // running together on an XCD share SR row panels and SC column panels in its L2.  Where only part of
 // the item space holds work (the upper triangle of the Hermitian polarization), the slices are cut
