@@ -697,3 +697,129 @@ def test_cpe_one_pole_weight_causality_and_qp():
     roots = np.roots([1.0, -(0.3 + p), 0.3 * p - r])
     exact = roots[np.argmin(np.abs(roots - 0.3))]
     assert ok.all() and abs(E[0, 0] - exact) < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# inverse bosonic transform of W~: the negative-frequency term
+# ---------------------------------------------------------------------------
+# For a Hermitian P(tau), P(-i nu) = P(i nu)^H, and with a real diagonal v the same holds for
+# W~ and R = W~ - v P v.  The truncated inverse sum must therefore pair each R(i nu_n) with
+# R(i nu_n)^H at -nu_n.  Two facts fix that pairing independently of the oracle's formula:
+# the result is Hermitian at every tau for any Hermitian P(tau) (also without the tau mirror),
+# and the forward transform of the result at +nu_m and at -nu_m returns R(i nu_m) and
+# R(i nu_m)^H.
+def _mutant_boson_inverse(kind):
+    """A literal loop of the inverse bosonic sum whose partner of R_n is R_n^H ("RH", the
+    reading) or a planted slip (R^T, conj R, R)."""
+    def inv(R, tau, beta, add_tau=None):
+        niw = R.shape[0]
+        nu = o.matsubara(o.BOSON, niw, beta)
+        partner = {"RH": np.conj(np.swapaxes(R, 1, 2)), "RT": np.swapaxes(R, 1, 2),
+                   "conjR": np.conj(R), "R": R}[kind]
+        out = np.zeros((tau.size,) + R.shape[1:], dtype=complex)
+        for i, t in enumerate(tau):
+            out[i] = R[0]
+            for n in range(1, niw):
+                out[i] += np.exp(-1j * nu[n] * t) * R[n] + np.exp(1j * nu[n] * t) * partner[n]
+        out /= beta
+        return out if add_tau is None else out + add_tau
+    return inv
+
+
+def _screen_chain_without_mirror():
+    """W~(tau) of one q for a Hermitian P(tau) without P(tau) = P(beta - tau) (independent M)."""
+    cfg = gi.tiny(grid=(3, 1, 1), nocc=2, nemp=3, ni=6, ntau=24, beta=8.0, niw=10)
+    p = gi.make_problem(cfg)
+    g = gi.MGenerator(cfg, symmetric=False)
+    G = o.green0(p.eps, p.nb, p.tau, cfg.beta)
+    q = 1
+    P = o.polarization(g.q_blocks(q), G, p.kmq[q], cfg.scale)
+    Piw = o.tau_to_iw(P, p.tau, cfg.beta, o.BOSON, cfg.niw_b)
+    _, R = o.screen(Piw, p.v[q])
+    return cfg, p, q, P, R
+
+
+def test_wt_tau_hermitian_without_tau_mirror():
+    cfg, p, q, P, R = _screen_chain_without_mirror()
+    # the inputs are generic: P(tau) Hermitian but not mirror symmetric, R neither Hermitian,
+    # real nor symmetric, so no partner other than R^H gives a Hermitian sum
+    assert np.abs(P - np.conj(np.swapaxes(P, 1, 2))).max() < 1e-13 * np.abs(P).max()
+    assert np.abs(P - P[::-1]).max() > 1e-3 * np.abs(P).max()
+    for other in (np.conj(np.swapaxes(R, 1, 2)), np.conj(R), np.swapaxes(R, 1, 2)):
+        assert np.abs(R[1:] - other[1:]).max() > 1e-3 * np.abs(R[1:]).max()
+    Wt = o.wt_tau(R, P, p.v[q], p.tau, cfg.beta)
+    herm = np.abs(Wt - np.conj(np.swapaxes(Wt, 1, 2))).max(axis=(1, 2))
+    assert herm.max() < 1e-12 * np.abs(Wt).max()
+
+
+def test_boson_inverse_round_trip_both_frequency_signs():
+    rng = np.random.default_rng(5)
+    beta, niw, n = 10.0, 6, 4
+    R = rng.normal(size=(niw, n, n)) + 1j * rng.normal(size=(niw, n, n))
+    tau = np.linspace(0.0, beta, 2001)
+    f = o.iw_to_tau_boson_herm(R, tau, beta)
+    pos = o.tau_to_iw(f, tau, beta, o.BOSON, niw)                   # int e^{+i nu tau} f
+    neg = np.conj(o.tau_to_iw(np.conj(f), tau, beta, o.BOSON, niw))  # int e^{-i nu tau} f
+    scale = np.abs(R).max()
+    assert np.abs(pos - R).max() < 1e-6 * scale
+    assert np.abs(neg[1:] - np.conj(np.swapaxes(R[1:], 1, 2))).max() < 1e-6 * scale
+    # the constant term appears once: at nu = 0 both signs give R_0
+    assert np.abs(neg[0] - R[0]).max() < 1e-6 * scale
+
+
+@pytest.mark.parametrize("kind", ["RT", "conjR", "R"])
+def test_planted_boson_inverse_mistakes_are_caught(kind):
+    bad = _mutant_boson_inverse(kind)
+    # the planted copy agrees with the oracle when its partner is the right one
+    cfg, p, q, P, R = _screen_chain_without_mirror()
+    good = _mutant_boson_inverse("RH")(R, p.tau, cfg.beta)
+    assert np.abs(good - o.iw_to_tau_boson_herm(R, p.tau, cfg.beta)).max() < 1e-12 * np.abs(good).max()
+    # Hermiticity pin
+    v = np.asarray(p.v[q])
+    Wt = bad(R, p.tau, cfg.beta, add_tau=v[None, :, None] * P * v[None, None, :])
+    herm = np.abs(Wt - np.conj(np.swapaxes(Wt, 1, 2))).max()
+    assert herm > 1e-4 * np.abs(Wt).max()
+    # round-trip pin
+    rng = np.random.default_rng(5)
+    beta, niw, n = 10.0, 6, 4
+    Rr = rng.normal(size=(niw, n, n)) + 1j * rng.normal(size=(niw, n, n))
+    tau = np.linspace(0.0, beta, 401)
+    f = bad(Rr, tau, beta)
+    neg = np.conj(o.tau_to_iw(np.conj(f), tau, beta, o.BOSON, niw))
+    assert np.abs(neg[1:] - np.conj(np.swapaxes(Rr[1:], 1, 2))).max() > 1e-2 * np.abs(Rr).max()
+
+
+# ---------------------------------------------------------------------------
+# gap proxy on a hand-built level list
+# ---------------------------------------------------------------------------
+def test_gap_proxy_hand_built_levels():
+    # two k points, three bands, the third band of k = 1 absent (Nb_1 = 2, its entries are
+    # ignored).  E^QP = eps + Sigma_static + Re Sigma^c(i w_0) - mu:
+    eps = np.array([[-0.50, 0.10, 0.90], [-0.30, 0.45, 99.0]])
+    stat = np.array([[0.05, -0.02, 0.00], [0.00, 0.01, -99.0]])
+    sc0 = np.array([[0.01 + 5j, 0.00 - 1j, 0.03 + 0j], [-0.02 + 0j, 0.00 + 2j, 0.0 + 0j]])
+    mu = 0.2
+    nb = np.array([3, 2])
+    # levels before the common -mu: k0: -0.44, 0.08, 0.93; k1: -0.32, 0.46
+    # ascending: -0.44, -0.32, 0.08, 0.46, 0.93 (the imaginary parts play no role)
+    want = {1: -0.32 - (-0.44), 2: 0.08 - (-0.32), 3: 0.46 - 0.08, 4: 0.93 - 0.46}
+    for n_target, N in ((1.0, 1), (2.4, 2), (2.6, 3), (4.0, 4)):
+        got = o.gap_proxy(eps, nb, stat, sc0, mu, n_target)
+        assert got == pytest.approx(want[N], abs=1e-14)
+
+
+def test_planted_gap_proxy_index_slip_is_caught():
+    eps = np.array([[-0.50, 0.10, 0.90], [-0.30, 0.45, 99.0]])
+    stat = np.zeros_like(eps)
+    sc0 = np.zeros(eps.shape, dtype=complex)
+    nb = np.array([3, 2])
+
+    def slipped(eps, nb, sig_static, sigc_iw0, mu, n_target):
+        mask = np.arange(eps.shape[1])[None, :] < np.asarray(nb)[:, None]
+        e = np.sort((eps + sig_static + np.real(sigc_iw0) - mu)[mask])
+        N = int(round(n_target))
+        return float(e[N + 1] - e[N])
+
+    ref = o.gap_proxy(eps, nb, stat, sc0, 0.0, 2.0)
+    assert ref == pytest.approx(0.10 - (-0.30), abs=1e-14)
+    assert abs(slipped(eps, nb, stat, sc0, 0.0, 2.0) - ref) > 0.01
