@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 # dense MFMA peaks of MI355X (TFLOP/s).  A split-BF16 product costs three BF16 products, so its
 # effective FP32-equivalent peak is the BF16 peak / 3.
 PEAK_BF16 = 2516.6
-PEAK = {"bf16x3": PEAK_BF16 / 3.0, "fp32": 157.3, "fp64": 78.6}
+PEAK = {"bf16x3": PEAK_BF16 / 3.0, "f16x3": PEAK_BF16 / 3.0, "fp32": 157.3, "fp64": 78.6}
 
 
 def log(*a):
@@ -196,7 +196,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--precision", default="bf16x3", choices=["bf16x3", "fp32", "fp64"])
+    ap.add_argument("--precision", default="f16x3", choices=["f16x3", "bf16x3", "fp32", "fp64"])
     ap.add_argument("--q-batch", type=int, default=16)
     ap.add_argument("--fp64-ref-q", type=int, default=1,
                     help="q points on which the FP64 GPU path is timed for comparison (0: skip)")
@@ -237,7 +237,7 @@ def main():
 
     cfg = gi.CONFIGS[args.config]
     prob = gi.make_problem(cfg)
-    prec = {"bf16x3": amd.BF16X3, "fp32": amd.FP32, "fp64": amd.FP64}[args.precision]
+    prec = {"f16x3": amd.F16X3, "bf16x3": amd.BF16X3, "fp32": amd.FP32, "fp64": amd.FP64}[args.precision]
     log(f"[bench] {cfg.name}: nk={cfg.nk} nb={int(prob.nb.max())} NI={int(prob.ni.max())} "
         f"ntau={prob.tau.size} niw={cfg.niw_f} precision={args.precision}")
     run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
@@ -397,7 +397,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"bf16x3": "bf16x3 (split fp32 on bf16 MFMA, fp32 accumulate) + f64",
+        "dtype": {"f16x3": "f16x3 (split fp32 on f16 MFMA, scaled, fp32 accumulate) + f64",
+                  "bf16x3": "bf16x3 (split fp32 on bf16 MFMA, fp32 accumulate) + f64",
                   "fp32": "f32 MFMA + f64", "fp64": "f64"}[args.precision],
         "data": "synthetic (seeded Philox matrix elements, model bands, diagonal Coulomb kernel)",
         "config": {"workload": f"{cfg.name}: one G0W0 + Dyson pass, all 64 q",

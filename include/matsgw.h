@@ -67,6 +67,11 @@ extern "C" {
 #define MSGW_FP64    0   /* FP64 arithmetic throughout                                  */
 #define MSGW_FP32    1   /* FP32 MFMA, FP32 accumulation per k, FP64 across k            */
 #define MSGW_BF16X3  2   /* 3-term BF16 split (hi*hi + hi*lo + lo*hi) on MFMA, FP32 accumulate */
+#define MSGW_F16X3   3   /* 3-term FP16 split of power-of-two-scaled operands on MFMA, FP32
+                            accumulate: M scaled per q, the weights (g for P, W~ for Sigma) per
+                            (q, tau), so that the largest element is near 2^14; hi = f16(x),
+                            lo = f16(x - hi), x.y ~ hi*hi + hi*lo + lo*hi (about 2^-21 relative
+                            per product against 2^-16 for BF16X3); the scales are undone in FP64 */
 
 /* storage type of M */
 #define MSGW_C128    0
@@ -88,6 +93,7 @@ extern "C" {
 #define MSGW_FLAG_NAN        1   /* a non-finite value in Sigma or G   */
 #define MSGW_FLAG_NOBRACKET  2   /* n_target outside [N(lo), N(hi)]     */
 #define MSGW_FLAG_NOCONV     4   /* a quasiparticle equation did not converge */
+#define MSGW_FLAG_SINGULAR   8   /* msgw_screen: an exactly zero pivot of 1 - v^1/2 P v^1/2 */
 
 /* hard limits (checked by set_problem / the calls) */
 #define MSGW_MAX_NI   1024   /* product-basis size per q (screen keeps a row per thread) */
@@ -145,7 +151,7 @@ int msgw_green0(msgw_ctx* c, void* stream, const double* eps, double mu, double*
 /* a2. Polarization (eq. irpol):
  * P_IJ(q,tau_i) = s sum_k sum_{n<Nb_k} sum_{m<Nb_{k-q}} M^I_nm G_n(k,tau_i) G_m(k-q,tau_{ntau-1-i}) conj(M^J_nm)
  * for q = q0..q0+nq-1.  M (device, m_dtype) starts at q0's block; G_tau device; P_tau (device c128)
- * is overwritten.  precision MSGW_FP64 needs MSGW_C128 M; FP32/BF16X3 need MSGW_C64 M. */
+ * is overwritten.  precision MSGW_FP64 needs MSGW_C128 M; FP32/BF16X3/F16X3 need MSGW_C64 M. */
 int msgw_polarization(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
                       const double* G_tau, int precision, void* P_tau);
 
@@ -175,9 +181,11 @@ int msgw_iw_to_tau(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t le
  * chi~ = v^1/2 P v^1/2;  W~ = v^1/2 [(1 - chi~)^-1 - 1] v^1/2;  R = W~ - v P v.
  * (1 - chi~) is inverted in FP64 by blocked Gauss-Jordan with partial (row) pivoting.
  * P_iw, Wt_iw, R_iw: device c128 [q][niw_b][NI_q][NI_q]; v: device f64 [q][NI_q]; R_iw may be NULL.
- * info: device int [nq*niw_b], 0 or 1 + the first column whose pivot was exactly zero. */
+ * info: device int [nq*niw_b], 0 or 1 + the first column whose pivot was exactly zero (the outputs of
+ * that matrix are then not finite).  flags: device int or NULL; MSGW_FLAG_SINGULAR is OR-ed into it
+ * when some info is not 0, so that one word can collect the status of every q batch of a pass. */
 int msgw_screen(msgw_ctx* c, void* stream, int q0, int nq, const void* P_iw, const double* v,
-                void* Wt_iw, void* R_iw, int* info);
+                void* Wt_iw, void* R_iw, int* info, int* flags);
 
 /* a5. W~(q,tau_i) = v P(q,tau_i) v + (1/beta)[R(i nu_0) + sum_{n>=1}(e^{-i nu_n tau_i} R(i nu_n)
  *                    + e^{i nu_n tau_i} R(i nu_n)^H)]
@@ -287,8 +295,10 @@ int msgw_get_variant(const msgw_ctx* c, int op, int precision, int* variant);
  * self-energy calls on c to the k blocks k0 <= k < k1, so that a loop over k reproduces one full call
  * launch by launch.  A polarization with k0 > 0 ADDS its blocks to P_tau (k0 == 0 overwrites); the
  * self-energy accumulates as always.  reuse_prepared != 0 skips the per-q preparations (the g planes
- * of the polarization, the weight blocks of the self-energy) and reuses what the previous call of the
- * same op and q batch left in the workspace.  k1 <= 0 restores the full range.  While a partial range
+ * of the polarization, the weight blocks of the self-energy, the operand scales of MSGW_F16X3) and
+ * reuses what the previous contraction call left in the workspace; that call must have been of the same
+ * op, q range, precision and variant (the two ops share the scratch), else the call fails with
+ * MSGW_EINVAL and enqueues nothing.  k1 <= 0 restores the full range.  While a partial range
  * is set, the other tile variants and precisions return MSGW_ENOTSUP. */
 int msgw_set_k_range(msgw_ctx* c, int k0, int k1, int reuse_prepared);
 

@@ -17,12 +17,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmatsgw.so")
 
 OK, EINVAL, ESHAPE, EHIP, ENOMEM, ENOCONV, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, F16X3 = 0, 1, 2, 3
 C128, C64 = 0, 1
 FERMION, BOSON = 0, 1
 SIGMA_DIAG, SIGMA_FULL = 0, 1
 MU_FIXED, MU_SEARCH = 0, 1
-FLAG_NAN, FLAG_NOBRACKET = 1, 2
+FLAG_NAN, FLAG_NOBRACKET, FLAG_NOCONV, FLAG_SINGULAR = 1, 2, 4, 8
 MAX_NI = 1024
 
 EXPORTS = [
@@ -80,7 +80,7 @@ def load_library():
         "msgw_polarization": [P, P, I, I, P, I, P, I, P],
         "msgw_tau_to_iw": [P, P, I, L, L, P, I, P, P],
         "msgw_iw_to_tau": [P, P, I, L, L, I, P, P, P, P],
-        "msgw_screen": [P, P, I, I, P, P, P, P, P],
+        "msgw_screen": [P, P, I, I, P, P, P, P, P, P],
         "msgw_screened_tau": [P, P, I, I, P, P, P, P],
         "msgw_self_energy": [P, P, I, I, P, I, P, P, I, P],
         "msgw_sigma_x": [P, P, I, I, P, I, P, P, P],
@@ -220,9 +220,9 @@ class Context:
                                             int(mat_n), _ptr(f_iw), _ptr(add_tau), _ptr(e_ref),
                                             _ptr(f_tau)))
 
-    def screen(self, q0, nq, P_iw, v, Wt_iw, R_iw, info, stream=None):
+    def screen(self, q0, nq, P_iw, v, Wt_iw, R_iw, info, flags=None, stream=None):
         self._check(self.lib.msgw_screen(self._c, _stream(stream), q0, nq, _ptr(P_iw), _ptr(v),
-                                         _ptr(Wt_iw), _ptr(R_iw), _ptr(info)))
+                                         _ptr(Wt_iw), _ptr(R_iw), _ptr(info), _ptr(flags)))
 
     def screened_tau(self, q0, nq, R_iw, P_tau, v, Wt_tau, stream=None):
         self._check(self.lib.msgw_screened_tau(self._c, _stream(stream), q0, nq, _ptr(R_iw),

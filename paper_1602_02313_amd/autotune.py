@@ -38,7 +38,7 @@ def _launch(op, ctx, run, M, q0, nq, st):
 def tune(run, M_source, reps=2, cache_path=None, log=None, ops=None):
     """Pick the fastest variant of each MFMA op for `run`; returns {op: (index, name, ms list)}."""
     import torch
-    if run.precision not in (L.FP32, L.BF16X3):
+    if run.precision not in (L.FP32, L.BF16X3, L.F16X3):
         return {}
     cache = {}
     if cache_path and os.path.exists(cache_path):

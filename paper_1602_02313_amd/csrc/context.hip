@@ -22,7 +22,12 @@ struct msgw_ctx {
     size_t ws_bytes = 0;
     bool ws_ready = false;
     Dev d;
-    int variant[2][3] = {{0, 0, 0}, {0, 0, 0}};  // [op][precision] tile shape of the MFMA paths
+    int variant[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};  // [op][precision] tile shape of the MFMA paths
+    // what the last contraction call left in the split-precision scratch (the per-q operands a call
+    // with reuse_prepared may reuse); op = -1: nothing reusable
+    struct Prepared {
+        int op = -1, q0 = 0, nq = 0, precision = 0, variant = 0;
+    } prep;
 };
 
 namespace {
@@ -260,6 +265,7 @@ int msgw_set_problem(msgw_ctx* c, const msgw_problem* p) {
         c->ef = std::move(ef);
         c->eb = std::move(eb);
         c->have_problem = true;
+        c->prep = msgw_ctx::Prepared();
         c->ws_ready = false;
         c->ws = nullptr;
         c->ws_bytes = 0;
@@ -333,12 +339,14 @@ int msgw_set_workspace(msgw_ctx* c, void* dptr, size_t bytes) {
         need(off == tb, MSGW_EINVAL, "internal: table size mismatch");
         d.scratch = base + off;
         d.scratch_bytes = bytes - off;
+        scratch_set_scales(d, h);
         d.kb0 = 0;
         d.kb1 = h.nk;
         c->d = d;
         c->ws = base;
         c->ws_bytes = bytes;
         c->ws_ready = true;
+        c->prep = msgw_ctx::Prepared();
     });
 }
 
@@ -376,22 +384,47 @@ int msgw_synth_M(msgw_ctx* c, void* stream, uint64_t seed, int q0, int nq, int s
 
 static bool full_k_range(const msgw_ctx* c) { return c->d.kb0 == 0 && c->d.kb1 == c->h.nk; }
 
+// A call with reuse_prepared set must follow a call of the same op, q range, precision and variant
+// (the polarization's g planes and the self-energy's weight blocks share the scratch); every other
+// call that writes the scratch records itself (or clears the record).
+static void check_reuse(msgw_ctx* c, int op, int q0, int nq, int precision) {
+    const auto& p = c->prep;
+    const int v = c->variant[op][precision];
+    if (c->d.kreuse)
+        need(p.op == op && p.q0 == q0 && p.nq == nq && p.precision == precision && p.variant == v, MSGW_EINVAL,
+             "reuse_prepared: the scratch holds no operands of this op, q range, precision and variant");
+}
+static void record_prep(msgw_ctx* c, int op, int q0, int nq, int precision) {
+    if (c->d.kreuse) return;
+    if (precision == MSGW_FP64) {
+        c->prep = msgw_ctx::Prepared();  // the FP64 kernels leave the scratch alone
+        return;
+    }
+    c->prep.op = op;
+    c->prep.q0 = q0;
+    c->prep.nq = nq;
+    c->prep.precision = precision;
+    c->prep.variant = c->variant[op][precision];
+}
+
 int msgw_polarization(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
                       const double* G_tau, int precision, void* P_tau) {
     return guarded(c, [&] {
         require_ready(c);
         check_qrange(c, q0, nq);
         need(M && G_tau && P_tau, MSGW_EINVAL, "null pointer");
-        need(full_k_range(c) || precision == MSGW_BF16X3, MSGW_ENOTSUP,
-             "a partial k range is supported by the MSGW_BF16X3 pair-space kernels only");
+        need(full_k_range(c) || precision == MSGW_BF16X3 || precision == MSGW_F16X3, MSGW_ENOTSUP,
+             "a partial k range is supported by the split-precision pair-space kernels only");
+        check_reuse(c, MSGW_OP_POLARIZATION, q0, nq, precision);
         if (precision == MSGW_FP64) {
             need(m_dtype == MSGW_C128, MSGW_EINVAL, "MSGW_FP64 needs MSGW_C128 M");
             launch_pol_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, P_tau);
-        } else if (precision == MSGW_FP32 || precision == MSGW_BF16X3) {
-            need(m_dtype == MSGW_C64, MSGW_EINVAL, "MSGW_FP32 / MSGW_BF16X3 need MSGW_C64 M");
+        } else if (precision == MSGW_FP32 || precision == MSGW_BF16X3 || precision == MSGW_F16X3) {
+            need(m_dtype == MSGW_C64, MSGW_EINVAL, "MSGW_FP32 / MSGW_BF16X3 / MSGW_F16X3 need MSGW_C64 M");
             int rc = launch_pol_mfma(c->d, c->h, S(stream), q0, nq, M, G_tau, precision,
                                      c->variant[MSGW_OP_POLARIZATION][precision], P_tau);
             need(rc == MSGW_OK, rc, "polarization: unsupported shape for the MFMA path");
+            record_prep(c, MSGW_OP_POLARIZATION, q0, nq, precision);
         } else {
             throw Error(MSGW_EINVAL, "bad precision");
         }
@@ -434,13 +467,13 @@ int msgw_iw_to_tau(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t le
 }
 
 int msgw_screen(msgw_ctx* c, void* stream, int q0, int nq, const void* P_iw, const double* v,
-                void* Wt_iw, void* R_iw, int* info) {
+                void* Wt_iw, void* R_iw, int* info, int* flags) {
     return guarded(c, [&] {
         require_ready(c);
         check_qrange(c, q0, nq);
         need(P_iw && v && Wt_iw && info, MSGW_EINVAL, "null pointer");
         need(P_iw != Wt_iw, MSGW_EINVAL, "P_iw and Wt_iw must not alias");
-        launch_screen(c->d, c->h, S(stream), q0, nq, P_iw, v, Wt_iw, R_iw, info);
+        launch_screen(c->d, c->h, S(stream), q0, nq, P_iw, v, Wt_iw, R_iw, info, flags);
     });
 }
 
@@ -468,8 +501,10 @@ int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, i
         require_ready(c);
         check_qrange(c, q0, nq);
         need(M && G_tau && Wt_tau && Sigma_tau, MSGW_EINVAL, "null pointer");
-        need(full_k_range(c) || (precision == MSGW_BF16X3 && c->h.sigma_mode != MSGW_SIGMA_FULL), MSGW_ENOTSUP,
-             "a partial k range is supported by the MSGW_BF16X3 pair-space kernels only");
+        need(full_k_range(c) || ((precision == MSGW_BF16X3 || precision == MSGW_F16X3) &&
+                                 c->h.sigma_mode != MSGW_SIGMA_FULL),
+             MSGW_ENOTSUP, "a partial k range is supported by the split-precision pair-space kernels only");
+        check_reuse(c, MSGW_OP_SELF_ENERGY, q0, nq, precision);
         if (c->h.sigma_mode == MSGW_SIGMA_FULL) {
             need(precision == MSGW_FP64 && m_dtype == MSGW_C128, MSGW_ENOTSUP,
                  "MSGW_SIGMA_FULL runs in MSGW_FP64 with MSGW_C128 M");
@@ -479,11 +514,12 @@ int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, i
         if (precision == MSGW_FP64) {
             need(m_dtype == MSGW_C128, MSGW_EINVAL, "MSGW_FP64 needs MSGW_C128 M");
             launch_sig_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, Sigma_tau);
-        } else if (precision == MSGW_FP32 || precision == MSGW_BF16X3) {
-            need(m_dtype == MSGW_C64, MSGW_EINVAL, "MSGW_FP32 / MSGW_BF16X3 need MSGW_C64 M");
+        } else if (precision == MSGW_FP32 || precision == MSGW_BF16X3 || precision == MSGW_F16X3) {
+            need(m_dtype == MSGW_C64, MSGW_EINVAL, "MSGW_FP32 / MSGW_BF16X3 / MSGW_F16X3 need MSGW_C64 M");
             int rc = launch_sig_mfma(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, precision,
                                      c->variant[MSGW_OP_SELF_ENERGY][precision], Sigma_tau);
             need(rc == MSGW_OK, rc, "self_energy: workspace too small or unsupported shape for the MFMA path");
+            record_prep(c, MSGW_OP_SELF_ENERGY, q0, nq, precision);
         } else {
             throw Error(MSGW_EINVAL, "bad precision");
         }
@@ -553,6 +589,7 @@ int msgw_continue_cpe(msgw_ctx* c, void* stream, int n_real, double w_min, doubl
         need(n_omega == 0 || (omega && A), MSGW_EINVAL, "n_omega > 0 needs omega and A");
         launch_cpe(c->d, c->h, S(stream), n_real, w_min, w_max, ridge, eta, eps, sigma_static, Sigma_c_iw, mu,
                    n_omega, n_omega ? omega : nullptr, n_omega ? A : nullptr, E_qp, coef, flags);
+        c->prep = msgw_ctx::Prepared();  // its design matrix overwrites the split-precision scratch
     });
 }
 
@@ -569,7 +606,7 @@ int msgw_gap_of(msgw_ctx* c, void* stream, const double* E, int n_index, double*
 
 int msgw_variant_count(int op, int precision) {
     if (op != MSGW_OP_POLARIZATION && op != MSGW_OP_SELF_ENERGY) return MSGW_EINVAL;
-    if (precision != MSGW_FP32 && precision != MSGW_BF16X3) return MSGW_EINVAL;
+    if (precision != MSGW_FP32 && precision != MSGW_BF16X3 && precision != MSGW_F16X3) return MSGW_EINVAL;
     return mfma_variant_count(op, precision);
 }
 

@@ -63,6 +63,11 @@ struct Dev {
     int kb0 = 0, kb1 = 0;             // k blocks [kb0, kb1) of the pair-space contractions
     int kreuse = 0;                   // 1: the per-q operands prepared by the previous call are reused
     int tau_mirror = 0;               // 1: P(q, tau_{N-1-i}) = P(q, tau_i) may be used (caller's assertion)
+    // operand scales of the MSGW_F16X3 contractions (in the scratch, indexed by absolute q):
+    unsigned long long* mx_m = nullptr;  // [nk]        bits of max |M^I_K|^2 over q's block (double >= 0)
+    unsigned long long* mx_w = nullptr;  // [nk][ntau]  bits of max |Re|, |Im| of W~(q, tau) (double >= 0)
+    double* g_max = nullptr;             // [nk][ntau]  max_n |G_n(k, tau)|
+    int* e_g = nullptr;                  // [nk][ntau]  power-of-two exponent of the polarization weights
 };
 
 // Host mirror of the problem (used for launch shapes and validation).
@@ -85,7 +90,7 @@ void launch_inv_fermion(const Dev& d, hipStream_t s, int64_t nblk, int64_t len, 
 void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, const void* F,
                       const void* add, const double* v, void* out);
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
-                   const double* v, void* Wt_iw, void* R_iw, int* info);
+                   const double* v, void* Wt_iw, void* R_iw, int* info, int* flags);
 void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
                     int m_dtype, const double* occ, const double* v, void* out, int full);
 void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
@@ -116,15 +121,32 @@ int mfma_variant_count(int op, int precision);
 const char* mfma_variant_name(int op, int precision, int variant);
 size_t mfma_scratch_bytes(const Host& h, int nq_max);
 
-// Scratch layout: [E array of msgw_dyson: nk*nbmax doubles][mu search state: 8 KB][MFMA conversion
-// buffers].
+// Scratch layout: [E array of msgw_dyson: nk*nbmax doubles][mu search state: 8 KB][operand scales
+// of the F16X3 contractions][MFMA conversion buffers].
 constexpr size_t kMuSearchBytes = 8192;
+inline size_t scratch_al(size_t x) { return (x + 255) & ~size_t(255); }
+inline size_t scratch_scale_bytes(const Host& h) {
+    const size_t nt = size_t(h.nk) * h.ntau;
+    return scratch_al(8 * size_t(h.nk)) + scratch_al(8 * nt) + scratch_al(8 * nt) + scratch_al(4 * nt);
+}
 inline size_t scratch_E_bytes(const Host& h) {
-    return ((sizeof(double) * size_t(h.nk) * h.nbmax + 255) & ~size_t(255)) + kMuSearchBytes;
+    return scratch_al(sizeof(double) * size_t(h.nk) * h.nbmax) + kMuSearchBytes + scratch_scale_bytes(h);
 }
 inline double* scratch_E(const Dev& d) { return reinterpret_cast<double*>(d.scratch); }
 inline double* scratch_mu_search(const Dev& d, const Host& h) {
-    return reinterpret_cast<double*>(d.scratch + scratch_E_bytes(h) - kMuSearchBytes);
+    return reinterpret_cast<double*>(d.scratch + scratch_al(sizeof(double) * size_t(h.nk) * h.nbmax));
+}
+// points the scale tables of d into its scratch (after the mu search state)
+inline void scratch_set_scales(Dev& d, const Host& h) {
+    char* p = d.scratch + scratch_al(sizeof(double) * size_t(h.nk) * h.nbmax) + kMuSearchBytes;
+    const size_t nt = size_t(h.nk) * h.ntau;
+    d.mx_m = reinterpret_cast<unsigned long long*>(p);
+    p += scratch_al(8 * size_t(h.nk));
+    d.mx_w = reinterpret_cast<unsigned long long*>(p);
+    p += scratch_al(8 * nt);
+    d.g_max = reinterpret_cast<double*>(p);
+    p += scratch_al(8 * nt);
+    d.e_g = reinterpret_cast<int*>(p);
 }
 inline char* scratch_mfma(const Dev& d, const Host& h) { return d.scratch + scratch_E_bytes(h); }
 inline size_t scratch_mfma_bytes(const Dev& d, const Host& h) {

@@ -38,11 +38,14 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int PREC_FP32 = MSGW_FP32;
 constexpr int PREC_BF16X3 = MSGW_BF16X3;
+constexpr int PREC_F16X3 = MSGW_F16X3;
 constexpr int NB_LDS = 256;       // band limit of the MFMA path (G slices staged in LDS)
 constexpr int FLUSH_STEPS = 256;  // K-steps of 16 complex between FP64 flushes
 constexpr int PAD = 64;           // W~ planes are zero-padded to a multiple of PAD
@@ -83,6 +86,54 @@ __device__ __forceinline__ uint32_t rot_pos(uint32_t p) {
 __device__ __forceinline__ uint32_t conj_pk(uint32_t p) { return p ^ 0x80000000u; }
 // (re, im) -> (im, re)
 __device__ __forceinline__ uint32_t swap_pk(uint32_t p) { return __builtin_amdgcn_alignbit(p, p, 16); }
+
+// ---- f16 helpers (MSGW_F16X3) --------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pk_f16(float a, float b) {
+    f16x2 v = {(_Float16)a, (_Float16)b};  // v_cvt_pk_f16_f32, round to nearest even
+    return __builtin_bit_cast(uint32_t, v);
+}
+// hi = f16(a), lo = f16(a - hi) for both halves of a pair; a - hi is exact in FP32.  The packed hi is
+// made opaque so that its halves are widened from the register rather than converted a second time.
+__device__ __forceinline__ void split_f16(float a, float b, uint32_t& h, uint32_t& l) {
+    h = pk_f16(a, b);
+    uint32_t hv = h;
+    asm("" : "+v"(hv));
+    const f16x2 hh = __builtin_bit_cast(f16x2, hv);
+    l = pk_f16(a - float(hh.x), b - float(hh.y));
+}
+// the split of the pair (a, b) into packed hi and lo halves in the element type of precision PR
+template <int PR>
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t& h, uint32_t& l) {
+    if constexpr (PR == PREC_F16X3) {
+        split_f16(a, b, h, l);
+    } else {
+        h = pk_bf16(a, b);
+        l = pk_bf16(a - bf_lo(h), b - bf_hi(h));
+    }
+}
+
+// Operand scales of MSGW_F16X3.  f16 holds 11 significant bits but overflows at 65504 (~2^16) and
+// loses relative precision below 2^-14, so each operand is scaled by a power of two that puts its
+// largest element in [2^13, 2^14]: M by 2^e_m per q (the pair products Z = M^I conj(M^J) then have
+// |Re Z|, |Im Z| <= max |M|^2 2^(2 e_m) <= 2^14), the real weights per (q, tau) column.  Elements
+// 2^-38 times the largest still keep f16 subnormal precision; the scales are undone in FP64.
+__device__ __forceinline__ int exp_above(double mx) {  // x with mx < 2^x, for mx > 0
+    int x;
+    frexp(mx, &x);
+    return x;
+}
+__device__ __forceinline__ int f16_exp_m(unsigned long long bits) {  // bits of max |M|^2
+    const double mx = __longlong_as_double(static_cast<long long>(bits));
+    if (!(mx > 0.0)) return 0;
+    const int t = 14 - exp_above(mx);           // 2 e_m <= t
+    const int e = t >= 0 ? t / 2 : -((1 - t) / 2);  // floor(t / 2)
+    return min(max(e, -100), 100);              // 2^e_m stays a normal float
+}
+__device__ __forceinline__ int f16_exp_w(unsigned long long bits) {  // bits of max |Re|, |Im| of W~
+    const double mx = __longlong_as_double(static_cast<long long>(bits));
+    // the weights c H_IJ = (c / 2)(W_IJ + conj W_JI), c <= 2, are bounded by 2 mx
+    return mx > 0.0 ? 14 - exp_above(2.0 * mx) : 0;
+}
 
 __device__ __forceinline__ floatx4 mfma_bf16(u32x4 a, u32x4 b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
@@ -816,6 +867,14 @@ __device__ __forceinline__ floatx16 mfma32(u32x4 a, u32x4 b, floatx16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
+template <int PR>
+__device__ __forceinline__ floatx16 mfma32p(u32x4 a, u32x4 b, floatx16 c) {
+    if constexpr (PR == PREC_F16X3)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    else
+        return mfma32(a, b, c);
+}
 __device__ __forceinline__ void zero16(floatx16& x) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) x[i] = 0.f;
@@ -1067,8 +1126,88 @@ __global__ __launch_bounds__(256) void k_tau_mirror(double2* __restrict__ P, int
     if (e < nn) P[int64_t(i) * nn + e] = P[int64_t(ntau - 1 - i) * nn + e];
 }
 
+// ---- F16X3 operand scales ------------------------------------------------------------------------
+// A fill kernel rather than a memset, so that the calls stay capturable in a graph.
+__global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* __restrict__ p, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+// largest value among the block's threads, then one atomic max on the bits (order-preserving for
+// non-negative doubles)
+__device__ __forceinline__ void block_max_atomic(double v, unsigned long long* out) {
+    __shared__ double part[4];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmax(v, __shfl_xor(v, m));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double b = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
+        atomicMax(out, static_cast<unsigned long long>(__double_as_longlong(b)));
+    }
+}
+// max |M^I_K|^2 over the n complex elements of one q's block
+__global__ __launch_bounds__(256) void k_mmax(const float2* __restrict__ M, int64_t n,
+                                              unsigned long long* __restrict__ out) {
+    double v = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        const float2 a = M[i];
+        v = fmax(v, double(a.x) * a.x + double(a.y) * a.y);
+    }
+    block_max_atomic(v, out);
+}
+// max |Re|, |Im| of W~(q, tau) for the tau plane blockIdx.y of one q
+__global__ __launch_bounds__(256) void k_wmax(const double2* __restrict__ W, int NI,
+                                              unsigned long long* __restrict__ out) {
+    const int64_t nn = int64_t(NI) * NI;
+    const double2* Wt = W + int64_t(blockIdx.y) * nn;
+    double v = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < nn; i += int64_t(gridDim.x) * 256) {
+        const double2 a = Wt[i];
+        v = fmax(v, fmax(fabs(a.x), fabs(a.y)));
+    }
+    block_max_atomic(v, out + blockIdx.y);
+}
+// max_n |G_n(k, tau)| for every (k, tau)
+__global__ __launch_bounds__(256) void k_gmax(Dev d, const double* __restrict__ G) {
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= d.nk * d.ntau) return;
+    const int k = id / d.ntau, t = id - k * d.ntau;
+    double v = 0.0;
+    for (int n = 0; n < d.nb[k]; ++n) v = fmax(v, fabs(G[(int64_t(k) * d.nbmax + n) * d.ntau + t]));
+    d.g_max[id] = v;
+}
+// exponent of the polarization weights of (q, tau): max_K |g_K(tau)| over the blocks of q is
+// max_k g_max(k, tau) g_max(k - q, beta - tau), attained by the two largest factors
+__global__ __launch_bounds__(256) void k_gexp(Dev d, int q0, int nq) {
+    const int id = blockIdx.x * 256 + threadIdx.x;
+    if (id >= nq * d.ntau) return;
+    const int q = q0 + id / d.ntau, t = id % d.ntau;
+    double u = 0.0;
+    for (int k = 0; k < d.nk; ++k)
+        u = fmax(u, d.g_max[k * d.ntau + t] * d.g_max[d.kmq[q * d.nk + k] * d.ntau + (d.ntau - 1 - t)]);
+    d.e_g[q * d.ntau + t] = u > 0.0 ? 14 - exp_above(u) : 0;
+}
+// the maxima of M for q0..q0+nq-1 (polarization and self-energy) and of W~ (self-energy)
+void launch_scales(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M, const void* W) {
+    MSGW_LAUNCH(k_fill_u64, dim3(ceil_div(nq, 256)), dim3(256), 0, s, d.mx_m + q0, nq);
+    if (W) MSGW_LAUNCH(k_fill_u64, dim3(ceil_div(int64_t(nq) * h.ntau, 256)), dim3(256), 0, s,
+                       d.mx_w + int64_t(q0) * h.ntau, nq * h.ntau);
+    for (int q = q0; q < q0 + nq; ++q) {
+        const int64_t n = h.mpre[q + 1] - h.mpre[q];
+        MSGW_LAUNCH(k_mmax, dim3(unsigned(std::min<int64_t>(ceil_div(n, 256), 4096))), dim3(256), 0, s,
+                    (const float2*)M + (h.mpre[q] - h.mpre[q0]), n, d.mx_m + q);
+        if (W) {
+            const int64_t nn = int64_t(h.ni[q]) * h.ni[q];
+            MSGW_LAUNCH(k_wmax, dim3(unsigned(std::min<int64_t>(ceil_div(nn, 256), 64)), h.ntau), dim3(256), 0, s,
+                        (const double2*)W + (h.ppre[q] - h.ppre[q0]), h.ni[q], d.mx_w + int64_t(q) * h.ntau);
+        }
+    }
+    MSGW_HIP(hipGetLastError());
+}
+
 // one thread per (tau, K pair): writes hi and lo of g for two consecutive K.  gz points at the planes
 // of q; the offset of block k inside them is summed over the k' < k by the whole work-group.
+template <int PR>
 __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __restrict__ G,
                                               uint32_t* __restrict__ gz) {
     __shared__ int64_t part[4];
@@ -1091,6 +1230,8 @@ __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __rest
     const int npair = KP / 2;
     if (id >= TP * npair) return;
     const int t = id / npair, K0 = 2 * (id - t * npair);
+    // F16X3: the column tau is scaled by 2^e_g(q, tau)
+    const double gs = (PR == PREC_F16X3 && t < ntau) ? ldexp(1.0, d.e_g[q * ntau + t]) : 1.0;
     float g[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -1099,12 +1240,11 @@ __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __rest
         if (t < ntau && K < Kk) {
             const int n = K / nm, m = K - n * nm;
             g[e] = float(G[(int64_t(k) * nbmax + n) * ntau + t] *
-                         G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - t)]);
+                         G[(int64_t(kq) * nbmax + m) * ntau + (ntau - 1 - t)] * gs);
         }
     }
     uint32_t h, l;
-    h = pk_bf16(g[0], g[1]);
-    l = pk_bf16(g[0] - bf_lo(h), g[1] - bf_hi(h));
+    split_pair<PR>(g[0], g[1], h, l);
     uint32_t* hp = gz + (off >> 1);
     hp[int64_t(t) * (KP / 2) + K0 / 2] = h;
     hp[int64_t(TP + t) * (KP / 2) + K0 / 2] = l;
@@ -1121,7 +1261,7 @@ __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __rest
 // after it.  NBUF = 3: the buffer written after stage s is the one for stage s + 2, so stage s + 1 is
 // already in LDS while stage s runs and the Z of its first step is formed during the last MFMAs of
 // stage s (one barrier per stage either way).
-template <int OCC, int KS, int WI, int NTT, int NBUF = 2>
+template <int OCC, int KS, int WI, int NTT, int NBUF = 2, int PR = PREC_BF16X3>
 __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const float2* __restrict__ M,
                                                         const uint32_t* __restrict__ gz,
                                                         double2* __restrict__ P, Order od, int t0, int ntc,
@@ -1144,6 +1284,9 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     const float2* Mq = M + (d.mpre[q] - d.mpre[q0]);
     double2* Pq = P + (d.ppre[q] - d.ppre[q0]);
     const int64_t gq = gz_block(d, q0, q, 0);
+    // F16X3: M is scaled by 2^em as it is staged, the g planes by 2^e_g(q, tau) (k_gtab)
+    const int em = PR == PREC_F16X3 ? f16_exp_m(d.mx_m[q]) : 0;
+    const float fm = PR == PREC_F16X3 ? ldexpf(1.f, em) : 1.f;
 
     // staging per thread: NX complex elements of the M rows and NG 16-B chunks of the g planes
     float2 rx[NX];
@@ -1218,7 +1361,12 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         for (int i = 0; i < NX; ++i) {
             const int id = tid + NT * i;
             const int row = id / KS, kc = id % KS;
-            *reinterpret_cast<float2*>(&Xs[buf][row][2 * kc]) = rx[i];
+            float2 x = rx[i];
+            if constexpr (PR == PREC_F16X3) {
+                x.x *= fm;
+                x.y *= fm;
+            }
+            *reinterpret_cast<float2*>(&Xs[buf][row][2 * kc]) = x;
         }
 #pragma unroll
         for (int i = 0; i < NG; ++i) {
@@ -1252,13 +1400,23 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            uint32_t h;
-            h = pk_bf16(zr[2 * e], zr[2 * e + 1]);
-            z[0][e] = h;
-            z[1][e] = pk_bf16(zr[2 * e] - bf_lo_perm(h), zr[2 * e + 1] - bf_hi(h));
-            h = pk_bf16(zi[2 * e], zi[2 * e + 1]);
-            z[2][e] = h;
-            z[3][e] = pk_bf16(zi[2 * e] - bf_lo_perm(h), zi[2 * e + 1] - bf_hi(h));
+            if constexpr (PR == PREC_F16X3) {
+                uint32_t h, l;
+                split_f16(zr[2 * e], zr[2 * e + 1], h, l);
+                z[0][e] = h;
+                z[1][e] = l;
+                split_f16(zi[2 * e], zi[2 * e + 1], h, l);
+                z[2][e] = h;
+                z[3][e] = l;
+            } else {
+                uint32_t h;
+                h = pk_bf16(zr[2 * e], zr[2 * e + 1]);
+                z[0][e] = h;
+                z[1][e] = pk_bf16(zr[2 * e] - bf_lo_perm(h), zr[2 * e + 1] - bf_hi(h));
+                h = pk_bf16(zi[2 * e], zi[2 * e + 1]);
+                z[2][e] = h;
+                z[3][e] = pk_bf16(zi[2 * e] - bf_lo_perm(h), zi[2 * e + 1] - bf_hi(h));
+            }
         }
     };
     // the 6 NTT MFMAs of one 16-K step: Z (re hi, re lo, im hi, im lo) against g (hi, lo) per tau tile
@@ -1268,12 +1426,12 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             const u32x4* grow = reinterpret_cast<const u32x4*>(&Gs[buf][0][32 * tt + r32][0]);
             const u32x4* lrow = reinterpret_cast<const u32x4*>(&Gs[buf][1][32 * tt + r32][0]);
             const u32x4 gh = grow[2 * kk + h2], gl = lrow[2 * kk + h2];
-            acc[tt][0] = mfma32(z[0], gh, acc[tt][0]);
-            acc[tt][1] = mfma32(z[2], gh, acc[tt][1]);
-            acc[tt][0] = mfma32(z[0], gl, acc[tt][0]);
-            acc[tt][1] = mfma32(z[2], gl, acc[tt][1]);
-            acc[tt][0] = mfma32(z[1], gh, acc[tt][0]);
-            acc[tt][1] = mfma32(z[3], gh, acc[tt][1]);
+            acc[tt][0] = mfma32p<PR>(z[0], gh, acc[tt][0]);
+            acc[tt][1] = mfma32p<PR>(z[2], gh, acc[tt][1]);
+            acc[tt][0] = mfma32p<PR>(z[0], gl, acc[tt][0]);
+            acc[tt][1] = mfma32p<PR>(z[2], gl, acc[tt][1]);
+            acc[tt][0] = mfma32p<PR>(z[1], gh, acc[tt][0]);
+            acc[tt][1] = mfma32p<PR>(z[3], gh, acc[tt][1]);
         }
     };
     // software pipeline over the 16-K steps of a stage: the VALU work that forms Z for step kk + 1 is
@@ -1327,6 +1485,13 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     };
 
     const double sc = d.scale;
+    // s, and for F16X3 the scales of the operands undone, for the tau column it (clamped to the mesh)
+    auto col_scale = [&](int it) {
+        if constexpr (PR == PREC_F16X3)
+            return ldexp(sc, -(2 * em + d.e_g[q * d.ntau + min(it, d.ntau - 1)]));
+        else
+            return sc;
+    };
     bool first = true;
     // P += s acc for this lane's 16 pairs per tau tile.  With one work-group per CU the partial sums
     // already in P are read in batches of 8 from clamped (always valid) addresses before any store,
@@ -1340,14 +1505,15 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
 #pragma unroll
             for (int tt = 0; tt < NTT; ++tt) {
                 const int it = tb + 32 * tt + r32 + z;
+                const double cs = col_scale(it);
 #pragma unroll
                 for (int x = 0; x < 16; ++x) {
                     const int p = 8 * (x >> 2) + 4 * h2 + (x & 3);
                     const int I = I0 + 4 * (wave % WI) + (p >> 3), J = J0 + 8 * (wave / WI) + (p & 7);
                     if (it < nt_eff && I < NI && J < NI) {
                         double2* pp = &Pq[(int64_t(it) * NI + I) * NI + J];
-                        double re = sc * double(acc[tt][0][x]);
-                        double im = sc * double(acc[tt][1][x]);
+                        double re = cs * double(acc[tt][0][x]);
+                        double im = cs * double(acc[tt][1][x]);
                         if (!first) {
                             const double2 o = *pp;
                             re += o.x;
@@ -1366,6 +1532,7 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         for (int tt = 0; tt < NTT; ++tt) {
             const int it = tb + 32 * tt + r32 + z;
             const int itc = min(it, nt_eff - 1);
+            const double cs = col_scale(itc);
 #pragma unroll
             for (int x0 = 0; x0 < 16; x0 += FB) {
                 double2 o[FB];
@@ -1385,8 +1552,8 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
                     const int I = I0 + 4 * (wave % WI) + (p >> 3), J = J0 + 8 * (wave / WI) + (p & 7);
                     if (it < nt_eff && I < NI && J < NI)
                         Pq[(int64_t(it) * NI + I) * NI + J] =
-                            make_double2(o[x].x + sc * double(acc[tt][0][x0 + x]),
-                                         o[x].y + sc * double(acc[tt][1][x0 + x]));
+                            make_double2(o[x].x + cs * double(acc[tt][0][x0 + x]),
+                                         o[x].y + cs * double(acc[tt][1][x0 + x]));
                 }
             }
             zero16(acc[tt][0]);
@@ -1509,7 +1676,8 @@ __device__ __host__ __forceinline__ int64_t sz_wq(int ni, int ntau) {
 // fp32 transposed M of q0..q0+nq-1, [k][K][NIp8] complex, NIp8 = NI rounded up to 8
 __device__ __host__ __forceinline__ int sz_np8(int ni) { return (ni + 7) / 8 * 8; }
 
-// transposed FP32 M of one q: mt[k][K][NIp8], zero-padded in I
+// transposed FP32 M of one q: mt[k][K][NIp8], zero-padded in I (F16X3: scaled by 2^e_m(q))
+template <int PR>
 __global__ __launch_bounds__(256) void k_trans32(Dev d, int q0, int q, const float2* __restrict__ M,
                                                  float2* __restrict__ mt) {
     __shared__ float2 tile[32][33];
@@ -1524,9 +1692,15 @@ __global__ __launch_bounds__(256) void k_trans32(Dev d, int q0, int q, const flo
     for (int qq = q0; qq < q; ++qq) ob += (d.mpre[qq + 1] - d.mpre[qq]) / d.ni[qq] * sz_np8(d.ni[qq]);
     float2* T = mt + ob + d.moff[q * nk + k] / NI * NP;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const float fm = PR == PREC_F16X3 ? ldexpf(1.f, f16_exp_m(d.mx_m[q])) : 1.f;
     for (int r = ty; r < 32; r += 8) {
         const int I = i0 + r, col = c0 + tx;
-        tile[r][tx] = (I < NI && col < Kk) ? A[int64_t(I) * Kk + col] : make_float2(0.f, 0.f);
+        float2 a = (I < NI && col < Kk) ? A[int64_t(I) * Kk + col] : make_float2(0.f, 0.f);
+        if constexpr (PR == PREC_F16X3) {
+            a.x *= fm;
+            a.y *= fm;
+        }
+        tile[r][tx] = a;
     }
     __syncthreads();
     for (int r = ty; r < 32; r += 8) {
@@ -1536,8 +1710,11 @@ __global__ __launch_bounds__(256) void k_trans32(Dev d, int q0, int q, const flo
 }
 
 // weight blocks of one q: for block (bi, bj), bj >= bi, tau row t and step s (I = 8 bi + s), the
-// 8 pairs J = 8 bj + j hold (w_re, w_im) = c_IJ (Re H_IJ, Im H_IJ) as packed bf16, hi and lo planes
+// 8 pairs J = 8 bj + j hold (w_re, w_im) = c_IJ (Re H_IJ, Im H_IJ) as packed bf16 (f16 for F16X3,
+// scaled by 2^e_w(q, tau)), hi and lo planes.  mxw: the maxima of W~ of this q per tau (F16X3).
+template <int PR>
 __global__ __launch_bounds__(256) void k_wpair(const double2* __restrict__ W, int NI, int ntau,
+                                               const unsigned long long* __restrict__ mxw,
                                                uint32_t* __restrict__ wz) {
     const int TP = gz_tp(ntau), nb = sz_nb8(NI);
     const int64_t nblk = sz_blocks(NI);
@@ -1558,12 +1735,13 @@ __global__ __launch_bounds__(256) void k_wpair(const double2* __restrict__ W, in
     if (t < ntau && I < NI && J < NI && J >= I) {
         const double2* Wt = W + int64_t(t) * NI * NI;
         const double2 a = Wt[int64_t(I) * NI + J], m = Wt[int64_t(J) * NI + I];
-        const double c = J > I ? 1.0 : 0.5;  // c_IJ H_IJ = c_IJ (W_IJ + conj W_JI) / 2
+        // c_IJ H_IJ = c_IJ (W_IJ + conj W_JI) / 2
+        const double c = (J > I ? 1.0 : 0.5) * (PR == PREC_F16X3 ? ldexp(1.0, f16_exp_w(mxw[t])) : 1.0);
         re = float(c * (a.x + m.x));
         im = J > I ? float(c * (a.y - m.y)) : 0.f;
     }
     uint32_t h, l;
-    split2(re, im, h, l);
+    split_pair<PR>(re, im, h, l);
     const int64_t blk = id >> 6;  // (block, tau) row of 64 u32
     wz[blk * 64 + 8 * s + j] = h;
     wz[nblk * TP * 64 + blk * 64 + 8 * s + j] = l;
@@ -1577,7 +1755,7 @@ __global__ __launch_bounds__(256) void k_wpair(const double2* __restrict__ W, in
 // (the 8 values a_I of the block row stay in registers across the block row), splits it into
 // bf16 hi/lo, and the FP32 accumulators go through the epilogue (G_m weight, sum over the m of each
 // band n, FP64 atomic) every 32 blocks.
-template <int OCC, int NTT>
+template <int OCC, int NTT, int PR = PREC_BF16X3>
 __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* __restrict__ G,
                                                    const float2* __restrict__ mt,
                                                    const uint32_t* __restrict__ wz,
@@ -1647,6 +1825,8 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
         for (int tt = 0; tt < NTT; ++tt) zero16(acc[kt][tt]);
 
     const double sc = d.scale;
+    // F16X3: the transposed M carries 2^e_m (k_trans32) and the weights 2^e_w(q, tau) (k_wpair)
+    const int em2 = PR == PREC_F16X3 ? 2 * f16_exp_m(d.mx_m[q]) : 0;
     // epilogue on the accumulators: weight each row K = (n, m) by G_m(k-q, tau), sum the rows of
     // each band n and add to Sigma_n(k, tau)
     const double* Gq = G + int64_t(kq) * nbmax * ntau;  // G_m(k - q, tau) = Gq[m * ntau + tau]
@@ -1662,6 +1842,8 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
             for (int tt = 0; tt < NTT; ++tt) {
                 const int it = tb + 32 * tt + r32;
                 const int itc = min(it, ntau - 1);
+                double cs = sc;
+                if constexpr (PR == PREC_F16X3) cs = ldexp(sc, -(em2 + f16_exp_w(d.mx_w[q * ntau + itc])));
                 for (int nx = nlo; nx <= nhi; ++nx) {
                     // the 16 weights are loaded together from clamped (always valid) rows m, so the
                     // epilogue waits once per band instead of once per element
@@ -1680,7 +1862,7 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
                     }
                     v += __shfl_xor(v, 32);
                     if (h2 == 0 && it < ntau)
-                        atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], sc * double(v));
+                        atomicAdd(&Sig[(int64_t(k) * nbmax + nx) * ntau + it], cs * double(v));
                 }
                 zero16(acc[kt][tt]);
             }
@@ -1749,7 +1931,7 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
                         const float cr = (j & 1) ? c4.z : c4.x, ci = (j & 1) ? c4.w : c4.y;
                         const float zr = ar * cr + aim * ci, zi = aim * cr - ar * ci;
                         uint32_t h, l;
-                        split2(zr, zi, h, l);
+                        split_pair<PR>(zr, zi, h, l);
                         zh[kt][j] = h;
                         zl[kt][j] = l;
                     }
@@ -1761,9 +1943,9 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
                     const u32x4 bh = hrow[2 * s + h2], bl = lrow[2 * s + h2];
 #pragma unroll
                     for (int kt = 0; kt < 2; ++kt) {
-                        acc[kt][tt] = mfma32(zh[kt], bh, acc[kt][tt]);
-                        acc[kt][tt] = mfma32(zh[kt], bl, acc[kt][tt]);
-                        acc[kt][tt] = mfma32(zl[kt], bh, acc[kt][tt]);
+                        acc[kt][tt] = mfma32p<PR>(zh[kt], bh, acc[kt][tt]);
+                        acc[kt][tt] = mfma32p<PR>(zh[kt], bl, acc[kt][tt]);
+                        acc[kt][tt] = mfma32p<PR>(zl[kt], bh, acc[kt][tt]);
                     }
                 }
                 // keeps the Z of later steps from being formed (and held) ahead of time
@@ -1839,7 +2021,7 @@ int64_t gz_elems(const Host& h, int q0, int nq) {
     return n;
 }
 
-template <int OCC, int SR, int SC, int KS = GZ_KS, int WI = 2, int NBUF = 2>
+template <int OCC, int SR, int SC, int KS = GZ_KS, int WI = 2, int NBUF = 2, int PR = PREC_BF16X3>
 void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, void* P) {
     int maxi = 0, maxk = 0;
@@ -1856,8 +2038,14 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
         throw Error(MSGW_ENOTSUP, "a (q, k) block too large for the pair-space polarization");
     uint32_t* gz = reinterpret_cast<uint32_t*>(scratch_mfma(d, h));
     const unsigned gx = unsigned(ceil_div(gz_tp(h.ntau) * round_up(maxk, GZ_KPAD) / 2, 256));
+    if (PR == PREC_F16X3 && !d.kreuse) {
+        launch_scales(d, h, s, q0, nq, M, nullptr);
+        MSGW_LAUNCH(k_gmax, dim3(ceil_div(int64_t(h.nk) * h.ntau, 256)), dim3(256), 0, s, d, G);
+        MSGW_LAUNCH(k_gexp, dim3(ceil_div(int64_t(nq) * h.ntau, 256)), dim3(256), 0, s, d, q0, nq);
+        MSGW_HIP(hipGetLastError());
+    }
     for (int q = q0; q < q0 + nq && !d.kreuse; ++q) {
-        MSGW_LAUNCH(k_gtab, dim3(gx, h.nk), dim3(256), 0, s, d, q, G, gz + gz_elems(h, q0, q - q0) / 2);
+        MSGW_LAUNCH(k_gtab<PR>, dim3(gx, h.nk), dim3(256), 0, s, d, q, G, gz + gz_elems(h, q0, q - q0) / 2);
         MSGW_HIP(hipGetLastError());
     }
     // tau in chunks of three 32-wide tiles, the last chunk with the one or two tiles left; with the
@@ -1877,12 +2065,13 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
                         t0, ntc, nt_eff);
         }, rows);
     };
-    if (n3 > 0) launch(k_polz<OCC, KS, WI, 3, NBUF>, 0, n3);
-    if (rest == 1) launch(k_polz<OCC, KS, WI, 1, NBUF>, 96 * n3, 1);
-    if (rest == 2) launch(k_polz<OCC, KS, WI, 2, NBUF>, 96 * n3, 1);
+    if (n3 > 0) launch(k_polz<OCC, KS, WI, 3, NBUF, PR>, 0, n3);
+    if (rest == 1) launch(k_polz<OCC, KS, WI, 1, NBUF, PR>, 96 * n3, 1);
+    if (rest == 2) launch(k_polz<OCC, KS, WI, 2, NBUF, PR>, 96 * n3, 1);
 }
 
 // pair-space self-energy: needs only the raw W~ (FP64), so it runs its own conversions
+template <int PR>
 void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, const void* W, void* Sig) {
     int64_t nmt = 0, nwz = 0;
@@ -1896,16 +2085,18 @@ void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
         throw Error(MSGW_ENOMEM, "workspace too small for the pair-space self-energy");
     float2* mt = reinterpret_cast<float2*>(scratch_mfma(d, h));
     uint32_t* wz = reinterpret_cast<uint32_t*>(mt + nmt);
+    if (PR == PREC_F16X3 && !d.kreuse) launch_scales(d, h, s, q0, nq, M, W);
     int64_t woff = 0;
     for (int q = q0; q < q0 + nq; ++q) {
         const int NI = h.ni[q];
         const unsigned gx = ceil_div(sz_np8(NI), 32) * ceil_div(maxk, 32);
-        MSGW_LAUNCH(k_trans32, dim3(gx, d.kb1 - d.kb0), dim3(256), 0, s, d, q0, q, (const float2*)M, mt);
+        MSGW_LAUNCH(k_trans32<PR>, dim3(gx, d.kb1 - d.kb0), dim3(256), 0, s, d, q0, q, (const float2*)M, mt);
         MSGW_HIP(hipGetLastError());
         const int64_t n = sz_blocks(NI) * gz_tp(h.ntau) * 64;
         if (!d.kreuse) {
-            MSGW_LAUNCH(k_wpair, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
-                        (const double2*)W + (h.ppre[q] - h.ppre[q0]), NI, h.ntau, wz + woff);
+            MSGW_LAUNCH(k_wpair<PR>, dim3(unsigned(ceil_div(n, 256))), dim3(256), 0, s,
+                        (const double2*)W + (h.ppre[q] - h.ppre[q0]), NI, h.ntau,
+                        (const unsigned long long*)(d.mx_w + int64_t(q) * h.ntau), wz + woff);
             MSGW_HIP(hipGetLastError());
         }
         woff += sz_wq(NI, h.ntau);
@@ -1917,9 +2108,9 @@ void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
                     (const float2*)mt, (const uint32_t*)wz, (double*)Sig, nkc, t0, ntc);
         MSGW_HIP(hipGetLastError());
     };
-    if (n3 > 0) launch(k_sigz<1, 3>, 0, n3);
-    if (rest == 1) launch(k_sigz<1, 1>, 96 * n3, 1);
-    if (rest == 2) launch(k_sigz<1, 2>, 96 * n3, 1);
+    if (n3 > 0) launch(k_sigz<1, 3, PR>, 0, n3);
+    if (rest == 1) launch(k_sigz<1, 1, PR>, 96 * n3, 1);
+    if (rest == 2) launch(k_sigz<1, 2, PR>, 96 * n3, 1);
 }
 
 template <int T, int SR = 4, int SC = 8, int OCC = 1>
@@ -1963,14 +2154,23 @@ const PolVariant kPolBF16[] = {
     {"pair-space 8x16 pairs 2 WG/CU st4x16", run_polz<2, 4, 16>, true},
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3>},
 };
+const PolVariant kPolF16[] = {
+    {"pair-space 16x16 pairs K64 st4x8 3-buffer", run_polz<1, 4, 8, 64, 4, 3, PREC_F16X3>, true},
+    {"pair-space 16x16 pairs K64 st4x8", run_polz<1, 4, 8, 64, 4, 2, PREC_F16X3>, true},
+    {"pair-space 8x16 pairs 2 WG/CU st4x16 K64", run_polz<2, 4, 16, 64, 2, 2, PREC_F16X3>, true},
+    {"pair-space 8x16 pairs 2 WG/CU st4x16", run_polz<2, 4, 16, GZ_KS, 2, 2, PREC_F16X3>, true},
+};
 const PolVariant kPolFP32[] = {
     {"WI2 WJ2 T4", run_pol<2, 2, 4, PREC_FP32>},
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_FP32>},
 };
 const SigVariant kSigBF16[] = {
-    {"pair-space 512 K x 8x8-pair blocks", nullptr, nullptr, run_sigz},
+    {"pair-space 512 K x 8x8-pair blocks", nullptr, nullptr, run_sigz<PREC_BF16X3>},
     {"LDS 2-stage 64x128 T2 2 WG/CU st8x8", nullptr, run_sig7<2, 8, 8, 2>},
     {"WI2 WJ4 T4", run_sig<2, 4, 4, PREC_BF16X3>, nullptr},
+};
+const SigVariant kSigF16[] = {
+    {"pair-space 512 K x 8x8-pair blocks", nullptr, nullptr, run_sigz<PREC_F16X3>},
 };
 const SigVariant kSigFP32[] = {
     {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>, nullptr},
@@ -2000,18 +2200,37 @@ int64_t mt_elems(const Host& h, int q0, int nq) {
 
 }  // namespace
 
+namespace {
+const PolVariant* pol_table(int precision, int* n) {
+    switch (precision) {
+        case MSGW_BF16X3: *n = count_of(kPolBF16); return kPolBF16;
+        case MSGW_F16X3: *n = count_of(kPolF16); return kPolF16;
+        case MSGW_FP32: *n = count_of(kPolFP32); return kPolFP32;
+        default: *n = 0; return nullptr;
+    }
+}
+const SigVariant* sig_table(int precision, int* n) {
+    switch (precision) {
+        case MSGW_BF16X3: *n = count_of(kSigBF16); return kSigBF16;
+        case MSGW_F16X3: *n = count_of(kSigF16); return kSigF16;
+        case MSGW_FP32: *n = count_of(kSigFP32); return kSigFP32;
+        default: *n = 0; return nullptr;
+    }
+}
+}  // namespace
+
 int mfma_variant_count(int op, int precision) {
-    if (op == MSGW_OP_POLARIZATION)
-        return precision == MSGW_BF16X3 ? count_of(kPolBF16) : precision == MSGW_FP32 ? count_of(kPolFP32) : 0;
-    if (op == MSGW_OP_SELF_ENERGY)
-        return precision == MSGW_BF16X3 ? count_of(kSigBF16) : precision == MSGW_FP32 ? count_of(kSigFP32) : 0;
-    return 0;
+    int n = 0;
+    if (op == MSGW_OP_POLARIZATION) pol_table(precision, &n);
+    if (op == MSGW_OP_SELF_ENERGY) sig_table(precision, &n);
+    return n;
 }
 
 const char* mfma_variant_name(int op, int precision, int v) {
     if (v < 0 || v >= mfma_variant_count(op, precision)) return nullptr;
-    if (op == MSGW_OP_POLARIZATION) return precision == MSGW_BF16X3 ? kPolBF16[v].name : kPolFP32[v].name;
-    return precision == MSGW_BF16X3 ? kSigBF16[v].name : kSigFP32[v].name;
+    int n;
+    if (op == MSGW_OP_POLARIZATION) return pol_table(precision, &n)[v].name;
+    return sig_table(precision, &n)[v].name;
 }
 
 size_t mfma_scratch_bytes(const Host& h, int nq_max) {
@@ -2034,9 +2253,10 @@ size_t mfma_scratch_bytes(const Host& h, int nq_max) {
 int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
                     const double* G, int precision, int variant, void* P) {
     if (h.nbmax > NB_LDS) return MSGW_ENOTSUP;
-    const int n = mfma_variant_count(MSGW_OP_POLARIZATION, precision);
+    int n = 0;
+    const PolVariant* table = pol_table(precision, &n);
     if (variant < 0 || variant >= n) return MSGW_EINVAL;
-    const PolVariant& V = (precision == MSGW_BF16X3 ? kPolBF16 : kPolFP32)[variant];
+    const PolVariant& V = table[variant];
     if ((d.kb0 != 0 || d.kb1 != h.nk) && !V.ranged) return MSGW_ENOTSUP;
     V.fn(d, h, s, q0, nq, M, G, P);
     const int nt_eff = V.ranged ? tau_points_computed(d, h) : h.ntau;  // only the pair-space kernels mirror
@@ -2058,7 +2278,8 @@ int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
                     const double* G, const void* W, int precision, int variant, void* Sig) {
     const int nv = mfma_variant_count(MSGW_OP_SELF_ENERGY, precision);
     if (variant < 0 || variant >= nv) return MSGW_EINVAL;
-    const SigVariant& V = (precision == MSGW_BF16X3 ? kSigBF16 : kSigFP32)[variant];
+    int nt = 0;
+    const SigVariant& V = sig_table(precision, &nt)[variant];
     if ((d.kb0 != 0 || d.kb1 != h.nk) && !V.fnz) return MSGW_ENOTSUP;
     if (V.fnz) {
         V.fnz(d, h, s, q0, nq, M, G, W, Sig);

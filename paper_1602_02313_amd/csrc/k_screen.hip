@@ -32,7 +32,7 @@ template <int NT, int SB>
 __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __restrict__ Piw,
                                                const double* __restrict__ v,
                                                double2* __restrict__ Wt, double2* __restrict__ R,
-                                               int* __restrict__ info) {
+                                               int* __restrict__ info, int* __restrict__ flags) {
     __shared__ double sv[MSGW_MAX_NI];
     __shared__ int perm[MSGW_MAX_NI];
     __shared__ int idx[MSGW_MAX_NI];
@@ -226,15 +226,18 @@ __global__ __launch_bounds__(NT) void k_screen(Dev d, int q0, const double2* __r
         }
         __syncthreads();
     }
-    if (tid == 0) info[mi] = s_info;
+    if (tid == 0) {
+        info[mi] = s_info;
+        if (flags && s_info) atomicOr(flags, MSGW_FLAG_SINGULAR);
+    }
 }
 
 }  // namespace
 
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
-                   const double* v, void* Wt_iw, void* R_iw, int* info) {
+                   const double* v, void* Wt_iw, void* R_iw, int* info, int* flags) {
     MSGW_LAUNCH((k_screen<1024, 16>), dim3(nq * h.niw_b), dim3(1024), 0, s, d, q0, (const double2*)P_iw, v,
-                (double2*)Wt_iw, (double2*)R_iw, info);
+                (double2*)Wt_iw, (double2*)R_iw, info, flags);
     MSGW_HIP(hipGetLastError());
 }
 

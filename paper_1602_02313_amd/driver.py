@@ -156,6 +156,7 @@ class GWRun:
         self.N = torch.zeros(1, dtype=f64, device=dev)
         self.gap_d = torch.zeros(1, dtype=f64, device=dev)
         self.flags = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.screen_flags = torch.zeros(1, dtype=torch.int32, device=dev)  # MSGW_FLAG_SINGULAR of a pass
         # per q batch
         maxp = max(int(self.ppre[q + self.q_batch] - self.ppre[q])
                    for q in range(0, nk - self.q_batch + 1)) if nk >= self.q_batch else int(self.ppre[-1])
@@ -207,7 +208,7 @@ class GWRun:
                                       stream=st)
             with self._t("screen"):
                 ctx.screen(q0, nq, self.P_iw, self.v[self.vpre[q0]:], self.Wt_iw, self.R_iw,
-                           self.info, stream=st)
+                           self.info, self.screen_flags, stream=st)
             with self._t("screened_tau"):
                 ctx.screened_tau(q0, nq, self.R_iw, self.P_tau, self.v[self.vpre[q0]:],
                                  self.Wt_tau, stream=st)
@@ -227,6 +228,8 @@ class GWRun:
         """Sigma^c(tau), Sigma^x and Sigma^c(i w) from the current G (all q)."""
         self.sig_tau.zero_()
         self.sig_x.zero_()
+        if self.W_frozen is None:  # with W~ frozen (GW0) the flags of its pass stay
+            self.screen_flags.zero_()
         keep = {} if keep_W else None
         for q0, nq in self._batches():
             self.q_block(M_source, q0, nq, keep=keep)
@@ -288,8 +291,11 @@ class GWRun:
         return E, A, gap, coef, flags
 
     def _record(self):
+        """Host copies of mu, N, the gap proxy and the status bits (MSGW_FLAG_*) of the Dyson step
+        and of the screens of the last pass."""
         return dict(mu=float(self.mu.item()), N=float(self.N.item()),
-                    gap=float(self.gap_d.item()), flags=int(self.flags.item()))
+                    gap=float(self.gap_d.item()),
+                    flags=int(self.flags.item()) | int(self.screen_flags.item()))
 
     def iteration(self, M_source, search=True):
         """One self-consistent iteration: Sigma from the current G, Dyson with the mu search, gap."""

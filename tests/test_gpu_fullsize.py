@@ -8,13 +8,14 @@ tile variants):
   * 5x5x5 k-points, 128 bands, NI = 700, 161 tau points (two 96-wide tau chunks, ragged).
 Compared entry by entry:
   * P_IJ(q, tau) on sampled (tau, I, J), covering both triangles, the diagonal, tile edges and the
-    last row I = NI - 1 (split-BF16 on every shape, FP32 on the first);
+    last row I = NI - 1 (split FP16, split BF16 and FP32 on every shape);
   * this q's contribution to Sigma^c_n(k, tau) for two k and three tau, with a synthetic Hermitian
     W~(tau) of the decaying profile of a screened interaction;
   * the FP64 screen at full NI on a synthetic negative-definite P(i nu): W~(i nu) on four
     frequencies and W~(tau) on a square index subset at five tau points.
-Gates: P and Sigma^c relative error <= 2e-6 (the full-size gate of the split and FP32 paths), the
-FP64 screen <= 1e-10.
+Gates: P and Sigma^c relative error <= 1e-6 (the split-precision tolerance on Sigma, for every
+precision at these sizes), with the worst tau slice and the max-abs error within 10x; the FP64 screen
+<= 1e-10.
 """
 from concurrent.futures import ThreadPoolExecutor
 
@@ -23,11 +24,11 @@ import pytest
 
 import gwinputs as gi
 import oracle as o
-from gpu_util import np_, rel
+from gpu_util import check, np_, rel
 
 pytestmark = pytest.mark.gpu
 
-GATE = 2e-6
+GATE = 1e-6
 
 
 def _pick_q(cfg):
@@ -81,12 +82,11 @@ def _G(prob):
     return o.green0(prob.eps, prob.nb, prob.tau, prob.cfg.beta, 0.0)
 
 
-@pytest.mark.parametrize("prec", [2, 1])
+@pytest.mark.parametrize("prec", [3, 2, 1])
 def test_polarization_sampled(torch, big, prec):
     import paper_1602_02313_amd as amd
     cfg, q, prob, run, M = big
-    if prec == amd.FP32 and cfg is not gi.C3:
-        pytest.skip("FP32 is sampled on the first shape only")
+    print(f"\n[{cfg.name}] polarization prec={prec}", flush=True)
     NI, ntau = int(prob.ni[q]), prob.tau.size
     run.ctx.polarization(q, 1, M, amd.C64, run.G_tau, prec, run.P_tau)
     rows = _sample(NI, 10 + q, 6)
@@ -99,9 +99,7 @@ def test_polarization_sampled(torch, big, prec):
     blocks = _host_blocks(cfg, q, rows=sel)
     ref = o.polarization([blocks[k] for k in range(cfg.nk)], _G(prob), prob.kmq[q], cfg.scale,
                          taus=taus, rows=np.searchsorted(sel, rows), cols=np.searchsorted(sel, cols))
-    e = rel(got, ref)
-    print(f"[{cfg.name}] P prec={prec}: rel {e:.2e} on {got.size} entries")
-    assert e < GATE
+    check(f"[{cfg.name}] P prec={prec} ({got.size} entries)", got, ref, GATE, 0)
 
 
 def _synthetic_W(cfg, NI, ntau, tau, seed):
@@ -122,12 +120,11 @@ def _synthetic_W(cfg, NI, ntau, tau, seed):
     return f[:, None, None] * A[None] + g[:, None, None] * B[None]
 
 
-@pytest.mark.parametrize("prec", [2, 1])
+@pytest.mark.parametrize("prec", [3, 2, 1])
 def test_self_energy_sampled(torch, big, prec):
     import paper_1602_02313_amd as amd
     cfg, q, prob, run, M = big
-    if prec == amd.FP32 and cfg is not gi.C3:
-        pytest.skip("FP32 is sampled on the first shape only")
+    print(f"\n[{cfg.name}] self-energy prec={prec}", flush=True)
     NI, ntau = int(prob.ni[q]), prob.tau.size
     W = _synthetic_W(cfg, NI, ntau, prob.tau, 3 + q)
     run.Wt_tau[:W.size].copy_(torch.from_numpy(W.ravel()))
@@ -139,9 +136,7 @@ def test_self_energy_sampled(torch, big, prec):
     blocks = _host_blocks(cfg, q, ks=ks)
     Mq = [blocks.get(k) for k in range(cfg.nk)]
     ref = o.sigma_c(Mq, _G(prob), prob.kmq[q], W, cfg.scale, taus=taus, ks=ks)
-    e = rel(got, ref)
-    print(f"[{cfg.name}] Sigma^c prec={prec}: rel {e:.2e}")
-    assert e < GATE
+    check(f"[{cfg.name}] Sigma^c prec={prec}", got, ref, GATE, -1)
 
 
 def test_screen_full_ni(torch, big):

@@ -307,6 +307,26 @@ def test_end_to_end_c1_g0w0_and_gw0(torch, c1_oracle):
         assert abs(out[-1]["gap"] - hist[-1]["gap"]) < 1e-10 * abs(hist[-1]["gap"])
 
 
+def test_screen_singular_flag(torch):
+    """An exactly singular 1 - chi~ (chi~ = 1 at nu_0: v = 4, P = I / 4) is reported in info and as
+    MSGW_FLAG_SINGULAR in the flag word; the other frequencies are regular."""
+    import paper_1602_02313_amd as amd
+    prob, run = make_run(SMALL, q_batch=1)
+    NI, niw = int(prob.ni[0]), SMALL.niw_b
+    P = np.broadcast_to(np.eye(NI) * 0.25, (niw, NI, NI)).astype(complex)
+    P[1:] *= 0.5
+    run.P_iw[:P.size].copy_(torch.from_numpy(P.ravel()))
+    v = torch.full((NI,), 4.0, dtype=torch.float64, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    run.ctx.screen(0, 1, run.P_iw, v, run.Wt_iw, run.R_iw, run.info, flags)
+    torch.cuda.synchronize()
+    info = np_(run.info[:niw])
+    assert info[0] == 1 and np.all(info[1:] == 0)
+    assert int(flags.item()) == amd.FLAG_SINGULAR
+    W, _ = o.screen(P[1:], np.full(NI, 4.0))
+    assert rel(np_(run.Wt_iw[:P.size]).reshape(P.shape)[1:], W) < TOL
+
+
 # ---------------------------------------------------------------------------------------------
 # error paths (host-side validation, nothing enqueued)
 # ---------------------------------------------------------------------------------------------
