@@ -220,6 +220,18 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
                const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
                double* G_tau, double* n_out, int* flags);
 
+/* For callers that cannot allocate device memory at the time of the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): msgw_dyson with the same arguments,
+ * results and errors, whose per-call scratch (the E array and the mu search state) lives in a static
+ * device array of 1 MiB that each device keeps until the process ends, instead of the workspace.  It
+ * calls no allocating routine.  The context still needs its workspace for the constant tables (set
+ * once at setup).  Limit: nk * nbmax <= 130048 states, else MSGW_ENOTSUP and nothing is enqueued.
+ * Every call on a device shares that device's array: calls that overlap on one device (two streams,
+ * two contexts, two threads) race and must be ordered by the caller. */
+int msgw_dyson_noalloc(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
+                       const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
+                       double* G_tau, double* n_out, int* flags);
+
 /* a9 (loop control).  Matsubara-axis gap proxy used to follow the self-consistent loop:
  * E^QP_nk = eps + sigma_static + Re Sigma^c_nk(i w_0) - mu over all (n < Nb_k, k), and
  * *gap = E_(N+1) - E_(N) (ascending order, 1-based) with N = n_index, 1 <= N < number of states.

@@ -12,6 +12,7 @@ using namespace msgw;
 
 struct msgw_ctx {
     int device = 0;
+    void* noalloc = nullptr;  // device address of the static scratch of msgw_dyson_noalloc on `device`
     std::string err;
     bool have_problem = false;
     Host h;
@@ -185,6 +186,12 @@ int msgw_create(msgw_ctx** out, int hip_device) {
     auto* c = new (std::nothrow) msgw_ctx();
     if (!c) return MSGW_EINVAL;
     c->device = hip_device;
+    try {
+        c->noalloc = noalloc_scratch(hip_device);  // once per device, that device current for the lookup
+    } catch (...) {
+        delete c;
+        return MSGW_EHIP;
+    }
     *out = c;
     return MSGW_OK;
 }
@@ -548,7 +555,34 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
         need(mu_mode == MSGW_MU_FIXED || mu_mode == MSGW_MU_SEARCH, MSGW_EINVAL, "bad mu_mode");
         need(std::isfinite(n_target) && n_target >= 0, MSGW_EINVAL, "bad n_target");
         launch_dyson(c->d, c->h, S(stream), eps, sigma_static, Sigma_c_iw, n_target,
-                     mu_mode == MSGW_MU_SEARCH, mu, G_iw, G_tau, n_out, flags);
+                     mu_mode == MSGW_MU_SEARCH, mu, G_iw, G_tau, n_out, flags, scratch_E(c->d),
+                     scratch_mu_search(c->d, c->h));
+    });
+}
+
+int msgw_dyson_noalloc(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
+                       const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
+                       double* G_tau, double* n_out, int* flags) {
+    return guarded(c, [&] {
+        need(c->have_problem, MSGW_EINVAL, "no problem set (msgw_set_problem)");
+        const size_t eb = align_up(sizeof(double) * size_t(c->h.nk) * c->h.nbmax);
+        if (eb + kMuSearchBytes > kNoAllocScratchBytes) {
+            std::ostringstream m;
+            m << "msgw_dyson_noalloc: nk * nbmax = " << size_t(c->h.nk) * c->h.nbmax
+              << " states exceed its static scratch (at most "
+              << (kNoAllocScratchBytes - kMuSearchBytes) / sizeof(double) << " states); use msgw_dyson";
+            throw Error(MSGW_ENOTSUP, m.str());
+        }
+        require_ready(c);
+        need(eps && sigma_static && Sigma_c_iw && mu && G_tau && n_out && flags, MSGW_EINVAL,
+             "null pointer");
+        need(mu_mode == MSGW_MU_FIXED || mu_mode == MSGW_MU_SEARCH, MSGW_EINVAL, "bad mu_mode");
+        need(std::isfinite(n_target) && n_target >= 0, MSGW_EINVAL, "bad n_target");
+        need(c->noalloc != nullptr, MSGW_EHIP, "static scratch address unknown");
+        char* base = static_cast<char*>(c->noalloc);
+        launch_dyson(c->d, c->h, S(stream), eps, sigma_static, Sigma_c_iw, n_target,
+                     mu_mode == MSGW_MU_SEARCH, mu, G_iw, G_tau, n_out, flags, reinterpret_cast<double*>(base),
+                     reinterpret_cast<double*>(base + eb));
     });
 }
 

@@ -93,9 +93,14 @@ void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, c
                    const double* v, void* Wt_iw, void* R_iw, int* info, int* flags);
 void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
                     int m_dtype, const double* occ, const double* v, void* out, int full);
+// E: [nk * nbmax] doubles, st: kMuSearchBytes of mu search state (every entry written before use)
 void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                   const double* sstat, const void* sigc, double n_target, int search, double* mu,
-                  void* G_iw, double* G_tau, double* n_out, int* flags);
+                  void* G_iw, double* G_tau, double* n_out, int* flags, double* E, double* st);
+// bytes of the static scratch of msgw_dyson_noalloc, and its device address on `device` (looked up
+// once per device, with that device made current for the lookup)
+constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;
+void* noalloc_scratch(int device);
 void launch_gap(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                 const double* sstat, const void* sigc, const double* mu, int n_index, double* gap);
 void launch_gap_given(const Dev& d, const Host& h, hipStream_t s, const double* E, int n_index, double* gap);

@@ -1,8 +1,37 @@
 // G0, synthetic M, tau <-> i omega transforms, exchange self-energy, Dyson + chemical potential.
 // All arithmetic here is FP64.
+#include <mutex>
+
 #include "internal.h"
 
+// Scratch of msgw_dyson_noalloc (the E array and the mu search state) in a static device array, so
+// that the call allocates nothing.  Each device the library runs on holds its own copy until the
+// process ends; host code uses only the device address looked up per device by noalloc_scratch().
+static __device__ __align__(256) char scratch[msgw::kNoAllocScratchBytes];
+
 namespace msgw {
+
+namespace {
+std::mutex g_noalloc_mu;
+std::vector<void*> g_noalloc_ptr;  // per device: the address of `scratch` there
+}  // namespace
+
+void* noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (int(g_noalloc_ptr.size()) <= device) g_noalloc_ptr.resize(device + 1, nullptr);
+    if (!g_noalloc_ptr[device]) {
+        int cur = 0;
+        MSGW_HIP(hipGetDevice(&cur));
+        MSGW_HIP(hipSetDevice(device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        MSGW_HIP(hipSetDevice(cur));
+        if (e != hipSuccess || p == nullptr)
+            throw Error(MSGW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_noalloc_ptr[device] = p;
+    }
+    return g_noalloc_ptr[device];
+}
 
 namespace {
 
@@ -792,10 +821,8 @@ void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
 
 void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                   const double* sstat, const void* sigc, double n_target, int search, double* mu,
-                  void* G_iw, double* G_tau, double* n_out, int* flags) {
+                  void* G_iw, double* G_tau, double* n_out, int* flags, double* E, double* st) {
     DysonArgs a{eps, sstat, (const double2*)sigc, d.nb, d.nk, d.nbmax, d.niw_f, d.beta, n_target};
-    double* E = scratch_E(d);
-    double* st = scratch_mu_search(d, h);
     static_assert(sizeof(double) * (5 + 2 * MS_NV) <= kMuSearchBytes, "mu search state fits its scratch");
     MSGW_LAUNCH(k_dyson_prep, dim3(1), dim3(1024), 0, s, a, E, st);
     MSGW_HIP(hipGetLastError());
