@@ -1,20 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the Matsubara-time GW hot path on one MI355X.
 
-A step is one full pass of the path over the 4x4x4 k-grid, 64-band, NI = 400,
-81-point UPM workload: G0 -> P(q,tau) -> P(q,i nu) -> W~(q,i nu) -> W~(q,tau) ->
-Sigma^c(k,tau), Sigma^x -> Sigma^c(k,i omega) -> Dyson with the mu search -> gap
-proxy, for all 64 q.  The inputs (energies, tau mesh, Coulomb kernel and the
-complex matrix elements M for every q, 54 GB in complex64) are resident in HBM
-before the timed region; M is drawn on the device by the library's Philox
-generator.  The metric is the P + Sigma effective TFLOP/s (dense complex flop
-model, 8 real flops per complex multiply-add) over the whole step.
+The timed work is ONE self-consistent (scGW) iteration of the 5x5x5 k-grid, 128-band, NI = 700,
+161-point power-mesh workload at beta = 400: for every q, M(q) is drawn on the device from the seed
+(11.5 GB per q in complex64), then P(q,tau) -> P(q,i nu) -> W~(q,i nu) -> W~(q,tau) -> Sigma^c(k,tau)
+and Sigma^x accumulate; after the last q, Sigma^c(k,i omega), the Dyson update with the
+chemical-potential search and the gap proxy.  The K timed steps split that iteration: step s runs
+the q in [s nk / K, (s + 1) nk / K) and the last step also runs the Dyson part, so K steps are
+exactly one iteration and ms_per_step * K is the time of one iteration.  The warm-up steps run the
+first W slices of an iteration that is then started over.
 
-    python bench.py [--steps K] [--warmup W] [--precision bf16x3|fp32|fp64]
+The metric is the P + Sigma effective TFLOP/s of the dense complex flop model (8 real flops per
+complex multiply-add) over the whole iteration, and the seconds per iteration.  The roofline object
+is the dominant contraction kernel's executed MFMA work (counted from the kernel's loop structure,
+the Hermitian triangle and tile padding included) over its time, measured with HIP events that the
+library records around its kernels, against MI355X's dense fp16/bf16 MFMA peak.
+
+    python bench.py [--steps K] [--warmup W] [--config c5] [--precision f16x3|bf16x3|fp32|fp64]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,45 +33,110 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# dense MFMA peaks of MI355X (TFLOP/s).  A split-BF16 product costs three BF16 products, so its
-# effective FP32-equivalent peak is the BF16 peak / 3.
-PEAK_BF16 = 2516.6
-PEAK = {"bf16x3": PEAK_BF16 / 3.0, "f16x3": PEAK_BF16 / 3.0, "fp32": 157.3, "fp64": 78.6}
+# dense MFMA peaks of MI355X (TFLOP/s).  A split product costs three 16-bit products, so the split
+# paths' FP32-equivalent peak is the 16-bit peak / 3.
+PEAK_16 = 2516.6
+PEAK = {"f16x3": PEAK_16 / 3.0, "bf16x3": PEAK_16 / 3.0, "fp32": 157.3, "fp64": 78.6}
+MFMA_32X32X16 = 2 * 32 * 32 * 16   # flops of one v_mfma_f32_32x32x16_{f16,bf16}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def flop_model(prob):
-    """Dense complex flop counts of P and Sigma^c (DIAG) for all q."""
+# ---------------------------------------------------------------------------------------------
+# work models (host logic; tested on the CPU)
+# ---------------------------------------------------------------------------------------------
+def flop_model(prob, qs=None, ks=None):
+    """Dense complex flop counts (F_P, F_Sigma) of the q in qs (default all) over the k in ks."""
     cfg = prob.cfg
     ntau = prob.tau.size
+    qs = range(cfg.nk) if qs is None else qs
+    ks = range(cfg.nk) if ks is None else ks
     fp = fs = 0.0
-    for q in range(cfg.nk):
-        for k in range(cfg.nk):
+    for q in qs:
+        ni = int(prob.ni[q])
+        for k in ks:
             nn, nm = int(prob.nb[k]), int(prob.nb[prob.kmq[q, k]])
-            ni = int(prob.ni[q])
             fp += 8.0 * ni * ni * nn * nm * ntau
             fs += 8.0 * ni * ni * nn * nm * ntau + 8.0 * ni * nn * nm * ntau
     return fp, fs
 
 
-def measured_record(kernel, tile, precision, cfg_name, q_batch):
-    """Counter record of one launch of `kernel` (HBM bytes, executed MFMA work), or None.
+# the pair-space kernels: (WI, KS) of the polarization variants, by name
+POLZ_SHAPES = {
+    "pair-space 16x16 pairs K64 st4x8 3-buffer": (4, 64),
+    "pair-space 16x16 pairs K64 st4x8": (4, 64),
+    "pair-space 8x16 pairs 2 WG/CU st4x16 K64": (2, 64),
+    "pair-space 8x16 pairs 2 WG/CU st4x16": (2, 32),
+}
+SIGZ_NAME = "pair-space 512 K x 8x8-pair blocks"
 
-    The record (profiles/traffic_c2_bf16x3.json) holds FETCH_SIZE and WRITE_SIZE of one launch over
-    its q_batch q, scaled by a plain copy of known size, together with the SHA-256 of the kernel source
-    it was taken on; it is used only for the same workload, precision, q batch, tile and unchanged
-    source.
-    """
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_c2_bf16x3.json")
-    if precision != "bf16x3" or not cfg_name.startswith("c2_") or not os.path.exists(path):
+
+def _tau_chunks(ntau):
+    """Tile counts NTT of the 96-wide tau chunks and the tail chunk (32-wide MFMA tiles)."""
+    nt = -(-ntau // 32)
+    return [3] * (nt // 3) + ([nt % 3] if nt % 3 else [])
+
+
+def executed_mfma_flops(prob, op, tile, q0, nq):
+    """MFMA flops the pair-space kernel executes for one call over q0..q0+nq-1 (None for a tile
+    form without a model).  Counted from the kernels' loops: the polarization runs, per work item
+    (a block of 4 WI rows I x 16 columns J touching the upper triangle, and a tau chunk of NTT
+    tiles), 2 WI waves x K_pad / 16 steps per k x 6 NTT MFMAs of 32x32x16; the self-energy runs,
+    per (q, k, 512-row chunk of K, tau chunk), 8 waves x (upper-triangle 8x8-pair blocks) x 8 steps
+    x 6 NTT MFMAs."""
+    cfg = prob.cfg
+    ntau = prob.tau.size
+    chunks = _tau_chunks(ntau)
+    n = 0
+    for q in range(q0, q0 + nq):
+        NI = int(prob.ni[q])
+        Ks = [int(prob.nb[k]) * int(prob.nb[prob.kmq[q, k]]) for k in range(cfg.nk)]
+        if op == 0:
+            if tile not in POLZ_SHAPES:
+                return None
+            WI, _ = POLZ_SHAPES[tile]
+            steps = sum(-(-K // 64) * 64 // 16 for K in Ks)
+            items = 0
+            for r in range(-(-NI // (4 * WI))):
+                I0 = 4 * WI * r
+                items += sum(1 for cj in range(-(-NI // 16)) if 16 * cj + 16 > I0)
+            n += items * 2 * WI * steps * 6 * sum(chunks)
+        else:
+            if tile != SIGZ_NAME:
+                return None
+            n8 = -(-NI // 8)
+            nblk = n8 * (n8 + 1) // 2
+            kchunks = sum(-(-K // 512) for K in Ks)
+            n += kchunks * 8 * nblk * 8 * 6 * sum(chunks)
+    return float(n) * MFMA_32X32X16
+
+
+def iteration_slices(nk, steps):
+    """The q range [a, b) of each of the `steps` steps of one iteration."""
+    return [(nk * s // steps, nk * (s + 1) // steps) for s in range(steps)]
+
+
+def sub_batches(a, b, qmax):
+    """[a, b) cut into the fewest nearly equal consecutive batches of at most qmax q."""
+    n = b - a
+    if n <= 0:
+        return []
+    m = -(-n // qmax)
+    cuts = [a + n * i // m for i in range(m + 1)]
+    return [(cuts[i], cuts[i + 1] - cuts[i]) for i in range(m)]
+
+
+def traffic_record(kernel, tile, precision, cfg_name, path=None):
+    """Counter record of `kernel` (HBM bytes per q from FETCH_SIZE / WRITE_SIZE of one launch), or
+    None.  Used only for the same workload, precision and tile and an unchanged kernel source."""
+    path = path or os.path.join(ROOT, "profiles", f"traffic_{cfg_name.split('_')[0]}_{precision}.json")
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("q_batch") != q_batch:
+    if rec.get("workload") != cfg_name or rec.get("precision") != precision:
         return None
     with open(os.path.join(ROOT, rec["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
@@ -75,8 +147,10 @@ def measured_record(kernel, tile, precision, cfg_name, q_batch):
     return k
 
 
-def cpu_baseline(cfg, prob, budget_s=12.0):
-    """The FP64 oracle's polarization on a bounded sample of the same workload (host cores)."""
+# ---------------------------------------------------------------------------------------------
+# the CPU oracle on a bounded sample of the same workload
+# ---------------------------------------------------------------------------------------------
+def cpu_baseline(cfg, prob, budget_s=12.0, R=96):
     import gwinputs as gi
     import oracle as o
     try:
@@ -84,7 +158,6 @@ def cpu_baseline(cfg, prob, budget_s=12.0):
         cores = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
     except Exception:
         cores = os.cpu_count() or 1
-    R = 160
     rows = np.arange(R)
     g = gi.MGenerator(cfg)
     blocks = [g.block(0, k, rows=rows) for k in range(cfg.nk)]
@@ -99,19 +172,21 @@ def cpu_baseline(cfg, prob, budget_s=12.0):
         if t_used > budget_s:
             break
     return {"value": flops / t_used / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"polarization of q=0, I,J < {R}, all 64 k, {len(done)} of {prob.tau.size} tau "
-                      f"points ({flops:.3e} flop in {t_used:.1f} s); numpy FP64 with "
-                      f"{cores} BLAS threads"}
+            "sample": f"the oracle's polarization of q = 0 for I, J < {R}, all {cfg.nk} k, {len(done)} of "
+                      f"{prob.tau.size} tau points ({flops:.3e} flop in {t_used:.1f} s; numpy FP64 on "
+                      f"{cores} BLAS threads)"}
 
 
+# ---------------------------------------------------------------------------------------------
+# the batching study (one launch vs a per-k launch loop), a mode of its own
+# ---------------------------------------------------------------------------------------------
 def batching_study(args):
     """One launch over all (k, tau) blocks of a q against one launch per k block, on one q.
 
     The uneven 6x6x6-k workload (Nb_k in [96, 160], NI_q in [500, 900], 121 tau points) by default,
-    on its q with the largest NI; split-BF16 pair-space kernels, M resident in HBM.  Prints one JSON
-    line with both times for the polarization and the self-energy and the relative difference of the
-    two results (they differ only in where the FP32 partial sums are flushed to FP64).
-    """
+    on its q with the largest NI; pair-space kernels of the split precision, M resident in HBM.
+    Prints one JSON line with both times for the polarization and the self-energy and the relative
+    difference of the two results (they differ only in where the FP32 partial sums are flushed)."""
     import torch
     import gwinputs as gi
     import paper_1602_02313_amd as amd
@@ -119,8 +194,9 @@ def batching_study(args):
     cfg = gi.CONFIGS[args.config]
     prob = gi.make_problem(cfg)
     q = int(np.argmax(prob.ni))
+    B = {"f16x3": amd.F16X3, "bf16x3": amd.BF16X3}[args.precision]
     run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
-                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=amd.BF16X3, q_batch=1)
+                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=B, q_batch=1)
     M = torch.empty(int(run.mpre[q + 1] - run.mpre[q]), dtype=torch.complex64, device="cuda")
     run.ctx.synth_M(cfg.seed, q, 1, 1, amd.C64, M)
     run.green0(0.0)
@@ -128,12 +204,8 @@ def batching_study(args):
     gen = torch.Generator(device="cuda").manual_seed(7)
     W = run.Wt_tau[:ntau * NI * NI]
     W.copy_(torch.randn(W.shape, dtype=torch.complex128, device="cuda", generator=gen) * 1e-3)
-    ctx, B = run.ctx, amd.BF16X3
-    fp, fs = 0.0, 0.0
-    for k in range(cfg.nk):
-        kk = int(prob.nb[k]) * int(prob.nb[prob.kmq[q, k]])
-        fp += 8.0 * NI * NI * kk * ntau
-        fs += 8.0 * NI * NI * kk * ntau + 8.0 * NI * kk * ntau
+    ctx = run.ctx
+    fp, fs = flop_model(prob, qs=[q])
     log(f"[batching] {cfg.name} q={q} NI={NI}: M {M.numel() * 8 / 1e9:.1f} GB")
 
     def timed(fn):
@@ -186,20 +258,56 @@ def batching_study(args):
     res["self_energy"]["loop_vs_one_rel"] = float((a - b).norm() / a.norm())
     print(json.dumps({"study": "batching: all (k, tau) blocks of a q in one launch vs one launch per k",
                       "workload": f"{cfg.name}, q = {q} (NI = {NI}), {cfg.nk} k blocks with uneven band "
-                                  f"counts, {ntau} tau points, split-BF16 pair-space kernels",
+                                  f"counts, {ntau} tau points, {args.precision} pair-space kernels",
                       "unit": "ms", **res}), flush=True)
 
 
+# ---------------------------------------------------------------------------------------------
+# the FP64 GPU path on a subset of the same inputs
+# ---------------------------------------------------------------------------------------------
+def fp64_reference(cfg, prob, kref):
+    import torch
+    import paper_1602_02313_amd as amd
+    from paper_1602_02313_amd.driver import EventTimer
+    ref = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
+                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=amd.FP64, q_batch=1)
+    M64 = torch.empty(int(ref.mpre[1]), dtype=torch.complex128, device="cuda")
+    ref.ctx.synth_M(cfg.seed, 0, 1, 1, amd.C128, M64)
+    ref.green0(0.0)
+    kref = min(kref, cfg.nk)
+    ref.ctx.set_k_range(0, kref)
+    src = amd.ResidentM(M64, ref.mpre)
+    ref.begin_pass()
+    ref.q_block(src, 0, 1)      # warm-up
+    t64 = EventTimer(ctx=ref.ctx)
+    ref.timer = t64
+    ref.begin_pass()
+    ref.q_block(src, 0, 1)
+    ref.timer = None
+    k64 = t64.kernel_summary()
+    ref.ctx.set_k_range()
+    fp1, fs1 = flop_model(prob, qs=[0], ks=range(kref))
+    tp, ts = k64["polarization"][0] / 1e3, k64["self_energy"][0] / 1e3
+    out = {"subset": f"q = 0, k blocks 0..{kref - 1} of {cfg.nk} (the workload's block shapes)",
+           "polarization_tflops": round(fp1 / tp / 1e12, 2), "self_energy_tflops": round(fs1 / ts / 1e12, 2),
+           "p_plus_sigma_tflops": round((fp1 + fs1) / (tp + ts) / 1e12, 2), "peak": PEAK["fp64"],
+           "p_plus_sigma_s_per_iteration_at_this_rate": None}
+    del M64, ref
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c5")
     ap.add_argument("--precision", default="f16x3", choices=["f16x3", "bf16x3", "fp32", "fp64"])
-    ap.add_argument("--q-batch", type=int, default=16)
-    ap.add_argument("--fp64-ref-q", type=int, default=1,
-                    help="q points on which the FP64 GPU path is timed for comparison (0: skip)")
+    ap.add_argument("--q-batch", type=int, default=8, help="largest q batch of one library call")
+    ap.add_argument("--fp64-ref-k", type=int, default=4,
+                    help="k blocks of q = 0 on which the FP64 GPU path is timed for comparison (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--variant-p", type=int, default=None,
@@ -207,25 +315,22 @@ def main():
     ap.add_argument("--variant-s", type=int, default=None,
                     help="self-energy tile variant (skips the autotuner for Sigma)")
     ap.add_argument("--profile-batch", action="store_true",
-                    help="counter runs: a plain device copy of --copy-mb MB, then one q batch of the path, "
-                         "no timing and no JSON line")
+                    help="counter runs: a plain device copy of --copy-mb MB, then the first q batch of the "
+                         "path, no timing and no JSON line")
     ap.add_argument("--copy-mb", type=int, default=1024)
     ap.add_argument("--graph", action="store_true",
-                    help="time replays of the iteration captured as a HIP graph (no per-kernel times)")
-    ap.add_argument("--tau-mirror", action="store_true",
-                    help="use P(tau) = P(beta - tau) of the symmetric inputs (the dense flop count of the "
-                         "metric is unchanged; the saving is reported as tau_mirror in config)")
+                    help="each step captured once as a HIP graph and replayed (no per-kernel times)")
     ap.add_argument("--batching", action="store_true",
-                    help="instead of the pass: one launch vs a per-k launch loop on one q of --config "
+                    help="instead of the iteration: one launch vs a per-k launch loop on one q of --config "
                          "(default c4, the uneven workload)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): there is no "
-              f"multi-GPU path; it would shard the q axis over GPUs with one all-reduce of Sigma "
-              f"per iteration, which is not implemented", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): there is no multi-GPU path; "
+              f"it would shard the q axis over GPUs with one all-reduce of Sigma per iteration, which is "
+              f"not implemented", file=sys.stderr)
         sys.exit(2)
     if args.batching:
-        if args.config == "c2":
+        if args.config == "c5":
             args.config = "c4"
         batching_study(args)
         return
@@ -238,26 +343,22 @@ def main():
     cfg = gi.CONFIGS[args.config]
     prob = gi.make_problem(cfg)
     prec = {"f16x3": amd.F16X3, "bf16x3": amd.BF16X3, "fp32": amd.FP32, "fp64": amd.FP64}[args.precision]
+    steps = max(1, min(args.steps, cfg.nk))
+    slices = iteration_slices(cfg.nk, steps)
+    qb = max(1, min(args.q_batch, max(b - a for a, b in slices)))
     log(f"[bench] {cfg.name}: nk={cfg.nk} nb={int(prob.nb.max())} NI={int(prob.ni.max())} "
-        f"ntau={prob.tau.size} niw={cfg.niw_f} precision={args.precision}")
+        f"ntau={prob.tau.size} niw={cfg.niw_f} precision={args.precision}; {steps} steps of "
+        f"{min(b - a for a, b in slices)}-{max(b - a for a, b in slices)} q per iteration, q batch {qb}")
     run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
-                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=prec,
-                    q_batch=args.q_batch, tau_mirror=args.tau_mirror)
-    ct = torch.complex128 if run.m_dtype == amd.C128 else torch.complex64
-    M = torch.empty(int(run.mpre[-1]), dtype=ct, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run.ctx.synth_M(cfg.seed, 0, cfg.nk, 1, run.m_dtype, M)
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t0
-    log(f"[bench] M resident: {M.numel() * M.element_size() / 1e9:.1f} GB generated in {t_gen:.2f} s")
-    src = amd.ResidentM(M, run.mpre)
+                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=prec, q_batch=qb)
+    src = amd.SynthM(cfg.seed, symmetric=True)
+    src.reserve(run)
     fixed = {amd.OP_POLARIZATION: args.variant_p, amd.OP_SELF_ENERGY: args.variant_s}
     for op, v in fixed.items():
         if v is not None:
             run.ctx.set_variant(op, prec, v)
     if args.profile_batch:
-        # a plain copy of known size calibrates the HBM byte counters, then one batch of the path
+        # a plain copy of known size calibrates the HBM byte counters, then one q batch of the path
         n = args.copy_mb * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -265,157 +366,172 @@ def main():
         torch.cuda.synchronize()
         del a, b
         run.green0(0.0)
-        run.sig_tau.zero_()
-        run.sig_x.zero_()
-        run.q_block(src, 0, min(args.q_batch, cfg.nk))
+        run.begin_pass()
+        run.q_block(src, 0, qb)
         torch.cuda.synchronize()
         vp = run.ctx.get_variant(amd.OP_POLARIZATION, prec)
         vs = run.ctx.get_variant(amd.OP_SELF_ENERGY, prec)
-        log(f"[bench] profile batch done: copy of {args.copy_mb} MB, q 0..{args.q_batch - 1}, variants "
+        log(f"[bench] profile batch done: copy of {args.copy_mb} MB, q 0..{qb - 1}, variants "
             f"P {vp} ({run.ctx.variants(amd.OP_POLARIZATION, prec)[vp]}) "
             f"S {vs} ({run.ctx.variants(amd.OP_SELF_ENERGY, prec)[vs]})")
         return
     tuned = {}
-    if not args.no_autotune and None in fixed.values():
+    if not args.no_autotune and prec != amd.FP64 and None in fixed.values():
         from paper_1602_02313_amd import autotune
         ops = [op for op, v in fixed.items() if v is None]
-        for op, (v, name, times) in autotune.tune(run, src, reps=1, log=log, ops=ops).items():
+        for op, (v, name, times) in autotune.tune(run, src, reps=1, log=log, ops=ops, nq=1).items():
             tuned[["polarization", "self_energy"][op]] = {"variant": v, "tile": name, "ms": times}
 
-    def step_eager():
+    run.green0(0.0)
+    run.mu.zero_()
+
+    def step(s):
+        a, b = slices[s]
+        if s == 0:
+            run.begin_pass()
+        for q0, nq in sub_batches(a, b, qb):
+            run.q_block(src, q0, nq)
+        if s == steps - 1:
+            run.sigma_to_iw()
+            run.dyson(True)
+            run.gap()
+
+    graphs = None
+    if args.graph:
+        torch.cuda.synchronize()
+        graphs = []
+        for s in range(steps):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                step(s)
+            graphs.append(g)
+        torch.cuda.synchronize()
         run.green0(0.0)
         run.mu.zero_()
-        run.iteration(src)
 
-    step = step_eager
-    if args.graph:
-        # one pass = G0 + the captured iteration (Sigma pass, Dyson with the mu search, gap)
-        graph = run.capture_iteration(src)
+    def do(s):
+        if graphs is not None:
+            graphs[s].replay()
+        else:
+            step(s)
 
-        def step():
-            run.green0(0.0)
-            run.mu.zero_()
-            graph.replay()
-
+    t0 = time.perf_counter()
     for w in range(args.warmup):
-        t0 = time.perf_counter()
-        step()
+        do(w % steps)
         torch.cuda.synchronize()
-        log(f"[bench] warmup {w}: {time.perf_counter() - t0:.2f} s")
-    timer = EventTimer()
-    run.timer = None if args.graph else timer
+        log(f"[bench] warmup {w} (q {slices[w % steps][0]}..{slices[w % steps][1] - 1}) done at "
+            f"{time.perf_counter() - t0:.2f} s")
+    timer = EventTimer(ctx=run.ctx)
+    run.timer = None if graphs is not None else timer
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        step()
+    for s in range(steps):
+        do(s)
         torch.cuda.synchronize()
-        log(f"[bench] step {s} done at {time.perf_counter() - t0:.2f} s")
+        log(f"[bench] step {s} (q {slices[s][0]}..{slices[s][1] - 1}) done at {time.perf_counter() - t0:.2f} s")
     t_tot = time.perf_counter() - t0
     run.timer = None
-    ms_step = 1e3 * t_tot / args.steps
-    kern_steps = args.steps
-    if args.graph:
-        # per-kernel times come from one extra eager pass (kernels cannot be timed inside a replay)
-        run.timer = timer
-        step_eager()
-        torch.cuda.synchronize()
-        run.timer = None
-        kern_steps = 1
-    kern = timer.summary()
+    ms_step = 1e3 * t_tot / steps
+    flags = int(run.flags.item()) | int(run.screen_flags.item())
+    gap, N, mu = float(run.gap_d.item()), float(run.N.item()), float(run.mu.item())
     fp, fs = flop_model(prob)
-    value = (fp + fs) / (ms_step / 1e3) / 1e12
-    flags, gap, N = int(run.flags.item()), float(run.gap_d.item()), float(run.N.item())
+    value = (fp + fs) / (t_tot) / 1e12
 
-    # per-kernel times and the dominant contraction's roofline
-    nb_q = -(-cfg.nk // args.q_batch)
-    ksum = {k: float(np.sum(v)) / kern_steps for k, v in kern.items()}
-    kavg = {k: float(np.mean(v)) for k, v in kern.items()}
-    per_launch = {"polarization": fp / nb_q, "self_energy": fs / nb_q}
-    dom_op = {"polarization": amd.OP_POLARIZATION, "self_energy": amd.OP_SELF_ENERGY}
-    dom = max(("polarization", "self_energy"), key=lambda k: ksum.get(k, 0.0))
-    achieved = per_launch[dom] / (kavg[dom] / 1e3) / 1e12
-    peak = PEAK[args.precision]
-    tile = (tuned.get(dom, {}).get("tile")
-            or run.ctx.variants(dom_op[dom], prec)[run.ctx.get_variant(dom_op[dom], prec)])
-    rec = measured_record(dom, tile, args.precision, cfg.name, args.q_batch)
-    roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": round(peak, 1),
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-            "traffic": rec["traffic_bytes"] if rec else None,
-            "kernel": dom, "tile": tile, "flop_per_launch": per_launch[dom],
-            "avg_launch_ms": round(kavg[dom], 3)}
-    if rec:
-        # the executed MFMA work (Hermitian savings and tile padding included) from the counters
-        ex = rec["mfma_bf16_flop_executed"] / (kavg[dom] / 1e3) / 1e12
-        roof["executed_bf16_tflops"] = round(ex, 1)
-        roof["executed_bf16_frac"] = round(ex / PEAK_BF16, 4)
-    if args.precision == "bf16x3":
-        roof["peak_basis"] = ("bf16 dense 2516.6 TFLOP/s / 3 products per split product; achieved "
-                              "counts the dense complex flop model, executed_* the MFMA work done")
-    kernels = {k: {"ms_per_step": round(ksum[k], 3), "launches_per_step": len(kern[k]) // kern_steps}
-               for k in kern}
-    kernels["polarization"]["tflops"] = round(fp / (ksum["polarization"] / 1e3) / 1e12, 2)
-    kernels["self_energy"]["tflops"] = round(fs / (ksum["self_energy"] / 1e3) / 1e12, 2)
+    line_extra = {}
+    roof = None
+    kernels = None
+    if graphs is None:
+        kern = timer.summary()
+        kk = timer.kernel_summary()
+        ksum = {k: float(np.sum(v)) for k, v in kern.items()}
+        dom = max(("polarization", "self_energy"), key=lambda k: ksum.get(k, 0.0))
+        op = {"polarization": amd.OP_POLARIZATION, "self_energy": amd.OP_SELF_ENERGY}[dom]
+        tile = run.ctx.variants(op, prec)[run.ctx.get_variant(op, prec)] if prec != amd.FP64 else "fp64"
+        calls = [(q0, nq) for a, b in slices for q0, nq in sub_batches(a, b, qb)]
+        ktimes = kk[dom]
+        assert len(ktimes) == len(calls), (len(ktimes), len(calls))
+        exe = [executed_mfma_flops(prob, op, tile, q0, nq) for q0, nq in calls]
+        dense = [flop_model(prob, qs=range(q0, q0 + nq))[op] for q0, nq in calls]
+        t_k = float(np.sum(ktimes)) / 1e3
+        avg_ms = float(np.mean(ktimes))
+        if exe[0] is not None and args.precision in ("f16x3", "bf16x3"):
+            achieved = float(np.sum(exe)) / t_k / 1e12
+            roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": PEAK_16, "unit": "TFLOP/s",
+                    "frac": round(achieved / PEAK_16, 4)}
+        else:
+            achieved = float(np.sum(dense)) / t_k / 1e12
+            roof = {"bound": "mfma", "achieved": round(achieved, 1), "peak": PEAK[args.precision],
+                    "unit": "TFLOP/s", "frac": round(achieved / PEAK[args.precision], 4)}
+        rec = traffic_record(dom, tile, args.precision, cfg.name)
+        qavg = float(np.mean([nq for _, nq in calls]))
+        roof.update({
+            "traffic": round(rec["bytes_per_q"] * qavg) if rec else None,
+            "kernel": {"polarization": "k_polz", "self_energy": "k_sigz"}[dom] if exe[0] is not None else dom,
+            "tile": tile,
+            "avg_launch_ms": round(avg_ms, 2),
+            "launches": len(ktimes),
+            "executed_flop_per_launch": round(float(np.mean(exe))) if exe[0] is not None else None,
+            "dense_equiv_tflops": round(float(np.sum(dense)) / t_k / 1e12, 1),
+            "basis": ("achieved = MFMA flops the kernel executes (counted from its loops: Hermitian "
+                      "triangle, real weight against complex pair products, tile padding) over its "
+                      "event-timed duration, against the dense 16-bit MFMA peak; dense_equiv_tflops = "
+                      "the dense complex flop model over the same time"),
+        })
+        kernels = {}
+        for k, v in kern.items():
+            kernels[k] = {"ms_per_iteration": round(float(np.sum(v)), 1), "calls": len(v)}
+            if k in kk:
+                kernels[k]["kernel_ms_per_iteration"] = round(float(np.sum(kk[k])), 1)
+        kernels["polarization"]["dense_tflops"] = round(fp / (ksum["polarization"] / 1e3) / 1e12, 1)
+        kernels["self_energy"]["dense_tflops"] = round(fs / (ksum["self_energy"] / 1e3) / 1e12, 1)
 
-    # the FP64 GPU path on the same inputs (a q subset, same shapes)
+    del src
+    run.timer = None
     fp64_ref = None
-    if args.fp64_ref_q > 0 and args.precision != "fp64":
-        nq = args.fp64_ref_q
-        ref = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f,
-                        cfg.niw_b, cfg.scale, prob.eps, prob.v, prob.n_target,
-                        precision=amd.FP64, q_batch=nq)
-        M64 = torch.empty(int(ref.mpre[nq]), dtype=torch.complex128, device="cuda")
-        ref.ctx.synth_M(cfg.seed, 0, nq, 1, amd.C128, M64)
-        ref.green0(0.0)
-        t64 = EventTimer()
-        ref.timer = t64
-        ref.sig_tau.zero_()
-        ref.sig_x.zero_()
-        ref.q_block(amd.ResidentM(M64, ref.mpre), 0, nq)
-        k64 = t64.summary()
-        fp1 = fp * nq / cfg.nk
-        fs1 = fs * nq / cfg.nk
-        tp, ts = k64["polarization"][0] / 1e3, k64["self_energy"][0] / 1e3
-        fp64_ref = {"q_points": nq, "polarization_tflops": round(fp1 / tp / 1e12, 2),
-                    "self_energy_tflops": round(fs1 / ts / 1e12, 2),
-                    "p_plus_sigma_tflops": round((fp1 + fs1) / (tp + ts) / 1e12, 2),
-                    "p_plus_sigma_s_extrapolated": round((tp + ts) * cfg.nk / nq, 2),
-                    "peak": PEAK["fp64"]}
-        del M64, ref
+    if args.fp64_ref_k > 0 and args.precision != "fp64":
+        del run
         torch.cuda.empty_cache()
-
+        fp64_ref = fp64_reference(cfg, prob, args.fp64_ref_k)
+        fp64_ref["p_plus_sigma_s_per_iteration_at_this_rate"] = round(
+            (fp + fs) / (fp64_ref["p_plus_sigma_tflops"] * 1e12), 1)
     cpu = None if args.no_cpu_baseline else cpu_baseline(cfg, prob)
 
     line = {
         "metric": "P+Sigma effective TFLOP/s and s per scGW iteration, split-FP32 vs FP64 GPU",
-        "value": round(value, 3),
+        "value": round(value, 2),
         "unit": "TFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_step, 2),
-        "s_per_iteration": round(ms_step / 1e3, 3),
+        "s_per_iteration": round(t_tot, 2),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f16x3": "f16x3 (split fp32 on f16 MFMA, scaled, fp32 accumulate) + f64",
+        "dtype": {"f16x3": "f16x3 (split fp32 on f16 MFMA, scaled operands, fp32 accumulate) + f64",
                   "bf16x3": "bf16x3 (split fp32 on bf16 MFMA, fp32 accumulate) + f64",
                   "fp32": "f32 MFMA + f64", "fp64": "f64"}[args.precision],
-        "data": "synthetic (seeded Philox matrix elements, model bands, diagonal Coulomb kernel)",
-        "config": {"workload": f"{cfg.name}: one G0W0 + Dyson pass, all 64 q",
+        "data": "synthetic (seeded Philox matrix elements drawn on the device per q, model bands, "
+                "diagonal Coulomb kernel)",
+        "config": {"workload": f"{cfg.name}: one scGW iteration (P, W~, Sigma for all {cfg.nk} q with M "
+                               f"generated per q, Dyson with the mu search, gap) in {steps} steps of "
+                               f"consecutive q slices",
                    "nk": cfg.nk, "nb": int(prob.nb.max()), "ni": int(prob.ni.max()),
                    "ntau": int(prob.tau.size), "niw_f": cfg.niw_f, "niw_b": cfg.niw_b,
-                   "beta": cfg.beta, "precision": args.precision, "q_batch": args.q_batch,
-                   "hip_graph": bool(args.graph), "tau_mirror": bool(args.tau_mirror),
-                   "flops_p": fp, "flops_sigma": fs},
+                   "beta": cfg.beta, "precision": args.precision, "q_batch": qb,
+                   "hip_graph": bool(args.graph), "flops_p": fp, "flops_sigma": fs},
         "roofline": roof,
         "kernels": kernels,
         "fp64_gpu_reference": fp64_ref,
         "cpu_baseline": cpu,
-        "m_generation_s": round(t_gen, 3),
         "autotune": tuned,
-        "check": {"flags": flags, "N": N, "n_target": prob.n_target, "gap_Ha": gap},
+        "check": {"flags": flags, "N": N, "n_target": prob.n_target, "mu": mu, "gap_Ha": gap},
+        **line_extra,
     }
     print(json.dumps(line), flush=True)
+    if flags:
+        log(f"[bench] the iteration raised status flags {flags} (MSGW_FLAG_*): the result is not valid")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -311,8 +311,15 @@ int msgw_get_variant(const msgw_ctx* c, int op, int precision, int* variant);
  * reuses what the previous contraction call left in the workspace; that call must have been of the same
  * op, q range, precision and variant (the two ops share the scratch), else the call fails with
  * MSGW_EINVAL and enqueues nothing.  k1 <= 0 restores the full range.  While a partial range
- * is set, the other tile variants and precisions return MSGW_ENOTSUP. */
+ * is set, the other tile variants and precisions return MSGW_ENOTSUP.  The FP64 contractions honour a
+ * partial range as well (DIAG self-energy; a polarization with k0 > 0 adds), without preparations. */
 int msgw_set_k_range(msgw_ctx* c, int k0, int k1, int reuse_prepared);
+
+/* Harness-only (measurement): the following polarization (op = MSGW_OP_POLARIZATION) or self-energy
+ * (MSGW_OP_SELF_ENERGY) calls on c record the HIP event `start` (a hipEvent_t) on their stream just
+ * before their contraction kernels and `stop` just after them, leaving out the per-q preparations, so
+ * that the caller can time the kernels alone.  The events are the caller's; NULL, NULL stops it. */
+int msgw_set_kernel_events(msgw_ctx* c, int op, void* start, void* stop);
 
 /* ---- input generation (not part of the method) ---------------------------------------------- */
 

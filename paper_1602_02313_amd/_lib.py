@@ -32,7 +32,7 @@ EXPORTS = [
     "msgw_screened_tau", "msgw_self_energy", "msgw_sigma_x", "msgw_dyson", "msgw_gap",
     "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant", "msgw_get_variant",
     "msgw_set_k_range", "msgw_continue_pade", "msgw_gap_of", "msgw_set_tau_mirror",
-    "msgw_continue_cpe", "msgw_dyson_noalloc",
+    "msgw_continue_cpe", "msgw_dyson_noalloc", "msgw_set_kernel_events",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 
@@ -86,6 +86,7 @@ def load_library():
         "msgw_sigma_x": [P, P, I, I, P, I, P, P, P],
         "msgw_dyson": [P, P, P, P, P, D, I, P, P, P, P, P],
         "msgw_dyson_noalloc": [P, P, P, P, P, D, I, P, P, P, P, P],
+        "msgw_set_kernel_events": [P, I, P, P],
         "msgw_gap": [P, P, P, P, P, P, I, P],
         "msgw_synth_M": [P, P, U64, I, I, I, I, P],
     }
@@ -295,6 +296,14 @@ class Context:
     def set_k_range(self, k0=0, k1=0, reuse_prepared=False):
         """Harness only: restrict the pair-space contractions to k blocks [k0, k1) (k1 <= 0: all)."""
         self._check(self.lib.msgw_set_k_range(self._c, int(k0), int(k1), int(bool(reuse_prepared))))
+
+    def set_kernel_events(self, op, start=None, stop=None):
+        """Harness only: record the torch.cuda.Events start / stop around the contraction kernels of the
+        following calls of op (None, None: stop).  The events must have been recorded once (torch
+        creates them lazily)."""
+        a = None if start is None else ctypes.c_void_p(start.cuda_event)
+        b = None if stop is None else ctypes.c_void_p(stop.cuda_event)
+        self._check(self.lib.msgw_set_kernel_events(self._c, int(op), a, b))
 
     def synth_M(self, seed, q0, nq, symmetric, m_dtype, M, stream=None):
         self._check(self.lib.msgw_synth_M(self._c, _stream(stream), int(seed), q0, nq,

@@ -35,8 +35,10 @@ def _launch(op, ctx, run, M, q0, nq, st):
                         stream=st)
 
 
-def tune(run, M_source, reps=2, cache_path=None, log=None, ops=None):
-    """Pick the fastest variant of each MFMA op for `run`; returns {op: (index, name, ms list)}."""
+def tune(run, M_source, reps=2, cache_path=None, log=None, ops=None, nq=None):
+    """Pick the fastest variant of each MFMA op for `run`; returns {op: (index, name, ms list)}.
+
+    The variants are timed on q = 0 .. nq - 1 (default: the run's q batch)."""
     import torch
     if run.precision not in (L.FP32, L.BF16X3, L.F16X3):
         return {}
@@ -45,7 +47,7 @@ def tune(run, M_source, reps=2, cache_path=None, log=None, ops=None):
         with open(cache_path) as f:
             cache = json.load(f)
     out = {}
-    q0, nq = 0, min(run.q_batch, run.nk)
+    q0, nq = 0, min(run.q_batch if nq is None else nq, run.q_batch, run.nk)
     M = M_source(run, q0, nq)
     ctx, st = run.ctx, run.stream
     # realistic W~(tau) and G for the timing launches

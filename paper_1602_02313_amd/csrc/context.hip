@@ -397,7 +397,7 @@ static bool full_k_range(const msgw_ctx* c) { return c->d.kb0 == 0 && c->d.kb1 =
 static void check_reuse(msgw_ctx* c, int op, int q0, int nq, int precision) {
     const auto& p = c->prep;
     const int v = c->variant[op][precision];
-    if (c->d.kreuse)
+    if (c->d.kreuse && precision != MSGW_FP64)  // the FP64 kernels prepare nothing
         need(p.op == op && p.q0 == q0 && p.nq == nq && p.precision == precision && p.variant == v, MSGW_EINVAL,
              "reuse_prepared: the scratch holds no operands of this op, q range, precision and variant");
 }
@@ -420,8 +420,8 @@ int msgw_polarization(msgw_ctx* c, void* stream, int q0, int nq, const void* M, 
         require_ready(c);
         check_qrange(c, q0, nq);
         need(M && G_tau && P_tau, MSGW_EINVAL, "null pointer");
-        need(full_k_range(c) || precision == MSGW_BF16X3 || precision == MSGW_F16X3, MSGW_ENOTSUP,
-             "a partial k range is supported by the split-precision pair-space kernels only");
+        need(full_k_range(c) || precision != MSGW_FP32, MSGW_ENOTSUP,
+             "a partial k range is supported by the FP64 and the split-precision pair-space kernels only");
         check_reuse(c, MSGW_OP_POLARIZATION, q0, nq, precision);
         if (precision == MSGW_FP64) {
             need(m_dtype == MSGW_C128, MSGW_EINVAL, "MSGW_FP64 needs MSGW_C128 M");
@@ -508,9 +508,8 @@ int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, i
         require_ready(c);
         check_qrange(c, q0, nq);
         need(M && G_tau && Wt_tau && Sigma_tau, MSGW_EINVAL, "null pointer");
-        need(full_k_range(c) || ((precision == MSGW_BF16X3 || precision == MSGW_F16X3) &&
-                                 c->h.sigma_mode != MSGW_SIGMA_FULL),
-             MSGW_ENOTSUP, "a partial k range is supported by the split-precision pair-space kernels only");
+        need(full_k_range(c) || (precision != MSGW_FP32 && c->h.sigma_mode != MSGW_SIGMA_FULL), MSGW_ENOTSUP,
+             "a partial k range is supported by the FP64 (DIAG) and the split-precision pair-space kernels only");
         check_reuse(c, MSGW_OP_SELF_ENERGY, q0, nq, precision);
         if (c->h.sigma_mode == MSGW_SIGMA_FULL) {
             need(precision == MSGW_FP64 && m_dtype == MSGW_C128, MSGW_ENOTSUP,
@@ -669,6 +668,16 @@ int msgw_set_k_range(msgw_ctx* c, int k0, int k1, int reuse_prepared) {
         c->d.kb0 = k0;
         c->d.kb1 = k1;
         c->d.kreuse = reuse_prepared ? 1 : 0;
+    });
+}
+
+int msgw_set_kernel_events(msgw_ctx* c, int op, void* start, void* stop) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(op == MSGW_OP_POLARIZATION || op == MSGW_OP_SELF_ENERGY, MSGW_EINVAL, "bad op");
+        need((start == nullptr) == (stop == nullptr), MSGW_EINVAL, "give both events or neither");
+        c->d.ev_start[op] = static_cast<hipEvent_t>(start);
+        c->d.ev_stop[op] = static_cast<hipEvent_t>(stop);
     });
 }
 

@@ -68,7 +68,16 @@ struct Dev {
     unsigned long long* mx_w = nullptr;  // [nk][ntau]  bits of max |Re|, |Im| of W~(q, tau) (double >= 0)
     double* g_max = nullptr;             // [nk][ntau]  max_n |G_n(k, tau)|
     int* e_g = nullptr;                  // [nk][ntau]  power-of-two exponent of the polarization weights
+    // harness-only timing: HIP events recorded around the contraction kernels of each polarization
+    // (index 0) and self-energy (index 1) call on the call's stream (null: none)
+    hipEvent_t ev_start[2] = {nullptr, nullptr}, ev_stop[2] = {nullptr, nullptr};
 };
+
+// records d's kernel-timing event of op (0 polarization, 1 self-energy) on s, if one is set
+inline void record_kernel_event(const Dev& d, int op, bool stop, hipStream_t s) {
+    hipEvent_t e = stop ? d.ev_stop[op] : d.ev_start[op];
+    if (e) MSGW_HIP(hipEventRecord(e, s));
+}
 
 // Host mirror of the problem (used for launch shapes and validation).
 struct Host {

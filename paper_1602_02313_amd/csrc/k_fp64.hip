@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void k_pol_fp64(Dev d, int q0, const double2* 
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
     const double2* Mq = M + (d.mpre[q] - d.mpre[q0]);
-    for (int k = 0; k < nk; ++k) {
+    for (int k = d.kb0; k < d.kb1; ++k) {  // all k unless a partial range is set
         const int kq = d.kmq[q * nk + k];
         const int nn = d.nb[k], nm = d.nb[kq];
         const int Kk = nn * nm;
@@ -87,8 +87,11 @@ __global__ __launch_bounds__(256) void k_pol_fp64(Dev d, int q0, const double2* 
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int I = i0 + ty + 16 * a, J = j0 + tx + 16 * b;
-            if (I < NI && J < NI)
-                Pq[int64_t(I) * NI + J] = make_double2(d.scale * acc[a][b].x, d.scale * acc[a][b].y);
+            if (I < NI && J < NI) {
+                double2 v = make_double2(d.scale * acc[a][b].x, d.scale * acc[a][b].y);
+                if (d.kb0 > 0) v = cadd(v, Pq[int64_t(I) * NI + J]);  // a range past k = 0 adds
+                Pq[int64_t(I) * NI + J] = v;
+            }
         }
 }
 
@@ -103,6 +106,7 @@ __global__ __launch_bounds__(256) void k_sig_fp64(Dev d, int q0, const double2* 
     __shared__ double red[16][TT];
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int q = q0 + blockIdx.z / nk, k = blockIdx.z % nk, it = blockIdx.y;
+    if (k < d.kb0 || k >= d.kb1) return;  // outside a partial k range
     const int kq = d.kmq[q * nk + k];
     const int nn = d.nb[k], nm = d.nb[kq], NI = d.ni[q];
     const int Kk = nn * nm;
@@ -225,9 +229,11 @@ void launch_pol_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
         int nt = (h.ni[q] + TT - 1) / TT;
         maxt = std::max(maxt, nt * nt);
     }
+    record_kernel_event(d, MSGW_OP_POLARIZATION, false, s);
     MSGW_LAUNCH(k_pol_fp64, dim3(maxt, h.ntau, nq), dim3(256), 0, s, d, q0,
                        (const double2*)M, G, (double2*)P);
     MSGW_HIP(hipGetLastError());
+    record_kernel_event(d, MSGW_OP_POLARIZATION, true, s);
 }
 
 void launch_sig_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
@@ -239,9 +245,11 @@ void launch_sig_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
             maxt = std::max(maxt, int(ceil_div(h.ni[q], TT) * ceil_div(Kk, TT)));
         }
     if (int64_t(nq) * h.nk > 65535) throw Error(MSGW_ENOTSUP, "self_energy: nq * nk must be <= 65535");
+    record_kernel_event(d, MSGW_OP_SELF_ENERGY, false, s);
     MSGW_LAUNCH(k_sig_fp64, dim3(maxt, h.ntau, nq * h.nk), dim3(256), 0, s, d, q0,
                        (const double2*)M, G, (const double2*)W, (double*)Sig);
     MSGW_HIP(hipGetLastError());
+    record_kernel_event(d, MSGW_OP_SELF_ENERGY, true, s);
 }
 
 void launch_sig_full_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,

@@ -2065,9 +2065,11 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
                         t0, ntc, nt_eff);
         }, rows);
     };
+    record_kernel_event(d, MSGW_OP_POLARIZATION, false, s);
     if (n3 > 0) launch(k_polz<OCC, KS, WI, 3, NBUF, PR>, 0, n3);
     if (rest == 1) launch(k_polz<OCC, KS, WI, 1, NBUF, PR>, 96 * n3, 1);
     if (rest == 2) launch(k_polz<OCC, KS, WI, 2, NBUF, PR>, 96 * n3, 1);
+    record_kernel_event(d, MSGW_OP_POLARIZATION, true, s);
 }
 
 // pair-space self-energy: needs only the raw W~ (FP64), so it runs its own conversions
@@ -2108,9 +2110,11 @@ void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
                     (const float2*)mt, (const uint32_t*)wz, (double*)Sig, nkc, t0, ntc);
         MSGW_HIP(hipGetLastError());
     };
+    record_kernel_event(d, MSGW_OP_SELF_ENERGY, false, s);
     if (n3 > 0) launch(k_sigz<1, 3, PR>, 0, n3);
     if (rest == 1) launch(k_sigz<1, 1, PR>, 96 * n3, 1);
     if (rest == 2) launch(k_sigz<1, 2, PR>, 96 * n3, 1);
+    record_kernel_event(d, MSGW_OP_SELF_ENERGY, true, s);
 }
 
 template <int T, int SR = 4, int SC = 8, int OCC = 1>

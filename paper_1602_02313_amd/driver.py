@@ -72,31 +72,56 @@ class SynthM:
 
 
 class EventTimer:
-    """HIP events recorded around each library call on the launch stream."""
+    """HIP events recorded around each library call on the launch stream.
 
-    def __init__(self, stream=None):
+    With ctx given, the polarization and self-energy calls also get a pair of events that the library
+    records around their contraction kernels alone (msgw_set_kernel_events), on the same stream."""
+
+    KERNEL_OPS = {"polarization": L.OP_POLARIZATION, "self_energy": L.OP_SELF_ENERGY}
+
+    def __init__(self, stream=None, ctx=None):
         import torch
         self.torch = torch
         self.stream = stream
+        self.ctx = ctx
         self.events = defaultdict(list)
+        self.kernel_events = defaultdict(list)
 
     @contextlib.contextmanager
     def __call__(self, name):
         T = self.torch
         st = self.stream if self.stream is not None else T.cuda.current_stream()
         a, b = T.cuda.Event(enable_timing=True), T.cuda.Event(enable_timing=True)
+        op = self.KERNEL_OPS.get(name) if self.ctx is not None else None
+        if op is not None:
+            ka, kb = T.cuda.Event(enable_timing=True), T.cuda.Event(enable_timing=True)
+            ka.record(st)  # creates the events; the library records them again around its kernels
+            kb.record(st)
+            self.ctx.set_kernel_events(op, ka, kb)
         a.record(st)
-        yield
-        b.record(st)
+        try:
+            yield
+        finally:
+            b.record(st)
+            if op is not None:
+                self.ctx.set_kernel_events(op)
         self.events[name].append((a, b))
+        if op is not None:
+            self.kernel_events[name].append((ka, kb))
 
     def reset(self):
         self.events.clear()
+        self.kernel_events.clear()
 
     def summary(self):
         """name -> list of durations in ms (synchronises)."""
         self.torch.cuda.synchronize()
         return {k: [a.elapsed_time(b) for a, b in v] for k, v in self.events.items()}
+
+    def kernel_summary(self):
+        """name -> list of durations in ms of the contraction kernels alone (synchronises)."""
+        self.torch.cuda.synchronize()
+        return {k: [a.elapsed_time(b) for a, b in v] for k, v in self.kernel_events.items()}
 
 
 class GWRun:
@@ -224,21 +249,29 @@ class GWRun:
             ctx.sigma_x(q0, nq, M, self.m_dtype, self.G_tau, self.v[self.vpre[q0]:], self.sig_x,
                         stream=st)
 
-    def sigma_pass(self, M_source, keep_W=False):
-        """Sigma^c(tau), Sigma^x and Sigma^c(i w) from the current G (all q)."""
+    def begin_pass(self):
+        """Zero the accumulated Sigma^c(tau), Sigma^x (and the screens' flags) before the q blocks."""
         self.sig_tau.zero_()
         self.sig_x.zero_()
         if self.W_frozen is None:  # with W~ frozen (GW0) the flags of its pass stay
             self.screen_flags.zero_()
+
+    def sigma_to_iw(self):
+        """Sigma^c(tau) -> Sigma^c(i w) after the last q block of a pass."""
+        if self.sigma_mode == L.SIGMA_DIAG:
+            with self._t("tau_to_iw_sigma"):
+                self.ctx.tau_to_iw(L.FERMION, self.nk * self.nbmax, 1, self.sig_tau, 0, None,
+                                   self.sig_iw, stream=self.stream)
+
+    def sigma_pass(self, M_source, keep_W=False):
+        """Sigma^c(tau), Sigma^x and Sigma^c(i w) from the current G (all q)."""
+        self.begin_pass()
         keep = {} if keep_W else None
         for q0, nq in self._batches():
             self.q_block(M_source, q0, nq, keep=keep)
         if keep_W:
             self.W_frozen = keep
-        if self.sigma_mode == L.SIGMA_DIAG:
-            with self._t("tau_to_iw_sigma"):
-                self.ctx.tau_to_iw(L.FERMION, self.nk * self.nbmax, 1, self.sig_tau, 0, None,
-                                   self.sig_iw, stream=self.stream)
+        self.sigma_to_iw()
 
     def dyson(self, search=True):
         with self._t("dyson"):

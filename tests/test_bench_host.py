@@ -1,4 +1,4 @@
-"""Host logic of bench.py (no GPU): the dense flop model and the use of the counter record."""
+"""Host logic of bench.py (no GPU): the flop models, the iteration slicing and the counter record."""
 import json
 import os
 import sys
@@ -35,23 +35,59 @@ def test_flop_model_uneven_counts():
     assert fp == ref
 
 
-def test_counter_record_is_used_only_when_it_matches():
-    """The committed record matches its kernel source; any other workload, precision, q batch or
-    tile gives no record."""
-    path = os.path.join(ROOT, "profiles", "traffic_c2_bf16x3.json")
-    with open(path) as f:
-        rec = json.load(f)
+def test_executed_mfma_model_closed_form():
+    """Uniform shapes, 16-row polarization blocks: ceil(NI/16)(ceil(NI/16)+1)/2 working blocks of
+    8 waves x (N_k K_pad / 16) steps x 6 MFMAs per 32-wide tau tile; the self-energy: N_k ceil(K/512)
+    chunks of 8 waves x (8x8-pair upper-triangle blocks) x 8 steps x 6 MFMAs per tau tile."""
+    cfg = gi.C5
+    prob = gi.make_problem(cfg)
+    NI, nb, nk, ntau = int(prob.ni[0]), int(prob.nb[0]), cfg.nk, prob.tau.size
+    K = nb * nb
+    tiles = -(-ntau // 32)
+    b16 = -(-NI // 16)
+    want_p = b16 * (b16 + 1) // 2 * 8 * (nk * (-(-K // 64) * 64) // 16) * 6 * tiles * 32768
+    got_p = bench.executed_mfma_flops(prob, 0, "pair-space 16x16 pairs K64 st4x8 3-buffer", 0, 1)
+    assert got_p == want_p
+    b8 = -(-NI // 8)
+    want_s = nk * (-(-K // 512)) * 8 * (b8 * (b8 + 1) // 2) * 8 * 6 * tiles * 32768
+    assert bench.executed_mfma_flops(prob, 1, bench.SIGZ_NAME, 0, 1) == want_s
+    # two q cost twice one; a tile form has no model
+    assert bench.executed_mfma_flops(prob, 1, bench.SIGZ_NAME, 3, 2) == 2 * want_s
+    assert bench.executed_mfma_flops(prob, 0, "WI2 WJ2 T2", 0, 1) is None
+    # the executed 16-bit work against the dense count of the flop model: about 3 x 3/4 (three split
+    # products, real weight against complex pairs of the upper triangle) plus tau padding
+    fp, fs = bench.flop_model(prob, qs=[0])
+    assert 0.8 < got_p / fp < 1.0 and 0.8 < want_s / fs < 1.0
+
+
+def test_iteration_slices_and_batches():
+    for nk, steps in ((125, 20), (64, 20), (8, 3), (125, 125), (7, 1)):
+        sl = bench.iteration_slices(nk, steps)
+        assert len(sl) == steps and sl[0][0] == 0 and sl[-1][1] == nk
+        assert all(a < b for a, b in sl) and all(sl[i][1] == sl[i + 1][0] for i in range(steps - 1))
+        for a, b in sl:
+            for qmax in (1, 3, 8):
+                bs = bench.sub_batches(a, b, qmax)
+                assert bs[0][0] == a and sum(n for _, n in bs) == b - a
+                assert all(1 <= n <= qmax for _, n in bs)
+                assert max(n for _, n in bs) - min(n for _, n in bs) <= 1
+
+
+def test_traffic_record_is_used_only_when_it_matches(tmp_path):
     import hashlib
-    qb = rec["q_batch"]
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        current = hashlib.sha256(f.read()).hexdigest() == rec["source_sha256"]
-    for kernel, k in rec["kernels"].items():
-        got = bench.measured_record(kernel, k["tile"], "bf16x3", "c2_k64_nb64_ni400", qb)
-        if not current:  # the kernel source changed since the counters were taken
-            assert got is None
-            continue
-        assert got is not None and got["traffic_bytes"] == k["traffic_bytes"]
-        assert bench.measured_record(kernel, k["tile"], "fp32", "c2_k64_nb64_ni400", qb) is None
-        assert bench.measured_record(kernel, k["tile"], "bf16x3", "c1_k8_nb16_ni64", qb) is None
-        assert bench.measured_record(kernel, k["tile"], "bf16x3", "c2_k64_nb64_ni400", qb + 1) is None
-        assert bench.measured_record(kernel, k["tile"] + " other", "bf16x3", "c2_k64_nb64_ni400", qb) is None
+    src = os.path.join("paper_1602_02313_amd", "csrc", "k_mfma.hip")
+    with open(os.path.join(ROOT, src), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    rec = {"workload": "c5_k125_nb128_ni700_scgw", "precision": "f16x3", "source": src,
+           "source_sha256": sha, "kernels": {"polarization": {"tile": "t", "bytes_per_q": 5.0}}}
+    path = tmp_path / "rec.json"
+    path.write_text(json.dumps(rec))
+    ok = bench.traffic_record("polarization", "t", "f16x3", "c5_k125_nb128_ni700_scgw", str(path))
+    assert ok is not None and ok["bytes_per_q"] == 5.0
+    assert bench.traffic_record("polarization", "t", "bf16x3", "c5_k125_nb128_ni700_scgw", str(path)) is None
+    assert bench.traffic_record("polarization", "u", "f16x3", "c5_k125_nb128_ni700_scgw", str(path)) is None
+    assert bench.traffic_record("self_energy", "t", "f16x3", "c5_k125_nb128_ni700_scgw", str(path)) is None
+    assert bench.traffic_record("polarization", "t", "f16x3", "c2_k64_nb64_ni400", str(path)) is None
+    rec["source_sha256"] = "0" * 64                     # the kernel source changed since the counters
+    path.write_text(json.dumps(rec))
+    assert bench.traffic_record("polarization", "t", "f16x3", "c5_k125_nb128_ni700_scgw", str(path)) is None
