@@ -220,6 +220,25 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
                const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
                double* G_tau, double* n_out, int* flags);
 
+/* f3. Dyson update with off-diagonal band matrices, the generalisation of the diagonal approximation
+ * (eqs. dysongf, zxjk, zcjk with Sigma_nn', solved on the fermionic axis):
+ *   H0(k) = diag(eps_k) + Sigma_static(k);  G(k, i w_n) = [(i w_n + mu) 1 - H0(k) - Sigma^c(k, i w_n)]^-1
+ *   over the bands n < Nb_k, inverted in FP64 (Gauss-Jordan with partial pivoting);
+ *   with D = G - diag(1 / (i w - E_jj)), E_jj = Re H0_jj - mu:
+ *   N(mu) = sum_k [sum_j n_F(E_jj) + (2/beta) sum_n Re Tr D(i w_n)],
+ *   G(tau) = diag(G0(E_jj, tau)) + (1/beta) sum_n [e^{-i w_n tau} D_n + e^{i w_n tau} D_n^H]
+ *   (negative frequencies D(-i w) = D(i w)^H, as for a Hermitian Sigma(tau)).
+ * MSGW_MU_SEARCH: mu by 64 fixed bisection rounds on the Gershgorin bracket of H0 widened by 50/beta
+ * (a fixed sequence of launches); MSGW_MU_FIXED: mu read from *mu.
+ * eps f64 [nk][nbmax]; sigma_static c128 [nk][nbmax][nbmax] (e.g. the FULL Sigma^x); Sigma_c_iw c128
+ * [nk][nbmax][nbmax][niw_f] (the FULL Sigma^c(tau) through msgw_tau_to_iw); G_iw c128
+ * [nk][nbmax][nbmax][niw_f]; G_tau c128 [nk][nbmax][nbmax][ntau]; mu, n_out device f64; flags device int
+ * (MSGW_FLAG_NAN for non-finite input or an exactly singular matrix, MSGW_FLAG_NOBRACKET).  nbmax <= 64
+ * (MSGW_ENOTSUP).  Uses the workspace's scratch. */
+int msgw_dyson_matrix(msgw_ctx* c, void* stream, const double* eps, const void* sigma_static,
+                      const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
+                      void* G_tau, double* n_out, int* flags);
+
 /* For callers that cannot allocate device memory at the time of the call (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): msgw_dyson with the same arguments,
  * results and errors, whose per-call scratch (the E array and the mu search state) lives in a static

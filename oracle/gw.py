@@ -393,6 +393,101 @@ def dyson(eps, nb, sig_static, sigc_iw, beta, tau, n_target, mu0=0.0,
     return dict(mu=mu, N=N, G_iw=G_iw, G_tau=G_tau, E=E)
 
 
+def iw_to_tau_fermion_matrix(D, tau, beta):
+    """(1/beta) sum_{n>=0} [e^{-i w_n tau} D_n + e^{+i w_n tau} D_n^H] for band matrices D_n.
+
+    The inverse of eq. trans for a Hermitian-in-tau fermionic matrix function, whose negative
+    frequencies are D(-i w) = D(i w)^H.  D: [..., nb, nb, niw] -> [..., nb, nb, ntau].
+    """
+    D = np.asarray(D)
+    niw = D.shape[-1]
+    w = matsubara(FERMION, niw, beta)
+    ph = np.exp(-1j * np.outer(tau, w))                     # [ntau, niw]
+    DH = np.conj(np.swapaxes(D, -3, -2))
+    return (np.tensordot(D, ph.T, axes=([-1], [0])) + np.tensordot(DH, np.conj(ph).T, axes=([-1], [0]))) / beta
+
+
+def static_bracket(H0, mask, beta):
+    """Bracket of the chemical potential for band matrices: the Gershgorin discs of the static
+    matrices H0 = eps + Sigma_static (each eigenvalue lies within sum_{i != j} |H0_ij| of some
+    diagonal entry H0_jj), widened by 50 / beta on both sides."""
+    lo, hi = np.inf, -np.inf
+    for k in range(H0.shape[0]):
+        n = int(mask[k].sum())
+        A = H0[k, :n, :n]
+        r = np.sum(np.abs(A), axis=1) - np.abs(np.diag(A))
+        d = np.real(np.diag(A))
+        lo, hi = min(lo, float(np.min(d - r))), max(hi, float(np.max(d + r)))
+    return lo - 50.0 / beta, hi + 50.0 / beta
+
+
+def dyson_matrix(eps, nb, sig_static, sigc_iw, beta, tau, n_target, mu0=0.0, search=True,
+                 nsteps=200):
+    """Dyson update of the full band-matrix G: the generalisation of the diagonal approximation to
+    off-diagonal Sigma_nn' (eqs. dysongf, zxjk, zcjk with matrices, solved on the fermionic axis).
+
+    H0(k) = diag(eps_k) + Sigma_static(k); G(k, i w) = [(i w + mu) 1 - H0(k) - Sigma^c(k, i w)]^-1
+    over the bands n < Nb_k.  With the diagonal reference G_ref = diag(1 / (i w - E_jj)),
+    E_jj = H0_jj - mu, and D = G - G_ref:
+      G(tau) = diag(G0(E_jj, tau)) + inverse transform of D (negative frequencies D^H),
+      N(mu) = sum_k [sum_j n_F(E_jj) + (2/beta) sum_n Re Tr D(i w_n)]  (= -sum_k Tr G(beta-)).
+    mu by bisection on the Gershgorin bracket of H0 (static_bracket), as in the diagonal case.
+    eps [nk, nbmax]; sig_static [nk, nbmax, nbmax]; sigc_iw [nk, nbmax, nbmax, niw].
+    Returns dict(mu, N, G_iw [nk, nb, nb, niw], G_tau [nk, nb, nb, ntau]).
+    """
+    nk, nbmax = eps.shape
+    niw = sigc_iw.shape[-1]
+    w = matsubara(FERMION, niw, beta)
+    mask = np.arange(nbmax)[None, :] < np.asarray(nb)[:, None]
+    H0 = np.zeros((nk, nbmax, nbmax), dtype=np.complex128)
+    for k in range(nk):
+        n = int(nb[k])
+        H0[k, :n, :n] = np.diag(eps[k, :n]) + sig_static[k, :n, :n]
+
+    def green(mu):
+        G = np.zeros((nk, nbmax, nbmax, niw), dtype=np.complex128)
+        for k in range(nk):
+            n = int(nb[k])
+            for i in range(niw):
+                A = (1j * w[i] + mu) * np.eye(n) - H0[k, :n, :n] - sigc_iw[k, :n, :n, i]
+                G[k, :n, :n, i] = np.linalg.inv(A)
+        return G
+
+    def number(mu):
+        G = green(mu)
+        tot = 0.0
+        for k in range(nk):
+            n = int(nb[k])
+            E = np.real(np.diag(H0[k, :n, :n])) - mu
+            ref = 1.0 / (1j * w[None, :] - E[:, None])          # [n, niw]
+            trD = np.trace(G[k, :n, :n, :], axis1=0, axis2=1) - ref.sum(axis=0)
+            tot += float(np.sum(fermi(E, beta)) + (2.0 / beta) * np.sum(trD.real))
+        return tot
+
+    if search:
+        lo, hi = static_bracket(H0, mask, beta)
+        for _ in range(nsteps):
+            mid = 0.5 * (lo + hi)
+            if number(mid) < n_target:
+                lo = mid
+            else:
+                hi = mid
+        mu = 0.5 * (lo + hi)
+    else:
+        mu = mu0
+    G_iw = green(mu)
+    G_tau = np.zeros((nk, nbmax, nbmax, tau.size), dtype=np.complex128)
+    for k in range(nk):
+        n = int(nb[k])
+        E = np.real(np.diag(H0[k, :n, :n])) - mu
+        ref = 1.0 / (1j * w[None, :] - E[:, None])
+        D = G_iw[k, :n, :n, :].copy()
+        D[np.arange(n), np.arange(n), :] -= ref
+        G_tau[k, :n, :n, :] = iw_to_tau_fermion_matrix(D, tau, beta)
+        G_tau[k, np.arange(n), np.arange(n), :] += green0_tau(E, tau, beta)
+    return dict(mu=mu, N=number(mu), G_iw=G_iw, G_tau=G_tau)
+
+
 def gap_proxy(eps, nb, sig_static, sigc_iw0, mu, n_target):
     """Matsubara-axis gap proxy: E^QP = eps + Sigma_static + Re Sigma^c(i w_0) - mu,
     sorted over all (n, k); gap = E_(N+1) - E_(N) with N = round(n_target)."""

@@ -32,7 +32,7 @@ EXPORTS = [
     "msgw_screened_tau", "msgw_self_energy", "msgw_sigma_x", "msgw_dyson", "msgw_gap",
     "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant", "msgw_get_variant",
     "msgw_set_k_range", "msgw_continue_pade", "msgw_gap_of", "msgw_set_tau_mirror",
-    "msgw_continue_cpe", "msgw_dyson_noalloc", "msgw_set_kernel_events",
+    "msgw_continue_cpe", "msgw_dyson_noalloc", "msgw_set_kernel_events", "msgw_dyson_matrix",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 
@@ -87,6 +87,7 @@ def load_library():
         "msgw_dyson": [P, P, P, P, P, D, I, P, P, P, P, P],
         "msgw_dyson_noalloc": [P, P, P, P, P, D, I, P, P, P, P, P],
         "msgw_set_kernel_events": [P, I, P, P],
+        "msgw_dyson_matrix": [P, P, P, P, P, D, I, P, P, P, P, P],
         "msgw_gap": [P, P, P, P, P, P, I, P],
         "msgw_synth_M": [P, P, U64, I, I, I, I, P],
     }
@@ -243,6 +244,12 @@ class Context:
         self._check(self.lib.msgw_dyson(self._c, _stream(stream), _ptr(eps), _ptr(sigma_static),
                                         _ptr(Sigma_c_iw), float(n_target), int(mu_mode), _ptr(mu),
                                         _ptr(G_iw), _ptr(G_tau), _ptr(n_out), _ptr(flags)))
+
+    def dyson_matrix(self, eps, sigma_static, Sigma_c_iw, n_target, mu_mode, mu, G_iw, G_tau, n_out,
+                     flags, stream=None):
+        self._check(self.lib.msgw_dyson_matrix(self._c, _stream(stream), _ptr(eps), _ptr(sigma_static),
+                                               _ptr(Sigma_c_iw), float(n_target), int(mu_mode), _ptr(mu),
+                                               _ptr(G_iw), _ptr(G_tau), _ptr(n_out), _ptr(flags)))
 
     def dyson_noalloc(self, eps, sigma_static, Sigma_c_iw, n_target, mu_mode, mu, G_iw, G_tau, n_out,
                       flags, stream=None):

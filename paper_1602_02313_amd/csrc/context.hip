@@ -559,6 +559,26 @@ int msgw_dyson(msgw_ctx* c, void* stream, const double* eps, const double* sigma
     });
 }
 
+int msgw_dyson_matrix(msgw_ctx* c, void* stream, const double* eps, const void* sigma_static,
+                      const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
+                      void* G_tau, double* n_out, int* flags) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(eps && sigma_static && Sigma_c_iw && mu && G_iw && G_tau && n_out && flags, MSGW_EINVAL,
+             "null pointer");
+        need(mu_mode == MSGW_MU_FIXED || mu_mode == MSGW_MU_SEARCH, MSGW_EINVAL, "bad mu_mode");
+        need(std::isfinite(n_target) && n_target >= 0, MSGW_EINVAL, "bad n_target");
+        need(c->h.nbmax <= 64, MSGW_ENOTSUP, "msgw_dyson_matrix: at most 64 bands (one matrix in LDS)");
+        need(int64_t(c->h.nk) <= 65535 && c->h.niw_f <= 65535, MSGW_ENOTSUP, "msgw_dyson_matrix: grid limits");
+        need(mdyson_scratch_bytes(c->h) <= scratch_mfma_bytes(c->d, c->h), MSGW_ENOMEM,
+             "msgw_dyson_matrix: workspace too small");
+        c->prep = msgw_ctx::Prepared();  // uses the split-precision scratch
+        launch_dyson_matrix(c->d, c->h, S(stream), eps, (const double2*)sigma_static, (const double2*)Sigma_c_iw,
+                            n_target, mu_mode == MSGW_MU_SEARCH, mu, (double2*)G_iw, (double2*)G_tau, n_out,
+                            flags, reinterpret_cast<double*>(scratch_mfma(c->d, c->h)));
+    });
+}
+
 int msgw_dyson_noalloc(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
                        const void* Sigma_c_iw, double n_target, int mu_mode, double* mu, void* G_iw,
                        double* G_tau, double* n_out, int* flags) {

@@ -106,6 +106,11 @@ void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, 
 void launch_dyson(const Dev& d, const Host& h, hipStream_t s, const double* eps,
                   const double* sstat, const void* sigc, double n_target, int search, double* mu,
                   void* G_iw, double* G_tau, double* n_out, int* flags, double* E, double* st);
+// matrix Dyson (off-diagonal Sigma_nn'): scratch of 8 + nk * niw_f doubles
+size_t mdyson_scratch_bytes(const Host& h);
+void launch_dyson_matrix(const Dev& d, const Host& h, hipStream_t s, const double* eps, const double2* S0,
+                         const double2* Sc, double n_target, int search, double* mu, double2* G_iw,
+                         double2* G_tau, double* n_out, int* flags, double* scratch);
 // bytes of the static scratch of msgw_dyson_noalloc, and its device address on `device` (looked up
 // once per device, with that device made current for the lookup)
 constexpr size_t kNoAllocScratchBytes = size_t(1) << 20;

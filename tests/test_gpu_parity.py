@@ -354,3 +354,78 @@ def test_validation_errors(torch):
     assert e.value.code == -1
     with pytest.raises(amd.MsgwError):
         run.ctx.polarization(0, 1, run.P_tau, amd.C128, run.G_tau, 7, run.P_tau)
+
+
+# ---------------------------------------------------------------------------------------------
+# Dyson update with off-diagonal band matrices
+# ---------------------------------------------------------------------------------------------
+def _matrix_inputs(prob, cfg, seed):
+    """A Hermitian static matrix and a causal matrix self-energy B / (i w - p), B Hermitian >= 0."""
+    rng = np.random.default_rng(seed)
+    nk, nb, niw = cfg.nk, int(prob.nb.max()), cfg.niw_f
+    w = o.matsubara(o.FERMION, niw, cfg.beta)
+    S0 = np.zeros((nk, nb, nb), dtype=complex)
+    S = np.zeros((nk, nb, nb, niw), dtype=complex)
+    for k in range(nk):
+        n = int(prob.nb[k])
+        A = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        S0[k, :n, :n] = 0.04 * (A + A.conj().T)
+        B = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+        B = 0.05 * (B @ B.conj().T) / n
+        S[k, :n, :n] = B[:, :, None] / (1j * w[None, None, :] - rng.uniform(-0.4, 0.4))
+    return S0, S
+
+
+def _run_matrix_dyson(torch, run, S0, S, n_target, mode=1, mu0=0.0):
+    dev = run.device
+    nk, nb = S0.shape[:2]
+    G_iw = torch.empty((nk, nb, nb, run.niw_f), dtype=torch.complex128, device=dev)
+    G_tau = torch.empty((nk, nb, nb, run.ntau), dtype=torch.complex128, device=dev)
+    mu = torch.full((1,), mu0, dtype=torch.float64, device=dev)
+    N = torch.zeros(1, dtype=torch.float64, device=dev)
+    flags = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    run.ctx.dyson_matrix(run.eps, torch.from_numpy(S0).to(dev), torch.from_numpy(S).to(dev), n_target, mode,
+                         mu, G_iw, G_tau, N, flags)
+    torch.cuda.synchronize()
+    return dict(mu=float(mu.item()), N=float(N.item()), flags=int(flags.item()), G_iw=np_(G_iw), G_tau=np_(G_tau))
+
+
+@pytest.mark.parametrize("cfg", [SMALL, UNEVEN])
+def test_dyson_matrix(torch, cfg):
+    prob, run = make_run(cfg)
+    S0, S = _matrix_inputs(prob, cfg, 3)
+    got = _run_matrix_dyson(torch, run, S0, S, prob.n_target)
+    ref = o.dyson_matrix(prob.eps, prob.nb, S0, S, cfg.beta, prob.tau, prob.n_target)
+    e_iw, e_tau = rel(got["G_iw"], ref["G_iw"]), rel(got["G_tau"], ref["G_tau"])
+    print(f"{cfg.name}: G(i w) rel {e_iw:.2e}, G(tau) rel {e_tau:.2e}, mu {got['mu']:.15f} ({ref['mu']:.15f}), "
+          f"N {got['N']:.12f} ({ref['N']:.12f}), flags {got['flags']}")
+    assert got["flags"] == 0
+    assert e_iw < TOL and e_tau < TOL
+    assert abs(got["N"] - ref["N"]) < 1e-10 * ref["N"]
+    # fixed mu: the oracle's mu given back
+    fix = _run_matrix_dyson(torch, run, S0, S, prob.n_target, mode=0, mu0=ref["mu"])
+    assert rel(fix["G_tau"], ref["G_tau"]) < TOL and fix["flags"] == 0
+
+
+def test_dyson_matrix_after_full_self_energy(torch):
+    """The FULL-mode pass (Sigma^c_nn'(tau), Sigma^x_nn') -> Sigma^c(i w) -> matrix Dyson, against the
+    oracle's chain; with Sigma diagonal the matrix Dyson is the diagonal one."""
+    import paper_1602_02313_amd as amd
+    cfg = SMALL
+    prob, run = make_run(cfg, sigma_mode=amd.SIGMA_FULL, q_batch=cfg.nk)
+    g, src = host_M(cfg, amd.C128)
+    run.green0(0.0)
+    run.sigma_pass(src)
+    nk, nb = cfg.nk, run.nbmax
+    Sc_iw = torch.empty((nk, nb, nb, cfg.niw_f), dtype=torch.complex128, device="cuda")
+    run.ctx.tau_to_iw(amd.FERMION, nk * nb * nb, 1, run.sig_tau, 1, None, Sc_iw)
+    torch.cuda.synchronize()
+    G = oracle_G(prob)
+    res = o.gw_pass(prob, g, G, full=True)
+    sc_iw = np.moveaxis(o.tau_to_iw(np.moveaxis(res["sigc_tau"], -1, 0), prob.tau, cfg.beta, o.FERMION,
+                                    cfg.niw_f), 0, -1)
+    ref = o.dyson_matrix(prob.eps, prob.nb, res["sigx"], sc_iw, cfg.beta, prob.tau, prob.n_target)
+    got = _run_matrix_dyson(torch, run, np_(run.sig_x), np_(Sc_iw), prob.n_target)
+    e = rel(got["G_tau"], ref["G_tau"])
+    print(f"FULL chain: G(tau) rel {e:.2e}, mu {got['mu']:.12f} ({ref['mu']:.12f})")
+    assert e < TOL and got["flags"] == 0

@@ -823,3 +823,103 @@ def test_planted_gap_proxy_index_slip_is_caught():
     ref = o.gap_proxy(eps, nb, stat, sc0, 0.0, 2.0)
     assert ref == pytest.approx(0.10 - (-0.30), abs=1e-14)
     assert abs(slipped(eps, nb, stat, sc0, 0.0, 2.0) - ref) > 0.01
+
+
+# ---------------------------------------------------------------------------
+# Dyson equation with off-diagonal band matrices
+# ---------------------------------------------------------------------------
+def _hermitian(rng, n, scale):
+    A = rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))
+    return 0.5 * scale * (A + A.conj().T)
+
+
+def test_dyson_matrix_reduces_to_the_diagonal_dyson():
+    cfg = gi.tiny(grid=(2, 1, 1), nocc=2, nemp=2, beta=15.0, ntau=20, niw=64)
+    p = gi.make_problem(cfg)
+    rng = np.random.default_rng(4)
+    w = o.matsubara(o.FERMION, cfg.niw_f, cfg.beta)
+    stat = rng.uniform(-0.1, 0.1, size=p.eps.shape)
+    sig = 0.2 / (1j * w[None, None, :] - rng.uniform(-0.5, 0.5, size=p.eps.shape + (1,)))
+    d = o.dyson(p.eps, p.nb, stat, sig, cfg.beta, p.tau, p.n_target)
+    nk, nb = p.eps.shape
+    S0 = np.zeros((nk, nb, nb), dtype=complex)
+    S = np.zeros((nk, nb, nb, cfg.niw_f), dtype=complex)
+    for k in range(nk):
+        S0[k] = np.diag(stat[k])
+        for n in range(nb):
+            S[k, n, n] = sig[k, n]
+    m = o.dyson_matrix(p.eps, p.nb, S0, S, cfg.beta, p.tau, p.n_target)
+    assert m["mu"] == pytest.approx(d["mu"], abs=1e-12)
+    assert abs(m["N"] - d["N"]) < 1e-10
+    diag = np.einsum("knnt->knt", m["G_tau"])
+    assert np.abs(diag - d["G_tau"]).max() < 1e-12
+    off = m["G_tau"] - np.einsum("knt,nm->knmt", diag, np.eye(nb))
+    assert np.abs(off).max() < 1e-14
+
+
+def _static_case(niw, seed=8):
+    beta, nb = 12.0, 4
+    rng = np.random.default_rng(seed)
+    eps = np.array([[-0.6, -0.2, 0.3, 0.8]])
+    S0 = _hermitian(rng, nb, 0.15)[None]                       # complex off-diagonal coupling
+    tau = np.linspace(0.0, beta, 25)
+    return beta, nb, eps, S0, tau, np.zeros((1, nb, nb, niw), dtype=complex)
+
+
+def test_dyson_matrix_static_closed_form():
+    """Static Hermitian Sigma: G(k, i w) = V diag(1 / (i w + mu - lambda)) V^H and
+    G(tau) = V diag(G0(lambda - mu, tau)) V^H with H0 = V diag(lambda) V^H (textbook), the tau
+    side within the O(1/niw) truncation of the Matsubara sum (error falls ~4x for 4x niw), and
+    mu placing sum_j n_F(lambda_j - mu) at the target within that truncation."""
+    errs = []
+    for niw in (256, 1024):
+        beta, nb, eps, S0, tau, S = _static_case(niw)
+        H0 = np.diag(eps[0]) + S0[0]
+        lam, V = np.linalg.eigh(H0)
+        n_target = 2.3
+        m = o.dyson_matrix(eps, np.array([nb]), S0, S, beta, tau, n_target)
+        mu = m["mu"]
+        w = o.matsubara(o.FERMION, niw, beta)
+        Gex = np.einsum("ij,jn,kj->ikn", V, 1.0 / (1j * w[None, :] + mu - lam[:, None]), V.conj())
+        assert np.abs(m["G_iw"][0] - Gex).max() < 1e-13
+        Gt = np.einsum("ij,jt,kj->ikt", V, o.green0_tau(lam - mu, tau, beta), V.conj())
+        errs.append((np.abs(m["G_tau"][0] - Gt).max(), abs(o.fermi(lam - mu, beta).sum() - n_target)))
+    (e1, n1), (e2, n2) = errs
+    assert e2 < 2e-4 and 3.0 < e1 / e2 < 5.0, errs
+    assert n2 < 1e-3 and n1 / n2 > 3.0, errs
+
+
+def test_dyson_matrix_jump_sum_rule_and_hermiticity():
+    beta, nb, eps, S0, tau, _ = _static_case(128)
+    niw = 128
+    w = o.matsubara(o.FERMION, niw, beta)
+    rng = np.random.default_rng(2)
+    # a causal matrix self-energy B / (i w - p) with B Hermitian positive: Sigma(-i w) = Sigma(i w)^H
+    Bm = _hermitian(rng, nb, 0.1)
+    Bm = Bm @ Bm.conj().T
+    S = (Bm[:, :, None] / (1j * w[None, None, :] - 0.35))[None]
+    m = o.dyson_matrix(eps, np.array([nb]), S0, S, beta, tau, 2.0)
+    G = m["G_tau"][0]
+    assert np.abs(G[:, :, 0] + G[:, :, -1] + np.eye(nb)).max() < 1e-13     # G(0+) + G(beta-) = -1
+    assert abs(-np.trace(G[:, :, -1]).real - m["N"]) < 1e-10               # N = -Tr G(beta-)
+    assert m["N"] == pytest.approx(2.0, abs=1e-9)
+    assert np.abs(G - np.conj(np.swapaxes(G, 0, 1))).max() < 1e-13       # Hermitian at every tau
+
+
+def test_planted_dyson_matrix_transpose_is_caught():
+    """D^T instead of D^H at the negative frequencies (a plausible slip) breaks the static closed form."""
+    beta, nb, eps, S0, tau, S = _static_case(256)
+    m = o.dyson_matrix(eps, np.array([nb]), S0, S, beta, tau, 2.3)
+    H0 = np.diag(eps[0]) + S0[0]
+    lam, V = np.linalg.eigh(H0)
+    Gt = np.einsum("ij,jt,kj->ikt", V, o.green0_tau(lam - m["mu"], tau, beta), V.conj())
+    D = m["G_iw"][0].copy()
+    E = np.real(np.diag(H0)) - m["mu"]
+    w = o.matsubara(o.FERMION, 256, beta)
+    D[np.arange(nb), np.arange(nb), :] -= 1.0 / (1j * w[None, :] - E[:, None])
+    ph = np.exp(-1j * np.outer(tau, w))
+    bad = (np.tensordot(D, ph.T, axes=([-1], [0]))
+           + np.tensordot(np.swapaxes(D, 0, 1), np.conj(ph).T, axes=([-1], [0]))) / beta
+    bad[np.arange(nb), np.arange(nb), :] += o.green0_tau(E, tau, beta)
+    good_err, bad_err = np.abs(m["G_tau"][0] - Gt).max(), np.abs(bad - Gt).max()
+    assert good_err < 1e-3 and bad_err > 10 * good_err, (good_err, bad_err)
