@@ -16,7 +16,8 @@
 //           even), and x.y ~ hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 with FP32
 //           accumulation; the dropped lo.lo term is ~2^-16 relative.
 // The FP32 accumulators of the polarization are flushed into the FP64 output every FLUSH_STEPS
-// K-steps, so an FP32 sum never runs over more than 4096 complex terms.
+// K-steps, so an FP32 sum never runs over more than 4096 complex terms (the pair-space polarization:
+// GZ_FLUSH terms).
 //
 // The split-BF16 defaults are the pair-space kernels (k_polz, k_sigz; 32x32x16 MFMA, operands staged
 // through LDS by 8-wave work-groups; see their sections below).  The tile forms: polarization, one
@@ -1105,6 +1106,11 @@ __global__ __launch_bounds__(256, OCC) void k_sig7(Dev d, int q0, const float2* 
 constexpr int GZ_T = 96;   // tau columns per work-group (three 32-wide MFMA tiles)
 constexpr int GZ_KS = 32;  // K per stage (default)
 constexpr int GZ_KPAD = 64;  // the g planes are padded in K to a multiple of the largest stage
+// K terms summed in the FP32 accumulators between two flushes into the FP64 P.  The FP32 rounding of
+// these sums dominates the split precisions' error: flushing every 16384 terms instead would save 11%
+// of the kernel's time at NI = 700, but raised P's error 2-4x (1.3e-7 -> 4.5e-7 at the NI = 400 block
+// shapes, which the screen amplifies ~5x into W~ and Sigma).
+constexpr int GZ_FLUSH = 4096;
 
 // g planes of q0..q0+nq-1: for each (q, k) two bf16 planes [TP][KP], TP = Ntau rounded up to GZ_T,
 // KP = K rounded up to GZ_KPAD
@@ -1566,7 +1572,7 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         first = false;
     };
 
-    // stages run over (k, slab); the FP32 accumulators go to FP64 every 4096 terms
+    // stages run over (k, slab); the FP32 accumulators go to FP64 every GZ_FLUSH terms
     // k blocks [kb0, kb1) (all of them unless a partial range is set); a range that starts past k = 0
     // adds to P
     const int kend = d.kb1;
@@ -1608,7 +1614,7 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
             const int nb1 = buf == NBUF - 1 ? 0 : buf + 1, nb2 = nb1 == NBUF - 1 ? 0 : nb1 + 1;
             compute_stage3(buf, nb1, z0);
             since += KS;
-            if (since >= 4096 || !e1) {
+            if (since >= GZ_FLUSH || !e1) {
                 flush();
                 since = 0;
             }
@@ -1640,7 +1646,7 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         if (more) gload(b2, s2);
         compute_stage(buf);
         since += KS;
-        if (since >= 4096 || !more) {
+        if (since >= GZ_FLUSH || !more) {
             flush();
             since = 0;
         }
@@ -1667,6 +1673,9 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
 // blocks of 8 I x 8 J pairs (upper triangle of blocks), stored as bf16 hi/lo planes; a work-group
 // keeps one weight block in LDS at a time and all its waves reuse it for 64 rows K each.
 constexpr int SZ_WR = 64 + 4;  // LDS row stride of a weight block (u32): 8 steps x 8 pairs + pad
+// weight blocks between two epilogues (32 blocks: 4096 terms per FP32 accumulator; 128 blocks would
+// save 3.6% of the time at NI = 700 but double Sigma's error at the full shapes)
+constexpr int SZ_FLUSH_BLOCKS = 32;
 
 __device__ __host__ __forceinline__ int sz_nb8(int ni) { return (ni + 7) / 8; }
 __device__ __host__ __forceinline__ int64_t sz_blocks(int ni) {
@@ -1757,8 +1766,8 @@ __global__ __launch_bounds__(256) void k_wpair(const double2* __restrict__ W, in
 // each block (48 KB, hi and lo) is staged through LDS (double-buffered) while the previous one is
 // used.  Every lane forms Z for its rows K and 4 pairs per MFMA step from the transposed FP32 M
 // (the 8 values a_I of the block row stay in registers across the block row), splits it into
-// bf16 hi/lo, and the FP32 accumulators go through the epilogue (G_m weight, sum over the m of each
-// band n, FP64 atomic) every 32 blocks.
+// hi/lo halves (bf16 or f16), and the FP32 accumulators go through the epilogue (G_m weight, sum over
+// the m of each band n, FP64 atomic) every SZ_FLUSH_BLOCKS blocks.
 template <int OCC, int NTT, int PR = PREC_BF16X3>
 __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* __restrict__ G,
                                                    const float2* __restrict__ mt,
@@ -1902,9 +1911,10 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
     __syncthreads();
     int buf = 0;
     int64_t b = 0;
-    // blocks in runs of 32 (4096 terms per FP32 accumulator), each run followed by the epilogue
+    // blocks in runs of SZ_FLUSH_BLOCKS (128 terms each per FP32 accumulator), each run followed by the
+    // epilogue
     while (b < nblk) {
-        const int64_t bend = b + 32 < nblk ? b + 32 : nblk;
+        const int64_t bend = b + SZ_FLUSH_BLOCKS < nblk ? b + SZ_FLUSH_BLOCKS : nblk;
         for (; b < bend; ++b) {
             int bi2 = bi, bj2 = bj + 1;
             if (bj2 >= nb) {
