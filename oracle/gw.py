@@ -393,6 +393,117 @@ def dyson(eps, nb, sig_static, sigc_iw, beta, tau, n_target, mu0=0.0,
     return dict(mu=mu, N=N, G_iw=G_iw, G_tau=G_tau, E=E)
 
 
+# ---------------------------------------------------------------------------
+# the paper's own tau-domain solvers (cross-checks of the Matsubara-axis forms)
+# ---------------------------------------------------------------------------
+def spline_eval(tau, f, x):
+    """The not-a-knot cubic spline of f (mesh tau, axis 0) evaluated at points x in [tau_0, tau_N]."""
+    tau = np.asarray(tau, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    a, b, c, d = spline_not_a_knot(tau, f)
+    i = np.clip(np.searchsorted(tau, x, side="right") - 1, 0, tau.size - 2)
+    t = (x - tau[i]).reshape(x.shape + (1,) * (np.ndim(f) - 1))
+    return a[i] + t * (b[i] + t * (c[i] + t * d[i]))
+
+
+def trapezoid_increments(tau):
+    """The paper's increments of the tau-domain linear systems: (tau_{i+1} - tau_{i-1}) / 2 inside,
+    (tau_1 - tau_0) / 2 and (tau_M - tau_{M-1}) / 2 at the ends ("Screened Coulomb potential")."""
+    tau = np.asarray(tau, dtype=np.float64)
+    d = np.empty_like(tau)
+    d[1:-1] = 0.5 * (tau[2:] - tau[:-2])
+    d[0] = 0.5 * (tau[1] - tau[0])
+    d[-1] = 0.5 * (tau[-1] - tau[-2])
+    return d
+
+
+def wt_tau_system(P_tau, v, tau, beta):
+    """W~(q, tau) on the mesh from the paper's tau-domain linear system (eq. tildeW):
+
+        sum_r [delta_pr 1 - A(tau_p - tau_r) dtau_r] W~(tau_r) = A(tau_p) v,   A = v P,
+
+    with the trapezoid increments dtau_r.  A at tau_p - tau_r < 0 is taken at tau_p - tau_r + beta
+    (bosonic periodicity of P), and between mesh points from the not-a-knot cubic spline of P(tau)
+    (the reading of "discretise on the UPM grid": the differences of mesh points are not mesh points).
+    P_tau: [ntau, NI, NI]; v: [NI].  One dense solve of order ntau * NI.  Returns [ntau, NI, NI].
+    """
+    tau = np.asarray(tau, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    N, NI = tau.size, v.size
+    dt = trapezoid_increments(tau)
+    x = tau[:, None] - tau[None, :]
+    x = np.where(x < 0.0, x + beta, x)
+    Px = spline_eval(tau, P_tau, x.reshape(-1)).reshape(N, N, NI, NI)
+    A = v[None, None, :, None] * Px                             # v P(tau_p - tau_r)
+    K = -A * dt[None, :, None, None]                           # [p, r, I, J]
+    K = np.moveaxis(K, 1, 2).reshape(N * NI, N * NI).astype(np.complex128)   # rows (p, I), cols (r, J)
+    K += np.eye(N * NI)
+    rhs = v[None, :, None] * np.asarray(P_tau) * v[None, None, :]   # A(tau_p) v
+    W = np.linalg.solve(K, rhs.reshape(N * NI, NI))
+    return W.reshape(N, NI, NI)
+
+
+def dense_grid(tau, beta):
+    """The uniform grid of the tau-domain Dyson solve: spacing tau_1 - tau_0 (the smallest of a
+    power mesh) from 0 to beta (eq. dysong)."""
+    h = tau[1] - tau[0]
+    n = int(round(beta / h))
+    if abs(n * h - beta) > 1e-9 * beta:
+        raise ValueError("beta is not a multiple of tau_1 - tau_0")
+    return np.linspace(0.0, beta, n + 1)
+
+
+def fermion_kernel(f_of, t, beta, integrate):
+    """The matrix f(t_a - t_b) over a grid t of [0, beta] for a fermionic f known on [0, beta]
+    (f(x) = -f(x + beta) for x < 0), as the integrand of a trapezoid sum over the columns
+    (integrate="cols", the variable is t_b) or over the rows (integrate="rows", the variable is t_a).
+    Where f jumps (x = 0) an interior node takes the mean of the two limits; an end node of the
+    integration range takes the one limit inside the range: at t_a = t_b = 0 the variable lies above
+    the other argument, at t_a = t_b = beta below it.
+    """
+    x = t[:, None] - t[None, :]
+    pos = f_of(np.where(x > 0, x, 0.0))
+    neg = -f_of(np.where(x < 0, x + beta, beta))
+    f0p, f0m = f_of(np.zeros(1))[0], -f_of(np.full(1, beta))[0]      # f(0+), f(0-)
+    out = np.where(x > 0, pos, neg)
+    n = t.size - 1
+    out[np.arange(n + 1), np.arange(n + 1)] = 0.5 * (f0p + f0m)
+    if integrate == "cols":          # variable t_b: at 0 it is above t_a = 0 (x -> 0-), at beta below
+        out[0, 0], out[n, n] = f0m, f0p
+    else:                            # variable t_a: at 0 it is above t_b = 0 (x -> 0+), at beta below
+        out[0, 0], out[n, n] = f0p, f0m
+    return out
+
+
+def dyson_tau(E, dsig, sigc_tau, tau, beta):
+    """G_j(k, tau) of one state from the paper's tau-domain Dyson equation (eqs. dysongf, zxjk, zcjk,
+    dysong): G = G0 + int_0^beta dt2 Z(t, t2) G(t2) with
+
+        Z^x(t, t2) = G0(t - t2) dsig,    Z^c(t, t2) = int_0^beta dt1 G0(t - t1) Sigma^c(t1 - t2),
+
+    solved as sum_r [delta_pr - dt_r Z(t_p, t_r)] G(t_r) = G0(t_p) on the dense uniform grid of
+    spacing tau_1 - tau_0 onto which Sigma^c is splined (not-a-knot).  G0 is the reference Green's
+    function at energy E (from mu), dsig = Sigma^x + Sigma^H - Sigma_0 the static difference; negative
+    arguments use antiperiodicity, and the jumps at zero argument are taken as fermion_kernel states;
+    both the t2 and the t1 integrals use the trapezoid increments of the dense grid.
+    Returns (t_dense, G on t_dense, G at the mesh points tau).
+    """
+    td = dense_grid(tau, beta)
+    n = td.size
+    dt = trapezoid_increments(td)
+    g0 = lambda x: green0_tau(E, np.ravel(x), beta).reshape(np.shape(x))  # noqa: E731
+    sc_d = spline_eval(tau, sigc_tau, td)                       # Sigma^c on the dense grid
+    sc = lambda x: np.interp(x, td, sc_d)                       # noqa: E731 (x on the grid)
+    G0c = fermion_kernel(g0, td, beta, "cols")                 # G0(t_p - t_r), r integrated
+    Scr = fermion_kernel(sc, td, beta, "rows")                 # Sigma^c(t_s - t_r), s integrated
+    Zc = G0c @ (dt[:, None] * Scr)
+    Z = G0c * dsig + Zc
+    A = np.eye(n) - Z * dt[None, :]
+    G = np.linalg.solve(A, g0(td))
+    idx = np.rint(np.asarray(tau) / (td[1] - td[0])).astype(int)
+    return td, G, G[idx]
+
+
 def iw_to_tau_fermion_matrix(D, tau, beta):
     """(1/beta) sum_{n>=0} [e^{-i w_n tau} D_n + e^{+i w_n tau} D_n^H] for band matrices D_n.
 
