@@ -96,7 +96,7 @@ extern "C" {
 #define MSGW_FLAG_SINGULAR   8   /* msgw_screen: an exactly zero pivot of 1 - v^1/2 P v^1/2 */
 
 /* hard limits (checked by set_problem / the calls) */
-#define MSGW_MAX_NI   1024   /* product-basis size per q (screen keeps a row per thread) */
+#define MSGW_MAX_NI   1024   /* product-basis size per q (the screen keeps panel rows in registers) */
 #define MSGW_MAX_NB   1024
 #define MSGW_MIN_NTAU 4      /* not-a-knot spline needs four points */
 
@@ -179,7 +179,9 @@ int msgw_iw_to_tau(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t le
 
 /* a4. Screened interaction on the bosonic axis (W~ Dyson equation, eq. scrv, on i nu):
  * chi~ = v^1/2 P v^1/2;  W~ = v^1/2 [(1 - chi~)^-1 - 1] v^1/2;  R = W~ - v P v.
- * (1 - chi~) is inverted in FP64 by blocked Gauss-Jordan with partial (row) pivoting.
+ * (1 - chi~) is inverted in FP64 by blocked Gauss-Jordan with partial (row) pivoting, all nq * niw_b
+ * matrices of the call together (panels of 16 columns, FP64 MFMA updates).  The pivot record uses
+ * the workspace's scratch: MSGW_ENOMEM unless the workspace was sized for nq_max >= nq.
  * P_iw, Wt_iw, R_iw: device c128 [q][niw_b][NI_q][NI_q]; v: device f64 [q][NI_q]; R_iw may be NULL.
  * info: device int [nq*niw_b], 0 or 1 + the first column whose pivot was exactly zero (the outputs of
  * that matrix are then not finite).  flags: device int or NULL; MSGW_FLAG_SINGULAR is OR-ed into it
@@ -258,6 +260,50 @@ int msgw_dyson_noalloc(msgw_ctx* c, void* stream, const double* eps, const doubl
  * continuation.  Sigma_c_iw: device c128 [nk][nbmax][niw_f]; mu: device scalar; gap: device f64. */
 int msgw_gap(msgw_ctx* c, void* stream, const double* eps, const double* sigma_static,
              const void* Sigma_c_iw, const double* mu, int n_index, double* gap);
+
+/* ---- the paper's tau-domain solvers (cross-checks of a4-a5 and a8), FP64 --------------------- */
+
+#define MSGW_TS_WTILDE 0   /* msgw_wt_tau_system   */
+#define MSGW_TS_DYSON  1   /* msgw_dyson_tau       */
+
+/* Bytes of the device work buffer that msgw_wt_tau_system (which = MSGW_TS_WTILDE, q range
+ * [first, first + count)) or msgw_dyson_tau (MSGW_TS_DYSON, k range [first, first + count)) needs:
+ * mostly the augmented systems, 16 * n * (n + rhs) bytes each.  The same range limits as the calls. */
+int msgw_tau_solver_work_size(msgw_ctx* c, int which, int first, int count, size_t* bytes);
+
+/* f2. W~(q, tau) from the paper's linear system on the tau mesh (eq. tildeW, "Screened Coulomb
+ * potential" in Sec. III.B), for q in [q0, q0 + nq):
+ *   sum_r [delta_pr 1 - v P(tau_p - tau_r) dtau_r] W~(tau_r) = v P(tau_p) v,
+ * dtau_r = (tau_{r+1} - tau_{r-1}) / 2 (half intervals at the ends), P at a difference of mesh points
+ * from the not-a-knot cubic spline of P(tau) on the mesh (a difference below zero is taken at
+ * + beta: P is bosonic).  One dense complex system of order ntau * NI_q per q (<= 4096, else
+ * MSGW_ENOTSUP), solved by the batched blocked Gauss-Jordan elimination of the screen.
+ * P_tau, Wt_tau: device c128 [q][ntau][NI_q][NI_q] (the layout of msgw_polarization); v: device f64
+ * [q][NI_q]; info: device int [nq], 0 or 1 + the first column whose pivot was exactly zero; work: device,
+ * 256-byte aligned, at least msgw_tau_solver_work_size(MSGW_TS_WTILDE, q0, nq) bytes, owned by the
+ * caller.  The call uploads its host-built tables into work on `stream` and waits for the stream
+ * before returning (host-synchronous). */
+int msgw_wt_tau_system(msgw_ctx* c, void* stream, int q0, int nq, const void* P_tau, const double* v,
+                       void* Wt_tau, int* info, void* work, size_t work_bytes);
+
+/* f2. G_n(k, tau) of every state (n < Nb_k) of k in [k0, k0 + nkc) from the paper's Dyson equation in
+ * the tau domain (eqs. dysongf, zxjk, zcjk, dysong), solved on the dense uniform grid t_a = a h,
+ * h = tau_1 - tau_0, a = 0..N, N h = beta:
+ *   sum_r [delta_pr - dt_r Z(t_p, t_r)] G(t_r) = G0(t_p),
+ *   Z(t, t2) = G0(t - t2) sigma_static + int_0^beta dt1 G0(t - t1) Sigma^c(t1 - t2),
+ * G0 the reference Green's function at E = eps - mu, Sigma^c the not-a-knot spline of Sigma_c_tau on
+ * the grid, dt the trapezoid increments of the grid (also for the t1 integral); arguments below zero
+ * are antiperiodic; at a zero argument an interior node takes the mean of the two limits, an end node
+ * of the integration range the limit inside the range.  One real system of order N + 1 per state.
+ * MSGW_ESHAPE unless beta and every tau_i are multiples of h (as on a uniform or uniform power mesh);
+ * MSGW_ENOTSUP above 2048 grid points or 65535 states.
+ * eps, sigma_static: device f64 [nk][nbmax]; mu: device scalar; Sigma_c_tau: device f64
+ * [nk][nbmax][ntau]; G_tau: device f64 [nk][nbmax][ntau], rows n < Nb_k of k in the range written;
+ * info: device int [nkc][nbmax], 0 or 1 + the first zero pivot of the state's system (0 for n >= Nb_k);
+ * work as for msgw_wt_tau_system (MSGW_TS_DYSON, k0, nkc).  Host-synchronous like msgw_wt_tau_system. */
+int msgw_dyson_tau(msgw_ctx* c, void* stream, int k0, int nkc, const double* eps, const double* sigma_static,
+                   const double* mu, const double* Sigma_c_tau, double* G_tau, int* info, void* work,
+                   size_t work_bytes);
 
 /* ---- symmetry ------------------------------------------------------------------------------ */
 

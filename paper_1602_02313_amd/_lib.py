@@ -33,8 +33,10 @@ EXPORTS = [
     "msgw_synth_M", "msgw_variant_count", "msgw_variant_name", "msgw_set_variant", "msgw_get_variant",
     "msgw_set_k_range", "msgw_continue_pade", "msgw_gap_of", "msgw_set_tau_mirror",
     "msgw_continue_cpe", "msgw_dyson_noalloc", "msgw_set_kernel_events", "msgw_dyson_matrix",
+    "msgw_tau_solver_work_size", "msgw_wt_tau_system", "msgw_dyson_tau",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
+TS_WTILDE, TS_DYSON = 0, 1
 
 
 class MsgwError(RuntimeError):
@@ -90,6 +92,9 @@ def load_library():
         "msgw_dyson_matrix": [P, P, P, P, P, D, I, P, P, P, P, P],
         "msgw_gap": [P, P, P, P, P, P, I, P],
         "msgw_synth_M": [P, P, U64, I, I, I, I, P],
+        "msgw_tau_solver_work_size": [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)],
+        "msgw_wt_tau_system": [P, P, I, I, P, P, P, P, P, ctypes.c_size_t],
+        "msgw_dyson_tau": [P, P, I, I, P, P, P, P, P, P, P, ctypes.c_size_t],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -256,6 +261,22 @@ class Context:
         self._check(self.lib.msgw_dyson_noalloc(self._c, _stream(stream), _ptr(eps), _ptr(sigma_static),
                                                 _ptr(Sigma_c_iw), float(n_target), int(mu_mode), _ptr(mu),
                                                 _ptr(G_iw), _ptr(G_tau), _ptr(n_out), _ptr(flags)))
+
+    def tau_solver_work_size(self, which, first, count):
+        b = ctypes.c_size_t(0)
+        self._check(self.lib.msgw_tau_solver_work_size(self._c, int(which), int(first), int(count),
+                                                       ctypes.byref(b)))
+        return b.value
+
+    def wt_tau_system(self, q0, nq, P_tau, v, Wt_tau, info, work, work_bytes, stream=None):
+        self._check(self.lib.msgw_wt_tau_system(self._c, _stream(stream), int(q0), int(nq), _ptr(P_tau), _ptr(v),
+                                                _ptr(Wt_tau), _ptr(info), _ptr(work), int(work_bytes)))
+
+    def dyson_tau(self, k0, nkc, eps, sigma_static, mu, Sigma_c_tau, G_tau, info, work, work_bytes,
+                  stream=None):
+        self._check(self.lib.msgw_dyson_tau(self._c, _stream(stream), int(k0), int(nkc), _ptr(eps),
+                                            _ptr(sigma_static), _ptr(mu), _ptr(Sigma_c_tau), _ptr(G_tau),
+                                            _ptr(info), _ptr(work), int(work_bytes)))
 
     def gap(self, eps, sigma_static, Sigma_c_iw, mu, n_index, gap, stream=None):
         self._check(self.lib.msgw_gap(self._c, _stream(stream), _ptr(eps), _ptr(sigma_static),

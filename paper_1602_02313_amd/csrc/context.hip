@@ -88,16 +88,14 @@ void moments(double w, double h, cplx J[4]) {
     }
 }
 
-// Forward weights W[n][j]: F(i w_n) = sum_j W[n][j] f_j for the not-a-knot cubic spline of f
-// integrated exactly against e^{i w tau} over [0, beta].
-void spline_filon_weights(const std::vector<double>& tau, int niw, bool fermion, double beta,
-                          std::vector<cplx>& W) {
+// Second derivatives of the not-a-knot cubic spline of f on the mesh as a linear map of the values:
+// sig = X f, X [n][n] row-major.
+std::vector<double> spline_second_derivs(const std::vector<double>& tau) {
     const int n = (int)tau.size();
-    const int N = n - 1;  // intervals
-    std::vector<double> h(N);
-    for (int i = 0; i < N; ++i) h[i] = tau[i + 1] - tau[i];
-    // second derivatives sig = X f, from A sig = Rm f
-    std::vector<double> A(n * n, 0.0), X(n * n, 0.0);
+    std::vector<double> h(n - 1);
+    for (int i = 0; i + 1 < n; ++i) h[i] = tau[i + 1] - tau[i];
+    // A sig = Rm f with the not-a-knot end conditions (third derivative continuous at tau_1, tau_{n-2})
+    std::vector<double> A(size_t(n) * n, 0.0), X(size_t(n) * n, 0.0);
     A[0 * n + 0] = -1.0 / h[0];
     A[0 * n + 1] = 1.0 / h[0] + 1.0 / h[1];
     A[0 * n + 2] = -1.0 / h[1];
@@ -113,6 +111,34 @@ void spline_filon_weights(const std::vector<double>& tau, int niw, bool fermion,
     A[(n - 1) * n + n - 2] = 1.0 / h[n - 3] + 1.0 / h[n - 2];
     A[(n - 1) * n + n - 1] = -1.0 / h[n - 2];
     lu_solve_multi(A, n, X, n);  // X[i][j] = d sig_i / d f_j
+    return X;
+}
+
+// Weights w[j] with S(x) = sum_j w[j] f_j for the spline of f at x in [tau_0, tau_{n-1}]: on the
+// interval [tau_i, tau_{i+1}], t = x - tau_i, S = f_i + b t + (s_i / 2) t^2 + (s_{i+1} - s_i) t^3 / (6 h)
+// with b = (f_{i+1} - f_i) / h - h (2 s_i + s_{i+1}) / 6.
+void spline_eval_weights(const std::vector<double>& tau, const std::vector<double>& X, double x, double* w) {
+    const int n = (int)tau.size();
+    int i = int(std::upper_bound(tau.begin(), tau.end(), x) - tau.begin()) - 1;
+    i = std::min(std::max(i, 0), n - 2);
+    const double h = tau[i + 1] - tau[i], t = x - tau[i];
+    for (int j = 0; j < n; ++j) {
+        const double si = X[size_t(i) * n + j], si1 = X[size_t(i + 1) * n + j];
+        w[j] = t * (-h * (2.0 * si + si1) / 6.0) + t * t * (si / 2.0) + t * t * t * ((si1 - si) / (6.0 * h));
+    }
+    w[i] += 1.0 - t / h;
+    w[i + 1] += t / h;
+}
+
+// Forward weights W[n][j]: F(i w_n) = sum_j W[n][j] f_j for the not-a-knot cubic spline of f
+// integrated exactly against e^{i w tau} over [0, beta].
+void spline_filon_weights(const std::vector<double>& tau, int niw, bool fermion, double beta,
+                          std::vector<cplx>& W) {
+    const int n = (int)tau.size();
+    const int N = n - 1;  // intervals
+    std::vector<double> h(N);
+    for (int i = 0; i < N; ++i) h[i] = tau[i + 1] - tau[i];
+    const std::vector<double> X = spline_second_derivs(tau);
     W.assign(size_t(niw) * n, cplx(0.0));
     for (int w = 0; w < niw; ++w) {
         double om = (fermion ? (2.0 * w + 1.0) : 2.0 * w) * kPi / beta;
@@ -172,6 +198,106 @@ void check_qrange(msgw_ctx* c, int q0, int nq) {
 }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- the tau-domain solvers: host tables and the layout of the caller's work buffer ----
+// Trapezoid increments of a grid: (t_{i+1} - t_{i-1}) / 2 inside, half intervals at the ends.
+std::vector<double> trapezoid_increments(const std::vector<double>& t) {
+    const int n = (int)t.size();
+    std::vector<double> d(n);
+    for (int i = 1; i + 1 < n; ++i) d[i] = 0.5 * (t[i + 1] - t[i - 1]);
+    d[0] = 0.5 * (t[1] - t[0]);
+    d[n - 1] = 0.5 * (t[n - 1] - t[n - 2]);
+    return d;
+}
+
+struct TauSysLayout {
+    size_t total = 0;
+    // offsets (bytes) of each table in the work buffer
+    size_t phi = 0, dt = 0, psi = 0, td = 0, dtd = 0, idx = 0, st_k = 0, st_n = 0, gpos = 0, scd = 0;
+    size_t tn = 0, tld = 0, koff = 0, perm = 0, ginfo = 0, K = 0;
+    int count = 0, nmax = 0, ldmax = 0, nd = 0;
+    std::vector<int> tn_h, tld_h, st_k_h, st_n_h;
+    std::vector<int64_t> koff_h;
+};
+
+// Dense uniform grid of the Dyson solve: spacing tau_1 - tau_0 from 0 to beta; every mesh point must
+// be one of its nodes.  Returns the number of nodes (0 if the mesh does not allow it) and idx.
+int dense_grid(const Host& h, std::vector<int>* idx) {
+    const double step = h.tau[1] - h.tau[0];
+    const double nf = h.beta / step;
+    const long N = std::lround(nf);
+    if (N < 1 || std::fabs(N * step - h.beta) > 1e-9 * h.beta) return 0;
+    if (N + 1 > kDysonTauMaxGrid) return int(std::min<long>(N + 1, 1L << 30));
+    if (idx) idx->resize(h.ntau);
+    for (int i = 0; i < h.ntau; ++i) {
+        const long a = std::lround(h.tau[i] / step);
+        if (std::fabs(a * step - h.tau[i]) > 1e-9 * h.beta) return 0;
+        if (idx) (*idx)[i] = int(a);
+    }
+    return int(N + 1);
+}
+
+// which = MSGW_TS_WTILDE: first = q0, count = nq; MSGW_TS_DYSON: first = k0, count = nkc
+TauSysLayout tau_sys_layout(const Host& h, int which, int first, int count) {
+    TauSysLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align_up(bytes);
+        return o;
+    };
+    const int nt = h.ntau;
+    if (which == MSGW_TS_WTILDE) {
+        L.count = count;
+        for (int q = first; q < first + count; ++q) {
+            const int n = nt * h.ni[q];
+            need(n <= kGjMaxN, MSGW_ENOTSUP, "W~ tau system: ntau * NI_q above 4096");
+            L.tn_h.push_back(n);
+            L.tld_h.push_back(n + h.ni[q]);
+            L.nmax = std::max(L.nmax, n);
+            L.ldmax = std::max(L.ldmax, n + h.ni[q]);
+        }
+        L.phi = take(sizeof(double) * size_t(nt) * nt * nt);
+        L.dt = take(sizeof(double) * nt);
+    } else {
+        const int nd = dense_grid(h, nullptr);
+        need(nd > 0, MSGW_ESHAPE, "tau Dyson: beta and every tau_i must be multiples of tau_1 - tau_0");
+        need(nd <= kDysonTauMaxGrid, MSGW_ENOTSUP, "tau Dyson: more than 2048 dense grid points");
+        L.nd = nd;
+        for (int k = first; k < first + count; ++k)
+            for (int n = 0; n < h.nb[k]; ++n) {
+                L.st_k_h.push_back(k);
+                L.st_n_h.push_back(n);
+                L.tn_h.push_back(nd);
+                L.tld_h.push_back(nd + 1);
+            }
+        L.count = (int)L.tn_h.size();
+        need(L.count <= 65535, MSGW_ENOTSUP, "tau Dyson: more than 65535 states in one call (use a smaller k range)");
+        L.nmax = nd;
+        L.ldmax = nd + 1;
+        L.psi = take(sizeof(double) * size_t(nd) * nt);
+        L.td = take(sizeof(double) * nd);
+        L.dtd = take(sizeof(double) * nd);
+        L.idx = take(sizeof(int) * nt);
+        L.st_k = take(sizeof(int) * L.count);
+        L.st_n = take(sizeof(int) * L.count);
+        L.gpos = take(sizeof(double) * size_t(L.count) * nd);
+        L.scd = take(sizeof(double) * size_t(L.count) * nd);
+    }
+    int64_t koff = 0;
+    for (int b = 0; b < L.count; ++b) {
+        L.koff_h.push_back(koff);
+        koff += int64_t(L.tn_h[b]) * L.tld_h[b];
+    }
+    L.tn = take(sizeof(int) * L.count);
+    L.tld = take(sizeof(int) * L.count);
+    L.koff = take(sizeof(int64_t) * L.count);
+    L.perm = take(sizeof(int) * size_t(L.count) * L.nmax);
+    L.ginfo = take(sizeof(int) * L.count);
+    L.K = take(sizeof(double2) * size_t(koff));
+    L.total = off;
+    return L;
+}
 
 }  // namespace
 
@@ -292,7 +418,8 @@ static size_t tables_bytes(const Host& h) {
 }
 
 static size_t scratch_needed(const Host& h, int nq_max) {
-    return scratch_E_bytes(h) + align_up(std::max(mfma_scratch_bytes(h, nq_max), cpe_scratch_bytes(h, 98)));
+    return scratch_E_bytes(h) + align_up(std::max({mfma_scratch_bytes(h, nq_max), cpe_scratch_bytes(h, 98),
+                                                   screen_scratch_bytes(h, nq_max)}));
 }
 
 int msgw_workspace_size(msgw_ctx* c, int nq_max, size_t* bytes) {
@@ -480,7 +607,11 @@ int msgw_screen(msgw_ctx* c, void* stream, int q0, int nq, const void* P_iw, con
         check_qrange(c, q0, nq);
         need(P_iw && v && Wt_iw && info, MSGW_EINVAL, "null pointer");
         need(P_iw != Wt_iw, MSGW_EINVAL, "P_iw and Wt_iw must not alias");
-        launch_screen(c->d, c->h, S(stream), q0, nq, P_iw, v, Wt_iw, R_iw, info, flags);
+        need(screen_scratch_bytes(c->h, nq) <= scratch_mfma_bytes(c->d, c->h), MSGW_ENOMEM,
+             "screen: workspace too small for nq (size it with msgw_workspace_size(nq_max >= nq))");
+        c->prep = msgw_ctx::Prepared();  // the pivot record uses the split-precision scratch
+        launch_screen(c->d, c->h, S(stream), q0, nq, P_iw, v, Wt_iw, R_iw, info, flags,
+                      reinterpret_cast<int*>(scratch_mfma(c->d, c->h)));
     });
 }
 
@@ -717,6 +848,128 @@ int msgw_gap(msgw_ctx* c, void* stream, const double* eps, const double* sigma_s
         for (int k = 0; k < c->h.nk; ++k) nstate += c->h.nb[k];
         need(n_index >= 1 && n_index < nstate, MSGW_EINVAL, "n_index outside [1, number of states)");
         launch_gap(c->d, c->h, S(stream), eps, sigma_static, Sigma_c_iw, mu, n_index, gap);
+    });
+}
+
+int msgw_tau_solver_work_size(msgw_ctx* c, int which, int first, int count, size_t* bytes) {
+    return guarded(c, [&] {
+        need(c->have_problem, MSGW_EINVAL, "no problem set");
+        need(bytes != nullptr, MSGW_EINVAL, "null bytes");
+        need(which == MSGW_TS_WTILDE || which == MSGW_TS_DYSON, MSGW_EINVAL, "bad solver");
+        need(first >= 0 && count >= 1 && first + count <= c->h.nk, MSGW_EINVAL, "range outside [0, nk)");
+        *bytes = tau_sys_layout(c->h, which, first, count).total;
+    });
+}
+
+static void upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes) MSGW_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+}
+
+int msgw_wt_tau_system(msgw_ctx* c, void* stream, int q0, int nq, const void* P_tau, const double* v,
+                       void* Wt_tau, int* info, void* work, size_t work_bytes) {
+    return guarded(c, [&] {
+        require_ready(c);
+        check_qrange(c, q0, nq);
+        need(P_tau && v && Wt_tau && info && work, MSGW_EINVAL, "null pointer");
+        need((reinterpret_cast<uintptr_t>(work) & 255) == 0, MSGW_EINVAL, "work must be 256-byte aligned");
+        const Host& h = c->h;
+        const TauSysLayout L = tau_sys_layout(h, MSGW_TS_WTILDE, q0, nq);
+        need(work_bytes >= L.total, MSGW_ENOMEM, "work smaller than msgw_tau_solver_work_size");
+        const int nt = h.ntau;
+        // spline weights of P at tau_p - tau_r (+ beta below zero) and the trapezoid increments
+        const std::vector<double> X = spline_second_derivs(h.tau);
+        std::vector<double> phi(size_t(nt) * nt * nt);
+        for (int p = 0; p < nt; ++p)
+            for (int r = 0; r < nt; ++r) {
+                double x = h.tau[p] - h.tau[r];
+                if (x < 0.0) x += h.beta;
+                spline_eval_weights(h.tau, X, x, &phi[(size_t(p) * nt + r) * nt]);
+            }
+        const std::vector<double> dt = trapezoid_increments(h.tau);
+        char* w = static_cast<char*>(work);
+        hipStream_t st = S(stream);
+        upload(w + L.phi, phi.data(), sizeof(double) * phi.size(), st);
+        upload(w + L.dt, dt.data(), sizeof(double) * nt, st);
+        upload(w + L.tn, L.tn_h.data(), sizeof(int) * L.count, st);
+        upload(w + L.tld, L.tld_h.data(), sizeof(int) * L.count, st);
+        upload(w + L.koff, L.koff_h.data(), sizeof(int64_t) * L.count, st);
+        TauSysArgs a;
+        a.ntau = nt;
+        a.nbmax = h.nbmax;
+        a.q0 = q0;
+        a.beta = h.beta;
+        a.ni = c->d.ni;
+        a.ppre = c->d.ppre;
+        a.vpre = c->d.vpre;
+        a.phi = reinterpret_cast<const double*>(w + L.phi);
+        a.dt = reinterpret_cast<const double*>(w + L.dt);
+        a.tn = reinterpret_cast<const int*>(w + L.tn);
+        a.tld = reinterpret_cast<const int*>(w + L.tld);
+        a.koff = reinterpret_cast<const int64_t*>(w + L.koff);
+        a.perm = reinterpret_cast<int*>(w + L.perm);
+        a.ginfo = info;
+        a.K = reinterpret_cast<double2*>(w + L.K);
+        launch_wt_tau_system(a, st, nq, L.nmax, L.ldmax, P_tau, v, Wt_tau);
+        MSGW_HIP(hipStreamSynchronize(st));  // the host tables above are released on return
+    });
+}
+
+int msgw_dyson_tau(msgw_ctx* c, void* stream, int k0, int nkc, const double* eps, const double* sigma_static,
+                   const double* mu, const double* Sigma_c_tau, double* G_tau, int* info, void* work,
+                   size_t work_bytes) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(k0 >= 0 && nkc >= 1 && k0 + nkc <= c->h.nk, MSGW_EINVAL, "k range outside [0, nk)");
+        need(eps && sigma_static && mu && Sigma_c_tau && G_tau && info && work, MSGW_EINVAL, "null pointer");
+        need((reinterpret_cast<uintptr_t>(work) & 255) == 0, MSGW_EINVAL, "work must be 256-byte aligned");
+        const Host& h = c->h;
+        const TauSysLayout L = tau_sys_layout(h, MSGW_TS_DYSON, k0, nkc);
+        need(work_bytes >= L.total, MSGW_ENOMEM, "work smaller than msgw_tau_solver_work_size");
+        const int nt = h.ntau, nd = L.nd;
+        std::vector<int> idx;
+        dense_grid(h, &idx);
+        const double step = h.tau[1] - h.tau[0];
+        std::vector<double> td(nd);
+        for (int a = 0; a < nd; ++a) td[a] = a * step;
+        td[nd - 1] = h.beta;
+        for (int i = 0; i < nt; ++i) td[idx[i]] = h.tau[i];  // the mesh's own values at its nodes
+        const std::vector<double> dtd = trapezoid_increments(td);
+        const std::vector<double> X = spline_second_derivs(h.tau);
+        std::vector<double> psi(size_t(nd) * nt);
+        for (int a = 0; a < nd; ++a) spline_eval_weights(h.tau, X, td[a], &psi[size_t(a) * nt]);
+        char* w = static_cast<char*>(work);
+        hipStream_t st = S(stream);
+        upload(w + L.psi, psi.data(), sizeof(double) * psi.size(), st);
+        upload(w + L.td, td.data(), sizeof(double) * nd, st);
+        upload(w + L.dtd, dtd.data(), sizeof(double) * nd, st);
+        upload(w + L.idx, idx.data(), sizeof(int) * nt, st);
+        upload(w + L.st_k, L.st_k_h.data(), sizeof(int) * L.count, st);
+        upload(w + L.st_n, L.st_n_h.data(), sizeof(int) * L.count, st);
+        upload(w + L.tn, L.tn_h.data(), sizeof(int) * L.count, st);
+        upload(w + L.tld, L.tld_h.data(), sizeof(int) * L.count, st);
+        upload(w + L.koff, L.koff_h.data(), sizeof(int64_t) * L.count, st);
+        TauSysArgs a;
+        a.ntau = nt;
+        a.nbmax = h.nbmax;
+        a.nd = nd;
+        a.k0 = k0;
+        a.beta = h.beta;
+        a.psi = reinterpret_cast<const double*>(w + L.psi);
+        a.td = reinterpret_cast<const double*>(w + L.td);
+        a.dtd = reinterpret_cast<const double*>(w + L.dtd);
+        a.idx = reinterpret_cast<const int*>(w + L.idx);
+        a.st_k = reinterpret_cast<const int*>(w + L.st_k);
+        a.st_n = reinterpret_cast<const int*>(w + L.st_n);
+        a.gpos = reinterpret_cast<double*>(w + L.gpos);
+        a.scd = reinterpret_cast<double*>(w + L.scd);
+        a.tn = reinterpret_cast<const int*>(w + L.tn);
+        a.tld = reinterpret_cast<const int*>(w + L.tld);
+        a.koff = reinterpret_cast<const int64_t*>(w + L.koff);
+        a.perm = reinterpret_cast<int*>(w + L.perm);
+        a.ginfo = reinterpret_cast<int*>(w + L.ginfo);
+        a.K = reinterpret_cast<double2*>(w + L.K);
+        launch_dyson_tau(a, st, L.count, nkc, eps, sigma_static, mu, Sigma_c_tau, G_tau, info);
+        MSGW_HIP(hipStreamSynchronize(st));  // the host tables above are released on return
     });
 }
 

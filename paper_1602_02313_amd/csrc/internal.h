@@ -98,8 +98,10 @@ void launch_inv_fermion(const Dev& d, hipStream_t s, int64_t nblk, int64_t len, 
                         const double* eref, double* out);
 void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, const void* F,
                       const void* add, const double* v, void* out);
+// perm: screen_scratch_bytes(h, nq) of scratch (the pivot rows of every (q, nu) matrix)
+size_t screen_scratch_bytes(const Host& h, int nq);
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
-                   const double* v, void* Wt_iw, void* R_iw, int* info, int* flags);
+                   const double* v, void* Wt_iw, void* R_iw, int* info, int* flags, int* perm);
 void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
                     int m_dtype, const double* occ, const double* v, void* out, int full);
 // E: [nk * nbmax] doubles, st: kMuSearchBytes of mu search state (every entry written before use)
@@ -171,6 +173,71 @@ inline char* scratch_mfma(const Dev& d, const Host& h) { return d.scratch + scra
 inline size_t scratch_mfma_bytes(const Dev& d, const Host& h) {
     return d.scratch_bytes > scratch_E_bytes(h) ? d.scratch_bytes - scratch_E_bytes(h) : 0;
 }
+
+// ---- batched Gauss-Jordan (k_gj.hip) ----
+constexpr int GJ_INVERT = 0;  // A <- A^-1 (columns permuted by the pivot swaps)
+constexpr int GJ_SOLVE = 1;   // [A | B] -> B <- A^-1 B
+constexpr int kGjMaxN = 4096;
+// A batch of matrices: either a table form (per-matrix order, row stride and offset in device arrays)
+// or the screen's form (matrix b is (q0 + b / niw_b, nu = b % niw_b) of NI_q x NI_q at the screen's
+// offsets).
+struct GjArgs {
+    double2* A = nullptr;
+    int mode = GJ_INVERT;
+    const int* tn = nullptr;           // [batch] order
+    const int* tld = nullptr;          // [batch] row stride (>= order; order + rhs columns in GJ_SOLVE)
+    const int64_t* toff = nullptr;     // [batch] offset of the matrix in A (elements)
+    const int* ni = nullptr;           // screen form (when set): NI_q
+    const int64_t* wpre = nullptr;     //   prefix over q of niw_b * NI_q^2
+    int q0 = 0, niw_b = 0;
+    int* perm = nullptr;               // [batch][pmax] pivot row chosen for each column
+    int pmax = 0;
+    int* info = nullptr;               // [batch] first zero pivot + 1, or 0
+};
+__device__ __forceinline__ void gj_item(const GjArgs& g, int b, int& n, int& ld, int64_t& off) {
+    if (g.ni) {
+        const int q = g.q0 + b / g.niw_b;
+        n = g.ni[q];
+        ld = n;
+        off = (g.wpre[q] - g.wpre[g.q0]) + int64_t(b % g.niw_b) * n * n;
+    } else {
+        n = g.tn[b];
+        ld = g.tld[b];
+        off = g.toff[b];
+    }
+}
+// Enqueues the elimination of `batch` matrices of order <= nmax (row stride <= ldmax) on s.
+void gj_run(const GjArgs& g, int batch, int nmax, int ldmax, hipStream_t s);
+
+// ---- the tau-domain solvers (k_tausys.hip) ----
+constexpr int kDysonTauMaxGrid = 2048;  // dense grid points of the tau-domain Dyson solve
+struct TauSysArgs {
+    int ntau = 0, nbmax = 0, nd = 0, q0 = 0, k0 = 0;
+    double beta = 0;
+    const int* ni = nullptr;            // problem tables (device)
+    const int64_t* ppre = nullptr;
+    const int64_t* vpre = nullptr;
+    const double* phi = nullptr;        // W~ system: spline weights [ntau][ntau][ntau] of P at tau_p - tau_r
+    const double* dt = nullptr;         //   trapezoid increments of the mesh [ntau]
+    const double* psi = nullptr;        // Dyson: spline weights [nd][ntau] of Sigma^c at the dense nodes
+    const double* td = nullptr;         //   dense nodes [nd]
+    const double* dtd = nullptr;        //   their trapezoid increments [nd]
+    const int* idx = nullptr;           //   dense node of each mesh point [ntau]
+    const int* st_k = nullptr;          //   state list (k, n) [nstates]
+    const int* st_n = nullptr;
+    double* gpos = nullptr;             //   G0(E, a h) per state [nstates][nd]
+    double* scd = nullptr;              //   Sigma^c(a h) per state [nstates][nd]
+    const int* tn = nullptr;            // systems: order, row stride, offset in K [count]
+    const int* tld = nullptr;
+    const int64_t* koff = nullptr;
+    int* perm = nullptr;                // [count][max order]
+    int* ginfo = nullptr;               // [count]
+    double2* K = nullptr;               // the augmented systems
+};
+void launch_wt_tau_system(const TauSysArgs& a, hipStream_t s, int nq, int nmax, int ldmax, const void* P_tau,
+                          const double* v, void* Wt_tau);
+void launch_dyson_tau(const TauSysArgs& a, hipStream_t s, int nstates, int nkc, const double* eps,
+                      const double* sstat, const double* mu, const double* Sigma_c_tau, double* G_tau, int* info);
 
 // ---- small device helpers ----
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
