@@ -401,6 +401,128 @@ class MGenerator:
         return np.concatenate([b.reshape(-1) for b in self.q_blocks(q, dtype)])
 
 
+# ---------------------------------------------------------------------------
+# cubic crystal symmetry (input generation for the irreducible-wedge reduction)
+# ---------------------------------------------------------------------------
+TAG_MC = 0x4D435542       # matrix elements M of the cubic-symmetric generator
+
+
+def cubic_group() -> np.ndarray:
+    """The 48 signed permutation matrices (the point group O_h of a simple cubic lattice), int [48, 3, 3],
+    the identity first."""
+    out = []
+    for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+        for sgn in range(8):
+            R = np.zeros((3, 3), dtype=np.int64)
+            for r in range(3):
+                R[r, perm[r]] = -1 if (sgn >> r) & 1 else 1
+            out.append(R)
+    return np.array(out)
+
+
+def basis_vectors(ni: int) -> np.ndarray:
+    """The first ni reciprocal-lattice vectors G in Z^3, ordered by |G|^2 then lexicographically
+    (int [ni, 3]).  ni must close a shell, so that the set is mapped onto itself by O_h."""
+    R = 1
+    while (2 * R + 1) ** 3 < 4 * ni or R * R < np.cbrt(ni):
+        R += 1
+    g = np.array([(a, b, c) for a in range(-R, R + 1) for b in range(-R, R + 1) for c in range(-R, R + 1)])
+    n2 = (g * g).sum(axis=1)
+    order = np.lexsort((g[:, 2], g[:, 1], g[:, 0], n2))
+    g, n2 = g[order], n2[order]
+    if ni < g.shape[0] and n2[ni] == n2[ni - 1]:
+        raise ValueError(f"NI = {ni} does not close a shell of reciprocal-lattice vectors")
+    return g[:ni]
+
+
+def rotation_k_maps(cfg: Config, group: np.ndarray | None = None) -> np.ndarray:
+    """rot_k[r, k] = index of R_r k on the n x n x n grid (int32 [nrot, nk])."""
+    group = cubic_group() if group is None else group
+    n = cfg.grid[0]
+    if not (cfg.grid[1] == n and cfg.grid[2] == n):
+        raise ValueError("the cubic group acts on an n x n x n grid")
+    ki = _kint(cfg)
+    out = np.empty((group.shape[0], cfg.nk), dtype=np.int32)
+    for r, R in enumerate(group):
+        rk = ki @ R.T
+        out[r] = _kindex(cfg, rk[:, 0], rk[:, 1], rk[:, 2])
+    return out
+
+
+def cubic_v(ni: int) -> np.ndarray:
+    """v_I = 4 pi / (0.1 + 0.5 |G_I|^2): a function of |G| only, as the Coulomb kernel is."""
+    g = basis_vectors(ni)
+    return 4.0 * np.pi / (0.1 + 0.5 * (g * g).sum(axis=1).astype(np.float64))
+
+
+class CubicGenerator:
+    """M for an n x n x n grid with the symmetry of a symmorphic cubic crystal: the product basis is the
+    set of the first NI vectors G (closed shells) and
+
+        M^I'_nm(R k, R q) = M^I_nm(k, q)  with  G_I' = R G_I,  for all 48 R in O_h,
+
+    the relation of the paper's symmetry subsection without fractional translations.  One complex
+    Gaussian (E|M|^2 = 1 / (1 + |G|^2 / 4)) is drawn per orbit of (k, q, G) and band pair (n, m), keyed by
+    the orbit's smallest index (q' nk + k') NI + I'.  Band counts and NI are the same at every k and q;
+    the energies of the model bands are invariant under O_h."""
+
+    def __init__(self, cfg: Config, seed: int | None = None):
+        if cfg.nb is None or cfg.ni is None:
+            raise ValueError("the cubic generator needs uniform band counts and basis size")
+        self.cfg = cfg
+        self.seed = cfg.seed if seed is None else seed
+        self.group = cubic_group()
+        self.rot_k = rotation_k_maps(cfg, self.group)
+        self.g = basis_vectors(cfg.ni)
+        self.nb = band_counts(cfg)
+        self.ni = basis_sizes(cfg)
+        self.kmq = kmq_table(cfg)
+        R = int(np.abs(self.g).max())
+        self._R = R
+        look = -np.ones((2 * R + 1,) * 3, dtype=np.int64)
+        look[self.g[:, 0] + R, self.g[:, 1] + R, self.g[:, 2] + R] = np.arange(cfg.ni)
+        self._look = look
+        # rot_g[r, I] = index of R_r G_I
+        rg = np.einsum("rij,gj->rgi", self.group, self.g) + R
+        self.rot_g = look[rg[..., 0], rg[..., 1], rg[..., 2]]
+        assert (self.rot_g >= 0).all()
+
+    def keys(self, q: int) -> np.ndarray:
+        """Orbit key of every (k, I) of q: uint64 [nk, NI]."""
+        nk, ni = self.cfg.nk, self.cfg.ni
+        qq = self.rot_k[:, q].astype(np.uint64)[:, None, None]            # [r, 1, 1]
+        kk = self.rot_k.astype(np.uint64)[:, :, None]                       # [r, k, 1]
+        ii = self.rot_g.astype(np.uint64)[:, None, :]                       # [r, 1, I]
+        key = (qq * np.uint64(nk) + kk) * np.uint64(ni) + ii
+        return key.min(axis=0)
+
+    def block(self, q: int, k: int, dtype=np.complex128, keys=None) -> np.ndarray:
+        nb = self.cfg.nb
+        key = (self.keys(q) if keys is None else keys)[k][:, None, None]     # [I, 1, 1]
+        nm = (np.arange(nb, dtype=np.uint32)[:, None] * np.uint32(nb) + np.arange(nb, dtype=np.uint32)[None, :])
+        c0 = (key & _U32).astype(np.uint32)
+        c1 = (key >> np.uint64(32)).astype(np.uint32)
+        r0, r1, r2, r3 = philox4x32_10(c0, c1, nm[None], np.uint32(TAG_MC), self.seed)
+        z0, z1 = box_muller(r0, r1, r2, r3)
+        g2 = (self.g * self.g).sum(axis=1).astype(np.float64)[:, None, None]
+        sc = np.sqrt(1.0 / (1.0 + g2 / 4.0) / 2.0)
+        return (sc * z0 + 1j * sc * z1).astype(dtype)
+
+    def q_blocks(self, q: int, dtype=np.complex128):
+        keys = self.keys(q)
+        return [self.block(q, k, dtype, keys) for k in range(self.cfg.nk)]
+
+    def q_packed(self, q: int, dtype=np.complex128) -> np.ndarray:
+        return np.concatenate([b.reshape(-1) for b in self.q_blocks(q, dtype)])
+
+
+def make_cubic_problem(cfg: Config) -> "Problem":
+    """A Problem whose Coulomb kernel is the cubic generator's v (a function of |G|)."""
+    prob = make_problem(cfg)
+    prob.v = [cubic_v(int(n)) for n in prob.ni]
+    return prob
+
+
 @dataclass
 class Problem:
     """Everything a run needs, derived from a Config."""

@@ -394,6 +394,53 @@ def dyson(eps, nb, sig_static, sigc_iw, beta, tau, n_target, mu0=0.0,
 
 
 # ---------------------------------------------------------------------------
+# crystal symmetry: q in the irreducible wedge (Sec. III.C)
+# ---------------------------------------------------------------------------
+def ibz_stars(rot_k):
+    """The irreducible q points and their stars under a point group given by its action on the k grid
+    (rot_k[r, k] = index of R_r k): every orbit {R q} is represented by its smallest index, and its star
+    lists each member q' once with the first operation r (in the given order) that maps the
+    representative onto it.  Returns [(q_ibz, [(q', r), ...]), ...] in increasing q_ibz."""
+    rot_k = np.asarray(rot_k)
+    nk = rot_k.shape[1]
+    seen = np.zeros(nk, dtype=bool)
+    out = []
+    for q in range(nk):
+        if seen[q]:
+            continue
+        star = []
+        for r in range(rot_k.shape[0]):
+            qp = int(rot_k[r, q])
+            if not seen[qp]:
+                seen[qp] = True
+                star.append((qp, r))
+        out.append((q, star))
+    return out
+
+
+def symmetrize_over_stars(contrib, stars, rot_k):
+    """The paper's regrouping of the self-energy's q sum over the irreducible wedge (the equation that
+    follows the relations for M, P and W~ in Sec. III.C): the contribution of q' = R q to state (k, n)
+    equals that of q to (R^-1 k, n), so
+
+        S_n(k) = sum_{q in IBZ} sum_{(q', R) in star(q)} C_q,n(R^-1 k),
+
+    contrib: {q_ibz: C_q [nk, ...]} (the contributions of each irreducible q to every k, e.g. sigma_c
+    or sigma_x of that q).  Returns the sum [nk, ...]."""
+    rot_k = np.asarray(rot_k)
+    nk = rot_k.shape[1]
+    total = None
+    for q, star in stars:
+        C = np.asarray(contrib[q])
+        for qp, r in star:
+            inv = np.empty(nk, dtype=np.int64)
+            inv[rot_k[r]] = np.arange(nk)          # inv[k] = R^-1 k
+            term = C[inv]
+            total = term if total is None else total + term
+    return total
+
+
+# ---------------------------------------------------------------------------
 # the paper's own tau-domain solvers (cross-checks of the Matsubara-axis forms)
 # ---------------------------------------------------------------------------
 def spline_eval(tau, f, x):
