@@ -315,6 +315,33 @@ int msgw_dyson_tau(msgw_ctx* c, void* stream, int k0, int nkc, const double* eps
  * With inputs that lack the symmetry the copied points are wrong.  Default off. */
 int msgw_set_tau_mirror(msgw_ctx* c, int on);
 
+/* f1. Crystal symmetry: q in the irreducible wedge (Sec. III.C, eqs. rso and qibz2bz with the relations
+ * for M, P and W~ that follow them).  For a point group whose operations R map the k grid onto itself,
+ * with M^{I'}_nm(R k, R q) = M^I_nm(k, q) for G_{I'} = R G_I (a symmorphic crystal: no fractional
+ * translations), R-invariant v and band energies, P and W~ at R q are those at q with permuted basis
+ * indices, and the contribution of q' = R q to Sigma_n(k) is that of q to Sigma_n(R^-1 k).  So P, W~ and
+ * the contractions run for the irreducible q only, and each irreducible q's contributions to every k are
+ * added over its star with rotated k (msgw_sigma_star); DIAG mode.
+ *
+ * msgw_set_symmetry: rot_k host int [nrot][nk], rot_k[r][k] = index of R_r k (1 <= nrot <= 48).  Each
+ * row must be a permutation with R (k - q) = R k - R q on the problem's kmq table, else MSGW_EINVAL.
+ * Every orbit {R q} is represented by its smallest q; its star lists each member once, reached by the
+ * first r (in the given order) that maps the representative onto it.  Host-synchronous: the maps go
+ * into the workspace (call after msgw_set_workspace, with no work on the context in flight); setting a
+ * problem or a workspace clears them. */
+int msgw_set_symmetry(msgw_ctx* c, int nrot, const int* rot_k);
+
+/* The irreducible q (increasing) and the size of each one's star: host int arrays of nk entries or
+ * NULL; *n_ibz receives their number.  MSGW_EINVAL before msgw_set_symmetry. */
+int msgw_ibz(const msgw_ctx* c, int* n_ibz, int* q_ibz, int* star_size);
+
+/* Sigma_tau[k][n][i] += sum over the star of q_ibz of C_tau[R^-1 k][n][i], and the same for Sigma_x from
+ * C_x (both NULL or both given): C_tau / C_x are the contributions of the single q_ibz to every k
+ * (msgw_self_energy / msgw_sigma_x of q_ibz alone into zeroed buffers).  Device f64 [nk][nbmax][ntau]
+ * and [nk][nbmax]; the star members are summed in a fixed order. */
+int msgw_sigma_star(msgw_ctx* c, void* stream, int q_ibz, const double* C_tau, const double* C_x,
+                    double* Sigma_tau, double* Sigma_x);
+
 /* ---- after the path: analytic continuation ---------------------------------------------------- */
 
 /* Analytic continuation of Sigma^c to the real axis by a Pade approximant (the route the paper
@@ -396,6 +423,15 @@ int msgw_set_kernel_events(msgw_ctx* c, int op, void* start, void* stop);
  * element is real.  -k and q-k are read from kmq (k index 0 must be Gamma). */
 int msgw_synth_M(msgw_ctx* c, void* stream, uint64_t seed, int q0, int nq, int symmetric,
                  int m_dtype, void* M);
+
+/* Harness-only input generation with the symmetry of a symmorphic cubic crystal, the twin of the host
+ * generator gwinputs.CubicGenerator: on an n x n x n grid (k = (i1 n + i2) n + i3) with one band count and
+ * NI = the number of vectors G in closed shells of |G|^2 (product basis = those G, in the order |G|^2,
+ * then lexicographic), one complex Gaussian per orbit of (k, q, G) under the 48 operations of O_h and band
+ * pair (n, m): Philox4x32-10 counter (key low, key high, n nb + m, 0x4D435542) with the orbit's smallest
+ * key (q' nk + k') NI + I', Box-Muller, E|M|^2 = 1 / (1 + |G|^2 / 4).  MSGW_ESHAPE for other shapes.
+ * The first call per NI writes its tables into the workspace (host-synchronous). */
+int msgw_synth_M_cubic(msgw_ctx* c, void* stream, uint64_t seed, int q0, int nq, int m_dtype, void* M);
 
 #ifdef __cplusplus
 }

@@ -8,4 +8,4 @@ from ._lib import (BF16X3, BOSON, C64, C128, EHIP, EINVAL, ENOMEM, ENOTSUP, ESHA
                    F16X3, FERMION, FLAG_NAN, FLAG_NOBRACKET, FLAG_NOCONV, FLAG_SINGULAR, FP32, FP64,
                    LIB_PATH, MU_FIXED, MU_SEARCH, OK, OP_POLARIZATION, OP_SELF_ENERGY, SIGMA_DIAG,
                    SIGMA_FULL, TS_DYSON, TS_WTILDE, Context, MsgwError, load_library)
-from .driver import GWRun, HostM, ResidentM, SynthM  # noqa: F401
+from .driver import GWRun, HostM, ResidentM, SynthCubicM, SynthM  # noqa: F401

@@ -34,6 +34,7 @@ EXPORTS = [
     "msgw_set_k_range", "msgw_continue_pade", "msgw_gap_of", "msgw_set_tau_mirror",
     "msgw_continue_cpe", "msgw_dyson_noalloc", "msgw_set_kernel_events", "msgw_dyson_matrix",
     "msgw_tau_solver_work_size", "msgw_wt_tau_system", "msgw_dyson_tau",
+    "msgw_set_symmetry", "msgw_ibz", "msgw_sigma_star", "msgw_synth_M_cubic",
 ]
 OP_POLARIZATION, OP_SELF_ENERGY = 0, 1
 TS_WTILDE, TS_DYSON = 0, 1
@@ -95,6 +96,10 @@ def load_library():
         "msgw_tau_solver_work_size": [P, I, I, I, ctypes.POINTER(ctypes.c_size_t)],
         "msgw_wt_tau_system": [P, P, I, I, P, P, P, P, P, ctypes.c_size_t],
         "msgw_dyson_tau": [P, P, I, I, P, P, P, P, P, P, P, ctypes.c_size_t],
+        "msgw_set_symmetry": [P, I, ctypes.POINTER(ctypes.c_int)],
+        "msgw_ibz": [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)],
+        "msgw_sigma_star": [P, P, I, P, P, P, P],
+        "msgw_synth_M_cubic": [P, P, U64, I, I, I, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -191,6 +196,7 @@ class Context:
                      tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(beta),
                      int(niw_f), int(niw_b), float(scale), int(sigma_mode))
         self._check(self.lib.msgw_set_problem(self._c, ctypes.byref(p)))
+        self._nk = int(nk)
 
     def workspace_size(self, nq_max=1):
         b = ctypes.c_size_t()
@@ -277,6 +283,28 @@ class Context:
         self._check(self.lib.msgw_dyson_tau(self._c, _stream(stream), int(k0), int(nkc), _ptr(eps),
                                             _ptr(sigma_static), _ptr(mu), _ptr(Sigma_c_tau), _ptr(G_tau),
                                             _ptr(info), _ptr(work), int(work_bytes)))
+
+    def set_symmetry(self, rot_k):
+        r = np.ascontiguousarray(rot_k, dtype=np.int32)
+        self._check(self.lib.msgw_set_symmetry(self._c, int(r.shape[0]),
+                                               r.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+
+    def ibz(self):
+        """(irreducible q list, star sizes)."""
+        n = ctypes.c_int(0)
+        nk = self._nk
+        q = (ctypes.c_int * nk)()
+        st = (ctypes.c_int * nk)()
+        self._check(self.lib.msgw_ibz(self._c, ctypes.byref(n), q, st))
+        return list(q[:n.value]), list(st[:n.value])
+
+    def sigma_star(self, q_ibz, C_tau, C_x, Sigma_tau, Sigma_x, stream=None):
+        self._check(self.lib.msgw_sigma_star(self._c, _stream(stream), int(q_ibz), _ptr(C_tau), _ptr(C_x),
+                                             _ptr(Sigma_tau), _ptr(Sigma_x)))
+
+    def synth_M_cubic(self, seed, q0, nq, m_dtype, M, stream=None):
+        self._check(self.lib.msgw_synth_M_cubic(self._c, _stream(stream), int(seed), int(q0), int(nq),
+                                                int(m_dtype), _ptr(M)))
 
     def gap(self, eps, sigma_static, Sigma_c_iw, mu, n_index, gap, stream=None):
         self._check(self.lib.msgw_gap(self._c, _stream(stream), _ptr(eps), _ptr(sigma_static),

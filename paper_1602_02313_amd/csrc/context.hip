@@ -1,8 +1,10 @@
 // Host side of the C ABI: context, validation, FP64 transform weights, workspace.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <sstream>
 
 #include "internal.h"
@@ -29,6 +31,11 @@ struct msgw_ctx {
     struct Prepared {
         int op = -1, q0 = 0, nq = 0, precision = 0, variant = 0;
     } prep;
+    // crystal symmetry (msgw_set_symmetry): the irreducible q and the stars
+    bool sym_set = false;
+    int cubic_ni = 0;  // NI of the cubic generator's tables in the workspace (0: none)
+    std::vector<int> sym_ibz, sym_off;  // representatives; star of sym_ibz[i] = sym_star[sym_off[i] .. sym_off[i+1])
+    std::vector<int> sym_star, sym_rep_of;  // star members grouped; representative index of every q
 };
 
 namespace {
@@ -198,6 +205,39 @@ void check_qrange(msgw_ctx* c, int q0, int nq) {
 }
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- crystal symmetry: the 48 operations of O_h and the closed-shell product basis of the cubic
+// input generator ----
+struct IMat {
+    int m[3][3];
+};
+std::vector<IMat> cubic_ops() {
+    static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    std::vector<IMat> out;
+    for (const auto& p : perms)
+        for (int sgn = 0; sgn < 8; ++sgn) {
+            IMat R{};
+            for (int r = 0; r < 3; ++r) R.m[r][p[r]] = (sgn >> r) & 1 ? -1 : 1;
+            out.push_back(R);
+        }
+    return out;
+}
+// the first ni vectors G of Z^3 by |G|^2, then lexicographically; empty if ni does not close a shell
+std::vector<std::array<int, 3>> shell_basis(int ni) {
+    int R = 1;
+    while ((2 * R + 1) * (2 * R + 1) * (2 * R + 1) < 4 * ni || R * R * R < ni) ++R;
+    std::vector<std::array<int, 3>> g;
+    for (int a = -R; a <= R; ++a)
+        for (int b = -R; b <= R; ++b)
+            for (int c = -R; c <= R; ++c) g.push_back({a, b, c});
+    auto n2 = [](const std::array<int, 3>& x) { return x[0] * x[0] + x[1] * x[1] + x[2] * x[2]; };
+    std::sort(g.begin(), g.end(), [&](const std::array<int, 3>& x, const std::array<int, 3>& y) {
+        return n2(x) != n2(y) ? n2(x) < n2(y) : x < y;
+    });
+    if (ni < (int)g.size() && n2(g[ni]) == n2(g[ni - 1])) return {};
+    g.resize(ni);
+    return g;
+}
 
 // ---- the tau-domain solvers: host tables and the layout of the caller's work buffer ----
 // Trapezoid increments of a grid: (t_{i+1} - t_{i-1}) / 2 inside, half intervals at the ends.
@@ -398,6 +438,7 @@ int msgw_set_problem(msgw_ctx* c, const msgw_problem* p) {
         c->ef = std::move(ef);
         c->eb = std::move(eb);
         c->have_problem = true;
+        c->sym_set = false;
         c->prep = msgw_ctx::Prepared();
         c->ws_ready = false;
         c->ws = nullptr;
@@ -407,6 +448,9 @@ int msgw_set_problem(msgw_ctx* c, const msgw_problem* p) {
 
 static size_t tables_bytes(const Host& h) {
     size_t b = 0;
+    b += align_up(sizeof(int) * size_t(h.nk) * h.nk) + align_up(sizeof(int) * h.nk);      // symmetry maps
+    b += align_up(sizeof(int) * size_t(kMaxRot) * h.nk) + align_up(sizeof(int) * size_t(kMaxRot) * h.nimax) +
+         align_up(sizeof(int) * h.nimax);                                                    // cubic generator
     b += align_up(sizeof(double) * h.ntau);
     b += align_up(sizeof(double2) * size_t(h.niw_f) * h.ntau) * 2;
     b += align_up(sizeof(double2) * size_t(h.niw_b) * h.ntau) * 2;
@@ -470,6 +514,16 @@ int msgw_set_workspace(msgw_ctx* c, void* dptr, size_t bytes) {
         d.ppre = (const int64_t*)put(h.ppre.data(), sizeof(int64_t) * (h.nk + 1));
         d.wpre = (const int64_t*)put(h.wpre.data(), sizeof(int64_t) * (h.nk + 1));
         d.vpre = (const int64_t*)put(h.vpre.data(), sizeof(int64_t) * (h.nk + 1));
+        auto room = [&](size_t n) {
+            void* p = base + off;
+            off += align_up(n);
+            return p;
+        };
+        d.sym_kmap = (int*)room(sizeof(int) * size_t(h.nk) * h.nk);
+        d.sym_star = (int*)room(sizeof(int) * h.nk);
+        d.sym_rk = (int*)room(sizeof(int) * size_t(kMaxRot) * h.nk);
+        d.sym_rg = (int*)room(sizeof(int) * size_t(kMaxRot) * h.nimax);
+        d.sym_g2 = (int*)room(sizeof(int) * h.nimax);
         need(off == tb, MSGW_EINVAL, "internal: table size mismatch");
         d.scratch = base + off;
         d.scratch_bytes = bytes - off;
@@ -480,6 +534,8 @@ int msgw_set_workspace(msgw_ctx* c, void* dptr, size_t bytes) {
         c->ws = base;
         c->ws_bytes = bytes;
         c->ws_ready = true;
+        c->sym_set = false;  // the tables live in the workspace
+        c->cubic_ni = 0;
         c->prep = msgw_ctx::Prepared();
     });
 }
@@ -970,6 +1026,139 @@ int msgw_dyson_tau(msgw_ctx* c, void* stream, int k0, int nkc, const double* eps
         a.K = reinterpret_cast<double2*>(w + L.K);
         launch_dyson_tau(a, st, L.count, nkc, eps, sigma_static, mu, Sigma_c_tau, G_tau, info);
         MSGW_HIP(hipStreamSynchronize(st));  // the host tables above are released on return
+    });
+}
+
+int msgw_set_symmetry(msgw_ctx* c, int nrot, const int* rot_k) {
+    return guarded(c, [&] {
+        require_ready(c);
+        const Host& h = c->h;
+        const int nk = h.nk;
+        need(rot_k != nullptr, MSGW_EINVAL, "null rot_k");
+        need(nrot >= 1 && nrot <= kMaxRot, MSGW_EINVAL, "nrot outside [1, 48]");
+        // every row a permutation of the grid that commutes with k - q
+        for (int r = 0; r < nrot; ++r) {
+            std::vector<char> hit(nk, 0);
+            for (int k = 0; k < nk; ++k) {
+                const int x = rot_k[size_t(r) * nk + k];
+                need(x >= 0 && x < nk && !hit[x], MSGW_EINVAL, "rot_k: a row is not a permutation of the k grid");
+                hit[x] = 1;
+            }
+            for (int q = 0; q < nk; ++q)
+                for (int k = 0; k < nk; ++k) {
+                    const int* R = rot_k + size_t(r) * nk;
+                    need(h.kmq[size_t(R[q]) * nk + R[k]] == R[h.kmq[size_t(q) * nk + k]], MSGW_EINVAL,
+                         "rot_k: R (k - q) != R k - R q");
+                }
+        }
+        // stars: each orbit represented by its smallest q, members with the first operation reaching them
+        std::vector<int> ibz, off(1, 0), star, rep_of(nk, -1), op_of(nk, -1);
+        for (int q = 0; q < nk; ++q) {
+            if (rep_of[q] >= 0) continue;
+            ibz.push_back(q);
+            for (int r = 0; r < nrot; ++r) {
+                const int qp = rot_k[size_t(r) * nk + q];
+                if (rep_of[qp] >= 0) continue;
+                rep_of[qp] = q;
+                op_of[qp] = r;
+                star.push_back(qp);
+            }
+            off.push_back((int)star.size());
+        }
+        need((int)star.size() == nk, MSGW_EINVAL, "rot_k: the operations do not close into orbits");
+        // kmap[q'][k] = R^-1 k for the operation R that maps the representative of q' onto q'
+        std::vector<int> kmap(size_t(nk) * nk);
+        for (int qp = 0; qp < nk; ++qp) {
+            const int* R = rot_k + size_t(op_of[qp]) * nk;
+            for (int k = 0; k < nk; ++k) kmap[size_t(qp) * nk + R[k]] = k;
+        }
+        MSGW_HIP(hipMemcpy(c->d.sym_kmap, kmap.data(), sizeof(int) * kmap.size(), hipMemcpyHostToDevice));
+        MSGW_HIP(hipMemcpy(c->d.sym_star, star.data(), sizeof(int) * nk, hipMemcpyHostToDevice));
+        c->sym_ibz = ibz;
+        c->sym_off = off;
+        c->sym_star = star;
+        c->sym_rep_of = rep_of;
+        c->sym_set = true;
+    });
+}
+
+int msgw_ibz(const msgw_ctx* cc, int* n_ibz, int* q_ibz, int* star_size) {
+    msgw_ctx* c = const_cast<msgw_ctx*>(cc);
+    return guarded(c, [&] {
+        need(c->sym_set, MSGW_EINVAL, "no symmetry set (msgw_set_symmetry)");
+        need(n_ibz != nullptr, MSGW_EINVAL, "null n_ibz");
+        *n_ibz = (int)c->sym_ibz.size();
+        for (size_t i = 0; i < c->sym_ibz.size(); ++i) {
+            if (q_ibz) q_ibz[i] = c->sym_ibz[i];
+            if (star_size) star_size[i] = c->sym_off[i + 1] - c->sym_off[i];
+        }
+    });
+}
+
+int msgw_sigma_star(msgw_ctx* c, void* stream, int q_ibz, const double* C_tau, const double* C_x, double* Sigma_tau,
+                    double* Sigma_x) {
+    return guarded(c, [&] {
+        require_ready(c);
+        need(c->sym_set, MSGW_EINVAL, "no symmetry set (msgw_set_symmetry)");
+        need(c->h.sigma_mode == MSGW_SIGMA_DIAG, MSGW_ENOTSUP, "msgw_sigma_star: MSGW_SIGMA_DIAG only");
+        need(C_tau && Sigma_tau, MSGW_EINVAL, "null pointer");
+        need((C_x == nullptr) == (Sigma_x == nullptr), MSGW_EINVAL, "give both C_x and Sigma_x or neither");
+        const auto it = std::find(c->sym_ibz.begin(), c->sym_ibz.end(), q_ibz);
+        need(it != c->sym_ibz.end(), MSGW_EINVAL, "q_ibz is not an irreducible q");
+        const int i = int(it - c->sym_ibz.begin());
+        launch_sigma_star(c->d, c->h, S(stream), c->d.sym_kmap, c->d.sym_star, c->sym_off[i], c->sym_off[i + 1], C_tau,
+                          C_x, Sigma_tau, Sigma_x);
+    });
+}
+
+int msgw_synth_M_cubic(msgw_ctx* c, void* stream, uint64_t seed, int q0, int nq, int m_dtype, void* M) {
+    return guarded(c, [&] {
+        require_ready(c);
+        check_qrange(c, q0, nq);
+        need(M != nullptr, MSGW_EINVAL, "null M");
+        need(m_dtype == MSGW_C128 || m_dtype == MSGW_C64, MSGW_EINVAL, "bad m_dtype");
+        const Host& h = c->h;
+        int n = 1;
+        while (n * n * n < h.nk) ++n;
+        need(n * n * n == h.nk, MSGW_ESHAPE, "the cubic generator needs an n x n x n grid (k = (i1 n + i2) n + i3)");
+        for (int k = 0; k < h.nk; ++k) need(h.nb[k] == h.nb[0], MSGW_ESHAPE, "the cubic generator needs one band count");
+        for (int q = 0; q < h.nk; ++q) need(h.ni[q] == h.ni[0], MSGW_ESHAPE, "the cubic generator needs one NI");
+        const int ni = h.ni[0];
+        const auto g = shell_basis(ni);
+        need(!g.empty(), MSGW_ESHAPE, "NI does not close a shell of reciprocal-lattice vectors");
+        if (c->cubic_ni == ni) {  // tables already in the workspace
+            launch_synth_cubic(c->d, h, S(stream), seed, q0, nq, m_dtype, M, c->d.sym_rk, c->d.sym_rg, c->d.sym_g2);
+            return;
+        }
+        const auto ops = cubic_ops();
+        std::map<std::array<int, 3>, int> index;
+        for (int i = 0; i < ni; ++i) index[g[i]] = i;
+        std::vector<int> rk(size_t(kMaxRot) * h.nk), rg(size_t(kMaxRot) * ni), g2(ni);
+        for (int r = 0; r < kMaxRot; ++r) {
+            const IMat& R = ops[r];
+            for (int k = 0; k < h.nk; ++k) {
+                const int ik[3] = {k / (n * n), (k / n) % n, k % n};
+                int x[3];
+                for (int a = 0; a < 3; ++a) {
+                    x[a] = 0;
+                    for (int b = 0; b < 3; ++b) x[a] += R.m[a][b] * ik[b];
+                    x[a] = ((x[a] % n) + n) % n;
+                }
+                rk[size_t(r) * h.nk + k] = (x[0] * n + x[1]) * n + x[2];
+            }
+            for (int i = 0; i < ni; ++i) {
+                std::array<int, 3> y{};
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) y[a] += R.m[a][b] * g[i][b];
+                rg[size_t(r) * ni + i] = index.at(y);
+            }
+        }
+        for (int i = 0; i < ni; ++i) g2[i] = g[i][0] * g[i][0] + g[i][1] * g[i][1] + g[i][2] * g[i][2];
+        MSGW_HIP(hipMemcpy(c->d.sym_rk, rk.data(), sizeof(int) * rk.size(), hipMemcpyHostToDevice));
+        MSGW_HIP(hipMemcpy(c->d.sym_rg, rg.data(), sizeof(int) * rg.size(), hipMemcpyHostToDevice));
+        MSGW_HIP(hipMemcpy(c->d.sym_g2, g2.data(), sizeof(int) * g2.size(), hipMemcpyHostToDevice));
+        c->cubic_ni = ni;
+        launch_synth_cubic(c->d, h, S(stream), seed, q0, nq, m_dtype, M, c->d.sym_rk, c->d.sym_rg, c->d.sym_g2);
     });
 }
 

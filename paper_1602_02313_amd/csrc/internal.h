@@ -58,6 +58,12 @@ struct Dev {
     const int64_t* ppre = nullptr;    // [nk+1]  prefix over q of ntau*NI_q^2
     const int64_t* wpre = nullptr;    // [nk+1]  prefix over q of niw_b*NI_q^2
     const int64_t* vpre = nullptr;    // [nk+1]  prefix over q of NI_q
+    // crystal symmetry tables (written by msgw_set_symmetry / msgw_synth_M_cubic)
+    int* sym_kmap = nullptr;          // [nk][nk]  R^-1 k for the operation R that maps q's representative onto q
+    int* sym_star = nullptr;          // [nk]      the q of every star, grouped by representative
+    int* sym_rk = nullptr;            // [48][nk]  cubic generator: index of R k
+    int* sym_rg = nullptr;            // [48][nimax] cubic generator: index of R G_I
+    int* sym_g2 = nullptr;            // [nimax]   cubic generator: |G_I|^2
     char* scratch = nullptr;          // per-call scratch
     size_t scratch_bytes = 0;
     int kb0 = 0, kb1 = 0;             // k blocks [kb0, kb1) of the pair-space contractions
@@ -173,6 +179,13 @@ inline char* scratch_mfma(const Dev& d, const Host& h) { return d.scratch + scra
 inline size_t scratch_mfma_bytes(const Dev& d, const Host& h) {
     return d.scratch_bytes > scratch_E_bytes(h) ? d.scratch_bytes - scratch_E_bytes(h) : 0;
 }
+
+// ---- crystal symmetry (k_misc.hip) ----
+constexpr int kMaxRot = 48;
+void launch_synth_cubic(const Dev& d, const Host& h, hipStream_t s, uint64_t seed, int q0, int nq, int m_dtype,
+                        void* M, const int* rk, const int* rg, const int* g2);
+void launch_sigma_star(const Dev& d, const Host& h, hipStream_t s, const int* kmap, const int* star, int s0,
+                       int s1, const double* C, const double* Cx, double* S, double* Sx);
 
 // ---- batched Gauss-Jordan (k_gj.hip) ----
 constexpr int GJ_INVERT = 0;  // A <- A^-1 (columns permuted by the pivot swaps)

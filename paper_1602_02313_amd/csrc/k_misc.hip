@@ -162,6 +162,57 @@ __global__ void k_synth(const int* __restrict__ kmq, const int* __restrict__ nb,
         reinterpret_cast<double2*>(M)[at] = make_double2(re, im);
 }
 
+// Cubic-symmetric M (harness-only input generation, the twin of the host generator): one draw per
+// orbit of (k, q, G) under the 48 operations of O_h, keyed by the orbit's smallest (q' nk + k') NI + I'.
+// rk: [48][nk] index of R k; rg: [48][NI] index of R G_I; g2: [NI] |G_I|^2.  One work-group per (q, k, I)
+// row of nb x nb band pairs.
+__global__ __launch_bounds__(256) void k_synth_cubic(const int* __restrict__ rk, const int* __restrict__ rg,
+                                                     const int* __restrict__ g2, const int64_t* __restrict__ moff,
+                                                     const int64_t* __restrict__ mpre, int nk, int nI, int nb,
+                                                     int q0, uint64_t seed, int c64, void* __restrict__ M) {
+    const int row = blockIdx.x;  // (qrel, k, I)
+    const int I = row % nI, k = (row / nI) % nk, q = q0 + row / (nI * nk);
+    uint64_t key = ~uint64_t(0);
+    for (int r = 0; r < 48; ++r) {
+        const uint64_t x = (uint64_t(rk[r * nk + q]) * nk + uint64_t(rk[r * nk + k])) * uint64_t(nI) + rg[r * nI + I];
+        key = x < key ? x : key;
+    }
+    const double sc = sqrt(1.0 / (1.0 + double(g2[I]) / 4.0) / 2.0);
+    const int64_t base = (mpre[q] - mpre[q0]) + moff[q * nk + k] + int64_t(I) * nb * nb;
+    for (int e = threadIdx.x; e < nb * nb; e += 256) {
+        uint32_t c[4] = {uint32_t(key), uint32_t(key >> 32), uint32_t(e), 0x4D435542u};
+        philox10(c, uint32_t(seed), uint32_t(seed >> 32));
+        const double u1 = u53(c[0], c[1]), u2 = u53(c[2], c[3]);
+        const double rad = sqrt(-2.0 * log(u1)), ang = 2.0 * kPi * u2;
+        const double re = sc * (rad * cos(ang)), im = sc * (rad * sin(ang));
+        if (c64)
+            reinterpret_cast<float2*>(M)[base + e] = make_float2(float(re), float(im));
+        else
+            reinterpret_cast<double2*>(M)[base + e] = make_double2(re, im);
+    }
+}
+
+// Sigma[k] += sum over the star of q_ibz of C[R^-1 k] (kmap[q'][k] = R^-1 k for the operation R that
+// maps q_ibz onto the star member q'), for Sigma^c (ntau values per state) and Sigma^x (one).
+__global__ __launch_bounds__(256) void k_sigma_star(const int* __restrict__ kmap, const int* __restrict__ star,
+                                                    int s0, int s1, int nk, int nbmax, int ntau,
+                                                    const double* __restrict__ C, const double* __restrict__ Cx,
+                                                    double* __restrict__ S, double* __restrict__ Sx) {
+    const int64_t per = int64_t(nbmax) * ntau;
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= int64_t(nk) * per) return;
+    const int k = int(e / per);
+    const int64_t rest = e - int64_t(k) * per;
+    double acc = 0.0, accx = 0.0;
+    for (int i = s0; i < s1; ++i) {
+        const int kk = kmap[int64_t(star[i]) * nk + k];
+        acc += C[int64_t(kk) * per + rest];
+        if (Cx && rest % ntau == 0) accx += Cx[int64_t(kk) * nbmax + rest / ntau];
+    }
+    S[e] += acc;
+    if (Sx && rest % ntau == 0) Sx[int64_t(k) * nbmax + rest / ntau] += accx;
+}
+
 // ---------------------------------------------------------------------------------------------
 // forward transform: out[b][n][e] = sum_i W[n][i] (f[b][i][e] - G0(E, tau_i)) (+ 1/(i w_n - E))
 // ---------------------------------------------------------------------------------------------
@@ -733,6 +784,23 @@ __global__ __launch_bounds__(1024) void k_gap_given(const double* __restrict__ E
 }
 
 }  // namespace
+
+void launch_synth_cubic(const Dev& d, const Host& h, hipStream_t s, uint64_t seed, int q0, int nq, int m_dtype,
+                        void* M, const int* rk, const int* rg, const int* g2) {
+    const int nI = h.ni[q0], nb = h.nb[0];
+    const dim3 grid(unsigned(int64_t(nq) * h.nk * nI));
+    MSGW_LAUNCH(k_synth_cubic, grid, dim3(256), 0, s, rk, rg, g2, d.moff, d.mpre, h.nk, nI, nb, q0, seed,
+                m_dtype == MSGW_C64 ? 1 : 0, M);
+    MSGW_HIP(hipGetLastError());
+}
+
+void launch_sigma_star(const Dev& d, const Host& h, hipStream_t s, const int* kmap, const int* star, int s0,
+                       int s1, const double* C, const double* Cx, double* S, double* Sx) {
+    const int64_t n = int64_t(h.nk) * h.nbmax * h.ntau;
+    MSGW_LAUNCH(k_sigma_star, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, kmap, star, s0, s1, h.nk, h.nbmax,
+                h.ntau, C, Cx, S, Sx);
+    MSGW_HIP(hipGetLastError());
+}
 
 void launch_gap_given(const Dev& d, const Host& h, hipStream_t s, const double* E, int n_index, double* gap) {
     MSGW_LAUNCH(k_gap_given, dim3(1), dim3(1024), 0, s, E, h.nk, h.nbmax, d.nb, n_index, gap);

@@ -71,6 +71,23 @@ class SynthM:
         return out
 
 
+class SynthCubicM(SynthM):
+    """M with the symmetry of a cubic crystal, generated on the device by msgw_synth_M_cubic."""
+
+    def __init__(self, seed):
+        super().__init__(seed, True)
+
+    def __call__(self, run, q0, nq):
+        import torch
+        size = int(run.mpre[q0 + nq] - run.mpre[q0])
+        ct = torch.complex128 if run.m_dtype == L.C128 else torch.complex64
+        if self.buf is None or self.buf.numel() < size or self.buf.dtype != ct:
+            self.buf = torch.empty(size, dtype=ct, device=run.device)
+        out = self.buf[:size]
+        run.ctx.synth_M_cubic(self.seed, q0, nq, run.m_dtype, out, stream=run.stream)
+        return out
+
+
 class EventTimer:
     """HIP events recorded around each library call on the launch stream.
 
@@ -195,6 +212,17 @@ class GWRun:
         self.info = torch.zeros(self.q_batch * self.niw_b, dtype=torch.int32, device=dev)
         self.W_frozen = None
         self.timer = None
+        self.ibz = None  # irreducible q (set_symmetry): the passes run over these and their stars
+
+    def set_symmetry(self, rot_k):
+        """Use the point group given by its action on the k grid (rot_k[r][k] = index of R_r k): the
+        self-energy passes then compute P, W~ and the contractions for the irreducible q only and add
+        each one's contributions over its star (msgw_sigma_star).  DIAG mode."""
+        import torch
+        self.ctx.set_symmetry(rot_k)
+        self.ibz, self.star_size = self.ctx.ibz()
+        self.C_tau = torch.zeros_like(self.sig_tau)
+        self.C_x = torch.zeros_like(self.sig_x)
 
     def _t(self, name):
         return self.timer(name) if self.timer is not None else contextlib.nullcontext()
@@ -263,12 +291,30 @@ class GWRun:
                 self.ctx.tau_to_iw(L.FERMION, self.nk * self.nbmax, 1, self.sig_tau, 0, None,
                                    self.sig_iw, stream=self.stream)
 
+    def q_block_star(self, M_source, q, keep=None):
+        """An irreducible q: P, W~ and its contributions to every k, added over its star."""
+        self.C_tau.zero_()
+        self.C_x.zero_()
+        sig, sx = self.sig_tau, self.sig_x
+        self.sig_tau, self.sig_x = self.C_tau, self.C_x
+        try:
+            self.q_block(M_source, q, 1, keep=keep)
+        finally:
+            self.sig_tau, self.sig_x = sig, sx
+        with self._t("sigma_star"):
+            self.ctx.sigma_star(q, self.C_tau, self.C_x, self.sig_tau, self.sig_x, stream=self.stream)
+
     def sigma_pass(self, M_source, keep_W=False):
-        """Sigma^c(tau), Sigma^x and Sigma^c(i w) from the current G (all q)."""
+        """Sigma^c(tau), Sigma^x and Sigma^c(i w) from the current G (all q, or the irreducible q and
+        their stars once set_symmetry was called)."""
         self.begin_pass()
         keep = {} if keep_W else None
-        for q0, nq in self._batches():
-            self.q_block(M_source, q0, nq, keep=keep)
+        if self.ibz is not None:
+            for q in self.ibz:
+                self.q_block_star(M_source, q, keep=keep)
+        else:
+            for q0, nq in self._batches():
+                self.q_block(M_source, q0, nq, keep=keep)
         if keep_W:
             self.W_frozen = keep
         self.sigma_to_iw()
