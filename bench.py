@@ -262,6 +262,117 @@ def batching_study(args):
                       "unit": "ms", **res}), flush=True)
 
 
+def queue_study(args):
+    """The pair-space polarization of one q batch with a static grid (hardware dispatch of an
+    XCD-ordered work list, equal item counts per XCD) against its persistent form (one work-group per CU
+    taking items from per-XCD device queues cut by equal cost, items in decreasing cost), on the uneven
+    workload: 6x6x6 k, Nb_k in [96, 160], NI_q in [500, 900], q = 0..nq-1 in one call.  Prints one JSON
+    line with both times and the difference of the results."""
+    import torch
+    import gwinputs as gi
+    import paper_1602_02313_amd as amd
+
+    cfg = gi.CONFIGS["c4"]
+    prob = gi.make_problem(cfg)
+    nq = args.q_batch
+    B = {"f16x3": amd.F16X3, "bf16x3": amd.BF16X3}[args.precision]
+    run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
+                    cfg.scale, prob.eps, prob.v, prob.n_target, precision=B, q_batch=nq)
+    M = torch.empty(int(run.mpre[nq]), dtype=torch.complex64, device="cuda")
+    run.ctx.synth_M(cfg.seed, 0, nq, 1, amd.C64, M)
+    run.green0(0.0)
+    names = run.ctx.variants(amd.OP_POLARIZATION, B)
+    vq = next(i for i, n in enumerate(names) if "queue" in n)
+    fp, _ = flop_model(prob, qs=range(nq))
+    log(f"[queue] {cfg.name} q 0..{nq - 1}, NI {list(prob.ni[:nq])}: M {M.numel() * 8 / 1e9:.1f} GB")
+    res, outs = {}, {}
+    for label, v in (("static_grid", 0), ("persistent_queue", vq)):
+        run.ctx.set_variant(amd.OP_POLARIZATION, B, v)
+        ts = []
+        for rep in range(3):
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            run.ctx.polarization(0, nq, M, amd.C64, run.G_tau, B, run.P_tau)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+            log(f"[queue] {label} rep {rep}: {ts[-1]:.1f} ms")
+        t = min(ts[1:])
+        res[label] = {"variant": names[v], "ms": round(t, 1), "dense_tflops": round(fp / (t / 1e3) / 1e12, 1)}
+        outs[label] = run.P_tau[: int(run.ppre[nq])].clone()
+    a, b = outs["static_grid"], outs["persistent_queue"]
+    print(json.dumps({"study": "persistent work queue vs static grid, pair-space polarization of one q batch",
+                      "workload": f"{cfg.name}: q 0..{nq - 1} (NI {[int(x) for x in prob.ni[:nq]]}), {cfg.nk} k "
+                                  f"blocks with Nb_k in [96, 160], {prob.tau.size} tau points, {args.precision}",
+                      **res, "queue_over_static": round(res["persistent_queue"]["ms"] / res["static_grid"]["ms"], 3),
+                      "rel_diff": float((a - b).abs().norm() / a.abs().norm())}), flush=True)
+
+
+def symmetry_study(args):
+    """One self-energy pass plus Dyson and gap over the full zone against the irreducible-wedge pass
+    (P, W~ and the contractions for the irreducible q only, contributions added over the stars), on
+    the metric's workload shapes with the symmetry of a cubic crystal: 5x5x5 k, 128 bands, NI = 691
+    (the closed shells of |G|^2 <= 29, the nearest to 700), 161 tau points, M generated on the device
+    per q (msgw_synth_M_cubic).  Prints one JSON line with both times and the difference of the results."""
+    import torch
+    import gwinputs as gi
+    import paper_1602_02313_amd as amd
+    from paper_1602_02313_amd.driver import EventTimer
+
+    base = gi.CONFIGS[args.config]
+    cfg = base.replace(name=base.name + "_cubic", ni=691)
+    prob = gi.make_cubic_problem(cfg)
+    prec = {"f16x3": amd.F16X3, "bf16x3": amd.BF16X3, "fp32": amd.FP32, "fp64": amd.FP64}[args.precision]
+    rot_k = gi.rotation_k_maps(cfg)
+    gen = amd.SynthCubicM(cfg.seed)
+    t_start = time.time()
+
+    def src(run, q0, nq):  # the device generator, with a progress line per q block (the wait costs ~0.1 ms)
+        torch.cuda.synchronize()
+        log(f"[symmetry] q {q0}..{q0 + nq - 1} at {time.time() - t_start:.0f} s")
+        return gen(run, q0, nq)
+
+    out = {}
+    results = {}
+    for mode in ("ibz", "full"):
+        run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b,
+                        cfg.scale, prob.eps, prob.v, prob.n_target, precision=prec,
+                        q_batch=1 if mode == "ibz" else args.q_batch)
+        if mode == "ibz":
+            run.set_symmetry(rot_k)
+        run.green0(0.0)
+        torch.cuda.synchronize()
+        t = EventTimer()
+        run.timer = t
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        run.sigma_pass(src)
+        run.dyson(True)
+        run.gap()
+        b.record()
+        torch.cuda.synchronize()
+        run.timer = None
+        sec = a.elapsed_time(b) / 1e3
+        nq = len(run.ibz) if mode == "ibz" else cfg.nk
+        log(f"[symmetry] {mode}: {nq} q, {sec:.1f} s")
+        out[mode] = {"q": nq, "s_per_iteration": round(sec, 2),
+                     "contraction_s": round(sum(sum(v) for k, v in t.summary().items()
+                                                if k in ("polarization", "self_energy")) / 1e3, 2)}
+        results[mode] = (run.sig_tau.clone(), run.sig_x.clone(), float(run.gap_d.item()), run.flags.item())
+        del run
+        torch.cuda.empty_cache()
+    (si, xi, gi_, fi), (sf, xf, gf, ff) = results["ibz"], results["full"]
+    print(json.dumps({
+        "study": "crystal symmetry: irreducible q with their stars vs the full zone (one iteration)",
+        "workload": f"{cfg.name}: 5x5x5 k, 128 bands, NI = 691, {prob.tau.size} tau points, {args.precision}",
+        "full_zone": out["full"], "irreducible_wedge": out["ibz"],
+        "speedup": round(out["full"]["s_per_iteration"] / out["ibz"]["s_per_iteration"], 2),
+        "sigma_c_rel_diff": float((si - sf).norm() / sf.norm()),
+        "sigma_x_rel_diff": float((xi - xf).norm() / xf.norm()),
+        "gap_diff_Ha": abs(gi_ - gf), "flags": int(fi) | int(ff)}), flush=True)
+
+
 # ---------------------------------------------------------------------------------------------
 # the FP64 GPU path on a subset of the same inputs
 # ---------------------------------------------------------------------------------------------
@@ -320,6 +431,12 @@ def main():
     ap.add_argument("--copy-mb", type=int, default=1024)
     ap.add_argument("--graph", action="store_true",
                     help="each step captured once as a HIP graph and replayed (no per-kernel times)")
+    ap.add_argument("--queue", action="store_true",
+                    help="instead of the iteration: static grid vs persistent work queue for the polarization "
+                         "of one --q-batch of the uneven workload")
+    ap.add_argument("--symmetry", action="store_true",
+                    help="instead of the iteration: full zone vs irreducible wedge on the cubic-symmetric "
+                         "form of --config (NI = 691)")
     ap.add_argument("--batching", action="store_true",
                     help="instead of the iteration: one launch vs a per-k launch loop on one q of --config "
                          "(default c4, the uneven workload)")
@@ -329,6 +446,12 @@ def main():
               f"it would shard the q axis over GPUs with one all-reduce of Sigma per iteration, which is "
               f"not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.symmetry:
+        symmetry_study(args)
+        return
+    if args.queue:
+        queue_study(args)
+        return
     if args.batching:
         if args.config == "c5":
             args.config = "c4"

@@ -1271,11 +1271,12 @@ __global__ __launch_bounds__(256) void k_gtab(Dev d, int q, const double* __rest
 // after it.  NBUF = 3: the buffer written after stage s is the one for stage s + 2, so stage s + 1 is
 // already in LDS while stage s runs and the Z of its first step is formed during the last MFMAs of
 // stage s (one barrier per stage either way).
-template <int OCC, int KS, int WI, int NTT, int NBUF = 2, int PR = PREC_BF16X3>
-__global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const float2* __restrict__ M,
-                                                        const uint32_t* __restrict__ gz,
-                                                        double2* __restrict__ P, Order od, int t0, int ntc,
-                                                        int nt_eff) {
+// One work item of the pair-space polarization: 4 WI rows I from I0 = 4 WI r, 16 columns J from
+// J0 = 16 (c / ntc), tau chunk c % ntc of the launch, over all k blocks of q = q0 + qrel.
+template <int OCC, int KS, int WI, int NTT, int NBUF, int PR>
+__device__ __forceinline__ void polz_item(const Dev& d, int q0, const float2* __restrict__ M,
+                                          const uint32_t* __restrict__ gz, double2* __restrict__ P, int qrel,
+                                          int r, int c, int t0, int ntc, int nt_eff) {
     constexpr int NT = 128 * WI, XROWS = 4 * WI + 16, CW = 32 * NTT;
     static_assert(KS % GZ_KS == 0, "stages hold whole 32-K slabs of the g planes");
     static_assert((XROWS * KS) % NT == 0 && (2 * CW * KS / 8) % NT == 0, "stage split over threads");
@@ -1283,8 +1284,6 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     static_assert(NBUF == 2 || (NBUF == 3 && (KS / 16) % 2 == 0), "three buffers need an even step count");
     __shared__ float Xs[NBUF][XROWS][XR];     // [buffer][row: 4 WI rows I then 16 rows J][K re, im]
     __shared__ uint32_t Gs[NBUF][2][CW][GR];  // [buffer][hi, lo][tau][K pair]
-    int qrel, r, c;
-    if (!work_item(od, qrel, r, c)) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r32 = lane & 31, h2 = lane >> 5;
     const int q = q0 + qrel, nk = d.nk, ntau = d.ntau;
     const int NI = d.ni[q];
@@ -1658,6 +1657,45 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
         slab = s2;
         nsl = n2;
         blk = b2;
+    }
+}
+
+template <int OCC, int KS, int WI, int NTT, int NBUF = 2, int PR = PREC_BF16X3>
+__global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const float2* __restrict__ M,
+                                                        const uint32_t* __restrict__ gz,
+                                                        double2* __restrict__ P, Order od, int t0, int ntc,
+                                                        int nt_eff) {
+    int qrel, r, c;
+    if (!work_item(od, qrel, r, c)) return;
+    polz_item<OCC, KS, WI, NTT, NBUF, PR>(d, q0, M, gz, P, qrel, r, c, t0, ntc, nt_eff);
+}
+
+// Persistent form: a fixed set of work-groups (the CUs' worth) takes items from a device queue per XCD.
+// The host lists the call's working items (all q of the batch) in decreasing cost, cuts the list into 8
+// contiguous parts of equal cost (one per XCD, so the items that share M rows stay on one L2) and a
+// work-group on XCD x takes the next item of part x from counter x until the part is exhausted; every
+// work-group leaves the loop when its part is empty.  items: qrel << 24 | r << 12 | c.
+template <int OCC, int KS, int WI, int NTT, int NBUF = 2, int PR = PREC_BF16X3>
+__global__ __launch_bounds__(128 * WI, OCC) void k_polz_queue(Dev d, int q0, const float2* __restrict__ M,
+                                                              const uint32_t* __restrict__ gz,
+                                                              double2* __restrict__ P, const int* __restrict__ items,
+                                                              const int* __restrict__ part, int* __restrict__ counter,
+                                                              int t0, int ntc, int nt_eff) {
+    __shared__ int s_item;
+    const int x = int(blockIdx.x & 7);
+    const int n = part[x + 1] - part[x];
+    while (true) {
+        if (threadIdx.x == 0) {
+            const int i = atomicAdd(&counter[x], 1);
+            s_item = i < n ? items[part[x] + i] : -1;
+        }
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();  // s_item is read by all before the next item's write
+        if (it < 0) return;
+        polz_item<OCC, KS, WI, NTT, NBUF, PR>(d, q0, M, gz, P, it >> 24, (it >> 12) & 4095, it & 4095, t0, ntc,
+                                              nt_eff);
+        __syncthreads();  // the item's LDS reads are done before the next item stages into LDS
     }
 }
 
@@ -2035,7 +2073,7 @@ int64_t gz_elems(const Host& h, int q0, int nq) {
     return n;
 }
 
-template <int OCC, int SR, int SC, int KS = GZ_KS, int WI = 2, int NBUF = 2, int PR = PREC_BF16X3>
+template <int OCC, int SR, int SC, int KS = GZ_KS, int WI = 2, int NBUF = 2, int PR = PREC_BF16X3, bool QUEUE = false>
 void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, void* P) {
     int maxi = 0, maxk = 0;
@@ -2079,10 +2117,71 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
                         t0, ntc, nt_eff);
         }, rows);
     };
+    // the persistent form: the call's working items in decreasing cost (the k blocks' padded K of their
+    // q), cut into 8 contiguous parts of equal cost, one queue per XCD in the scratch after the g planes
+    const size_t gz_bytes = size_t(gz_elems(h, q0, nq)) * 2;
+    auto launch_queue = [&](auto kern, int t0, int ntc) {
+        // the host copy stays untouched until its upload has run: the previous upload's event is waited
+        // for before the buffer is refilled
+        static thread_local std::vector<int> host;
+        static thread_local hipEvent_t uploaded = nullptr;
+        if (uploaded) MSGW_HIP(hipEventSynchronize(uploaded));
+        else MSGW_HIP(hipEventCreateWithFlags(&uploaded, hipEventDisableTiming));
+        if (nq > 127) throw Error(MSGW_ENOTSUP, "the polarization's work queue takes at most 127 q per call");
+        std::vector<std::pair<int64_t, int>> it;     // (cost, item)
+        for (int qrel = 0; qrel < nq; ++qrel) {
+            const int q = q0 + qrel, NI = h.ni[q];
+            int64_t cost = 0;
+            for (int k = d.kb0; k < d.kb1; ++k)
+                cost += round_up(h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]], GZ_KPAD);
+            for (int r = 0; r * 4 * WI < NI; ++r)
+                for (int c = 0; c < ceil_div(NI, 16) * ntc; ++c) {
+                    const int J0 = c / ntc * 16;
+                    if (J0 + 16 > r * 4 * WI) it.push_back({cost, (qrel << 24) | (r << 12) | c});
+                }
+        }
+        if (it.empty()) return;
+        std::stable_sort(it.begin(), it.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        int64_t total = 0;
+        for (const auto& e : it) total += e.first;
+        // [items (n)] [part (9)] [pad] [counters (8), 8-B aligned for the fill kernel]
+        const size_t n = it.size(), off_cnt = round_up(int(n + 9), 2);
+        host.assign(off_cnt + 8, 0);
+        int x = 1;
+        int64_t run = 0;
+        for (size_t i = 0; i < n; ++i) {
+            host[i] = it[i].second;
+            while (x < 8 && run >= total * x / 8) host[n + x++] = int(i);
+            run += it[i].first;
+        }
+        while (x < 8) host[n + x++] = int(n);
+        host[n + 8] = int(n);  // part[0] = 0 already
+        const size_t bytes = sizeof(int) * host.size();
+        if (gz_bytes + 256 + bytes > scratch_mfma_bytes(d, h))
+            throw Error(MSGW_ENOMEM, "workspace too small for the polarization's work queue");
+        int* dev = reinterpret_cast<int*>(scratch_mfma(d, h) + scratch_al(gz_bytes));
+        MSGW_HIP(hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, s));
+        MSGW_HIP(hipEventRecord(uploaded, s));
+        // the counters start at zero (a fill kernel, so that the call stays capturable)
+        MSGW_LAUNCH(k_fill_u64, dim3(1), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(dev + off_cnt), 4);
+        int dev_id = 0, cus = 0;
+        MSGW_HIP(hipGetDevice(&dev_id));
+        MSGW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
+        const unsigned grid = unsigned(8 * ceil_div(cus, 8) * OCC);
+        MSGW_LAUNCH(kern, dim3(grid), dim3(128 * WI), 0, s, d, q0, (const float2*)M, (const uint32_t*)gz, (double2*)P,
+                    dev, dev + n, dev + off_cnt, t0, ntc, nt_eff);
+        MSGW_HIP(hipGetLastError());
+    };
     record_kernel_event(d, MSGW_OP_POLARIZATION, false, s);
-    if (n3 > 0) launch(k_polz<OCC, KS, WI, 3, NBUF, PR>, 0, n3);
-    if (rest == 1) launch(k_polz<OCC, KS, WI, 1, NBUF, PR>, 96 * n3, 1);
-    if (rest == 2) launch(k_polz<OCC, KS, WI, 2, NBUF, PR>, 96 * n3, 1);
+    if constexpr (QUEUE) {
+        if (n3 > 0) launch_queue(k_polz_queue<OCC, KS, WI, 3, NBUF, PR>, 0, n3);
+        if (rest == 1) launch_queue(k_polz_queue<OCC, KS, WI, 1, NBUF, PR>, 96 * n3, 1);
+        if (rest == 2) launch_queue(k_polz_queue<OCC, KS, WI, 2, NBUF, PR>, 96 * n3, 1);
+    } else {
+        if (n3 > 0) launch(k_polz<OCC, KS, WI, 3, NBUF, PR>, 0, n3);
+        if (rest == 1) launch(k_polz<OCC, KS, WI, 1, NBUF, PR>, 96 * n3, 1);
+        if (rest == 2) launch(k_polz<OCC, KS, WI, 2, NBUF, PR>, 96 * n3, 1);
+    }
     record_kernel_event(d, MSGW_OP_POLARIZATION, true, s);
 }
 
@@ -2174,6 +2273,7 @@ const PolVariant kPolBF16[] = {
 };
 const PolVariant kPolF16[] = {
     {"pair-space 16x16 pairs K64 st4x8 3-buffer", run_polz<1, 4, 8, 64, 4, 3, PREC_F16X3>, true},
+    {"pair-space 16x16 pairs K64 3-buffer persistent LPT queue", run_polz<1, 4, 8, 64, 4, 3, PREC_F16X3, true>, true},
     {"pair-space 16x16 pairs K64 st4x8", run_polz<1, 4, 8, 64, 4, 2, PREC_F16X3>, true},
     {"pair-space 8x16 pairs 2 WG/CU st4x16 K64", run_polz<2, 4, 16, 64, 2, 2, PREC_F16X3>, true},
     {"pair-space 8x16 pairs 2 WG/CU st4x16", run_polz<2, 4, 16, GZ_KS, 2, 2, PREC_F16X3>, true},
