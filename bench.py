@@ -66,11 +66,12 @@ def flop_model(prob, qs=None, ks=None):
 # the pair-space kernels: (WI, KS) of the polarization variants, by name
 POLZ_SHAPES = {
     "pair-space 16x16 pairs K64 st4x8 3-buffer": (4, 64),
+    "pair-space 16x16 pairs K64 3-buffer persistent LPT queue": (4, 64),
     "pair-space 16x16 pairs K64 st4x8": (4, 64),
     "pair-space 8x16 pairs 2 WG/CU st4x16 K64": (2, 64),
     "pair-space 8x16 pairs 2 WG/CU st4x16": (2, 32),
 }
-SIGZ_NAME = "pair-space 512 K x 8x8-pair blocks"
+SIGZ_NAMES = ("pair-space 512 K x 8x8-pair blocks", "pair-space 512 K x 8x8-pair blocks persistent LPT queue")
 
 
 def _tau_chunks(ntau):
@@ -104,7 +105,7 @@ def executed_mfma_flops(prob, op, tile, q0, nq):
                 items += sum(1 for cj in range(-(-NI // 16)) if 16 * cj + 16 > I0)
             n += items * 2 * WI * steps * 6 * sum(chunks)
         else:
-            if tile != SIGZ_NAME:
+            if tile not in SIGZ_NAMES:
                 return None
             n8 = -(-NI // 8)
             nblk = n8 * (n8 + 1) // 2
@@ -283,10 +284,11 @@ def queue_study(args):
     run.green0(0.0)
     names = run.ctx.variants(amd.OP_POLARIZATION, B)
     vq = next(i for i, n in enumerate(names) if "queue" in n)
+    vs = names.index("pair-space 16x16 pairs K64 st4x8 3-buffer")
     fp, _ = flop_model(prob, qs=range(nq))
     log(f"[queue] {cfg.name} q 0..{nq - 1}, NI {list(prob.ni[:nq])}: M {M.numel() * 8 / 1e9:.1f} GB")
     res, outs = {}, {}
-    for label, v in (("static_grid", 0), ("persistent_queue", vq)):
+    for label, v in (("static_grid", vs), ("persistent_queue", vq)):
         run.ctx.set_variant(amd.OP_POLARIZATION, B, v)
         ts = []
         for rep in range(3):

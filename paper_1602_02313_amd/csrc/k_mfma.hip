@@ -1807,22 +1807,15 @@ __global__ __launch_bounds__(256) void k_wpair(const double2* __restrict__ W, in
 // hi/lo halves (bf16 or f16), and the FP32 accumulators go through the epilogue (G_m weight, sum over
 // the m of each band n, FP64 atomic) every SZ_FLUSH_BLOCKS blocks.
 template <int OCC, int NTT, int PR = PREC_BF16X3>
-__global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* __restrict__ G,
-                                                   const float2* __restrict__ mt,
-                                                   const uint32_t* __restrict__ wz,
-                                                   double* __restrict__ Sig, int nkc, int t0, int ntc) {
+__device__ __forceinline__ void sigz_item(const Dev& d, int q0, const double* __restrict__ G,
+                                          const float2* __restrict__ mt, const uint32_t* __restrict__ wz,
+                                          double* __restrict__ Sig, int t0, int qrel, int k, int kc, int tc) {
     constexpr int CW = 32 * NTT;
     __shared__ uint32_t Ws[2][2][CW][SZ_WR];  // [buffer][hi, lo][tau][8 s x 8 j]
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int TP = gz_tp(ntau);
     // work item: (q, k, K chunk of 512, tau chunk)
-    int w = blockIdx.x;
-    const int tc = w % ntc;
-    w /= ntc;
-    const int kc = w % nkc;
-    w /= nkc;
-    const int nkr = d.kb1 - d.kb0;
-    const int k = d.kb0 + w % nkr, qrel = w / nkr, q = q0 + qrel;
+    const int q = q0 + qrel;
     const int kq = d.kmq[q * nk + k];
     const int nm = d.nb[kq], Kk = d.nb[k] * nm;
     const int K0 = kc * 512;
@@ -2021,6 +2014,44 @@ __global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* 
     }
 }
 
+template <int OCC, int NTT, int PR = PREC_BF16X3>
+__global__ __launch_bounds__(512, OCC) void k_sigz(Dev d, int q0, const double* __restrict__ G,
+                                                   const float2* __restrict__ mt,
+                                                   const uint32_t* __restrict__ wz,
+                                                   double* __restrict__ Sig, int nkc, int t0, int ntc) {
+    int w = blockIdx.x;
+    const int tc = w % ntc;
+    w /= ntc;
+    const int kc = w % nkc;
+    w /= nkc;
+    const int nkr = d.kb1 - d.kb0;
+    sigz_item<OCC, NTT, PR>(d, q0, G, mt, wz, Sig, t0, w / nkr, d.kb0 + w % nkr, kc, tc);
+}
+
+// Persistent form, as k_polz_queue: items qrel << 24 | k << 16 | kc << 8 | tc from per-XCD queues.
+template <int OCC, int NTT, int PR = PREC_BF16X3>
+__global__ __launch_bounds__(512, OCC) void k_sigz_queue(Dev d, int q0, const double* __restrict__ G,
+                                                         const float2* __restrict__ mt,
+                                                         const uint32_t* __restrict__ wz, double* __restrict__ Sig,
+                                                         const int* __restrict__ items, const int* __restrict__ part,
+                                                         int* __restrict__ counter, int t0) {
+    __shared__ int s_item;
+    const int x = int(blockIdx.x & 7);
+    const int n = part[x + 1] - part[x];
+    while (true) {
+        if (threadIdx.x == 0) {
+            const int i = atomicAdd(&counter[x], 1);
+            s_item = i < n ? items[part[x] + i] : -1;
+        }
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it < 0) return;
+        sigz_item<OCC, NTT, PR>(d, q0, G, mt, wz, Sig, t0, it >> 24, (it >> 16) & 255, (it >> 8) & 255, it & 255);
+        __syncthreads();
+    }
+}
+
 // =================================================================================================
 // variants (tile shapes) and dispatch
 // =================================================================================================
@@ -2186,7 +2217,7 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
 }
 
 // pair-space self-energy: needs only the raw W~ (FP64), so it runs its own conversions
-template <int PR>
+template <int PR, bool QUEUE = false>
 void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
               const double* G, const void* W, void* Sig) {
     int64_t nmt = 0, nwz = 0;
@@ -2223,10 +2254,65 @@ void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
                     (const float2*)mt, (const uint32_t*)wz, (double*)Sig, nkc, t0, ntc);
         MSGW_HIP(hipGetLastError());
     };
+    // the persistent form: items in decreasing cost (weight blocks x rows of the K chunk), 8 parts of
+    // equal cost, in the scratch after the transposed M and the weight blocks
+    const size_t used = scratch_al(size_t(nmt) * 8 + size_t(nwz) * 4);
+    auto launch_queue = [&](auto kern, int t0, int ntc) {
+        static thread_local std::vector<int> host;  // refilled only after its previous upload has run
+        static thread_local hipEvent_t uploaded = nullptr;
+        if (uploaded) MSGW_HIP(hipEventSynchronize(uploaded));
+        else MSGW_HIP(hipEventCreateWithFlags(&uploaded, hipEventDisableTiming));
+        if (nq > 127) throw Error(MSGW_ENOTSUP, "the self-energy's work queue takes at most 127 q per call");
+        std::vector<std::pair<int64_t, int>> it;
+        for (int qrel = 0; qrel < nq; ++qrel) {
+            const int q = q0 + qrel;
+            for (int k = d.kb0; k < d.kb1; ++k) {
+                const int Kk = h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]];
+                for (int kc = 0; kc * 512 < Kk; ++kc)
+                    for (int tc = 0; tc < ntc; ++tc)
+                        it.push_back({int64_t(std::min(512, Kk - kc * 512)) * sz_blocks(h.ni[q]),
+                                      (qrel << 24) | (k << 16) | (kc << 8) | tc});
+            }
+        }
+        if (it.empty()) return;
+        std::stable_sort(it.begin(), it.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+        int64_t total = 0;
+        for (const auto& e : it) total += e.first;
+        const size_t n = it.size(), off_cnt = round_up(int(n + 9), 2);
+        host.assign(off_cnt + 8, 0);
+        int x = 1;
+        int64_t run = 0;
+        for (size_t i = 0; i < n; ++i) {
+            host[i] = it[i].second;
+            while (x < 8 && run >= total * x / 8) host[n + x++] = int(i);
+            run += it[i].first;
+        }
+        while (x < 8) host[n + x++] = int(n);
+        host[n + 8] = int(n);
+        const size_t bytes = sizeof(int) * host.size();
+        if (used + bytes > scratch_mfma_bytes(d, h))
+            throw Error(MSGW_ENOMEM, "workspace too small for the self-energy's work queue");
+        int* dev = reinterpret_cast<int*>(scratch_mfma(d, h) + used);
+        MSGW_HIP(hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, s));
+        MSGW_HIP(hipEventRecord(uploaded, s));
+        MSGW_LAUNCH(k_fill_u64, dim3(1), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(dev + off_cnt), 4);
+        int dev_id = 0, cus = 0;
+        MSGW_HIP(hipGetDevice(&dev_id));
+        MSGW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
+        MSGW_LAUNCH(kern, dim3(unsigned(8 * ceil_div(cus, 8))), dim3(512), 0, s, d, q0, G, (const float2*)mt,
+                    (const uint32_t*)wz, (double*)Sig, dev, dev + n, dev + off_cnt, t0);
+        MSGW_HIP(hipGetLastError());
+    };
     record_kernel_event(d, MSGW_OP_SELF_ENERGY, false, s);
-    if (n3 > 0) launch(k_sigz<1, 3, PR>, 0, n3);
-    if (rest == 1) launch(k_sigz<1, 1, PR>, 96 * n3, 1);
-    if (rest == 2) launch(k_sigz<1, 2, PR>, 96 * n3, 1);
+    if constexpr (QUEUE) {
+        if (n3 > 0) launch_queue(k_sigz_queue<1, 3, PR>, 0, n3);
+        if (rest == 1) launch_queue(k_sigz_queue<1, 1, PR>, 96 * n3, 1);
+        if (rest == 2) launch_queue(k_sigz_queue<1, 2, PR>, 96 * n3, 1);
+    } else {
+        if (n3 > 0) launch(k_sigz<1, 3, PR>, 0, n3);
+        if (rest == 1) launch(k_sigz<1, 1, PR>, 96 * n3, 1);
+        if (rest == 2) launch(k_sigz<1, 2, PR>, 96 * n3, 1);
+    }
     record_kernel_event(d, MSGW_OP_SELF_ENERGY, true, s);
 }
 
@@ -2263,7 +2349,8 @@ struct SigVariant {
     SigZFn fnz = nullptr;  // raw W~ (runs its own conversions)
 };
 
-// index 0 of each table is the default (the fastest on the 4x4x4-k, 64-band, NI = 400 shapes)
+// index 0 of each table is the default (the fastest on the metric's 5x5x5-k, 128-band, NI = 700 shapes for
+// F16X3; on the 4x4x4-k, 64-band, NI = 400 shapes for the others)
 const PolVariant kPolBF16[] = {
     {"pair-space 16x16 pairs K64 st4x8 3-buffer", run_polz<1, 4, 8, 64, 4, 3>, true},
     {"pair-space 16x16 pairs K64 st4x8", run_polz<1, 4, 8, 64, 4>, true},
@@ -2272,8 +2359,8 @@ const PolVariant kPolBF16[] = {
     {"WI2 WJ2 T2", run_pol<2, 2, 2, PREC_BF16X3>},
 };
 const PolVariant kPolF16[] = {
-    {"pair-space 16x16 pairs K64 st4x8 3-buffer", run_polz<1, 4, 8, 64, 4, 3, PREC_F16X3>, true},
     {"pair-space 16x16 pairs K64 3-buffer persistent LPT queue", run_polz<1, 4, 8, 64, 4, 3, PREC_F16X3, true>, true},
+    {"pair-space 16x16 pairs K64 st4x8 3-buffer", run_polz<1, 4, 8, 64, 4, 3, PREC_F16X3>, true},
     {"pair-space 16x16 pairs K64 st4x8", run_polz<1, 4, 8, 64, 4, 2, PREC_F16X3>, true},
     {"pair-space 8x16 pairs 2 WG/CU st4x16 K64", run_polz<2, 4, 16, 64, 2, 2, PREC_F16X3>, true},
     {"pair-space 8x16 pairs 2 WG/CU st4x16", run_polz<2, 4, 16, GZ_KS, 2, 2, PREC_F16X3>, true},
@@ -2289,6 +2376,7 @@ const SigVariant kSigBF16[] = {
 };
 const SigVariant kSigF16[] = {
     {"pair-space 512 K x 8x8-pair blocks", nullptr, nullptr, run_sigz<PREC_F16X3>},
+    {"pair-space 512 K x 8x8-pair blocks persistent LPT queue", nullptr, nullptr, run_sigz<PREC_F16X3, true>},
 };
 const SigVariant kSigFP32[] = {
     {"WI2 WJ2 T4", run_sig<2, 2, 4, PREC_FP32>, nullptr},
@@ -2359,11 +2447,18 @@ size_t mfma_scratch_bytes(const Host& h, int nq_max) {
     for (int q = 0; q + nq_max <= h.nk; ++q) {
         best = std::max(best, 8 * (round_up(int(std::min<int64_t>(plane_elems(h, q, nq_max), 1 << 30)), 64) +
                                    mt_elems(h, q, nq_max)));
-        best = std::max(best, 2 * gz_elems(h, q, nq_max));
+        // the persistent forms' work queues (items, 8 part bounds, 8 counters; at most max(n3, 1) tau chunks)
+        const int64_t nch = std::max<int64_t>(1, ceil_div(h.ntau, 32) / 3);
+        int64_t pq = 0, sq = 0;
+        for (int qq = q; qq < q + nq_max; ++qq) {
+            pq += int64_t(ceil_div(h.ni[qq], 16)) * ceil_div(h.ni[qq], 16) * nch;
+            for (int k = 0; k < h.nk; ++k) sq += ceil_div(h.nb[k] * h.nb[h.kmq[size_t(qq) * h.nk + k]], 512) * nch;
+        }
+        best = std::max(best, int64_t(scratch_al(size_t(2 * gz_elems(h, q, nq_max)))) + 4 * (pq + 32));
         int64_t zs = 0;  // pair-space self-energy: FP32 transposed M and the weight blocks
         for (int qq = q; qq < q + nq_max; ++qq)
             zs += 8 * ((h.mpre[qq + 1] - h.mpre[qq]) / h.ni[qq] * sz_np8(h.ni[qq])) + 4 * sz_wq(h.ni[qq], h.ntau);
-        best = std::max(best, zs);
+        best = std::max(best, int64_t(scratch_al(size_t(zs))) + 4 * (sq + 32));
     }
     return size_t(best);
 }

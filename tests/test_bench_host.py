@@ -50,9 +50,11 @@ def test_executed_mfma_model_closed_form():
     assert got_p == want_p
     b8 = -(-NI // 8)
     want_s = nk * (-(-K // 512)) * 8 * (b8 * (b8 + 1) // 2) * 8 * 6 * tiles * 32768
-    assert bench.executed_mfma_flops(prob, 1, bench.SIGZ_NAME, 0, 1) == want_s
+    for name in bench.SIGZ_NAMES:  # the static grid and the persistent queue execute the same items
+        assert bench.executed_mfma_flops(prob, 1, name, 0, 1) == want_s
+    assert bench.executed_mfma_flops(prob, 0, "pair-space 16x16 pairs K64 3-buffer persistent LPT queue", 0, 1) == got_p
     # two q cost twice one; a tile form has no model
-    assert bench.executed_mfma_flops(prob, 1, bench.SIGZ_NAME, 3, 2) == 2 * want_s
+    assert bench.executed_mfma_flops(prob, 1, bench.SIGZ_NAMES[0], 3, 2) == 2 * want_s
     assert bench.executed_mfma_flops(prob, 0, "WI2 WJ2 T2", 0, 1) is None
     # the executed 16-bit work against the dense count of the flop model: about 3 x 3/4 (three split
     # products, real weight against complex pairs of the upper triangle) plus tau padding
