@@ -4,18 +4,22 @@
 //   GJ_INVERT  A (n x n, row stride n) is replaced by A^-1 with its columns permuted by the pivot
 //              swaps; the pivot row of every column is recorded so the caller can undo them;
 //   GJ_SOLVE   [A | B] (n x (ld - n) right-hand sides, row stride ld) is reduced until B holds A^-1 B.
-// A step handles a panel of NB columns [j0, j0 + jb) in two launches:
-//   k_gj_panel   one work-group per matrix, the panel in registers (row i in thread i mod NT, slot
-//                i / NT): per column it picks the pivot (largest |re| + |im| at or below the diagonal,
-//                the smallest row on ties), swaps the whole rows, scales the pivot row and eliminates
-//                the column from every other row.  The panel columns then hold T[:, J], the columns of
-//                the product of the step's elementary eliminations.
-//   k_gj_update  C <- C + T[:, J] C_J on every column outside the panel, for the rows outside J, on
-//                16x16x4 FP64 MFMA tiles of 64 x 64 (the rows J of T - I vanish outside J's rows).
-// The pivot rows themselves, C_J <- T_JJ C_J, need the old C_J that every update tile reads, so they
-// are finished at the start of the next step's panel kernel (or by k_gj_tail after the last step).
-// A zero pivot sets info = its column + 1 (the first one) and the elimination runs on with IEEE
-// infinities / NaN, as in the single-matrix form.
+// A step eliminates a panel of columns J = [a, a + w) within a window of columns [lo, hi):
+//   k_gj_panel   one work-group per matrix, a 16 (or 8, 4) column panel in registers (row i in thread
+//                i mod NT, slot i / NT): per column it picks the pivot (largest |re| + |im| at or below
+//                the diagonal, the smallest row on ties), swaps the whole rows (every column), scales the
+//                pivot row and eliminates the column from every other row.  The panel columns then hold
+//                T[:, J], the columns of the product of the panel's elementary eliminations.
+//   k_gj_update  C <- C + T[:, J] C_J on the window's columns outside the panel, for the rows outside
+//                J, on 16x16x4 FP64 MFMA tiles of 64 x 64 (K = w in chunks of 16).
+//   k_gj_finish  C_J <- T_JJ C_J on the same columns: the pivot rows need the old C_J that the update
+//                tiles read, so they are finished after it, 16 columns per work-group.
+// Matrices of order <= 1024 run two levels: 16-column panels update only the 64-column outer panel
+// they belong to (window [P, P + 64)); the outer panel then holds T[:, J64] of its 64 eliminations and
+// one K = 64 update (window: every column) applies them to the rest, so the whole matrix is read and
+// written once per 64 columns instead of once per 16.  Larger orders run one level with 8- or
+// 4-column panels.  A zero pivot sets info = its column + 1 (the first one) and the elimination runs on
+// with IEEE infinities / NaN, as in the single-matrix form.
 #include "internal.h"
 
 namespace msgw {
@@ -44,46 +48,29 @@ __device__ __forceinline__ double2 pick(const double2 (&row)[NB], int jj) {
     return make_double2(__longlong_as_double(rx), __longlong_as_double(ry));
 }
 
-// The columns a step with panel [j0, j0 + jb) updates.
-__device__ __forceinline__ bool gj_outside(int mode, int c, int n, int ld, int j0, int jb) {
-    return mode == GJ_INVERT ? (c < n && (c < j0 || c >= j0 + jb)) : (c >= j0 + jb && c < ld);
+// A step's columns: the window [lo, hi) (clipped to the matrix's columns) without the panel
+// [a, a + jb) when the panel lies inside it.  ov is the panel's overlap with the clipped window.
+struct GjCols {
+    int lo, hiC, a, ov;
+    __device__ int count() const { return max(0, hiC - lo - ov); }
+    __device__ int col(int cc) const {
+        const int c = lo + cc;
+        return (ov > 0 && c >= a) ? c + ov : c;
+    }
+};
+__device__ __forceinline__ GjCols gj_cols(int lo, int hi, int ncol, int a, int jb) {
+    GjCols w;
+    w.lo = lo;
+    w.hiC = min(hi, ncol);
+    w.a = a;
+    w.ov = max(0, min(w.hiC, a + jb) - max(lo, a));
+    return w;
 }
 
-// C_J <- T_JJ C_J for the pivot rows of the panel at P0 (every column that step updated).
-template <int NT, int NB>
-__device__ void gj_finish_rows(const GjArgs& g, double2* A, int n, int ld, int P0, double2 (*tjj)[NB]) {
-    const int jbp = min(NB, n - P0);
-    for (int e = threadIdx.x; e < NB * NB; e += NT) {
-        const int i = e / NB, t = e % NB;
-        tjj[i][t] = (i < jbp && t < jbp) ? A[int64_t(P0 + i) * ld + P0 + t] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    const int cend = g.mode == GJ_INVERT ? n : ld;
-    for (int c = threadIdx.x; c < cend; c += NT) {
-        if (!gj_outside(g.mode, c, n, ld, P0, jbp)) continue;
-        double2 old[NB];
-#pragma unroll
-        for (int t = 0; t < NB; ++t)
-            old[t] = t < jbp ? A[int64_t(P0 + t) * ld + c] : make_double2(0.0, 0.0);
-        // one row of T_JJ at a time (its LDS reads stay inside the column loop)
-#pragma unroll 1
-        for (int i = 0; i < jbp; ++i) {
-            double2 s = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int t = 0; t < NB; ++t) {
-                const double2 a = tjj[i][t];
-                s.x += a.x * old[t].x - a.y * old[t].y;
-                s.y += a.x * old[t].y + a.y * old[t].x;
-            }
-            A[int64_t(P0 + i) * ld + c] = s;
-        }
-    }
-    __syncthreads();
-}
-
+// swap_lo: the first column whose rows are swapped (0 when inverting; the outer panel's first column
+// when solving, since the columns left of it are no longer read)
 template <int NT, int RPT, int NB>
-__global__ __launch_bounds__(NT) void k_gj_panel(GjArgs g, int j0) {
-    __shared__ double2 tjj[NB][NB];
+__global__ __launch_bounds__(NT) void k_gj_panel(GjArgs g, int j0, int swap_lo) {
     __shared__ double rv[NT / 64];
     __shared__ int ri[NT / 64];
     __shared__ double2 srow[2][NB];
@@ -94,7 +81,6 @@ __global__ __launch_bounds__(NT) void k_gj_panel(GjArgs g, int j0) {
     int64_t off;
     gj_item(g, b, n, ld, off);
     double2* A = g.A + off;
-    if (j0 > 0 && j0 - NB < n) gj_finish_rows<NT, NB>(g, A, n, ld, j0 - NB, tjj);
     if (j0 >= n) return;
     const int jb = min(NB, n - j0);
     const int tid = threadIdx.x;
@@ -170,8 +156,8 @@ __global__ __launch_bounds__(NT) void k_gj_panel(GjArgs g, int j0) {
 #pragma unroll
                             for (int c = 0; c < NB; ++c) srow[1][c] = x[u][c];
                 }
-                for (int c = tid; c < cend; c += NT) {
-                    if (!gj_outside(g.mode, c, n, ld, j0, jb)) continue;
+                for (int c = swap_lo + tid; c < cend; c += NT) {
+                    if (c >= j0 && c < j0 + jb) continue;
                     const double2 t = A[int64_t(j) * ld + c];
                     A[int64_t(j) * ld + c] = A[int64_t(p) * ld + c];
                     A[int64_t(p) * ld + c] = t;
@@ -239,43 +225,29 @@ __global__ __launch_bounds__(NT) void k_gj_panel(GjArgs g, int j0) {
     }
 }
 
-template <int NB>
-__global__ __launch_bounds__(256) void k_gj_update(GjArgs g, int j0, int tiles_m) {
-    __shared__ double2 As[64][NB + 1];
-    __shared__ double2 Bs[NB][64];
+// C <- C + T[:, J] C_J for the rows outside J = [a, a + w) on the step's columns (window [lo, hi)
+// without the panel), K = w in chunks of 16, 64 x 64 tiles of four waves.
+template <int W>
+__global__ __launch_bounds__(256) void k_gj_update(GjArgs g, int a, int lo, int hi, int tiles_m) {
+    constexpr int KC = W < 16 ? W : 16;
+    __shared__ double2 As[64][KC + 1];
+    __shared__ double2 Bs[KC][64];
 
     const int b = blockIdx.y;
     int n, ld;
     int64_t off;
     gj_item(g, b, n, ld, off);
-    if (j0 >= n) return;
-    const int jb = min(NB, n - j0);
+    if (a >= n) return;
+    const int jb = min(W, n - a);
+    const GjCols cols = gj_cols(lo, hi, g.mode == GJ_INVERT ? n : ld, a, jb);
+    const int ncols = cols.count();
     const int row0 = (blockIdx.x % tiles_m) * 64, col0 = (blockIdx.x / tiles_m) * 64;
-    const int ncols = g.mode == GJ_INVERT ? n - jb : ld - j0 - jb;
     if (row0 >= n || col0 >= ncols) return;
     double2* A = g.A + off;
-    const bool inv_mode = g.mode == GJ_INVERT;
-    auto colmap = [&](int cc) { return inv_mode ? (cc < j0 ? cc : cc + jb) : j0 + jb + cc; };
     const int tid = threadIdx.x;
-
-    // T[rows, J] (zero on the pivot rows, which the next panel kernel finishes) and C_J[:, cols]
-    for (int e = tid; e < 64 * NB; e += 256) {
-        const int r = e / NB, t = e % NB, i = row0 + r;
-        double2 a = make_double2(0.0, 0.0);
-        if (i < n && t < jb && (i < j0 || i >= j0 + jb)) a = A[int64_t(i) * ld + j0 + t];
-        As[r][t] = a;
-    }
-    for (int e = tid; e < NB * 64; e += 256) {
-        const int t = e / 64, cc = col0 + (e % 64);
-        double2 v = make_double2(0.0, 0.0);
-        if (t < jb && cc < ncols) v = A[int64_t(j0 + t) * ld + colmap(cc)];
-        Bs[t][e % 64] = v;
-    }
-    __syncthreads();
-
-    // each wave a 32 x 32 quarter of the tile: 2 x 2 blocks of 16 x 16, real and imaginary parts
     const int lane = tid & 63, w = tid >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int r16 = lane & 15, k4 = lane >> 4;
     dbl4 cre[2][2], cim[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -284,23 +256,39 @@ __global__ __launch_bounds__(256) void k_gj_update(GjArgs g, int j0, int tiles_m
             cre[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
             cim[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
         }
-    const int r16 = lane & 15, k4 = lane >> 4;
+    for (int t0 = 0; t0 < jb; t0 += KC) {
+        // T[rows, J] (zero on the pivot rows, which k_gj_finish handles) and C_J[:, cols]
+        for (int e = tid; e < 64 * KC; e += 256) {
+            const int r = e / KC, t = e % KC, i = row0 + r;
+            double2 v = make_double2(0.0, 0.0);
+            if (i < n && t0 + t < jb && (i < a || i >= a + jb)) v = A[int64_t(i) * ld + a + t0 + t];
+            As[r][t] = v;
+        }
+        for (int e = tid; e < KC * 64; e += 256) {
+            const int t = e / 64, cc = col0 + (e % 64);
+            double2 v = make_double2(0.0, 0.0);
+            if (t0 + t < jb && cc < ncols) v = A[int64_t(a + t0 + t) * ld + cols.col(cc)];
+            Bs[t][e % 64] = v;
+        }
+        __syncthreads();
 #pragma unroll
-    for (int k0 = 0; k0 < NB; k0 += 4) {
-        double2 a[2], v[2];
+        for (int k0 = 0; k0 < KC; k0 += 4) {
+            double2 av[2], bv[2];
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi) a[bi] = As[wr + bi * 16 + r16][k0 + k4];
+            for (int bi = 0; bi < 2; ++bi) av[bi] = As[wr + bi * 16 + r16][k0 + k4];
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) v[bj] = Bs[k0 + k4][wc + bj * 16 + r16];
+            for (int bj = 0; bj < 2; ++bj) bv[bj] = Bs[k0 + k4][wc + bj * 16 + r16];
 #pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
+            for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                cre[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, v[bj].x, cre[bi][bj], 0, 0, 0);
-                cre[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[bi].y, v[bj].y, cre[bi][bj], 0, 0, 0);
-                cim[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].x, v[bj].y, cim[bi][bj], 0, 0, 0);
-                cim[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi].y, v[bj].x, cim[bi][bj], 0, 0, 0);
-            }
+                for (int bj = 0; bj < 2; ++bj) {
+                    cre[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi].x, bv[bj].x, cre[bi][bj], 0, 0, 0);
+                    cre[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[bi].y, bv[bj].y, cre[bi][bj], 0, 0, 0);
+                    cim[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi].x, bv[bj].y, cim[bi][bj], 0, 0, 0);
+                    cim[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bi].y, bv[bj].x, cim[bi][bj], 0, 0, 0);
+                }
+        }
+        __syncthreads();
     }
     // D[i][j] of a 16 x 16 block sits in lane j + 16 (i % 4), element i / 4 (A[i][k] in lane i + 16 k,
     // B[k][j] in lane j + 16 k)
@@ -312,8 +300,8 @@ __global__ __launch_bounds__(256) void k_gj_update(GjArgs g, int j0, int tiles_m
             for (int r4 = 0; r4 < 4; ++r4) {
                 const int i = row0 + wr + bi * 16 + 4 * r4 + k4;
                 const int cc = col0 + wc + bj * 16 + r16;
-                if (i < n && (i < j0 || i >= j0 + jb) && cc < ncols) {
-                    double2* p = &A[int64_t(i) * ld + colmap(cc)];
+                if (i < n && (i < a || i >= a + jb) && cc < ncols) {
+                    double2* p = &A[int64_t(i) * ld + cols.col(cc)];
                     double2 y = *p;
                     y.x += cre[bi][bj][r4];
                     y.y += cim[bi][bj][r4];
@@ -322,14 +310,41 @@ __global__ __launch_bounds__(256) void k_gj_update(GjArgs g, int j0, int tiles_m
             }
 }
 
-// the pivot rows of the last panel of every matrix whose last panel started at j0 - NB
-template <int NT, int NB>
-__global__ __launch_bounds__(NT) void k_gj_tail(GjArgs g, int j0) {
-    __shared__ double2 tjj[NB][NB];
+// C_J <- T_JJ C_J for the pivot rows J = [a, a + w) on the step's columns, 16 columns per work-group.
+template <int W>
+__global__ __launch_bounds__(256) void k_gj_finish(GjArgs g, int a, int lo, int hi) {
+    __shared__ double2 T[W][W + 1];
+    __shared__ double2 C[W][17];
+    const int b = blockIdx.y;
     int n, ld;
     int64_t off;
-    gj_item(g, blockIdx.x, n, ld, off);
-    if (j0 - NB >= 0 && j0 - NB < n) gj_finish_rows<NT, NB>(g, g.A + off, n, ld, j0 - NB, tjj);
+    gj_item(g, b, n, ld, off);
+    if (a >= n) return;
+    const int jb = min(W, n - a);
+    const GjCols cols = gj_cols(lo, hi, g.mode == GJ_INVERT ? n : ld, a, jb);
+    const int c0 = blockIdx.x * 16, nc = min(16, cols.count() - c0);
+    if (nc <= 0) return;
+    double2* A = g.A + off;
+    for (int e = threadIdx.x; e < W * W; e += 256) {
+        const int i = e / W, t = e % W;
+        T[i][t] = (i < jb && t < jb) ? A[int64_t(a + i) * ld + a + t] : make_double2(0.0, 0.0);
+    }
+    for (int e = threadIdx.x; e < W * 16; e += 256) {
+        const int t = e / 16, c = e % 16;
+        C[t][c] = (t < jb && c < nc) ? A[int64_t(a + t) * ld + cols.col(c0 + c)] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < W * 16; e += 256) {
+        const int i = e / 16, c = e % 16;
+        if (i >= jb || c >= nc) continue;
+        double2 s2 = make_double2(0.0, 0.0);
+        for (int t = 0; t < jb; ++t) {
+            const double2 x = T[i][t], y = C[t][c];
+            s2.x += x.x * y.x - x.y * y.y;
+            s2.y += x.x * y.y + x.y * y.x;
+        }
+        A[int64_t(a + i) * ld + cols.col(c0 + c)] = s2;
+    }
 }
 
 __global__ void k_gj_zero(int* p, int count) {
@@ -337,15 +352,40 @@ __global__ void k_gj_zero(int* p, int count) {
     if (i < count) p[i] = 0;
 }
 
+// one elimination step's update and finish on the window [lo, hi) without the panel [a, a + W)
+template <int W>
+void gj_apply(const GjArgs& g, int batch, int nmax, int cmax, int a, int lo, int hi, hipStream_t s) {
+    const int tiles_m = (nmax + 63) / 64, span = std::max(0, std::min(hi, cmax) - lo);
+    const int tiles_n = (span + 63) / 64;
+    if (tiles_n == 0) return;
+    MSGW_LAUNCH((k_gj_update<W>), dim3(tiles_m * tiles_n, batch), dim3(256), 0, s, g, a, lo, hi, tiles_m);
+    MSGW_LAUNCH((k_gj_finish<W>), dim3((span + 15) / 16, batch), dim3(256), 0, s, g, a, lo, hi);
+}
+
+// one level: panels of NB columns, each applied to every column of its step
 template <int NT, int RPT, int NB>
-void gj_steps(const GjArgs& g, int batch, int nmax, int cmax, hipStream_t s) {
-    const int tiles_m = (nmax + 63) / 64, tiles_n = (cmax + 63) / 64;
-    int j0 = 0;
-    for (; j0 < nmax; j0 += NB) {
-        MSGW_LAUNCH((k_gj_panel<NT, RPT, NB>), dim3(batch), dim3(NT), 0, s, g, j0);
-        MSGW_LAUNCH((k_gj_update<NB>), dim3(tiles_m * tiles_n, batch), dim3(256), 0, s, g, j0, tiles_m);
+void gj_one_level(const GjArgs& g, int batch, int nmax, int cmax, hipStream_t s) {
+    for (int j0 = 0; j0 < nmax; j0 += NB) {
+        MSGW_LAUNCH((k_gj_panel<NT, RPT, NB>), dim3(batch), dim3(NT), 0, s, g, j0, g.mode == GJ_INVERT ? 0 : j0);
+        // solving: from the panel on (a matrix whose order ends inside the panel has right-hand sides there)
+        gj_apply<NB>(g, batch, nmax, cmax, j0, g.mode == GJ_INVERT ? 0 : j0, cmax, s);
     }
-    MSGW_LAUNCH((k_gj_tail<NT, NB>), dim3(batch), dim3(NT), 0, s, g, j0);
+}
+
+// two levels: 16-column panels within 64-column outer panels (orders <= 1024, every matrix's panels
+// at the same columns; a matrix whose order ends inside a panel sees a narrower one)
+void gj_two_level(const GjArgs& g, int batch, int nmax, int cmax, hipStream_t s) {
+    constexpr int NB = 16, NBO = 64;
+    for (int P = 0; P < nmax; P += NBO) {
+        for (int j0 = P; j0 < std::min(P + NBO, nmax); j0 += NB) {
+            MSGW_LAUNCH((k_gj_panel<512, 2, NB>), dim3(batch), dim3(512), 0, s, g, j0, g.mode == GJ_INVERT ? 0 : P);
+            gj_apply<NB>(g, batch, nmax, cmax, j0, P, P + NBO, s);  // within the outer panel only
+        }
+        if (g.mode == GJ_INVERT)
+            gj_apply<NBO>(g, batch, nmax, cmax, P, 0, cmax, s);
+        else
+            gj_apply<NBO>(g, batch, nmax, cmax, P, P + NBO, cmax, s);
+    }
 }
 
 }  // namespace
@@ -358,11 +398,11 @@ void gj_run(const GjArgs& g, int batch, int nmax, int ldmax, hipStream_t s) {
     const int cmax = g.mode == GJ_INVERT ? nmax : ldmax;
     // the panel stays in registers: RPT rows of NB complex columns per thread
     if (nmax <= 1024)
-        gj_steps<512, 2, 16>(g, batch, nmax, cmax, s);
+        gj_two_level(g, batch, nmax, cmax, s);
     else if (nmax <= 2048)
-        gj_steps<512, 4, 8>(g, batch, nmax, cmax, s);
+        gj_one_level<512, 4, 8>(g, batch, nmax, cmax, s);
     else
-        gj_steps<512, 8, 4>(g, batch, nmax, cmax, s);
+        gj_one_level<512, 8, 4>(g, batch, nmax, cmax, s);
     MSGW_HIP(hipGetLastError());
 }
 

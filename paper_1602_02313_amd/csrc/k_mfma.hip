@@ -1670,8 +1670,81 @@ __global__ __launch_bounds__(128 * WI, OCC) void k_polz(Dev d, int q0, const flo
     polz_item<OCC, KS, WI, NTT, NBUF, PR>(d, q0, M, gz, P, qrel, r, c, t0, ntc, nt_eff);
 }
 
+// The persistent polarization's queue, built on the device (so that a captured call replays it):
+// the items (qrel, r, c) of every q of the call, the q in decreasing cost (the padded K of their k blocks;
+// equal costs keep the q order) and each q's items in row-major (r, c) order; part[x] is the first item
+// whose preceding items cost at least x/8 of the total, part[0] = 0, part[8] = n; the 8 counters are
+// cleared.  One work-group of 256 threads, nq <= 127.
+__global__ __launch_bounds__(256) void k_polz_qbuild(Dev d, int q0, int nq, int wi4, int ntc, int* __restrict__ items,
+                                                     int* __restrict__ part, int* __restrict__ counter) {
+    __shared__ long long cost[128], cstart[128];
+    __shared__ int cnt[128], order[128], istart[128];
+    const int tid = threadIdx.x;
+    if (tid < nq) {
+        const int q = q0 + tid, NI = d.ni[q];
+        long long c = 0;
+        for (int k = d.kb0; k < d.kb1; ++k) {
+            const int K = d.nb[k] * d.nb[d.kmq[int64_t(q) * d.nk + k]];
+            c += (K + GZ_KPAD - 1) / GZ_KPAD * GZ_KPAD;
+        }
+        const int nblk = (NI + 15) / 16;
+        int m = 0;
+        for (int r = 0; r * wi4 < NI; ++r) m += (nblk - r * wi4 / 16) * ntc;
+        cost[tid] = c;
+        cnt[tid] = m;
+    }
+    __syncthreads();
+    if (tid < nq) {
+        int rank = 0;
+        for (int u = 0; u < nq; ++u) rank += (cost[u] > cost[tid] || (cost[u] == cost[tid] && u < tid)) ? 1 : 0;
+        order[rank] = tid;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        long long cs = 0;
+        int is = 0;
+        for (int s = 0; s < nq; ++s) {
+            const int t = order[s];
+            cstart[s] = cs;
+            istart[s] = is;
+            cs += cost[t] * cnt[t];
+            is += cnt[t];
+        }
+        cstart[nq] = cs;  // the total
+        istart[nq] = is;  // n
+    }
+    __syncthreads();
+    for (int s = 0; s < nq; ++s) {
+        const int t = order[s], NI = d.ni[q0 + t];
+        const int nblk = (NI + 15) / 16, nr = (NI + wi4 - 1) / wi4;
+        for (int r = tid; r < nr; r += 256) {
+            int base = istart[s];
+            for (int rp = 0; rp < r; ++rp) base += (nblk - rp * wi4 / 16) * ntc;
+            const int c0 = r * wi4 / 16 * ntc;
+            for (int c = c0; c < nblk * ntc; ++c) items[base + c - c0] = (t << 24) | (r << 12) | c;
+        }
+    }
+    if (tid >= 1 && tid < 8) {
+        const long long th = cstart[nq] * tid / 8;
+        int p = istart[nq];
+        for (int s = 0; s < nq; ++s) {
+            const int t = order[s];
+            if (cnt[t] > 0 && cstart[s] + (long long)(cnt[t] - 1) * cost[t] >= th) {
+                p = istart[s] + (th <= cstart[s] ? 0 : int((th - cstart[s] + cost[t] - 1) / cost[t]));
+                break;
+            }
+        }
+        part[tid] = p;
+    }
+    if (tid == 0) {
+        part[0] = 0;
+        part[8] = istart[nq];
+    }
+    if (tid < 8) counter[tid] = 0;
+}
+
 // Persistent form: a fixed set of work-groups (the CUs' worth) takes items from a device queue per XCD.
-// The host lists the call's working items (all q of the batch) in decreasing cost, cuts the list into 8
+// k_polz_qbuild lists the call's working items (all q of the batch) in decreasing cost, cuts the list into 8
 // contiguous parts of equal cost (one per XCD, so the items that share M rows stay on one L2) and a
 // work-group on XCD x takes the next item of part x from counter x until the part is exhausted; every
 // work-group leaves the loop when its part is empty.  items: qrel << 24 | r << 12 | c.
@@ -2152,49 +2225,21 @@ void run_polz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     // q), cut into 8 contiguous parts of equal cost, one queue per XCD in the scratch after the g planes
     const size_t gz_bytes = size_t(gz_elems(h, q0, nq)) * 2;
     auto launch_queue = [&](auto kern, int t0, int ntc) {
-        // the host copy stays untouched until its upload has run: the previous upload's event is waited
-        // for before the buffer is refilled
-        static thread_local std::vector<int> host;
-        static thread_local hipEvent_t uploaded = nullptr;
-        if (uploaded) MSGW_HIP(hipEventSynchronize(uploaded));
-        else MSGW_HIP(hipEventCreateWithFlags(&uploaded, hipEventDisableTiming));
         if (nq > 127) throw Error(MSGW_ENOTSUP, "the polarization's work queue takes at most 127 q per call");
-        std::vector<std::pair<int64_t, int>> it;     // (cost, item)
+        // the item count (k_polz_qbuild lists them): row r holds the column blocks from r * 4 WI / 16 on
+        size_t n = 0;
         for (int qrel = 0; qrel < nq; ++qrel) {
-            const int q = q0 + qrel, NI = h.ni[q];
-            int64_t cost = 0;
-            for (int k = d.kb0; k < d.kb1; ++k)
-                cost += round_up(h.nb[k] * h.nb[h.kmq[size_t(q) * h.nk + k]], GZ_KPAD);
-            for (int r = 0; r * 4 * WI < NI; ++r)
-                for (int c = 0; c < ceil_div(NI, 16) * ntc; ++c) {
-                    const int J0 = c / ntc * 16;
-                    if (J0 + 16 > r * 4 * WI) it.push_back({cost, (qrel << 24) | (r << 12) | c});
-                }
+            const int NI = h.ni[q0 + qrel], nblk = ceil_div(NI, 16);
+            for (int r = 0; r * 4 * WI < NI; ++r) n += size_t(nblk - r * 4 * WI / 16) * ntc;
         }
-        if (it.empty()) return;
-        std::stable_sort(it.begin(), it.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
-        int64_t total = 0;
-        for (const auto& e : it) total += e.first;
-        // [items (n)] [part (9)] [pad] [counters (8), 8-B aligned for the fill kernel]
-        const size_t n = it.size(), off_cnt = round_up(int(n + 9), 2);
-        host.assign(off_cnt + 8, 0);
-        int x = 1;
-        int64_t run = 0;
-        for (size_t i = 0; i < n; ++i) {
-            host[i] = it[i].second;
-            while (x < 8 && run >= total * x / 8) host[n + x++] = int(i);
-            run += it[i].first;
-        }
-        while (x < 8) host[n + x++] = int(n);
-        host[n + 8] = int(n);  // part[0] = 0 already
-        const size_t bytes = sizeof(int) * host.size();
+        if (n == 0) return;
+        // [items (n)] [part (9)] [pad] [counters (8)]
+        const size_t off_cnt = size_t(round_up(int(n + 9), 2));
+        const size_t bytes = sizeof(int) * (off_cnt + 8);
         if (gz_bytes + 256 + bytes > scratch_mfma_bytes(d, h))
             throw Error(MSGW_ENOMEM, "workspace too small for the polarization's work queue");
         int* dev = reinterpret_cast<int*>(scratch_mfma(d, h) + scratch_al(gz_bytes));
-        MSGW_HIP(hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, s));
-        MSGW_HIP(hipEventRecord(uploaded, s));
-        // the counters start at zero (a fill kernel, so that the call stays capturable)
-        MSGW_LAUNCH(k_fill_u64, dim3(1), dim3(256), 0, s, reinterpret_cast<unsigned long long*>(dev + off_cnt), 4);
+        MSGW_LAUNCH(k_polz_qbuild, dim3(1), dim3(256), 0, s, d, q0, nq, 4 * WI, ntc, dev, dev + n, dev + off_cnt);
         int dev_id = 0, cus = 0;
         MSGW_HIP(hipGetDevice(&dev_id));
         MSGW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
@@ -2258,6 +2303,11 @@ void run_sigz(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const 
     // equal cost, in the scratch after the transposed M and the weight blocks
     const size_t used = scratch_al(size_t(nmt) * 8 + size_t(nwz) * 4);
     auto launch_queue = [&](auto kern, int t0, int ntc) {
+        // the queue is built on the host and uploaded, which a captured graph could not replay
+        hipStreamCaptureStatus capturing = hipStreamCaptureStatusNone;
+        MSGW_HIP(hipStreamIsCapturing(s, &capturing));
+        if (capturing != hipStreamCaptureStatusNone)
+            throw Error(MSGW_ENOTSUP, "the persistent self-energy variant cannot be captured in a graph");
         static thread_local std::vector<int> host;  // refilled only after its previous upload has run
         static thread_local hipEvent_t uploaded = nullptr;
         if (uploaded) MSGW_HIP(hipEventSynchronize(uploaded));
