@@ -311,6 +311,56 @@ def queue_study(args):
                       "rel_diff": float((a - b).abs().norm() / a.abs().norm())}), flush=True)
 
 
+def screen_study(args):
+    """The FP64 screen (msgw_screen: the batched Gauss-Jordan inversion of 1 - v^1/2 P v^1/2 and the
+    forming of W~ and R) on one call of the iteration's shape: 7 q x Niv matrices of the workload's NI,
+    on a synthetic negative-definite P(i nu) = -1e-3 X X^H (X complex Gaussian / sqrt(NI)), the same for
+    every matrix.  Times four calls with HIP events and checks the first W~ against numpy's solve of
+    (1 - chi) Y = chi, W~ = v^1/2 Y v^1/2.  Prints one JSON line."""
+    import numpy as np
+    import torch
+    import gwinputs as gi
+    import paper_1602_02313_amd as amd
+
+    cfg = gi.CONFIGS[args.config]
+    prob = gi.make_problem(cfg)
+    nq = 7
+    run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b, cfg.scale,
+                    prob.eps, prob.v, prob.n_target, precision=amd.F16X3, q_batch=nq)
+    NI, nw = int(prob.ni[0]), cfg.niw_b
+    if any(int(x) != NI for x in prob.ni[:nq]):
+        raise SystemExit("the screen study needs equal NI over its q")
+    rng = np.random.default_rng(3)
+    X = (rng.normal(size=(NI, NI)) + 1j * rng.normal(size=(NI, NI))) / np.sqrt(NI)
+    B = -(X @ X.conj().T) * 1e-3
+    Piw = torch.from_numpy(np.broadcast_to(B, (nq * nw, NI, NI)).copy().ravel()).to("cuda")
+    Wt, R = torch.zeros_like(Piw), torch.zeros_like(Piw)
+    info = torch.zeros(nq * nw, dtype=torch.int32, device="cuda")
+    flags = torch.zeros(1, dtype=torch.int32, device="cuda")
+    v = run.v[: nq * NI]
+    log(f"[screen] {cfg.name}: {nq} q x {nw} nu matrices of NI = {NI}")
+    ts = []
+    for rep in range(4):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        run.ctx.screen(0, nq, Piw, v, Wt, R, info, flags)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+        log(f"[screen] rep {rep}: {ts[-1]:.2f} ms")
+    sv = np.sqrt(v[:NI].cpu().numpy())
+    chi = sv[:, None] * B * sv[None, :]
+    Wr = sv[:, None] * np.linalg.solve(np.eye(NI) - chi, chi) * sv[None, :]
+    W0 = Wt[: NI * NI].cpu().numpy().reshape(NI, NI)
+    t = min(ts)
+    print(json.dumps({"study": "FP64 screen (batched two-level Gauss-Jordan) of one q batch",
+                      "workload": f"{cfg.name}: {nq} q x {nw} nu = {nq * nw} matrices of NI = {NI}",
+                      "ms_per_call": round(t, 2), "s_per_iteration": round(t * cfg.nk / nq / 1e3, 2),
+                      "tflops_at_10.7_NI3": round(10.7 * NI ** 3 * nq * nw / (t / 1e3) / 1e12, 1),
+                      "rel_err_vs_numpy": float(np.linalg.norm(W0 - Wr) / np.linalg.norm(Wr)),
+                      "info": int(info.abs().sum()), "flags": int(flags.item())}), flush=True)
+
+
 def symmetry_study(args):
     """One self-energy pass plus Dyson and gap over the full zone against the irreducible-wedge pass
     (P, W~ and the contractions for the irreducible q only, contributions added over the stars), on
@@ -439,6 +489,8 @@ def main():
     ap.add_argument("--symmetry", action="store_true",
                     help="instead of the iteration: full zone vs irreducible wedge on the cubic-symmetric "
                          "form of --config (NI = 691)")
+    ap.add_argument("--screen", action="store_true",
+                    help="instead of the iteration: time the FP64 screen on one 7-q call of --config")
     ap.add_argument("--batching", action="store_true",
                     help="instead of the iteration: one launch vs a per-k launch loop on one q of --config "
                          "(default c4, the uneven workload)")
@@ -453,6 +505,9 @@ def main():
         return
     if args.queue:
         queue_study(args)
+        return
+    if args.screen:
+        screen_study(args)
         return
     if args.batching:
         if args.config == "c5":

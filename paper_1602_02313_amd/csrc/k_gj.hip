@@ -12,8 +12,8 @@
 //                T[:, J], the columns of the product of the panel's elementary eliminations.
 //   k_gj_update  C <- C + T[:, J] C_J on the window's columns outside the panel, for the rows outside
 //                J, on 16x16x4 FP64 MFMA tiles of 64 x 64 (K = w in chunks of 16).
-//   k_gj_finish  C_J <- T_JJ C_J on the same columns: the pivot rows need the old C_J that the update
-//                tiles read, so they are finished after it, 16 columns per work-group.
+//   k_gj_update<FIN>  C_J <- T_JJ C_J on the same columns: the pivot rows need the old C_J that the
+//                update tiles read, so they are finished after it, by a second launch of the same tiles.
 // Matrices of order <= 1024 run two levels: 16-column panels update only the 64-column outer panel
 // they belong to (window [P, P + 64)); the outer panel then holds T[:, J64] of its 64 eliminations and
 // one K = 64 update (window: every column) applies them to the rest, so the whole matrix is read and
@@ -156,11 +156,26 @@ __global__ __launch_bounds__(NT) void k_gj_panel(GjArgs g, int j0, int swap_lo) 
 #pragma unroll
                             for (int c = 0; c < NB; ++c) srow[1][c] = x[u][c];
                 }
-                for (int c = swap_lo + tid; c < cend; c += NT) {
-                    if (c >= j0 && c < j0 + jb) continue;
-                    const double2 t = A[int64_t(j) * ld + c];
-                    A[int64_t(j) * ld + c] = A[int64_t(p) * ld + c];
-                    A[int64_t(p) * ld + c] = t;
+                // four columns per round: their loads are all issued before the stores
+                double2* rj = A + int64_t(j) * ld;
+                double2* rp = A + int64_t(p) * ld;
+                for (int c0 = swap_lo + tid; c0 < cend; c0 += 4 * NT) {
+                    double2 tj[4], tp[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int c = c0 + u * NT;
+                        const bool ok = c < cend && (c < j0 || c >= j0 + jb);
+                        tj[u] = ok ? rj[c] : make_double2(0.0, 0.0);
+                        tp[u] = ok ? rp[c] : make_double2(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int c = c0 + u * NT;
+                        if (c < cend && (c < j0 || c >= j0 + jb)) {
+                            rj[c] = tp[u];
+                            rp[c] = tj[u];
+                        }
+                    }
                 }
                 __syncthreads();
                 if (tid == oj) {
@@ -226,14 +241,23 @@ __global__ __launch_bounds__(NT) void k_gj_panel(GjArgs g, int j0, int swap_lo) 
 }
 
 // C <- C + T[:, J] C_J for the rows outside J = [a, a + w) on the step's columns (window [lo, hi)
-// without the panel), K = w in chunks of 16, 64 x 64 tiles of four waves.
-template <int W>
-__global__ __launch_bounds__(256) void k_gj_update(GjArgs g, int a, int lo, int hi, int tiles_m) {
+// without the panel), K = w in chunks of 16, 64 x 64 tiles of four waves.  FIN: the pivot rows'
+// C_J <- T_JJ C_J instead (one row tile; a work-group reads all of its columns' C_J before it writes
+// them, and no other work-group touches those columns).
+// The grid is 1-D and XCD-aware: work-group L runs on XCD L mod 8 (round-robin dispatch), and the
+// tiles of matrix b all run on XCD b mod 8 (as its panel kernel does), so a matrix's T and C_J tiles are
+// fetched into one L2 instead of eight: L = 8 k + x takes tile k mod ntiles of matrix x + 8 (k / ntiles).
+// Three waves per SIMD: the accumulators then live in VGPRs.
+template <int W, bool FIN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_gj_update(
+    GjArgs g, int a, int lo, int hi, int tiles_m, int ntiles, int batch) {
     constexpr int KC = W < 16 ? W : 16;
     __shared__ double2 As[64][KC + 1];
     __shared__ double2 Bs[KC][64];
 
-    const int b = blockIdx.y;
+    const int xcd = int(blockIdx.x & 7), kx = int(blockIdx.x >> 3);
+    const int b = xcd + 8 * (kx / ntiles), tile = kx % ntiles;
+    if (b >= batch) return;
     int n, ld;
     int64_t off;
     gj_item(g, b, n, ld, off);
@@ -241,36 +265,57 @@ __global__ __launch_bounds__(256) void k_gj_update(GjArgs g, int a, int lo, int 
     const int jb = min(W, n - a);
     const GjCols cols = gj_cols(lo, hi, g.mode == GJ_INVERT ? n : ld, a, jb);
     const int ncols = cols.count();
-    const int row0 = (blockIdx.x % tiles_m) * 64, col0 = (blockIdx.x / tiles_m) * 64;
-    if (row0 >= n || col0 >= ncols) return;
+    const int row0 = FIN ? a : (tile % tiles_m) * 64;
+    const int col0 = (FIN ? tile : tile / tiles_m) * 64;
+    const int rend = FIN ? a + jb : n;
+    if (row0 >= rend || col0 >= ncols) return;
     double2* A = g.A + off;
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
     const int r16 = lane & 15, k4 = lane >> 4;
+    auto row_ok = [&](int i) { return i < rend && (FIN || i < a || i >= a + jb); };
+    // the accumulators start from C (the update) or from zero (FIN): the tile's C is fetched once, while
+    // the first chunk is staged, and written once at the end
     dbl4 cre[2][2], cim[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            cre[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
-            cim[bi][bj] = dbl4{0.0, 0.0, 0.0, 0.0};
-        }
-    for (int t0 = 0; t0 < jb; t0 += KC) {
-        // T[rows, J] (zero on the pivot rows, which k_gj_finish handles) and C_J[:, cols]
-        for (int e = tid; e < 64 * KC; e += 256) {
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int i = row0 + wr + bi * 16 + 4 * r4 + k4;
+                const int cc = col0 + wc + bj * 16 + r16;
+                double2 y = make_double2(0.0, 0.0);
+                if (!FIN && row_ok(i) && cc < ncols) y = A[int64_t(i) * ld + cols.col(cc)];
+                cre[bi][bj][r4] = y.x;
+                cim[bi][bj][r4] = y.y;
+            }
+    // T[rows, J] (the update: zero on the pivot rows) and C_J[:, cols] of a K chunk, fetched into
+    // registers one chunk ahead of the MFMAs
+    constexpr int NE = 64 * KC / 256;
+    double2 pa[NE], pb[NE];
+    auto fetch = [&](int t0) {
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = tid + u * 256;
             const int r = e / KC, t = e % KC, i = row0 + r;
-            double2 v = make_double2(0.0, 0.0);
-            if (i < n && t0 + t < jb && (i < a || i >= a + jb)) v = A[int64_t(i) * ld + a + t0 + t];
-            As[r][t] = v;
+            pa[u] = (t0 + t < jb && row_ok(i)) ? A[int64_t(i) * ld + a + t0 + t] : make_double2(0.0, 0.0);
+            const int tb = e / 64, cc = col0 + (e % 64);
+            pb[u] = (t0 + tb < jb && cc < ncols) ? A[int64_t(a + t0 + tb) * ld + cols.col(cc)]
+                                                 : make_double2(0.0, 0.0);
         }
-        for (int e = tid; e < KC * 64; e += 256) {
-            const int t = e / 64, cc = col0 + (e % 64);
-            double2 v = make_double2(0.0, 0.0);
-            if (t0 + t < jb && cc < ncols) v = A[int64_t(a + t0 + t) * ld + cols.col(cc)];
-            Bs[t][e % 64] = v;
+    };
+    fetch(0);
+    for (int t0 = 0; t0 < jb; t0 += KC) {
+#pragma unroll
+        for (int u = 0; u < NE; ++u) {
+            const int e = tid + u * 256;
+            As[e / KC][e % KC] = pa[u];
+            Bs[e / 64][e % 64] = pb[u];
         }
         __syncthreads();
+        if (t0 + KC < jb) fetch(t0 + KC);
 #pragma unroll
         for (int k0 = 0; k0 < KC; k0 += 4) {
             double2 av[2], bv[2];
@@ -300,51 +345,9 @@ __global__ __launch_bounds__(256) void k_gj_update(GjArgs g, int a, int lo, int 
             for (int r4 = 0; r4 < 4; ++r4) {
                 const int i = row0 + wr + bi * 16 + 4 * r4 + k4;
                 const int cc = col0 + wc + bj * 16 + r16;
-                if (i < n && (i < a || i >= a + jb) && cc < ncols) {
-                    double2* p = &A[int64_t(i) * ld + cols.col(cc)];
-                    double2 y = *p;
-                    y.x += cre[bi][bj][r4];
-                    y.y += cim[bi][bj][r4];
-                    *p = y;
-                }
+                if (row_ok(i) && cc < ncols)
+                    A[int64_t(i) * ld + cols.col(cc)] = make_double2(cre[bi][bj][r4], cim[bi][bj][r4]);
             }
-}
-
-// C_J <- T_JJ C_J for the pivot rows J = [a, a + w) on the step's columns, 16 columns per work-group.
-template <int W>
-__global__ __launch_bounds__(256) void k_gj_finish(GjArgs g, int a, int lo, int hi) {
-    __shared__ double2 T[W][W + 1];
-    __shared__ double2 C[W][17];
-    const int b = blockIdx.y;
-    int n, ld;
-    int64_t off;
-    gj_item(g, b, n, ld, off);
-    if (a >= n) return;
-    const int jb = min(W, n - a);
-    const GjCols cols = gj_cols(lo, hi, g.mode == GJ_INVERT ? n : ld, a, jb);
-    const int c0 = blockIdx.x * 16, nc = min(16, cols.count() - c0);
-    if (nc <= 0) return;
-    double2* A = g.A + off;
-    for (int e = threadIdx.x; e < W * W; e += 256) {
-        const int i = e / W, t = e % W;
-        T[i][t] = (i < jb && t < jb) ? A[int64_t(a + i) * ld + a + t] : make_double2(0.0, 0.0);
-    }
-    for (int e = threadIdx.x; e < W * 16; e += 256) {
-        const int t = e / 16, c = e % 16;
-        C[t][c] = (t < jb && c < nc) ? A[int64_t(a + t) * ld + cols.col(c0 + c)] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < W * 16; e += 256) {
-        const int i = e / 16, c = e % 16;
-        if (i >= jb || c >= nc) continue;
-        double2 s2 = make_double2(0.0, 0.0);
-        for (int t = 0; t < jb; ++t) {
-            const double2 x = T[i][t], y = C[t][c];
-            s2.x += x.x * y.x - x.y * y.y;
-            s2.y += x.x * y.y + x.y * y.x;
-        }
-        A[int64_t(a + i) * ld + cols.col(c0 + c)] = s2;
-    }
 }
 
 __global__ void k_gj_zero(int* p, int count) {
@@ -358,8 +361,11 @@ void gj_apply(const GjArgs& g, int batch, int nmax, int cmax, int a, int lo, int
     const int tiles_m = (nmax + 63) / 64, span = std::max(0, std::min(hi, cmax) - lo);
     const int tiles_n = (span + 63) / 64;
     if (tiles_n == 0) return;
-    MSGW_LAUNCH((k_gj_update<W>), dim3(tiles_m * tiles_n, batch), dim3(256), 0, s, g, a, lo, hi, tiles_m);
-    MSGW_LAUNCH((k_gj_finish<W>), dim3((span + 15) / 16, batch), dim3(256), 0, s, g, a, lo, hi);
+    const unsigned groups = unsigned(batch + 7) / 8;
+    MSGW_LAUNCH((k_gj_update<W, false>), dim3(8u * groups * unsigned(tiles_m * tiles_n)), dim3(256), 0, s, g, a, lo,
+                hi, tiles_m, tiles_m * tiles_n, batch);
+    MSGW_LAUNCH((k_gj_update<W, true>), dim3(8u * groups * unsigned(tiles_n)), dim3(256), 0, s, g, a, lo, hi, 1,
+                tiles_n, batch);
 }
 
 // one level: panels of NB columns, each applied to every column of its step
@@ -394,8 +400,11 @@ void gj_run(const GjArgs& g, int batch, int nmax, int ldmax, hipStream_t s) {
     if (batch <= 0 || nmax <= 0) return;
     if (nmax > kGjMaxN) throw Error(MSGW_ENOTSUP, "Gauss-Jordan: order above 4096");
     if (batch > 65535) throw Error(MSGW_ENOTSUP, "Gauss-Jordan: more than 65535 matrices in one call");
-    MSGW_LAUNCH(k_gj_zero, dim3((batch + 255) / 256), dim3(256), 0, s, g.info, batch);
     const int cmax = g.mode == GJ_INVERT ? nmax : ldmax;
+    // the update's 1-D grid holds at most 2^32 - 1 threads
+    if (8.0 * ((batch + 7) / 8) * ((nmax + 63) / 64) * ((cmax + 63) / 64) * 256.0 > 4294967295.0)
+        throw Error(MSGW_ENOTSUP, "Gauss-Jordan: too many update tiles for one launch (split the call)");
+    MSGW_LAUNCH(k_gj_zero, dim3((batch + 255) / 256), dim3(256), 0, s, g.info, batch);
     // the panel stays in registers: RPT rows of NB complex columns per thread
     if (nmax <= 1024)
         gj_two_level(g, batch, nmax, cmax, s);
