@@ -83,7 +83,7 @@ extern "C" {
 
 /* self-energy mode */
 #define MSGW_SIGMA_DIAG 0   /* Sigma_nn(k,tau), the diagonal approximation of the paper */
-#define MSGW_SIGMA_FULL 1   /* Sigma_nn'(k,tau), full band matrix (FP64 only)           */
+#define MSGW_SIGMA_FULL 1   /* Sigma_nn'(k,tau), full band matrix (FP64 or F16X3)      */
 
 /* chemical potential handling in msgw_dyson */
 #define MSGW_MU_FIXED  0
@@ -197,7 +197,9 @@ int msgw_screened_tau(msgw_ctx* c, void* stream, int q0, int nq, const void* R_i
 
 /* a6. Correlation self-energy (eq. sigc), ACCUMULATED into Sigma_tau:
  * DIAG: Sigma_n(k,tau_i) += s sum_q sum_m G_m(k-q,tau_i) Re sum_IJ conj(M^I_nm) W~_IJ(q,tau_i) M^J_nm
- * FULL: Sigma_nn'(k,tau_i) += s sum_q sum_m G_m(k-q,tau_i) sum_IJ conj(M^I_nm) W~_IJ M^J_n'm (FP64 only).
+ * FULL: Sigma_nn'(k,tau_i) += s sum_q sum_m G_m(k-q,tau_i) sum_IJ conj(M^I_nm) W~_IJ M^J_n'm, in MSGW_FP64
+ * (M c128) or MSGW_F16X3 (M c64: W~ M split into FP16 pairs on MFMA, the contraction with conj(M) G in
+ * FP64; other precisions return MSGW_ENOTSUP; the whole k range only).
  * The caller zeroes Sigma_tau before the first q.  Wt_tau: device c128 [q][ntau][NI_q][NI_q]. */
 int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, int m_dtype,
                      const double* G_tau, const void* Wt_tau, int precision, void* Sigma_tau);

@@ -463,7 +463,8 @@ static size_t tables_bytes(const Host& h) {
 
 static size_t scratch_needed(const Host& h, int nq_max) {
     return scratch_E_bytes(h) + align_up(std::max({mfma_scratch_bytes(h, nq_max), cpe_scratch_bytes(h, 98),
-                                                   screen_scratch_bytes(h, nq_max)}));
+                                                   screen_scratch_bytes(h, nq_max),
+                                                   sigfull_split_scratch_bytes(h)}));
 }
 
 int msgw_workspace_size(msgw_ctx* c, int nq_max, size_t* bytes) {
@@ -699,9 +700,16 @@ int msgw_self_energy(msgw_ctx* c, void* stream, int q0, int nq, const void* M, i
              "a partial k range is supported by the FP64 (DIAG) and the split-precision pair-space kernels only");
         check_reuse(c, MSGW_OP_SELF_ENERGY, q0, nq, precision);
         if (c->h.sigma_mode == MSGW_SIGMA_FULL) {
-            need(precision == MSGW_FP64 && m_dtype == MSGW_C128, MSGW_ENOTSUP,
-                 "MSGW_SIGMA_FULL runs in MSGW_FP64 with MSGW_C128 M");
-            launch_sig_full_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, Sigma_tau);
+            if (precision == MSGW_FP64) {
+                need(m_dtype == MSGW_C128, MSGW_EINVAL, "MSGW_FP64 needs MSGW_C128 M");
+                launch_sig_full_fp64(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, Sigma_tau);
+                return;
+            }
+            need(precision == MSGW_F16X3 && m_dtype == MSGW_C64, MSGW_ENOTSUP,
+                 "MSGW_SIGMA_FULL runs in MSGW_FP64 (MSGW_C128 M) or MSGW_F16X3 (MSGW_C64 M)");
+            launch_sig_full_split(c->d, c->h, S(stream), q0, nq, M, G_tau, Wt_tau, Sigma_tau,
+                                  scratch_mfma(c->d, c->h), scratch_mfma_bytes(c->d, c->h));
+            c->prep = msgw_ctx::Prepared();  // the scratch no longer holds prepared operands
             return;
         }
         if (precision == MSGW_FP64) {

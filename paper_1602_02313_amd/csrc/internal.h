@@ -140,6 +140,11 @@ void launch_sig_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
                      const double* G, const void* W, void* Sig);
 void launch_sig_full_fp64(const Dev& d, const Host& h, hipStream_t s, int q0, int nq,
                           const void* M, const double* G, const void* W, void* Sig);
+// the FULL band-matrix self-energy in MSGW_F16X3 (k_sigfull.hip), M c64, W~ c128; scratch: the FP32
+// product W~ M of one (q, k) for a chunk of tau points plus the operand maxima
+size_t sigfull_split_scratch_bytes(const Host& h);
+void launch_sig_full_split(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
+                           const double* G, const void* W, void* Sig, char* scratch, size_t scratch_bytes);
 int launch_pol_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
                     const double* G, int precision, int variant, void* P);
 int launch_sig_mfma(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
