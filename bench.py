@@ -361,6 +361,71 @@ def screen_study(args):
                       "info": int(info.abs().sum()), "flags": int(flags.item())}), flush=True)
 
 
+def full_study(args):
+    """The FULL band-matrix self-energy in split FP16 against the diagonal one on one q of the 4x4x4 k,
+    64-band, NI = 400, 81-tau workload: P, the screen and W~(tau) of q = 0 in FP64 (M drawn on the
+    device), then Sigma^c of that q in FULL (k_sf_ywm + k_sf_contract) and in DIAG (k_sigz) mode, both
+    F16X3 on the same W~ and M.  The real part of FULL's diagonal is DIAG's Sigma (the DIAG kernels use
+    the Hermitian part of W~, the same sum).  Prints one JSON line with both times, their dense-model
+    rates and the largest difference."""
+    import torch
+    import gwinputs as gi
+    import paper_1602_02313_amd as amd
+
+    cfg = gi.CONFIGS["c2"]
+    prob = gi.make_problem(cfg)
+    mk = lambda prec, mode: amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f,
+                                      cfg.niw_b, cfg.scale, prob.eps, prob.v, prob.n_target, precision=prec,
+                                      sigma_mode=mode, q_batch=1)
+    r64 = mk(amd.FP64, amd.SIGMA_DIAG)
+    M64 = torch.empty(int(r64.mpre[1]), dtype=torch.complex128, device="cuda")
+    r64.ctx.synth_M(cfg.seed, 0, 1, 1, amd.C128, M64)
+    r64.green0(0.0)
+    r64.begin_pass()
+    r64.q_block(amd.ResidentM(M64, r64.mpre), 0, 1)
+    W = r64.Wt_tau[: int(r64.ppre[1])].clone()
+    del M64, r64
+    torch.cuda.empty_cache()
+    log(f"[full] {cfg.name}: W~ of q = 0 in FP64")
+    res, out = {}, {}
+    for label, mode in (("full", amd.SIGMA_FULL), ("diag", amd.SIGMA_DIAG)):
+        run = mk(amd.F16X3, mode)
+        M = torch.empty(int(run.mpre[1]), dtype=torch.complex64, device="cuda")
+        run.ctx.synth_M(cfg.seed, 0, 1, 1, amd.C64, M)
+        run.green0(0.0)
+        ts = []
+        for rep in range(2):
+            run.sig_tau.zero_()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            run.ctx.self_energy(0, 1, M, amd.C64, run.G_tau, W, amd.F16X3, run.sig_tau)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+            log(f"[full] {label} rep {rep}: {ts[-1]:.1f} ms")
+        out[label] = run.sig_tau.clone()
+        res[label] = {"ms": round(min(ts), 1)}
+        del run, M
+        torch.cuda.empty_cache()
+    ntau = prob.tau.size
+    ni = int(prob.ni[0])
+    f_full = f_diag = 0.0
+    for k in range(cfg.nk):
+        nn, nm = int(prob.nb[k]), int(prob.nb[prob.kmq[0, k]])
+        f_diag += 8.0 * ni * ni * nn * nm * ntau + 8.0 * ni * nn * nm * ntau
+        f_full += 8.0 * ni * ni * nn * nm * ntau + 8.0 * ni * nn * nn * nm * ntau
+    res["full"]["dense_tflops"] = round(f_full / (res["full"]["ms"] / 1e3) / 1e12, 1)
+    res["diag"]["dense_tflops"] = round(f_diag / (res["diag"]["ms"] / 1e3) / 1e12, 1)
+    diag_of_full = torch.diagonal(out["full"], dim1=1, dim2=2).real.permute(0, 2, 1)
+    d = out["diag"]
+    print(json.dumps({"study": "FULL band-matrix Sigma^c vs DIAG in split FP16, one q",
+                      "workload": f"{cfg.name}: q = 0, {cfg.nk} k blocks of {int(prob.nb[0])} bands, NI = {ni}, "
+                                  f"{ntau} tau points, W~ from the FP64 chain",
+                      **res, "full_over_diag": round(res["full"]["ms"] / res["diag"]["ms"], 2),
+                      "rel_diff_re_diag_full_vs_diag": float((diag_of_full - d).norm() / d.norm())}), flush=True)
+
+
 def symmetry_study(args):
     """One self-energy pass plus Dyson and gap over the full zone against the irreducible-wedge pass
     (P, W~ and the contractions for the irreducible q only, contributions added over the stars), on
@@ -489,6 +554,8 @@ def main():
     ap.add_argument("--symmetry", action="store_true",
                     help="instead of the iteration: full zone vs irreducible wedge on the cubic-symmetric "
                          "form of --config (NI = 691)")
+    ap.add_argument("--full", action="store_true",
+                    help="instead of the iteration: FULL vs DIAG split-FP16 self-energy on one q of c2")
     ap.add_argument("--screen", action="store_true",
                     help="instead of the iteration: time the FP64 screen on one 7-q call of --config")
     ap.add_argument("--batching", action="store_true",
@@ -508,6 +575,9 @@ def main():
         return
     if args.screen:
         screen_study(args)
+        return
+    if args.full:
+        full_study(args)
         return
     if args.batching:
         if args.config == "c5":

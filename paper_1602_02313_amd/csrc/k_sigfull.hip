@@ -5,7 +5,7 @@
 //   k_sf_ywm      Y(tau) = W~(q, tau) M(q, k): NI x NI times NI x K (K = Nb_k Nb_{k-q} columns (n', m)),
 //                 F16X3 on v_mfma_f32_32x32x16_f16 with FP32 accumulation, written to the scratch in FP32;
 //   k_sf_contract Sigma_nn' += s sum_I sum_m conj(M^I_nm) G_m(tau) Y^I_n'm: an Nb x Nb product with the
-//                 reduction over (I, m), on v_mfma_f64_16x16x4f64 in FP64, split over 64-row groups of I
+//                 reduction over (I, m), on v_mfma_f64_16x16x4f64 in FP64, split over 16-row groups of I
 //                 with FP64 atomics into Sigma.
 // The second contraction costs Nb_k / NI of the first (18% at 128 bands and NI = 700).
 // F16X3 operands: each element x of W~(q, tau) and of M(q) is scaled by a power of two that puts the
@@ -27,6 +27,7 @@ typedef double sf_dbl4 __attribute__((ext_vector_type(4)));
 constexpr int SF_TC = 8;    // tau points per chunk (the scratch holds Y of one (q, k) and chunk)
 constexpr int SF_KS = 16;   // J per stage of k_sf_ywm
 constexpr int SF_RS = 20;   // LDS row stride in u32 (80 B)
+constexpr int SF_IG = 16;   // rows I per work-group of k_sf_contract (its split of the reduction)
 
 __device__ __forceinline__ uint32_t sf_pk(float a, float b) {
     sf_f16x2 v = {(_Float16)a, (_Float16)b};
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256) void k_sf_ywm(const double2* __restrict__ Wq, 
 }
 
 // Sigma_nn'(k, t) += s sum_{I in the group} sum_m conj(M^I_nm) G_m(k - q, t) Y^I_n'm(t), for a 64 x 64
-// tile (n, n'), one 64-row group of I and one tau point per work-group, FP64.  The reduction index
+// tile (n, n'), one group of SF_IG rows I and one tau point per work-group, FP64.  The reduction index
 // runs over (I, m) in chunks of 16 m; the complex product on real MFMAs with K interleaving (re, im):
 // the row n holds (Re M, Im M), the column n' for Re Sigma (Re Y, Im Y), for Im Sigma (Im Y, -Re Y).
 // Grid: (tiles_n * tiles_n * groups of I, nt).
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(256) void k_sf_contract(const float2* __restrict__ 
     const int t = t0 + int(blockIdx.y);
     const int tile = int(blockIdx.x) % (tiles_n * tiles_n), grp = int(blockIdx.x) / (tiles_n * tiles_n);
     const int n0 = (tile % tiles_n) * 64, p0 = (tile / tiles_n) * 64;
-    const int I0 = grp * 64, I1 = min(I0 + 64, NI);
+    const int I0 = grp * SF_IG, I1 = min(I0 + SF_IG, NI);
     const float2* Yt = Y + int64_t(blockIdx.y) * NI * K;
     const int wr = (wave >> 1) * 32, wcl = (wave & 1) * 32;
     const int r16 = lane & 15, k4 = lane >> 4;
@@ -326,7 +327,7 @@ void launch_sig_full_split(const Dev& d, const Host& h, hipStream_t s, int q0, i
             if (K == 0 || NI == 0) continue;
             const float2* A = (const float2*)M + (h.mpre[q] - h.mpre[q0]) + h.moff[size_t(q) * nk + k];
             const int tiles_i = (NI + 63) / 64, tiles_c = (K + 127) / 128, tiles_n = (nn + 63) / 64;
-            const int groups = (NI + 63) / 64;
+            const int groups = (NI + SF_IG - 1) / SF_IG;
             for (int t0 = 0; t0 < ntau; t0 += SF_TC) {
                 const int nt = std::min(SF_TC, ntau - t0);
                 MSGW_LAUNCH(k_sf_ywm, dim3(tiles_i * tiles_c, nt), dim3(256), 0, s, Wq, A, Y, NI, K, t0, tiles_i,
