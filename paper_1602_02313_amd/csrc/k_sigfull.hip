@@ -24,7 +24,7 @@ typedef float sf_floatx16 __attribute__((ext_vector_type(16)));
 typedef uint32_t sf_u32x4 __attribute__((ext_vector_type(4)));
 typedef double sf_dbl4 __attribute__((ext_vector_type(4)));
 
-constexpr int SF_TC = 8;    // tau points per chunk (the scratch holds Y of one (q, k) and chunk)
+constexpr int SF_TC = 8;    // tau points per chunk at most (the scratch holds Y of one (q, k) and chunk)
 constexpr int SF_KS = 16;   // J per stage of k_sf_ywm
 constexpr int SF_RS = 20;   // LDS row stride in u32 (80 B)
 constexpr int SF_IG = 16;   // rows I per work-group of k_sf_contract (its split of the reduction)
@@ -293,13 +293,26 @@ __global__ __launch_bounds__(256) void k_sf_contract(const float2* __restrict__ 
 
 }  // namespace
 
-size_t sigfull_split_scratch_bytes(const Host& h) {
-    if (h.sigma_mode != MSGW_SIGMA_FULL) return 0;
+namespace {
+// bytes of Y for one tau point at the largest (q, k) block
+size_t sf_plane_bytes(const Host& h) {
     int64_t kmax = 0;
     for (int k = 0; k < h.nk; ++k)
         for (int q = 0; q < h.nk; ++q) kmax = std::max<int64_t>(kmax, int64_t(h.nb[k]) * h.nb[h.kmq[size_t(q) * h.nk + k]]);
-    const size_t maxima = (size_t(h.nk) * (1 + h.ntau) * 8 + 255) / 256 * 256;
-    return maxima + size_t(h.nimax) * size_t(kmax) * size_t(std::min(SF_TC, h.ntau)) * sizeof(float2);
+    return size_t(h.nimax) * size_t(kmax) * sizeof(float2);
+}
+// tau points per chunk: up to SF_TC while Y stays within 1 GiB, at least one
+int sf_tau_chunk(const Host& h) {
+    const size_t plane = sf_plane_bytes(h);
+    const int64_t fit = int64_t((size_t(1) << 30) / std::max<size_t>(plane, 1));
+    return int(std::max<int64_t>(1, std::min<int64_t>({int64_t(SF_TC), int64_t(h.ntau), fit})));
+}
+size_t sf_maxima_bytes(const Host& h) { return (size_t(h.nk) * (1 + h.ntau) * 8 + 255) / 256 * 256; }
+}  // namespace
+
+size_t sigfull_split_scratch_bytes(const Host& h) {
+    if (h.sigma_mode != MSGW_SIGMA_FULL) return 0;
+    return sf_maxima_bytes(h) + sf_plane_bytes(h) * size_t(sf_tau_chunk(h));
 }
 
 void launch_sig_full_split(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,
@@ -309,14 +322,17 @@ void launch_sig_full_split(const Dev& d, const Host& h, hipStream_t s, int q0, i
     const int nk = h.nk, ntau = h.ntau, nbmax = h.nbmax;
     auto* mxm = reinterpret_cast<unsigned long long*>(scratch);       // [nk]        max |Re|, |Im| of M(q)
     auto* mxw = mxm + nk;                                             // [nk][ntau]  the same of W~(q, tau)
-    float2* Y = reinterpret_cast<float2*>(scratch + (size_t(nk) * (1 + ntau) * 8 + 255) / 256 * 256);
+    float2* Y = reinterpret_cast<float2*>(scratch + sf_maxima_bytes(h));
+    const int tc = sf_tau_chunk(h);
     MSGW_LAUNCH(k_sf_zero, dim3((nk * (1 + ntau) + 255) / 256), dim3(256), 0, s, mxm, nk * (1 + ntau));
     for (int q = q0; q < q0 + nq; ++q) {
         const int64_t msz = h.mpre[q + 1] - h.mpre[q], nn = int64_t(h.ni[q]) * h.ni[q];
-        MSGW_LAUNCH(k_sf_max_c64, dim3(unsigned(std::min<int64_t>((msz + 255) / 256, 2048))), dim3(256), 0, s,
-                    (const float2*)M + (h.mpre[q] - h.mpre[q0]), msz, mxm + q);
-        MSGW_LAUNCH(k_sf_max_w, dim3(unsigned(std::min<int64_t>((nn + 255) / 256, 64)), ntau), dim3(256), 0, s,
-                    (const double2*)W + (h.ppre[q] - h.ppre[q0]), nn, mxw + int64_t(q) * ntau);
+        if (msz > 0)
+            MSGW_LAUNCH(k_sf_max_c64, dim3(unsigned(std::min<int64_t>((msz + 255) / 256, 2048))), dim3(256), 0, s,
+                        (const float2*)M + (h.mpre[q] - h.mpre[q0]), msz, mxm + q);
+        if (nn > 0)
+            MSGW_LAUNCH(k_sf_max_w, dim3(unsigned(std::min<int64_t>((nn + 255) / 256, 64)), ntau), dim3(256), 0, s,
+                        (const double2*)W + (h.ppre[q] - h.ppre[q0]), nn, mxw + int64_t(q) * ntau);
     }
     for (int q = q0; q < q0 + nq; ++q) {
         const int NI = h.ni[q];
@@ -328,8 +344,8 @@ void launch_sig_full_split(const Dev& d, const Host& h, hipStream_t s, int q0, i
             const float2* A = (const float2*)M + (h.mpre[q] - h.mpre[q0]) + h.moff[size_t(q) * nk + k];
             const int tiles_i = (NI + 63) / 64, tiles_c = (K + 127) / 128, tiles_n = (nn + 63) / 64;
             const int groups = (NI + SF_IG - 1) / SF_IG;
-            for (int t0 = 0; t0 < ntau; t0 += SF_TC) {
-                const int nt = std::min(SF_TC, ntau - t0);
+            for (int t0 = 0; t0 < ntau; t0 += tc) {
+                const int nt = std::min(tc, ntau - t0);
                 MSGW_LAUNCH(k_sf_ywm, dim3(tiles_i * tiles_c, nt), dim3(256), 0, s, Wq, A, Y, NI, K, t0, tiles_i,
                             mxw + int64_t(q) * ntau, mxm + q);
                 MSGW_LAUNCH(k_sf_contract, dim3(tiles_n * tiles_n * groups, nt), dim3(256), 0, s, A, Y,
