@@ -13,25 +13,29 @@
 // Precisions
 //   FP32:   v_mfma_f32_16x16x4_f32, FP32 operands and accumulation.
 //   BF16X3: each FP32 operand x is split into hi = bf16(x) and lo = bf16(x - hi) (round to nearest
-//           even), and x.y ~ hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 with FP32
-//           accumulation; the dropped lo.lo term is ~2^-16 relative.
+//           even), and x.y ~ hi.hi + hi.lo + lo.hi on bf16 MFMA with FP32 accumulation; the dropped
+//           lo.lo term is ~2^-16 relative.
+//   F16X3:  the same split into f16 halves (11 significant bits, so the dropped lo.lo is ~2^-22
+//           relative), with every operand scaled by a power of two that keeps it inside the f16 range
+//           (M per q, the weights per (q, tau)); the scales are undone in FP64.
 // The FP32 accumulators of the polarization are flushed into the FP64 output every FLUSH_STEPS
 // K-steps, so an FP32 sum never runs over more than 4096 complex terms (the pair-space polarization:
 // GZ_FLUSH terms).
 //
-// The split-BF16 defaults are the pair-space kernels (k_polz, k_sigz; 32x32x16 MFMA, operands staged
-// through LDS by 8-wave work-groups; see their sections below).  The tile forms: polarization, one
-// wave (64 lanes) per work-group owning a (16 WI) x (16 WJ) x T output tile and streaming its operands
-// from global memory (reuse between waves served by L2); self-energy, one-wave variants of the same
-// kind and a 4-wave variant (v7) that stages its operands through LDS and runs on
-// v_mfma_f32_32x32x16_bf16.  To make the reuse happen, work-groups are ordered XCD-aware: the
-// hardware deals consecutive work-group ids round-robin to the 8 XCDs, so id b is mapped to item
-// b / 8 of the slice of XCD b % 8 -- each XCD walks a contiguous slice of the work -- and the work
-// space (rows x columns) is cut into
-// super-tiles of SR x SC items (about the number of waves resident on one XCD), so the waves
-// running together on an XCD share SR row panels and SC column panels in its L2.  Where only part of
-// the item space holds work (the upper triangle of the Hermitian polarization), the slices are cut
-// so that every XCD gets the same number of working items, not the same number of indices.
+// The split-precision defaults are the pair-space kernels (32x32x16 MFMA, operands staged through LDS
+// by 8-wave work-groups; see their sections below): the polarization in its persistent form
+// (k_polz_queue: one work-group per CU taking items from per-XCD queues that k_polz_qbuild lists on
+// the device), the self-energy k_sigz.  The tile forms: polarization, one wave (64 lanes) per
+// work-group owning a (16 WI) x (16 WJ) x T output tile and streaming its operands from global memory
+// (reuse between waves served by L2); self-energy, one-wave variants of the same kind and a 4-wave
+// variant (v7) that stages its operands through LDS and runs on v_mfma_f32_32x32x16_bf16.  To make the
+// reuse happen, the static grids are ordered XCD-aware: the hardware deals consecutive work-group ids
+// round-robin to the 8 XCDs, so id b is mapped to item b / 8 of the slice of XCD b % 8 -- each XCD
+// walks a contiguous slice of the work -- and the work space (rows x columns) is cut into super-tiles
+// of SR x SC items (about the number of waves resident on one XCD), so the waves running together on
+// an XCD share SR row panels and SC column panels in its L2.  Where only part of the item space holds
+// work (the upper triangle of the Hermitian polarization), the slices are cut so that every XCD gets
+// the same number of working items, not the same number of indices.
 #include "internal.h"
 
 namespace msgw {
