@@ -178,11 +178,11 @@ def test_screen_full_ni(torch, big):
     assert e_w < 1e-10 and e_t < 1e-10
 
 
-@pytest.mark.parametrize("ni", [400, 512, 513])
+@pytest.mark.parametrize("ni", [400, 512, 513, 1024])
 def test_screen_panel_sizes(torch, ni):
-    """The FP64 screen at C2's product-basis size (400), at a multiple of the 16-column panel (512)
-    and one past it (513, a last panel of one column), against the oracle on sampled frequencies of
-    a synthetic negative-definite P(i nu) with a non-Hermitian part."""
+    """The FP64 screen at C2's product-basis size (400), at a multiple of the 64-column outer panel
+    (512), one past it (513, a last panel of one column) and at the largest NI (1024), against the
+    oracle on sampled frequencies of a synthetic negative-definite P(i nu) with a non-Hermitian part."""
     import paper_1602_02313_amd as amd
     cfg = gi.C2.replace(ni=ni, name=f"c2_ni{ni}")
     prob = gi.make_problem(cfg)

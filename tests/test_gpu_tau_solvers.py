@@ -3,7 +3,8 @@ oracle's wt_tau_system and dyson_tau, FP64 gate rel 1e-10, and their agreement w
 Matsubara-axis path to discretisation error.
 
 Shapes: the W~ system at orders ntau * NI = 777, 1470 and 2520 (one per register layout of the
-Gauss-Jordan panel), two q per call with unequal NI; the Dyson solve on a UPM mesh of 31 points
+Gauss-Jordan panel), two q per call with unequal NI, and at 1024 and 1040 (the largest order of the
+two-level elimination and the first of the one-level one); the Dyson solve on a UPM mesh of 31 points
 whose dense grid has 41 nodes, with uneven band counts.
 """
 import numpy as np
@@ -22,6 +23,9 @@ WSYS = {
     "n1470": gi.Config(name="ws1470", grid=(3, 1, 1), bands=((2, -1.0, -0.2), (4, 0.1, 1.5)), nb=None, ni=None,
                        nb_range=(3, 6), ni_range=(40, 70), ntau=20, mesh="upm", beta=20.0, niw_f=16, niw_b=16),
     "n2520": gi.tiny(name="ws2520", grid=(2, 1, 1), nocc=2, nemp=3, ni=120, ntau=20, beta=10.0, niw=16),
+    # the largest order of the two-level elimination and the first of the one-level one
+    "n1024": gi.tiny(name="ws1024", grid=(2, 1, 1), nocc=3, nemp=3, ni=64, ntau=15, beta=10.0, niw=16),
+    "n1040": gi.tiny(name="ws1040", grid=(2, 1, 1), nocc=3, nemp=3, ni=65, ntau=15, beta=10.0, niw=16),
 }
 DYS = gi.Config(name="dys", grid=(3, 1, 1), bands=((3, -1.0, -0.2), (4, 0.1, 1.5)), nb=None, ni=6,
                 nb_range=(4, 7), ntau=30, mesh="upm", beta=20.0, niw_f=64, niw_b=16)
