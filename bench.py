@@ -312,10 +312,10 @@ def queue_study(args):
 
 
 def screen_study(args):
-    """The FP64 screen (msgw_screen: the batched Gauss-Jordan inversion of 1 - v^1/2 P v^1/2 and the
-    forming of W~ and R) on one call of the iteration's shape: 7 q x Niv matrices of the workload's NI,
-    on a synthetic negative-definite P(i nu) = -1e-3 X X^H (X complex Gaussian / sqrt(NI)), the same for
-    every matrix.  Times four calls with HIP events and checks the first W~ against numpy's solve of
+    """The FP64 screen (msgw_screen: the inversion of 1 - v^1/2 P v^1/2 and the forming of W~ and R) on
+    one call of the iteration's shape: 7 q x Niv matrices of the workload's NI, on a synthetic
+    negative-definite Hermitian P(i nu) = -1e-3 X X^H (X complex Gaussian / sqrt(NI)), the same for
+    every matrix (so the Hermitian sweep inverts them all).  Times four calls with HIP events and checks the first W~ against numpy's solve of
     (1 - chi) Y = chi, W~ = v^1/2 Y v^1/2.  Prints one JSON line."""
     import numpy as np
     import torch
@@ -353,7 +353,7 @@ def screen_study(args):
     Wr = sv[:, None] * np.linalg.solve(np.eye(NI) - chi, chi) * sv[None, :]
     W0 = Wt[: NI * NI].cpu().numpy().reshape(NI, NI)
     t = min(ts)
-    print(json.dumps({"study": "FP64 screen (batched two-level Gauss-Jordan) of one q batch",
+    print(json.dumps({"study": "FP64 screen (Hermitian P: blocked sweep; else pivoting Gauss-Jordan) of one q batch",
                       "workload": f"{cfg.name}: {nq} q x {nw} nu = {nq * nw} matrices of NI = {NI}",
                       "ms_per_call": round(t, 2), "s_per_iteration": round(t * cfg.nk / nq / 1e3, 2),
                       "tflops_at_10.7_NI3": round(10.7 * NI ** 3 * nq * nw / (t / 1e3) / 1e12, 1),

@@ -104,7 +104,8 @@ void launch_inv_fermion(const Dev& d, hipStream_t s, int64_t nblk, int64_t len, 
                         const double* eref, double* out);
 void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, const void* F,
                       const void* add, const double* v, void* out);
-// perm: screen_scratch_bytes(h, nq) of scratch (the pivot rows of every (q, nu) matrix)
+// scratch: screen_scratch_bytes(h, nq) bytes (the pivot rows of every (q, nu) matrix, and the state of
+// the Hermitian path, k_hscreen.hip)
 size_t screen_scratch_bytes(const Host& h, int nq);
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
                    const double* v, void* Wt_iw, void* R_iw, int* info, int* flags, int* perm);
@@ -211,8 +212,14 @@ struct GjArgs {
     int* perm = nullptr;               // [batch][pmax] pivot row chosen for each column
     int pmax = 0;
     int* info = nullptr;               // [batch] first zero pivot + 1, or 0
+    const int* skip = nullptr;         // [batch] (when set) 1: leave the matrix alone (order 0)
 };
 __device__ __forceinline__ void gj_item(const GjArgs& g, int b, int& n, int& ld, int64_t& off) {
+    if (g.skip && g.skip[b]) {
+        n = ld = 0;
+        off = 0;
+        return;
+    }
     if (g.ni) {
         const int q = g.q0 + b / g.niw_b;
         n = g.ni[q];
@@ -226,6 +233,17 @@ __device__ __forceinline__ void gj_item(const GjArgs& g, int b, int& n, int& ld,
 }
 // Enqueues the elimination of `batch` matrices of order <= nmax (row stride <= ldmax) on s.
 void gj_run(const GjArgs& g, int batch, int nmax, int ldmax, hipStream_t s);
+// the Hermitian path of the screen (k_hscreen.hip): scratch bytes for `batch` matrices of order <= nimax
+size_t hp_scratch_bytes(int batch, int nimax);
+// decides per matrix whether P(i nu) is Hermitian (to 1e-6 of max |v^1/2 P v^1/2|), and inverts those
+// matrices (their Hermitian part) by the blocked sweep; on return skip_gj[b] = 1 for the matrices it
+// finished and skip_rb[b] = 0 for those whose sweep met a non-positive pivot (their A must be rebuilt
+// for the pivoting elimination)
+void hp_run(const GjArgs& g, int batch, int nmax, int nimax, char* scratch, hipStream_t s, const int** skip_gj,
+            const int** skip_rb);
+// W~ and R of the matrices the sweep finished (from the upper triangle of -A^-1)
+void hp_finish(const GjArgs& g, int batch, int nmax, int nimax, char* scratch, const double2* Piw, const double* v,
+               const int64_t* vpre, double2* R, hipStream_t s);
 
 // ---- the tau-domain solvers (k_tausys.hip) ----
 constexpr int kDysonTauMaxGrid = 2048;  // dense grid points of the tau-domain Dyson solve

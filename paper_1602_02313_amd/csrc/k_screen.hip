@@ -89,7 +89,8 @@ __global__ __launch_bounds__(256) void k_screen_finish(GjArgs g, const double2* 
 }  // namespace
 
 size_t screen_scratch_bytes(const Host& h, int nq) {
-    return sizeof(int) * size_t(nq) * h.niw_b * h.nimax;
+    const size_t perm = (sizeof(int) * size_t(nq) * h.niw_b * h.nimax + 255) / 256 * 256;
+    return perm + hp_scratch_bytes(nq * h.niw_b, h.nimax);
 }
 
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
@@ -109,9 +110,20 @@ void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, c
     g.info = info;
     const dim3 grid((nmax + SROWS - 1) / SROWS, batch);
     MSGW_LAUNCH(k_screen_build, grid, dim3(256), 0, s, g, (const double2*)P_iw, v, d.vpre);
-    gj_run(g, batch, nmax, nmax, s);
-    MSGW_LAUNCH(k_screen_finish, grid, dim3(256), 0, s, g, (const double2*)P_iw, v, d.vpre, (double2*)R_iw,
+    // the Hermitian matrices by the blocked sweep; the rest (and those whose sweep failed, rebuilt) by
+    // the pivoting Gauss-Jordan
+    char* hp = reinterpret_cast<char*>(perm) + (sizeof(int) * size_t(batch) * h.nimax + 255) / 256 * 256;
+    const int *skip_gj = nullptr, *skip_rb = nullptr;
+    hp_run(g, batch, nmax, h.nimax, hp, s, &skip_gj, &skip_rb);
+    GjArgs grb = g;
+    grb.skip = skip_rb;
+    MSGW_LAUNCH(k_screen_build, grid, dim3(256), 0, s, grb, (const double2*)P_iw, v, d.vpre);
+    GjArgs gg = g;
+    gg.skip = skip_gj;
+    gj_run(gg, batch, nmax, nmax, s);
+    MSGW_LAUNCH(k_screen_finish, grid, dim3(256), 0, s, gg, (const double2*)P_iw, v, d.vpre, (double2*)R_iw,
                 flags);
+    hp_finish(g, batch, nmax, h.nimax, hp, (const double2*)P_iw, v, d.vpre, (double2*)R_iw, s);
     MSGW_HIP(hipGetLastError());
 }
 
