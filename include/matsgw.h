@@ -179,9 +179,13 @@ int msgw_iw_to_tau(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t le
 
 /* a4. Screened interaction on the bosonic axis (W~ Dyson equation, eq. scrv, on i nu):
  * chi~ = v^1/2 P v^1/2;  W~ = v^1/2 [(1 - chi~)^-1 - 1] v^1/2;  R = W~ - v P v.
- * (1 - chi~) is inverted in FP64 by blocked Gauss-Jordan with partial (row) pivoting, all nq * niw_b
- * matrices of the call together (panels of 16 columns, FP64 MFMA updates).  The pivot record uses
- * the workspace's scratch: MSGW_ENOMEM unless the workspace was sized for nq_max >= nq.
+ * (1 - chi~) is inverted in FP64, all nq * niw_b matrices of the call together: a matrix whose
+ * anti-Hermitian part is at most 1e-6 of max |chi~| is taken as Hermitian, and its Hermitian part is
+ * inverted by the blocked sweep without pivoting (valid while it is positive definite, as for P <= 0;
+ * every pivot is checked); the others, and those whose sweep met a non-positive pivot, by blocked
+ * Gauss-Jordan with partial (row) pivoting (FP64 MFMA updates either way).  R keeps the P given.  The
+ * state of both uses the workspace's scratch: MSGW_ENOMEM unless the workspace was sized for
+ * nq_max >= nq.
  * P_iw, Wt_iw, R_iw: device c128 [q][niw_b][NI_q][NI_q]; v: device f64 [q][NI_q]; R_iw may be NULL.
  * info: device int [nq*niw_b], 0 or 1 + the first column whose pivot was exactly zero (the outputs of
  * that matrix are then not finite).  flags: device int or NULL; MSGW_FLAG_SINGULAR is OR-ed into it

@@ -1,14 +1,16 @@
 // Screened interaction on the bosonic Matsubara axis, FP64.
 //
-// For each (q, nu):  A = 1 - v^1/2 P v^1/2 is inverted in place by the batched blocked Gauss-Jordan
-// elimination of k_gj.hip (partial row pivoting, FP64 MFMA updates), then
-// W~ = v^1/2 (A^-1 - 1) v^1/2 and R = W~ - v P v.  This is the W~ Dyson equation
-// W~ = v P v + v P W~ after the tau convolution becomes a product on i nu.
+// For each (q, nu):  A = 1 - v^1/2 P v^1/2 is inverted in place, then W~ = v^1/2 (A^-1 - 1) v^1/2 and
+// R = W~ - v P v.  This is the W~ Dyson equation W~ = v P v + v P W~ after the tau convolution becomes a
+// product on i nu.
 //
 //   k_screen_build   A = 1 - v^1/2 P v^1/2 into the W~ buffer (16 rows per work-group);
-//   gj_run           A <- A^-1 with permuted columns, all (q, nu) matrices of the call at once;
-//   k_screen_finish  undoes the column permutation (the pivot swaps in reverse), forms W~ and R and
-//                    raises the singular flag of a matrix with a zero pivot.
+//   hp_run           the Hermitian matrices by the blocked sweep (k_hscreen.hip), which marks them done;
+//   k_screen_build   again for the matrices whose sweep met a non-positive pivot;
+//   gj_run           A <- A^-1 with permuted columns for the rest (k_gj.hip, partial row pivoting);
+//   k_screen_finish  undoes their column permutation (the pivot swaps in reverse), forms W~ and R and
+//                    raises the singular flag of a matrix with a zero pivot;
+//   hp_finish        W~ and R of the swept matrices.
 #include "internal.h"
 
 namespace msgw {
