@@ -194,16 +194,28 @@ __device__ __forceinline__ void hp_mma(int K, bool AR, bool BT, FA fa, FB fb, hp
                                        hp_dbl4 (&cim)[2][2], double2 (&As)[64][17], double2 (&Bs)[16][65]) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32, r16 = lane & 15, k4 = lane >> 4;
-    for (int t0 = 0; t0 < K; t0 += 16) {
-        for (int e = tid; e < 64 * 16; e += 256) {
+    // each chunk is fetched into registers while the previous one is multiplied
+    double2 pa[4], pb[4];
+    auto fetch = [&](int t0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
             const int r = AR ? (e & 63) : (e >> 4), t = AR ? (e >> 6) : (e & 15);
-            As[r][t] = t0 + t < K ? fa(r, t0 + t) : make_double2(0.0, 0.0);
+            pa[u] = t0 + t < K ? fa(r, t0 + t) : make_double2(0.0, 0.0);
+            const int tb = BT ? (e & 15) : (e >> 6), c = BT ? (e >> 4) : (e & 63);
+            pb[u] = t0 + tb < K ? fb(t0 + tb, c) : make_double2(0.0, 0.0);
         }
-        for (int e = tid; e < 16 * 64; e += 256) {
-            const int t = BT ? (e & 15) : (e >> 6), c = BT ? (e >> 4) : (e & 63);
-            Bs[t][c] = t0 + t < K ? fb(t0 + t, c) : make_double2(0.0, 0.0);
+    };
+    fetch(0);
+    for (int t0 = 0; t0 < K; t0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = tid + 256 * u;
+            As[AR ? (e & 63) : (e >> 4)][AR ? (e >> 6) : (e & 15)] = pa[u];
+            Bs[BT ? (e & 15) : (e >> 6)][BT ? (e >> 4) : (e & 63)] = pb[u];
         }
         __syncthreads();
+        if (t0 + 16 < K) fetch(t0 + 16);
 #pragma unroll
         for (int k0 = 0; k0 < 16; k0 += 4) {
             double2 av[2], bv[2];
