@@ -426,6 +426,114 @@ def full_study(args):
                       "rel_diff_re_diag_full_vs_diag": float((diag_of_full - d).norm() / d.norm())}), flush=True)
 
 
+def tau_solver_study(args):
+    """The paper's tau-domain solvers against the Matsubara-axis route on the same inputs, FP64:
+    W~(q, tau) of 4 q from the linear system of order 81 x 50 = 4050 (the 4x4x4-k workload's 81-point
+    UPM mesh, beta = 200, NI = 50 so that the system fits the 4096 limit; P from the library's FP64
+    polarization on M drawn on the device) against P(tau) -> P(i nu) -> screen -> W~(tau), with the
+    workload's Coulomb matrix and with it scaled by 1e-5; and G(k, tau)
+    of the states of 2 k from the Dyson equation on the dense uniform grid (an 81-point UPM mesh at
+    beta = 50: 1281 dense points, one system of order 1281 per state) against Sigma(i w) -> Dyson on i w
+    -> G(tau), at a fixed mu, for a synthetic Sigma^c(tau) of two fermionic poles per state and a static
+    shift.  Both tau routes call the library's host-synchronous entry points; the times are wall
+    clock around them (the i nu routes with a device synchronization).  Prints one JSON line."""
+    import torch
+    import gwinputs as gi
+    import paper_1602_02313_amd as amd
+
+    out = {}
+    # the W~ system
+    cfg = gi.CONFIGS["c2"].replace(name="c2_ni50", ni=50, grid=(2, 2, 1))
+    prob = gi.make_problem(cfg)
+    nq = 4
+    run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b, cfg.scale,
+                    prob.eps, prob.v, prob.n_target, precision=amd.FP64, q_batch=nq)
+    M = torch.empty(int(run.mpre[nq]), dtype=torch.complex128, device="cuda")
+    run.ctx.synth_M(cfg.seed, 0, nq, 1, amd.C128, M)
+    run.green0(0.0)
+    run.ctx.polarization(0, nq, M, amd.C128, run.G_tau, amd.FP64, run.P_tau)
+    NI, nt = int(prob.ni[0]), prob.tau.size
+    nbytes = run.ctx.tau_solver_work_size(amd.TS_WTILDE, 0, nq)
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    info = torch.zeros(nq, dtype=torch.int32, device="cuda")
+    Wsys = torch.zeros(nq * nt * NI * NI, dtype=torch.complex128, device="cuda")
+    out["w_tilde"] = {"shape": f"{nq} q, {nt} tau points, NI = {NI}: systems of order {nt * NI} with {NI} "
+                               f"right-hand sides"}
+    # the workload's Coulomb matrix, whose screening is far faster than the mesh spacing at tau = 0, and
+    # the same scaled by 1e-5 (largest eigenvalue of v^1/2 P(0) v^1/2 of order 1), where the mesh
+    # resolves W~(tau)
+    for label, f in (("coulomb", 1.0), ("coulomb_x1e-5", 1e-5)):
+        v = (run.v[: nq * NI] * f).contiguous()
+        tnu, tsys = [], []
+        for rep in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run.ctx.tau_to_iw(amd.BOSON, nq, NI * NI, run.P_tau, 1, None, run.P_iw)
+            run.ctx.screen(0, nq, run.P_iw, v, run.Wt_iw, run.R_iw, run.info, run.screen_flags)
+            run.ctx.screened_tau(0, nq, run.R_iw, run.P_tau, v, run.Wt_tau)
+            torch.cuda.synchronize()
+            tnu.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            run.ctx.wt_tau_system(0, nq, run.P_tau, v, Wsys, info, work, nbytes)
+            torch.cuda.synchronize()
+            tsys.append(time.perf_counter() - t0)
+            log(f"[tau] W~ ({label}): nu route {tnu[-1] * 1e3:.1f} ms, tau system {tsys[-1] * 1e3:.1f} ms")
+        Wnu = run.Wt_tau[: nq * nt * NI * NI]
+        out["w_tilde"][label] = {"nu_route_ms": round(1e3 * min(tnu[1:]), 2),
+                                 "tau_system_ms": round(1e3 * min(tsys[1:]), 2), "info": int(info.abs().max()),
+                                 "max_diff_over_max": float((Wsys - Wnu).abs().max() / Wnu.abs().max())}
+    del run, M, work, Wsys
+    torch.cuda.empty_cache()
+    # the G Dyson on the dense grid
+    cfg = gi.Config(name="dys_upm81", grid=(2, 1, 1), bands=((4, -1.0, -0.2), (4, 0.1, 1.5)), nb=None, ni=6,
+                    nb_range=(4, 8), ntau=80, mesh="upm", beta=50.0, niw_f=256, niw_b=16)
+    prob = gi.make_problem(cfg)
+    run = amd.GWRun(cfg.nk, prob.kmq, prob.nb, prob.ni, prob.tau, cfg.beta, cfg.niw_f, cfg.niw_b, cfg.scale,
+                    prob.eps, prob.v, prob.n_target, precision=amd.FP64, q_batch=1)
+    rng = np.random.default_rng(5)
+    nk, nbmax, nt, beta = cfg.nk, prob.eps.shape[1], prob.tau.size, cfg.beta
+
+    def g0(e, tau):  # -e^{-e tau} / (1 + e^{-beta e}) in its overflow-free form
+        return -np.exp(-e * tau) / (1.0 + np.exp(-beta * e)) if e >= 0 else \
+            -np.exp(e * (beta - tau)) / (1.0 + np.exp(beta * e))
+    sig = np.zeros((nk, nbmax, nt))
+    sst = np.zeros((nk, nbmax))
+    for k in range(nk):
+        for n in range(int(prob.nb[k])):
+            for _ in range(2):
+                sig[k, n] += rng.uniform(0.01, 0.05) * g0(rng.uniform(-1.0, 1.0), prob.tau)
+            sst[k, n] = rng.uniform(-0.1, 0.1)
+    mu = 0.05
+    run.sig_tau.copy_(torch.from_numpy(sig))
+    run.sig_x.copy_(torch.from_numpy(sst))
+    nbytes = run.ctx.tau_solver_work_size(amd.TS_DYSON, 0, nk)
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    Gt = torch.zeros((nk, nbmax, nt), dtype=torch.float64, device="cuda")
+    info = torch.zeros(nk * nbmax, dtype=torch.int32, device="cuda")
+    tnu, tsys = [], []
+    for rep in range(3):
+        run.mu.fill_(mu)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.sigma_to_iw()
+        run._dyson(search=False)
+        torch.cuda.synchronize()
+        tnu.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        run.ctx.dyson_tau(0, nk, run.eps, run.sig_x, run.mu, run.sig_tau, Gt, info, work, nbytes)
+        torch.cuda.synchronize()
+        tsys.append(time.perf_counter() - t0)
+        log(f"[tau] G: i w route {tnu[-1] * 1e3:.1f} ms, dense-grid Dyson {tsys[-1] * 1e3:.1f} ms")
+    nstates = int(sum(int(x) for x in prob.nb))
+    out["dyson"] = {"shape": f"{nstates} states on {nk} k, {nt} tau points (UPM, beta = {beta:g}), dense grid of "
+                             f"{int(round(beta / (prob.tau[1] - prob.tau[0]))) + 1} points",
+                    "iw_route_ms": round(1e3 * min(tnu[1:]), 2), "tau_dyson_ms": round(1e3 * min(tsys[1:]), 2),
+                    "info": int(info.abs().max()),
+                    "max_abs_diff": float((Gt - run.G_tau).abs().max())}
+    print(json.dumps({"study": "the paper's tau-domain solvers against the Matsubara-axis route, FP64", **out}),
+          flush=True)
+
+
 def symmetry_study(args):
     """One self-energy pass plus Dyson and gap over the full zone against the irreducible-wedge pass
     (P, W~ and the contractions for the irreducible q only, contributions added over the stars), on
@@ -554,6 +662,8 @@ def main():
     ap.add_argument("--symmetry", action="store_true",
                     help="instead of the iteration: full zone vs irreducible wedge on the cubic-symmetric "
                          "form of --config (NI = 691)")
+    ap.add_argument("--tau-solvers", action="store_true",
+                    help="instead of the iteration: the tau-domain W~ system and G Dyson against the i nu / i w routes")
     ap.add_argument("--full", action="store_true",
                     help="instead of the iteration: FULL vs DIAG split-FP16 self-energy on one q of c2")
     ap.add_argument("--screen", action="store_true",
@@ -578,6 +688,9 @@ def main():
         return
     if args.full:
         full_study(args)
+        return
+    if args.tau_solvers:
+        tau_solver_study(args)
         return
     if args.batching:
         if args.config == "c5":
