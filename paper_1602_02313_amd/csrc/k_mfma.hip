@@ -1889,6 +1889,9 @@ __device__ __forceinline__ void sigz_item(const Dev& d, int q0, const double* __
                                           double* __restrict__ Sig, int t0, int qrel, int k, int kc, int tc) {
     constexpr int CW = 32 * NTT;
     __shared__ uint32_t Ws[2][2][CW][SZ_WR];  // [buffer][hi, lo][tau][8 s x 8 j]
+    // a_I, I = 8 bi .. 8 bi + 7, of each thread's second row K: a slot per thread, written and read by
+    // that thread only (it frees the registers that hold the weight fragments one tau tile ahead)
+    __shared__ float2 As1[8][512];
     const int nk = d.nk, ntau = d.ntau, nbmax = d.nbmax;
     const int TP = gz_tp(ntau);
     // work item: (q, k, K chunk of 512, tau chunk)
@@ -1990,14 +1993,26 @@ __device__ __forceinline__ void sigz_item(const Dev& d, int q0, const double* __
         }
     };
 
-    float4 ai[2][4];   // a_I, I = 8 bi .. 8 bi + 7, for both rows (re, im pairs in float4)
+    float4 ai[4];      // a_I, I = 8 bi .. 8 bi + 7, of the first row (re, im pairs in float4); the
+                       // second row's are in As1
     float4 aj[2][2];   // a_J, J = 8 bj + 4 h2 .. + 3
     auto load_ai = [&](int bi) {
+        float4 a1[4];
 #pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
+        for (int e = 0; e < 4; ++e) {
+            ai[e] = *reinterpret_cast<const float4*>(Tb + (trow[0] + uint32_t(64 * bi + 16 * e)));
+            a1[e] = *reinterpret_cast<const float4*>(Tb + (trow[1] + uint32_t(64 * bi + 16 * e)));
+        }
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                ai[kt][e] = *reinterpret_cast<const float4*>(Tb + (trow[kt] + uint32_t(64 * bi + 16 * e)));
+        for (int e = 0; e < 4; ++e) {
+            As1[2 * e][tid] = make_float2(a1[e].x, a1[e].y);
+            As1[2 * e + 1][tid] = make_float2(a1[e].z, a1[e].w);
+        }
+    };
+    // the hi and lo weight fragments of MFMA step s, tau tile tt
+    auto bload = [&](int bf, int s, int tt, u32x4& bh, u32x4& bl) {
+        bh = reinterpret_cast<const u32x4*>(&Ws[bf][0][32 * tt + r32][0])[2 * s + h2];
+        bl = reinterpret_cast<const u32x4*>(&Ws[bf][1][32 * tt + r32][0])[2 * s + h2];
     };
     auto load_aj = [&](int bj, float4 (&dst)[2][2]) {
 #pragma unroll
@@ -2035,7 +2050,13 @@ __device__ __forceinline__ void sigz_item(const Dev& d, int q0, const double* __
                 load_aj(bj2, ajn);
                 wload(b + 1, 0);
             }
-            // 8 MFMA steps: step s pairs I = 8 bi + s with J = 8 bj + 4 h2 .. + 3 (this lane's half)
+            // 8 MFMA steps: step s pairs I = 8 bi + s with J = 8 bj + 4 h2 .. + 3 (this lane's half).
+            // The weight fragments of the next tau tile (of the next step's first tile after the last)
+            // are read from LDS before the MFMAs of the current one, and the second row's a_I of the
+            // next step during the current step.
+            float2 a1 = As1[0][tid];
+            u32x4 bh, bl;
+            bload(buf, 0, 0, bh, bl);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
                 if (s == 4 && more) {  // the other buffer is not read in this block
@@ -2045,8 +2066,15 @@ __device__ __forceinline__ void sigz_item(const Dev& d, int q0, const double* __
                 u32x4 zh[2], zl[2];
 #pragma unroll
                 for (int kt = 0; kt < 2; ++kt) {
-                    const float4 a4 = ai[kt][s >> 1];
-                    const float ar = (s & 1) ? a4.z : a4.x, aim = (s & 1) ? a4.w : a4.y;
+                    float ar, aim;
+                    if (kt == 0) {
+                        const float4 a4 = ai[s >> 1];
+                        ar = (s & 1) ? a4.z : a4.x;
+                        aim = (s & 1) ? a4.w : a4.y;
+                    } else {
+                        ar = a1.x;
+                        aim = a1.y;
+                    }
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const float4 c4 = aj[kt][j >> 1];
@@ -2058,16 +2086,23 @@ __device__ __forceinline__ void sigz_item(const Dev& d, int q0, const double* __
                         zl[kt][j] = l;
                     }
                 }
+                if (s < 7) a1 = As1[s + 1][tid];
 #pragma unroll
                 for (int tt = 0; tt < NTT; ++tt) {
-                    const u32x4* hrow = reinterpret_cast<const u32x4*>(&Ws[buf][0][32 * tt + r32][0]);
-                    const u32x4* lrow = reinterpret_cast<const u32x4*>(&Ws[buf][1][32 * tt + r32][0]);
-                    const u32x4 bh = hrow[2 * s + h2], bl = lrow[2 * s + h2];
+                    u32x4 bhn, bln;
+                    if (tt + 1 < NTT) bload(buf, s, tt + 1, bhn, bln);
+                    else if (s < 7) bload(buf, s + 1, 0, bhn, bln);
+                    // the reads above are issued before these MFMAs
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int kt = 0; kt < 2; ++kt) {
                         acc[kt][tt] = mfma32p<PR>(zh[kt], bh, acc[kt][tt]);
                         acc[kt][tt] = mfma32p<PR>(zh[kt], bl, acc[kt][tt]);
                         acc[kt][tt] = mfma32p<PR>(zl[kt], bh, acc[kt][tt]);
+                    }
+                    if (tt + 1 < NTT || s < 7) {
+                        bh = bhn;
+                        bl = bln;
                     }
                 }
                 // keeps the Z of later steps from being formed (and held) ahead of time
