@@ -185,7 +185,9 @@ int msgw_iw_to_tau(msgw_ctx* c, void* stream, int stat, int64_t nblk, int64_t le
  * every pivot is checked); the others, and those whose sweep met a non-positive pivot, by blocked
  * Gauss-Jordan with partial (row) pivoting (FP64 MFMA updates either way).  R keeps the P given.  The
  * state of both uses the workspace's scratch: MSGW_ENOMEM unless the workspace was sized for
- * nq_max >= nq.
+ * nq_max >= nq.  MSGW_ENOTSUP, before anything is enqueued, for more than 65535 matrices
+ * (nq * niw_b) in one call or more 64 x 64 update tiles than one launch takes
+ * (8 ceil(nq niw_b / 8) ceil(NI/64)^2 * 256 threads >= 2^32): split the q range.
  * P_iw, Wt_iw, R_iw: device c128 [q][niw_b][NI_q][NI_q]; v: device f64 [q][NI_q]; R_iw may be NULL.
  * info: device int [nq*niw_b], 0 or 1 + the first column whose pivot was exactly zero (the outputs of
  * that matrix are then not finite).  flags: device int or NULL; MSGW_FLAG_SINGULAR is OR-ed into it

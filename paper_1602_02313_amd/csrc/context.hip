@@ -664,6 +664,7 @@ int msgw_screen(msgw_ctx* c, void* stream, int q0, int nq, const void* P_iw, con
         check_qrange(c, q0, nq);
         need(P_iw && v && Wt_iw && info, MSGW_EINVAL, "null pointer");
         need(P_iw != Wt_iw, MSGW_EINVAL, "P_iw and Wt_iw must not alias");
+        screen_validate(c->h, q0, nq);
         need(screen_scratch_bytes(c->h, nq) <= scratch_mfma_bytes(c->d, c->h), MSGW_ENOMEM,
              "screen: workspace too small for nq (size it with msgw_workspace_size(nq_max >= nq))");
         c->prep = msgw_ctx::Prepared();  // the pivot record uses the split-precision scratch

@@ -107,6 +107,9 @@ void launch_inv_boson(const Dev& d, hipStream_t s, int64_t nblk, int mat_n, cons
 // scratch: screen_scratch_bytes(h, nq) bytes (the pivot rows of every (q, nu) matrix, and the state of
 // the Hermitian path, k_hscreen.hip)
 size_t screen_scratch_bytes(const Host& h, int nq);
+// throws MSGW_ENOTSUP for a call the screen's launches cannot take (NI above 4096, more than 65535
+// matrices, an update grid beyond 2^32 threads); called before anything is enqueued
+void screen_validate(const Host& h, int q0, int nq);
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
                    const double* v, void* Wt_iw, void* R_iw, int* info, int* flags, int* perm);
 void launch_sigma_x(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* M,

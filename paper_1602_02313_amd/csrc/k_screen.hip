@@ -95,6 +95,20 @@ size_t screen_scratch_bytes(const Host& h, int nq) {
     return perm + hp_scratch_bytes(nq * h.niw_b, h.nimax);
 }
 
+void screen_validate(const Host& h, int q0, int nq) {
+    int nmax = 0;
+    for (int q = q0; q < q0 + nq; ++q) nmax = std::max(nmax, h.ni[q]);
+    const int64_t batch = int64_t(nq) * h.niw_b;
+    if (nmax > kGjMaxN) throw Error(MSGW_ENOTSUP, "screen: NI above 4096");
+    if (batch > 65535)
+        throw Error(MSGW_ENOTSUP, "screen: nq * niw_b above 65535 matrices in one call (split the q range)");
+    // the 1-D grids of the two eliminations' updates hold at most 2^32 - 1 threads (the Gauss-Jordan's,
+    // all 64 x 64 tiles of every matrix, is the larger)
+    const double tiles = 8.0 * double((batch + 7) / 8) * ((nmax + 63) / 64) * ((nmax + 63) / 64);
+    if (tiles * 256.0 > 4294967295.0)
+        throw Error(MSGW_ENOTSUP, "screen: too many update tiles for one launch (split the q range)");
+}
+
 void launch_screen(const Dev& d, const Host& h, hipStream_t s, int q0, int nq, const void* P_iw,
                    const double* v, void* Wt_iw, void* R_iw, int* info, int* flags, int* perm) {
     int nmax = 0;

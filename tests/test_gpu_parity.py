@@ -429,3 +429,25 @@ def test_dyson_matrix_after_full_self_energy(torch):
     e = rel(got["G_tau"], ref["G_tau"])
     print(f"FULL chain: G(tau) rel {e:.2e}, mu {got['mu']:.12f} ({ref['mu']:.12f})")
     assert e < TOL and got["flags"] == 0
+
+
+def test_screen_refuses_shapes_before_launching(torch):
+    """More than 65535 matrices (nq * niw_b) in one call are refused with MSGW_ENOTSUP before anything
+    is enqueued (the output buffers are never touched)."""
+    import paper_1602_02313_amd as amd
+    tau = np.array([0.0, 1.0 / 3.0, 2.0 / 3.0, 1.0])
+    ni, niw_b = 2, 65536
+    ctx = amd.Context(0)
+    ctx.set_problem(1, [0], [1], [ni], tau, 1.0, 2, niw_b, -1.0)
+    ws = torch.empty(ctx.workspace_size(1) + 256, dtype=torch.uint8, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ctx.set_workspace(ws[off:], ws.numel() - off)
+    dummy = torch.full((4,), 7.0, dtype=torch.complex128, device="cuda")
+    v = torch.ones(ni, dtype=torch.float64, device="cuda")
+    info = torch.full((4,), -3, dtype=torch.int32, device="cuda")
+    print(f"NI = {ni}, niw_b = {niw_b}: workspace {ws.numel() / 2**30:.2f} GiB", flush=True)
+    with pytest.raises(amd.MsgwError) as e:
+        ctx.screen(0, 1, dummy, v, dummy.clone(), None, info)
+    assert e.value.code == amd.ENOTSUP
+    torch.cuda.synchronize()
+    assert (info == -3).all() and (dummy == 7.0).all()
